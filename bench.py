@@ -1,0 +1,162 @@
+"""Benchmark: frames/sec and seed x pixel updates/sec of Faster Mean-shift on one
+MI355X, 512 x 512 frame, D = 32, BF16 + FP32-refine form against the FP32 form.
+
+One step = one fms_cluster call on one frame already resident in HBM: compaction
+and normalisation, the seed rounds of the online seed policy (seed selection,
+fused mean-shift iterations, window counts, pruning, coverage), and the labels.
+
+Prints one JSON line.  ``value`` is BF16+FP32-refine frames/sec; the FP32 form,
+update rates, the BF16 mode error against the FP64 oracle, the roofline of the
+dominant kernel (live HIP-event timings from the library) and the oracle's CPU
+rate on the same frame are carried alongside.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
+    for _ in range(warmup):
+        fms.cluster(emb, mask, h, precision=precision)
+    torch.cuda.synchronize()
+    agg = {"step_ms": [0.0, 0.0], "step_updates": [0, 0], "step_launches": [0, 0], "updates": 0,
+           "refine_updates": 0}
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = fms.cluster(emb, mask, h, precision=precision, timing=1)
+        st = last[2]
+        for k in range(2):
+            agg["step_ms"][k] += st["step_ms"][k]
+            agg["step_updates"][k] += st["step_updates"][k]
+            agg["step_launches"][k] += st["step_launches"][k]
+        agg["updates"] += st["seed_pixel_updates"]
+        agg["refine_updates"] += st["refine_updates"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, agg, last
+
+
+def _roofline(agg, dim):
+    # Dominant kernel: the fused-step form with the larger summed duration.
+    k = 1 if agg["step_ms"][1] >= agg["step_ms"][0] else 0
+    dtype = "bf16" if k == 1 else "fp32"
+    ms = agg["step_ms"][k]
+    flops = agg["step_updates"][k] * 4.0 * dim  # 2D for the dot product + 2D for the masked sum
+    launches = max(1, agg["step_launches"][k])
+    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    peak = PEAK_TFLOPS[dtype]
+    return {"kernel": "k_shift_" + dtype, "bound": "mfma", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "avg_launch_us": ms * 1e3 / launches, "launches": agg["step_launches"][k],
+            "flops_per_launch": flops / launches}
+
+
+def _cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        return max([int(i.get("num_threads", 1)) for i in info] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2007_14283_amd as fms
+    import synth
+
+    spec = synth.PLAIN512
+    frame = synth.make_frame(spec)
+    h = frame.bandwidth
+    emb = torch.from_numpy(frame.emb).cuda()
+    mask = torch.from_numpy(frame.mask).cuda()
+    torch.cuda.synchronize()
+
+    dt_b, agg_b, last_b = _time_form(fms, torch, emb, mask, h, fms.BF16_REFINE, a.steps, a.warmup)
+    print(f"bf16+refine: {a.steps} frames in {dt_b:.3f}s", file=sys.stderr, flush=True)
+    dt_f, agg_f, last_f = _time_form(fms, torch, emb, mask, h, fms.FP32, a.steps, a.warmup)
+    print(f"fp32: {a.steps} frames in {dt_f:.3f}s", file=sys.stderr, flush=True)
+
+    fps_b = a.steps / dt_b
+    fps_f = a.steps / dt_f
+    upd_b = (agg_b["updates"] + agg_b["refine_updates"]) / dt_b
+    upd_f = agg_f["updates"] / dt_f
+
+    out = {
+        "metric": "frames/sec (BF16+FP32-refine) and seed-pixel updates/sec, 512x512 D=32",
+        "value": fps_b,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt_b / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": f"one {spec.height}x{spec.width} frame, {spec.n_cells} elliptic cells "
+                               f"(radii {spec.r_min}-{spec.r_max}), D={spec.dim}, sigma={spec.sigma}, "
+                               f"<=5% overlap, h={h}, seed {spec.seed}",
+                   "n_fg": frame.n_fg, "bandwidth": h, "parallelism": "single GPU"},
+        "updates_per_s": upd_b,
+        "modes": int(len(last_b[0])),
+        "fp32": {"frames_per_s": fps_f, "ms_per_frame": 1e3 * dt_f / a.steps, "updates_per_s": upd_f,
+                 "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim),
+                 "kernel_ms_per_frame": agg_f["step_ms"][0] / a.steps},
+        "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
+        "roofline": _roofline(agg_b, spec.dim),
+    }
+
+    if not a.no_cpu:
+        from oracle import cluster as C
+        from tests import parity
+        runs, t_cpu, res = 0, 0.0, None
+        while runs == 0 or (t_cpu < a.cpu_seconds and runs < 10):
+            t0 = time.perf_counter()
+            res = C.cluster(frame.emb, frame.mask, C.Params(bandwidth=h))
+            t_cpu += time.perf_counter() - t0
+            runs += 1
+        out["cpu_baseline"] = {"value": runs / t_cpu, "unit": "frames/s", "cores": _cpu_threads(),
+                               "kind": "oracle",
+                               "sample": f"{runs} full frames of the same 512x512 workload (FP64 NumPy)"}
+        for name, last in (("bf16", last_b), ("fp32", last_f)):
+            mm = parity.match_modes(last[0].cpu().numpy(), res.modes)
+            lc = parity.compare_labels(last[1].cpu().numpy(), res, mm, 1.0 - h)
+            out[f"{name}_vs_oracle"] = {"max_mode_err": mm.max_error,
+                                        "modes_within_tol": int(np.sum(mm.errors <= (1e-3 if name == "bf16"
+                                                                                     else 1e-5))),
+                                        "unmatched_gpu": mm.unmatched_gpu, "unmatched_oracle": mm.unmatched_oracle,
+                                        "label_mismatch": lc.mismatched}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * fms.h - C ABI of the MI355X (gfx950) Faster Mean-shift library.
+ *
+ * The library clusters L2-normalised per-pixel embeddings with cosine,
+ * flat-kernel mean shift (Eq. 8-11 of "Faster Mean-shift: GPU-accelerated
+ * clustering for cosine embedding-based cell segmentation and tracking",
+ * arXiv 2007.14283), iterating a batch of seeds in parallel with early stopping
+ * (Sec. 3.2.3) under the online seed optimisation policy (Eq. 14, Eq. 19,
+ * Sec. 3.2.4), then prunes the modes and assigns every foreground pixel to
+ * its most similar mode (Alg. 2).
+ *
+ * Conventions shared by every entry point
+ *   - Buffers marked "device" live in the memory of the handle's GPU; buffers
+ *     marked "host" live in ordinary host memory.  The caller owns every input
+ *     and output buffer; the library owns only the workspace inside a handle,
+ *     which grows on demand and is released by fms_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is enqueued on it.  fms_cluster and fms_shift_seeds make
+ *     host decisions between GPU steps (the CPU steers the seed count, Fig. 3),
+ *     so they synchronise `stream` internally; their outputs are complete when
+ *     they return.  fms_seed_order only enqueues.
+ *   - Errors are reported by status code only: nothing throws across the ABI
+ *     and nothing aborts.  On error the output contents are unspecified except
+ *     where stated.
+ *   - One host thread at a time per handle.  Handles are independent.
+ *   - Embeddings: FP32, any D from 1 to 128, addressed through strides, so
+ *     pixel-major (NHWC: pixel_stride = D, channel_stride = 1) and
+ *     channel-major (NCHW: pixel_stride = 1, channel_stride = H*W) layouts are
+ *     both read in place.  Pixel p = y*W + x (raster order).
+ */
+#ifndef FMS_H
+#define FMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fms_handle_s* fms_handle;
+
+typedef enum {
+  FMS_OK = 0,
+  FMS_ERR_INVALID_ARG = -1, /* null pointer, bad size or parameter out of range */
+  FMS_ERR_UNSUPPORTED = -2, /* e.g. D > 128 */
+  FMS_ERR_BAD_INPUT = -3,   /* a foreground embedding is zero or not finite */
+  FMS_ERR_CAPACITY = -4,    /* k_max too small; *n_modes holds the required count */
+  FMS_ERR_HIP = -5          /* the HIP runtime reported an error */
+} fms_status;
+
+typedef enum {
+  FMS_PREC_FP32 = 0,        /* every step's contractions on FP32 MFMA */
+  FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) until the early stop, then
+                               refine_iters FP32 steps on the converged seeds */
+} fms_precision;
+
+/* Clustering parameters.  fms_default_params fills the paper's values. */
+typedef struct {
+  double bandwidth;   /* h in cosine distance: a vector is in a window when
+                         1 - cos <= h (Eq. 9, Eq. 11).  Required, 0 < h < 2.
+                         The paper uses 0.1 (Sec. 4.1 Design, Sec. 4.2). */
+  double conv_tol;    /* a seed has converged when the cosine distance between
+                         consecutive centres is below this; <= 0 means h/1000
+                         (Sec. 3.2.1). */
+  double gamma;       /* early stop: the iteration of a round ends once more than
+                         gamma of its seeds have converged (Sec. 3.2.3); 0.9. */
+  double big_l;       /* L: double N while N < L * N_min (Eq. 21, Sec. 3.2.4); 2. */
+  double big_h;       /* H: next frame starts at N - N_min when N > H * N_min; 8. */
+  double p_target;    /* P in Eq. 19; 0.99 (Sec. 3.2.2). */
+  uint64_t seed;      /* key of the seed order (SplitMix64-keyed permutation). */
+  int32_t n_initial;  /* N_initial = 128 (Sec. 3.2.4). */
+  int32_t n_state_in; /* N carried over from the previous frame; <= 0: n_initial. */
+  int32_t max_iter;   /* cap on iterations per round (not in the paper); 100. */
+  int32_t max_rounds; /* cap on seed rounds per frame (not in the paper); 32. */
+  int32_t precision;  /* fms_precision. */
+  int32_t refine_iters; /* FP32 steps after a BF16 round; 3. */
+  int32_t timing;     /* nonzero: time every fused-step launch with HIP events on
+                         `stream` and report the totals in fms_stats. */
+  int32_t reserved;
+} fms_params;
+
+/* Per-call statistics (host struct). */
+typedef struct {
+  int64_t seed_pixel_updates; /* sum over iterations of (active seeds) * n */
+  double n_min;               /* last Eq. 19 value; NaN when no mode was found */
+  int32_t n_fg;               /* foreground pixels n */
+  int32_t rounds;             /* seed rounds run */
+  int32_t seeds_used;         /* seeds iterated */
+  int32_t iterations_total;   /* iterations summed over rounds (refine steps excluded) */
+  int32_t refine_steps;       /* FP32 refine steps run (BF16 form) */
+  int32_t n_discarded;        /* seeds dropped unconverged by the early stop */
+  int32_t n_uncovered;        /* foreground pixels farther than h from every mode */
+  int32_t n_state_out;        /* N to carry into the next frame (Sec. 3.2.4) */
+  int32_t refine_unconverged; /* BF16 form: seeds whose last refine step moved >= tol */
+  int32_t reserved;
+  int64_t refine_updates;     /* (seeds) * n summed over FP32 refine steps */
+  /* Fused-step kernel timing, filled when fms_params.timing is nonzero.
+   * Index 0: FP32 form of the step, index 1: BF16 form. */
+  double step_ms[2];          /* summed launch durations (HIP events), ms */
+  int64_t step_updates[2];    /* (active seeds) * n summed over those launches */
+  int32_t step_launches[2];
+} fms_stats;
+
+/* Fill *p with the paper's defaults (bandwidth 0.1, tol h/1000, gamma 0.9,
+ * N_initial 128, L 2, H 8, P 0.99) and this library's caps (max_iter 100,
+ * max_rounds 32, FP32, 3 refine steps, seed 0).  p: host, not NULL. */
+void fms_default_params(fms_params* p);
+
+/* Create a handle bound to GPU `device_ordinal`.  *out receives the handle.
+ * Errors: FMS_ERR_INVALID_ARG (out NULL, bad ordinal), FMS_ERR_HIP. */
+fms_status fms_create(fms_handle* out, int32_t device_ordinal);
+
+/* Release a handle and its workspace.  NULL is accepted. */
+fms_status fms_destroy(fms_handle h);
+
+/* Cluster one frame (Alg. 2 under the online seed optimisation policy).
+ *
+ *  emb            device, FP32; element (pixel p, channel c) at
+ *                 emb[p*pixel_stride + c*channel_stride].
+ *  mask           device, height*width bytes, nonzero = foreground
+ *                 (the predicted segmentation of Sec. 3.2.2); NULL = all pixels.
+ *  height, width  frame size (>= 1 each); dim = D (1..128).
+ *  p              host, clustering parameters.
+ *  modes          device, k_max*dim FP32: unit-norm modes in acceptance order.
+ *  mode_counts    device, k_max int32 window counts of the modes, or NULL.
+ *  k_max          capacity of `modes` in rows.
+ *  n_modes        host: number of modes written (or required, on CAPACITY).
+ *  labels         device, height*width int32: -1 on background, else the index
+ *                 of the most similar mode (lowest index on ties).
+ *  stats          host, or NULL.
+ * An all-background mask returns FMS_OK with *n_modes = 0 and all labels -1.
+ * Errors: INVALID_ARG, UNSUPPORTED (dim > 128), BAD_INPUT, CAPACITY, HIP. */
+fms_status fms_cluster(fms_handle h, void* stream,
+                       const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                       const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                       const fms_params* p,
+                       float* modes, int32_t* mode_counts, int32_t k_max, int32_t* n_modes,
+                       int32_t* labels, fms_stats* stats);
+
+/* One round of the parallel seed iteration (Alg. 2, the loop over seeds, with
+ * the early stop of Sec. 3.2.3) on an explicit seed list, for lockstep checks
+ * and benchmarking of the hot loop.
+ *
+ *  emb, strides, mask, height, width, dim: as fms_cluster.
+ *  seed_fg        device, n_seeds int32 foreground ordinals (index into the
+ *                 raster-ordered list of foreground pixels), each in [0, n).
+ *  p              host; bandwidth, conv_tol, gamma, max_iter, precision and
+ *                 refine_iters are used.
+ *  endpoints      device, n_seeds*dim FP32: final centre of each seed.
+ *  iters          device, n_seeds int32: steps taken until it converged or
+ *                 the round stopped (refine steps excluded).
+ *  converged      device, n_seeds bytes: 1 = converged, 0 = discarded.
+ *  counts         device, n_seeds int32: window count at converged endpoints,
+ *                 -1 for discarded seeds; may be NULL.
+ *  stats          host or NULL (seed_pixel_updates, iterations_total,
+ *                 refine_unconverged, n_fg are filled).
+ * Errors: INVALID_ARG (including a seed index outside [0, n)), UNSUPPORTED,
+ * BAD_INPUT, HIP. */
+fms_status fms_shift_seeds(fms_handle h, void* stream,
+                           const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                           const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                           const int32_t* seed_fg, int32_t n_seeds, const fms_params* p,
+                           float* endpoints, int32_t* iters, uint8_t* converged,
+                           int32_t* counts, fms_stats* stats);
+
+/* The seed order: order[j] = foreground ordinal at position j, j in [0, n),
+ * a permutation of [0, n) keyed by `seed` (four-round Feistel network whose
+ * round keys and round function come from SplitMix64, with cycle walking).
+ *  order  device, n int32.  Enqueued on `stream`; does not synchronise.
+ * Errors: INVALID_ARG (n < 0, order NULL with n > 0), HIP. */
+fms_status fms_seed_order(fms_handle h, void* stream, int32_t n, uint64_t seed, int32_t* order);
+
+/* Static text for a status code. */
+const char* fms_status_string(fms_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMS_H */

@@ -173,18 +173,21 @@ def cluster(emb: np.ndarray, mask: Optional[np.ndarray], params: Params) -> Resu
 
 def lockstep(emb: np.ndarray, mask: Optional[np.ndarray], seeds_fg: np.ndarray, params: Params):
     """One round of the seed iteration on an explicit seed list (foreground
-    ordinals), plus window counts at the converged endpoints."""
+    ordinals), plus window counts at the converged endpoints, with the margin
+    bookkeeping of ``meanshift.iterate(trace=True)`` and ``end_margin``, the
+    window margin at each endpoint."""
     emb = np.asarray(emb)
     dim = emb.shape[-1]
     rows = emb.reshape(-1, dim)
     fg = ms.foreground(mask, rows.shape[0])
     x = ms.normalise(rows[fg])
     thr = 1.0 - params.bandwidth
-    it = ms.iterate(x, np.asarray(seeds_fg), thr, params.tol, params.gamma, params.max_iter)
+    it = ms.iterate(x, np.asarray(seeds_fg), thr, params.tol, params.gamma, params.max_iter, trace=True)
     counts = np.full(len(seeds_fg), -1, np.int64)
     c = np.flatnonzero(it["converged"])
     counts[c] = ms.window_counts(it["endpoints"][c], x, thr)
     it["counts"] = counts
+    it["end_margin"] = ms.window_margin(np.nan_to_num(it["endpoints"]), x, thr)
     it["x"] = x
     return it
 

@@ -82,15 +82,29 @@ def shift(y: np.ndarray, x: np.ndarray, thr: float):
     return out, delta, members
 
 
+def window_margin(y: np.ndarray, x: np.ndarray, thr: float) -> np.ndarray:
+    """Distance of the closest vector to each window's edge, min_i |y . x_i - thr|
+    (bookkeeping for the comparison with lower-precision results)."""
+    out = np.empty(len(y))
+    blk = _seed_block(len(x))
+    for a in range(0, len(y), blk):
+        out[a:a + blk] = np.min(np.abs(y[a:a + blk] @ x.T - thr), axis=1)
+    return out
+
+
 def iterate(x: np.ndarray, seeds: np.ndarray, thr: float, tol: float, gamma: float,
-            max_iter: int) -> Dict[str, np.ndarray]:
+            max_iter: int, trace: bool = False) -> Dict[str, np.ndarray]:
     """Parallel seed iteration of Alg. 2 with the early stop of Sec. 3.2.3.
 
     ``seeds`` are row indices into ``x``; each centre starts at its seed vector.
     Every iteration moves all still-active centres one step.  A centre whose
     delta falls below ``tol`` is frozen (converged).  Iteration stops after the
     step in which the number of converged centres exceeds gamma * len(seeds), when
-    no centre is active, or after ``max_iter`` steps."""
+    no centre is active, or after ``max_iter`` steps.
+
+    With ``trace`` the result also holds, per seed, the smallest window margin
+    over the centres it was evaluated at (``margin``) and the smallest
+    |delta - tol| (``tol_margin``); neither changes the iteration."""
     seeds = np.asarray(seeds, dtype=np.int64)
     m = len(seeds)
     y = x[seeds].copy()
@@ -101,6 +115,8 @@ def iterate(x: np.ndarray, seeds: np.ndarray, thr: float, tol: float, gamma: flo
     updates = 0
     steps = 0
     active_per_step: List[int] = []
+    margin = np.full(m, np.inf)
+    tol_margin = np.full(m, np.inf)
     for _ in range(max_iter):
         idx = np.flatnonzero(active)
         if idx.size == 0:
@@ -108,7 +124,11 @@ def iterate(x: np.ndarray, seeds: np.ndarray, thr: float, tol: float, gamma: flo
         steps += 1
         active_per_step.append(int(idx.size))
         updates += int(idx.size) * len(x)
+        if trace:
+            margin[idx] = np.minimum(margin[idx], window_margin(y[idx], x, thr))
         yn, delta, _ = shift(y[idx], x, thr)
+        if trace:
+            tol_margin[idx] = np.minimum(tol_margin[idx], np.abs(np.nan_to_num(delta, nan=np.inf) - tol))
         dead = ~np.isfinite(delta)
         iters[idx] += 1
         live = idx[~dead]
@@ -120,8 +140,12 @@ def iterate(x: np.ndarray, seeds: np.ndarray, thr: float, tol: float, gamma: flo
         active[done] = False
         if conv.sum() > gamma * m:
             break
-    return {"endpoints": y, "converged": conv, "iters": iters, "updates": updates,
-            "steps": steps, "last_delta": last_delta, "active_per_step": active_per_step}
+    out = {"endpoints": y, "converged": conv, "iters": iters, "updates": updates,
+           "steps": steps, "last_delta": last_delta, "active_per_step": active_per_step}
+    if trace:
+        out["margin"] = margin
+        out["tol_margin"] = tol_margin
+    return out
 
 
 def window_counts(y: np.ndarray, x: np.ndarray, thr: float) -> np.ndarray:

@@ -1,0 +1,210 @@
+"""Faster Mean-shift (arXiv 2007.14283) on MI355X: Python binding of libfms.so.
+
+Cosine, flat-kernel mean shift over per-pixel embeddings (Eq. 8-11), seeds
+iterated in parallel with early stopping (Sec. 3.2.3) under the online seed
+optimisation policy (Sec. 3.2.2, 3.2.4), then mode pruning and pixel
+assignment (Alg. 2).  Every step runs in the library's HIP kernels; this module
+only marshals arguments.  PyTorch provides device memory and the stream.
+
+    modes, labels, stats = cluster(emb, mask, bandwidth=0.2)
+
+``emb`` is a float32 GPU tensor, (H, W, D) by default or (D, H, W) with
+``layout="nchw"``; ``mask`` is an (H, W) GPU tensor (nonzero = foreground) or
+None.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Dict, Optional
+
+from . import _binding as B
+
+__all__ = ["Params", "FmsError", "cluster", "shift_seeds", "seed_order", "default_params", "library"]
+
+FP32 = B.FMS_PREC_FP32
+BF16_REFINE = B.FMS_PREC_BF16_REFINE
+
+
+class FmsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        lib = B.load()
+        msg = lib.fms_status_string(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+        self.status = status
+
+
+@dataclasses.dataclass
+class Params:
+    bandwidth: float = 0.1
+    conv_tol: float = 0.0
+    gamma: float = 0.9
+    big_l: float = 2.0
+    big_h: float = 8.0
+    p_target: float = 0.99
+    seed: int = 0
+    n_initial: int = 128
+    n_state_in: int = 0
+    max_iter: int = 100
+    max_rounds: int = 32
+    precision: int = FP32
+    refine_iters: int = 3
+    timing: int = 0
+
+    def to_c(self) -> B.FmsParams:
+        c = B.FmsParams()
+        for f in dataclasses.fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+def library():
+    """The loaded libfms.so (raises when it is not built)."""
+    return B.load()
+
+
+def default_params() -> Params:
+    c = B.FmsParams()
+    library().fms_default_params(ctypes.byref(c))
+    return Params(**{f.name: getattr(c, f.name) for f in dataclasses.fields(Params)})
+
+
+_handles: Dict[int, ctypes.c_void_p] = {}
+
+
+def _handle(device_index: int) -> ctypes.c_void_p:
+    h = _handles.get(device_index)
+    if h is None:
+        h = ctypes.c_void_p()
+        st = library().fms_create(ctypes.byref(h), device_index)
+        if st != B.FMS_OK:
+            raise FmsError(st, "fms_create")
+        _handles[device_index] = h
+    return h
+
+
+def _params(params: Optional[Params], kw) -> Params:
+    p = dataclasses.replace(params) if params is not None else Params()
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def _frame_args(emb, layout: str):
+    import torch
+    if not isinstance(emb, torch.Tensor) or not emb.is_cuda:
+        raise TypeError("emb must be a GPU tensor")
+    if emb.dtype != torch.float32:
+        raise TypeError("emb must be float32")
+    if emb.dim() != 3:
+        raise ValueError("emb must be 3-D")
+    if layout == "nhwc":
+        h, w, d = emb.shape
+        if emb.stride(0) != w * emb.stride(1):
+            emb = emb.contiguous()
+        ps, cs = emb.stride(1), emb.stride(2)
+    elif layout == "nchw":
+        d, h, w = emb.shape
+        if emb.stride(1) != w * emb.stride(2):
+            emb = emb.contiguous()
+        ps, cs = emb.stride(2), emb.stride(0)
+    else:
+        raise ValueError("layout must be 'nhwc' or 'nchw'")
+    return emb, h, w, d, ps, cs
+
+
+def _mask_arg(mask, h, w, device):
+    import torch
+    if mask is None:
+        return None, None
+    if not isinstance(mask, torch.Tensor):
+        raise TypeError("mask must be a tensor or None")
+    m = mask.to(device=device, dtype=torch.uint8).reshape(h * w).contiguous()
+    return m, m.data_ptr()
+
+
+def _stream_ptr(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def cluster(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str = "nhwc",
+            params: Optional[Params] = None, k_max: int = 4096, **kw):
+    """Cluster one frame.  Returns (modes [K, D] float32, labels [H, W] int32,
+    stats dict with ``mode_counts`` added)."""
+    import torch
+    if bandwidth is not None:
+        kw["bandwidth"] = bandwidth
+    p = _params(params, kw)
+    emb, h, w, d, ps, cs = _frame_args(emb, layout)
+    dev = emb.device
+    m, mptr = _mask_arg(mask, h, w, dev)
+    lib = library()
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    cp = p.to_c()
+    while True:
+        modes = torch.empty((max(k_max, 1), d), dtype=torch.float32, device=dev)
+        counts = torch.empty((max(k_max, 1),), dtype=torch.int32, device=dev)
+        labels = torch.empty((h, w), dtype=torch.int32, device=dev)
+        nm = ctypes.c_int32(0)
+        stats = B.FmsStats()
+        st = lib.fms_cluster(hdl, _stream_ptr(dev), ctypes.c_void_p(emb.data_ptr()), ps, cs,
+                             ctypes.c_void_p(mptr) if mptr else None, h, w, d, ctypes.byref(cp),
+                             ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()), k_max,
+                             ctypes.byref(nm), ctypes.c_void_p(labels.data_ptr()), ctypes.byref(stats))
+        if st == B.FMS_ERR_CAPACITY and nm.value > k_max:
+            k_max = nm.value
+            continue
+        if st != B.FMS_OK:
+            raise FmsError(st, "fms_cluster")
+        break
+    k = nm.value
+    out = stats.as_dict()
+    out["mode_counts"] = counts[:k]
+    return modes[:k], labels, out
+
+
+def shift_seeds(emb, mask, seeds, *, layout: str = "nhwc", params: Optional[Params] = None, **kw):
+    """One round of the parallel seed iteration on explicit seeds (foreground
+    ordinals).  Returns a dict with endpoints [m, D], iters, converged,
+    counts and stats."""
+    import torch
+    p = _params(params, kw)
+    emb, h, w, d, ps, cs = _frame_args(emb, layout)
+    dev = emb.device
+    m, mptr = _mask_arg(mask, h, w, dev)
+    sd = torch.as_tensor(seeds).to(device=dev, dtype=torch.int32).contiguous()
+    ns = int(sd.numel())
+    endpoints = torch.empty((max(ns, 1), d), dtype=torch.float32, device=dev)
+    iters = torch.empty((max(ns, 1),), dtype=torch.int32, device=dev)
+    conv = torch.empty((max(ns, 1),), dtype=torch.uint8, device=dev)
+    counts = torch.empty((max(ns, 1),), dtype=torch.int32, device=dev)
+    stats = B.FmsStats()
+    lib = library()
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    cp = p.to_c()
+    st = lib.fms_shift_seeds(hdl, _stream_ptr(dev), ctypes.c_void_p(emb.data_ptr()), ps, cs,
+                             ctypes.c_void_p(mptr) if mptr else None, h, w, d,
+                             ctypes.c_void_p(sd.data_ptr()), ns, ctypes.byref(cp),
+                             ctypes.c_void_p(endpoints.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
+                             ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                             ctypes.byref(stats))
+    if st != B.FMS_OK:
+        raise FmsError(st, "fms_shift_seeds")
+    return {"endpoints": endpoints[:ns], "iters": iters[:ns], "converged": conv[:ns],
+            "counts": counts[:ns], "stats": stats.as_dict()}
+
+
+def seed_order(n: int, seed: int = 0, device=None):
+    """The library's seed order: a permutation of range(n) as an int32 tensor."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((max(n, 1),), dtype=torch.int32, device=dev)
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    st = library().fms_seed_order(hdl, _stream_ptr(dev), n, seed, ctypes.c_void_p(out.data_ptr()))
+    if st != B.FMS_OK:
+        raise FmsError(st, "fms_seed_order")
+    torch.cuda.current_stream(dev).synchronize()
+    return out[:n]

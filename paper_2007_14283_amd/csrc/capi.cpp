@@ -1,0 +1,697 @@
+// Host runtime of the Faster Mean-shift library: handle and workspace, frame
+// preparation, the round loop of the online seed optimisation policy
+// (Sec. 3.2.2-3.2.4) and the C ABI declared in include/fms.h.
+//
+// The CPU steers the seed count and the GPU iterates the seeds (Fig. 3): the
+// host reads a few counters back after each GPU step (iteration, round) and
+// decides what to launch next.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "fms.h"
+#include "fms_internal.h"
+
+namespace {
+
+using fms::META_BAD;
+using fms::META_BADSEED;
+using fms::META_COUNT;
+using fms::META_CURSOR;
+using fms::META_LEFT;
+using fms::META_N;
+using fms::META_NCONV;
+using fms::META_NNEXT;
+using fms::META_NSEL;
+using fms::META_REFINE_BAD;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  // Grow like ensure(), keeping the first `keep` bytes (the old buffer is
+  // copied on `st` and freed once the copy has finished).
+  hipError_t grow_keep(size_t bytes, size_t keep, hipStream_t st) {
+    if (bytes <= cap) return hipSuccess;
+    size_t want = std::max<size_t>(bytes + bytes / 2, 4096);
+    void* np = nullptr;
+    hipError_t e = hipMalloc(&np, want);
+    if (e != hipSuccess) return e;
+    if (p && keep > 0) {
+      e = hipMemcpyAsync(np, p, std::min(keep, cap), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        (void)hipFree(np);
+        return e;
+      }
+    }
+    if (p) (void)hipFree(p);
+    p = np;
+    cap = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// SplitMix64 (Steele, Lea and Flood 2014): the seed order's round keys are
+// the first four outputs for the user's seed.
+uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void round_keys(uint64_t seed, uint64_t keys[4]) {
+  uint64_t st = seed;
+  for (int r = 0; r < 4; ++r) {
+    st += 0x9E3779B97F4A7C15ull;
+    keys[r] = splitmix_mix(st);
+  }
+}
+
+int half_bits(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return std::max(1, (k + 1) / 2);
+}
+
+// Eq. 19 with the guards of the controller: no value without an instance, one
+// seed when r / I >= 1.
+bool eq19_n_min(double p_target, int64_t n_inst, double r, double* out) {
+  if (n_inst <= 0) return false;
+  const double ratio = r / double(n_inst);
+  if (ratio >= 1.0) {
+    *out = 1.0;
+    return true;
+  }
+  *out = std::log(1.0 - std::exp(std::log(p_target) / double(n_inst))) / std::log(1.0 - ratio);
+  return true;
+}
+
+int pad_dim(int dim) { return dim <= 32 ? 32 : (dim <= 64 ? 64 : 128); }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct fms_handle_s {
+  int device = 0;
+  // Frame data.
+  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, uncovered, used;
+  // Round data.
+  DevBuf y, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, pcount, partial;
+  DevBuf bits, blocked, acc;
+  // Modes found so far.
+  DevBuf modes, mode_counts;
+  DevBuf meta;
+  // Event pairs for timing fused-step launches (created on first use).
+  std::vector<hipEvent_t> events;
+  hipError_t ensure_events(size_t count) {
+    while (events.size() < count) {
+      hipEvent_t e;
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      events.push_back(e);
+    }
+    return hipSuccess;
+  }
+  // Pinned host staging.
+  int* hmeta = nullptr;
+  void* hstage = nullptr;
+  size_t hstage_cap = 0;
+
+  hipError_t stage(size_t bytes) {
+    if (bytes <= hstage_cap) return hipSuccess;
+    if (hstage) (void)hipHostFree(hstage);
+    hstage = nullptr;
+    hstage_cap = 0;
+    size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 16);
+    hipError_t e = hipHostMalloc(&hstage, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      hstage = nullptr;
+      return e;
+    }
+    hstage_cap = want;
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+#define HIP_TRY(expr)                       \
+  do {                                      \
+    hipError_t _e = (expr);                 \
+    if (_e != hipSuccess) return FMS_ERR_HIP; \
+  } while (0)
+
+struct Frame {
+  fms::FrameDesc desc;
+  int n = 0;
+  int dp = 32;
+  int n_pad = 0;
+  fms::StepGeom geom{};
+};
+
+fms_status check_params(const fms_params* p) {
+  if (!p) return FMS_ERR_INVALID_ARG;
+  if (!(p->bandwidth > 0.0 && p->bandwidth < 2.0)) return FMS_ERR_INVALID_ARG;
+  if (!(p->gamma >= 0.0 && p->gamma <= 1.0)) return FMS_ERR_INVALID_ARG;
+  if (!(p->big_l > 0.0) || !(p->big_h > 0.0)) return FMS_ERR_INVALID_ARG;
+  if (!(p->p_target > 0.0 && p->p_target < 1.0)) return FMS_ERR_INVALID_ARG;
+  if (!std::isfinite(p->conv_tol)) return FMS_ERR_INVALID_ARG;
+  if (p->n_initial < 1 || p->max_iter < 1 || p->max_rounds < 1 || p->refine_iters < 0) return FMS_ERR_INVALID_ARG;
+  if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE) return FMS_ERR_INVALID_ARG;
+  return FMS_OK;
+}
+
+fms_status check_frame_args(fms_handle h, const float* emb, int64_t ps, int64_t cs, int32_t height, int32_t width,
+                            int32_t dim) {
+  if (!h || !emb) return FMS_ERR_INVALID_ARG;
+  if (height < 1 || width < 1 || ps < 0 || cs < 0) return FMS_ERR_INVALID_ARG;
+  if (dim < 1) return FMS_ERR_INVALID_ARG;
+  if (dim > 128) return FMS_ERR_UNSUPPORTED;
+  if (int64_t(height) * int64_t(width) > int64_t(std::numeric_limits<int32_t>::max())) return FMS_ERR_UNSUPPORTED;
+  return FMS_OK;
+}
+
+// Compact the foreground, normalise it and write the four layouts.
+fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t ps, int64_t cs, const uint8_t* mask,
+                         int32_t height, int32_t width, int32_t dim, Frame& fr) {
+  const int64_t P = int64_t(height) * int64_t(width);
+  const int nmb = int((P + fms::kMaskBlockPix - 1) / fms::kMaskBlockPix);
+  fr.dp = pad_dim(dim);
+  fr.desc = fms::FrameDesc{emb, ps, cs, mask, P, dim, fr.dp};
+  HIP_TRY(h->blk.ensure(size_t(nmb) * sizeof(int)));
+  HIP_TRY(h->meta.ensure(META_COUNT * sizeof(int)));
+  HIP_TRY(hipMemsetAsync(h->meta.p, 0, META_COUNT * sizeof(int), st));
+  HIP_TRY(fms::launch_mask_count(st, mask, P, h->blk.as<int>(), nmb));
+  HIP_TRY(fms::launch_scan_blocks(st, h->blk.as<int>(), nmb, h->meta.as<int>()));
+  HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  fr.n = h->hmeta[META_N];
+  fr.n_pad = ((fr.n + fms::kBlockPix - 1) / fms::kBlockPix) * fms::kBlockPix;
+  fr.geom = fms::make_geom(fr.n);
+  if (fr.n == 0) return FMS_OK;
+  const size_t rows = size_t(fr.n_pad);
+  const size_t dp = size_t(fr.dp);
+  HIP_TRY(h->fg_idx.ensure(rows * sizeof(int)));
+  HIP_TRY(h->x32.ensure(rows * dp * sizeof(float)));
+  HIP_TRY(h->x32t.ensure(rows * dp * sizeof(float)));
+  HIP_TRY(h->x16.ensure(rows * dp * sizeof(uint16_t)));
+  HIP_TRY(h->x16t.ensure(rows * dp * sizeof(uint16_t)));
+  // Zero the last (possibly partial) block so padding rows contribute nothing.
+  const size_t last = rows - fms::kBlockPix;
+  HIP_TRY(hipMemsetAsync(h->x32.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
+  HIP_TRY(hipMemsetAsync(h->x32t.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
+  HIP_TRY(hipMemsetAsync(h->x16.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
+  HIP_TRY(hipMemsetAsync(h->x16t.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
+  HIP_TRY(fms::launch_compact(st, fr.desc, h->blk.as<int>(), nmb, h->fg_idx.as<int>(), h->x32.as<float>(),
+                              h->x32t.as<float>(), h->x16.as<uint16_t>(), h->x16t.as<uint16_t>(),
+                              h->meta.as<int>()));
+  HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  return FMS_OK;
+}
+
+fms_status ensure_round(fms_handle h, const Frame& fr, int m) {
+  const size_t mm = size_t(std::max(m, 1));
+  const size_t dp = size_t(fr.dp);
+  HIP_TRY(h->y.ensure(mm * dp * sizeof(float)));
+  HIP_TRY(h->active.ensure(mm * sizeof(int)));
+  HIP_TRY(h->next_active.ensure(mm * sizeof(int)));
+  HIP_TRY(h->state.ensure(mm));
+  HIP_TRY(h->iters.ensure(mm * sizeof(int)));
+  HIP_TRY(h->seed_pos.ensure(mm * sizeof(int)));
+  HIP_TRY(h->seed_fg.ensure(mm * sizeof(int)));
+  HIP_TRY(h->ident.ensure(mm * sizeof(int)));
+  HIP_TRY(h->cand.ensure(mm * sizeof(int)));
+  HIP_TRY(h->counts.ensure(mm * sizeof(int)));
+  HIP_TRY(h->pcount.ensure(mm * size_t(std::max(fr.geom.n_chunks, 1)) * sizeof(int)));
+  HIP_TRY(h->partial.ensure(mm * size_t(std::max(fr.geom.n_chunks, 1)) * dp * sizeof(float)));
+  // Host staging for the whole round (conflict bits, counts, flags, lists),
+  // sized once so it is never reallocated while a copy is in flight.
+  const size_t words = (mm + 31) / 32;
+  HIP_TRY(h->stage(mm * words * sizeof(uint32_t) + mm * (2 * sizeof(int) + 1) + 256));
+  return FMS_OK;
+}
+
+struct RoundOut {
+  int steps = 0;
+  int64_t updates = 0;
+  int refine_steps = 0;
+  int refine_bad = 0;
+  int64_t refine_updates = 0;
+  double step_ms[2] = {0.0, 0.0};
+  int64_t step_updates[2] = {0, 0};
+  int step_launches[2] = {0, 0};
+  std::vector<int> conv;  // converged slots, ascending
+};
+
+void add_timing(fms_stats& sx, const RoundOut& ro) {
+  for (int k = 0; k < 2; ++k) {
+    sx.step_ms[k] += ro.step_ms[k];
+    sx.step_updates[k] += ro.step_updates[k];
+    sx.step_launches[k] += ro.step_launches[k];
+  }
+}
+
+// Iterate the m seeds whose centres are in y[0..m) (Alg. 2, the parallel seed
+// loop) until more than gamma of them converged (Sec. 3.2.3), no seed is
+// active, or max_iter steps.  The BF16 form then runs refine_iters FP32 steps
+// on the converged seeds.  The converged slots end up in h->cand.
+fms_status run_round(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr, float tol,
+                     RoundOut& out) {
+  int* meta = h->meta.as<int>();
+  HIP_TRY(fms::launch_round_init(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>()));
+  HIP_TRY(hipMemsetAsync(meta + META_NCONV, 0, sizeof(int), st));
+  const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
+  const void* xrm = bf16 ? h->x16.p : h->x32.p;
+  const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+  const bool timing = p->timing != 0;
+  const int pk = bf16 ? 1 : 0;
+  if (timing) HIP_TRY(h->ensure_events(2 * size_t(std::max(p->refine_iters, 1))));
+  int n_act = m;
+  int* act = h->active.as<int>();
+  int* nxt = h->next_active.as<int>();
+  for (int t = 0; t < p->max_iter && n_act > 0; ++t) {
+    HIP_TRY(hipMemsetAsync(meta + META_NNEXT, 0, sizeof(int), st));
+    if (timing) HIP_TRY(hipEventRecord(h->events[0], st));
+    HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom, xrm, xt, h->y.as<float>(), act, n_act, thr,
+                              h->partial.as<float>()));
+    if (timing) HIP_TRY(hipEventRecord(h->events[1], st));
+    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom, h->partial.as<float>(), n_act, act, h->y.as<float>(),
+                               h->state.as<uint8_t>(), h->iters.as<int>(), tol, 0, meta, nxt));
+    HIP_TRY(hipMemcpyAsync(h->hmeta + META_NCONV, meta + META_NCONV, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (timing) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->events[0], h->events[1]));
+      out.step_ms[pk] += ms;
+      out.step_updates[pk] += int64_t(n_act) * int64_t(fr.n);
+      out.step_launches[pk] += 1;
+    }
+    out.steps += 1;
+    out.updates += int64_t(n_act) * int64_t(fr.n);
+    n_act = h->hmeta[META_NNEXT];
+    std::swap(act, nxt);
+    if (double(h->hmeta[META_NCONV]) > p->gamma * double(m)) break;
+  }
+  // Converged slots, in slot (= seed-order) order.
+  HIP_TRY(hipMemcpyAsync(h->hstage, h->state.p, size_t(m), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const uint8_t* stt = static_cast<const uint8_t*>(h->hstage);
+  out.conv.clear();
+  for (int k = 0; k < m; ++k)
+    if (stt[k] == 1) out.conv.push_back(k);
+  const int nc = int(out.conv.size());
+  if (nc > 0) {
+    std::memcpy(h->hstage, out.conv.data(), size_t(nc) * sizeof(int));
+    HIP_TRY(hipMemcpyAsync(h->cand.p, h->hstage, size_t(nc) * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  if (bf16 && p->refine_iters > 0 && nc > 0) {
+    HIP_TRY(hipMemsetAsync(meta + META_REFINE_BAD, 0, sizeof(int), st));
+    for (int r = 0; r < p->refine_iters; ++r) {
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
+      HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom, h->x32.p, h->x32t.p, h->y.as<float>(), h->cand.as<int>(),
+                                nc, thr, h->partial.as<float>()));
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
+      out.refine_updates += int64_t(nc) * int64_t(fr.n);
+      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom, h->partial.as<float>(), nc, h->cand.as<int>(),
+                                 h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(), tol,
+                                 r + 1 == p->refine_iters ? 2 : 1, meta, nullptr));
+      out.refine_steps += 1;
+    }
+    HIP_TRY(hipMemcpyAsync(h->hmeta + META_REFINE_BAD, meta + META_REFINE_BAD, sizeof(int), hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out.refine_bad = h->hmeta[META_REFINE_BAD];
+    if (timing) {
+      for (int r = 0; r < p->refine_iters; ++r) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
+        out.step_ms[0] += ms;
+        out.step_updates[0] += int64_t(nc) * int64_t(fr.n);
+        out.step_launches[0] += 1;
+      }
+    }
+  }
+  return FMS_OK;
+}
+
+double tol_of(const fms_params* p) { return p->conv_tol > 0.0 ? p->conv_tol : p->bandwidth / 1000.0; }
+
+}  // namespace
+
+extern "C" {
+
+void fms_default_params(fms_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->bandwidth = 0.1;
+  p->conv_tol = 0.0;
+  p->gamma = 0.9;
+  p->big_l = 2.0;
+  p->big_h = 8.0;
+  p->p_target = 0.99;
+  p->seed = 0;
+  p->n_initial = 128;
+  p->n_state_in = 0;
+  p->max_iter = 100;
+  p->max_rounds = 32;
+  p->precision = FMS_PREC_FP32;
+  p->refine_iters = 3;
+}
+
+const char* fms_status_string(fms_status s) {
+  switch (s) {
+    case FMS_OK: return "ok";
+    case FMS_ERR_INVALID_ARG: return "invalid argument";
+    case FMS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FMS_ERR_BAD_INPUT: return "a foreground embedding is zero or not finite";
+    case FMS_ERR_CAPACITY: return "mode buffer too small";
+    case FMS_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
+  if (!out) return FMS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return FMS_ERR_HIP;
+  if (device_ordinal < 0 || device_ordinal >= count) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(device_ordinal);
+  fms_handle h = new (std::nothrow) fms_handle_s();
+  if (!h) return FMS_ERR_HIP;
+  h->device = device_ordinal;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), META_COUNT * sizeof(int), hipHostMallocDefault) !=
+          hipSuccess ||
+      h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess) {
+    fms_destroy(h);
+    return FMS_ERR_HIP;
+  }
+  *out = h;
+  return FMS_OK;
+}
+
+fms_status fms_destroy(fms_handle h) {
+  if (!h) return FMS_OK;
+  DeviceGuard guard(h->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&h->blk,   &h->fg_idx, &h->x32,     &h->x32t,        &h->x16,     &h->x16t,     &h->order,
+                    &h->uncovered, &h->used, &h->y, &h->active, &h->next_active, &h->state, &h->iters,
+                    &h->seed_pos, &h->seed_fg, &h->ident, &h->cand, &h->counts, &h->pcount, &h->partial,
+                    &h->bits, &h->blocked, &h->acc, &h->modes, &h->mode_counts, &h->meta};
+  for (DevBuf* b : bufs) b->release();
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  if (h->hmeta) (void)hipHostFree(h->hmeta);
+  if (h->hstage) (void)hipHostFree(h->hstage);
+  delete h;
+  return FMS_OK;
+}
+
+fms_status fms_seed_order(fms_handle h, void* stream, int32_t n, uint64_t seed, int32_t* order) {
+  if (!h || n < 0 || (n > 0 && !order)) return FMS_ERR_INVALID_ARG;
+  if (n == 0) return FMS_OK;
+  DeviceGuard guard(h->device);
+  uint64_t keys[4];
+  round_keys(seed, keys);
+  HIP_TRY(fms::launch_seed_order(static_cast<hipStream_t>(stream), n, half_bits(n), keys, order));
+  return FMS_OK;
+}
+
+fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                       const uint8_t* mask, int32_t height, int32_t width, int32_t dim, const fms_params* p,
+                       float* modes_out, int32_t* mode_counts_out, int32_t k_max, int32_t* n_modes, int32_t* labels,
+                       fms_stats* stats) {
+  fms_status stt = check_frame_args(h, emb, pixel_stride, channel_stride, height, width, dim);
+  if (stt != FMS_OK) return stt;
+  stt = check_params(p);
+  if (stt != FMS_OK) return stt;
+  if (!n_modes || !labels || k_max < 0 || (k_max > 0 && !modes_out)) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t P = int64_t(height) * int64_t(width);
+  fms_stats sx;
+  std::memset(&sx, 0, sizeof(sx));
+  sx.n_min = std::numeric_limits<double>::quiet_NaN();
+  int64_t n_seeds = p->n_state_in > 0 ? p->n_state_in : p->n_initial;
+
+  Frame fr;
+  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim, fr);
+  if (stt != FMS_OK) return stt;
+  sx.n_fg = fr.n;
+  HIP_TRY(fms::launch_fill_i32(st, labels, P, -1));
+  if (fr.n == 0) {
+    HIP_TRY(hipStreamSynchronize(st));
+    *n_modes = 0;
+    sx.n_state_out = int32_t(std::min<int64_t>(n_seeds, std::numeric_limits<int32_t>::max()));
+    if (stats) *stats = sx;
+    return FMS_OK;
+  }
+  const int n = fr.n;
+  const float thr = float(1.0 - p->bandwidth);
+  const float tol = float(tol_of(p));
+  const double r = double(n) / double(P);
+  int* meta = h->meta.as<int>();
+
+  // Seed order, coverage and use flags.
+  HIP_TRY(h->order.ensure(size_t(n) * sizeof(int)));
+  HIP_TRY(h->uncovered.ensure(size_t(n)));
+  HIP_TRY(h->used.ensure(size_t(n)));
+  uint64_t keys[4];
+  round_keys(p->seed, keys);
+  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>()));
+  HIP_TRY(hipMemsetAsync(h->uncovered.p, 1, size_t(n), st));
+  HIP_TRY(hipMemsetAsync(h->used.p, 0, size_t(n), st));
+  HIP_TRY(hipMemsetAsync(meta + META_CURSOR, 0, sizeof(int), st));
+
+  int64_t n_used = 0;
+  int k_modes = 0;
+  bool have_nmin = false;
+  double nmin = 0.0;
+  for (int round = 0; round < p->max_rounds; ++round) {
+    const int64_t want64 = std::min<int64_t>(n_seeds - n_used, n);
+    if (want64 <= 0) break;
+    const int want = int(want64);
+    stt = ensure_round(h, fr, want);
+    if (stt != FMS_OK) return stt;
+    HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->uncovered.as<uint8_t>(), h->used.as<uint8_t>(), n, want,
+                               meta, h->seed_pos.as<int>(), h->seed_fg.as<int>(), h->x32.as<float>(), fr.dp,
+                               h->y.as<float>()));
+    HIP_TRY(hipMemcpyAsync(h->hmeta + META_NSEL, meta + META_NSEL, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int m = h->hmeta[META_NSEL];
+    if (m == 0) break;
+    n_used += m;
+    sx.rounds += 1;
+    sx.seeds_used += m;
+
+    RoundOut ro;
+    stt = run_round(h, st, fr, m, p, thr, tol, ro);
+    if (stt != FMS_OK) return stt;
+    sx.iterations_total += ro.steps;
+    sx.refine_steps += ro.refine_steps;
+    sx.seed_pixel_updates += ro.updates;
+    sx.refine_unconverged += ro.refine_bad;
+    sx.refine_updates += ro.refine_updates;
+    add_timing(sx, ro);
+    const int nc = int(ro.conv.size());
+    sx.n_discarded += m - nc;
+
+    // Prune (Alg. 2): window counts at the endpoints, conflicts on the GPU,
+    // greedy acceptance on the host.
+    int accepted = 0;
+    if (nc > 0) {
+      const int words = (nc + 31) / 32;
+      HIP_TRY(h->bits.ensure(size_t(nc) * words * sizeof(uint32_t)));
+      HIP_TRY(h->blocked.ensure(size_t(nc)));
+      HIP_TRY(h->acc.ensure(size_t(nc) * sizeof(int)));
+      HIP_TRY(fms::launch_count(st, fr.dp, fr.geom, h->x32.as<float>(), h->y.as<float>(), h->cand.as<int>(), nc, thr,
+                                h->pcount.as<int>(), h->counts.as<int>()));
+      HIP_TRY(fms::launch_conflicts(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->modes.as<float>(),
+                                    k_modes, thr, h->bits.as<uint32_t>(), words, h->blocked.as<uint8_t>()));
+      const size_t nb_bits = size_t(nc) * words * sizeof(uint32_t);
+      uint8_t* hs = static_cast<uint8_t*>(h->hstage);
+      uint32_t* hbits = reinterpret_cast<uint32_t*>(hs);
+      int* hcounts = reinterpret_cast<int*>(hs + nb_bits);
+      uint8_t* hblocked = hs + nb_bits + size_t(nc) * sizeof(int);
+      HIP_TRY(hipMemcpyAsync(hbits, h->bits.p, nb_bits, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hcounts, h->counts.p, size_t(nc) * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hblocked, h->blocked.p, size_t(nc), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      std::vector<int> ord(nc);
+      for (int a = 0; a < nc; ++a) ord[a] = a;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hcounts[a] > hcounts[b]; });
+      std::vector<uint32_t> taken(size_t(words), 0u);
+      std::vector<int> acc;
+      for (int a : ord) {
+        if (hblocked[a]) continue;
+        const uint32_t* row = hbits + size_t(a) * words;
+        bool clash = false;
+        for (int w = 0; w < words && !clash; ++w) clash = (row[w] & taken[w]) != 0;
+        if (clash) continue;
+        taken[a >> 5] |= 1u << (a & 31);
+        acc.push_back(a);
+      }
+      accepted = int(acc.size());
+      if (accepted > 0) {
+        // The mode set persists across rounds: grow it without losing rows.
+        HIP_TRY(h->modes.grow_keep(size_t(k_modes + accepted) * fr.dp * sizeof(float),
+                                   size_t(k_modes) * fr.dp * sizeof(float), st));
+        HIP_TRY(h->mode_counts.grow_keep(size_t(k_modes + accepted) * sizeof(int), size_t(k_modes) * sizeof(int),
+                                         st));
+        // acc holds candidate indices; translate to slots on the host.
+        int* hacc = reinterpret_cast<int*>(hs);  // staging is free again after the sync above
+        for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
+        HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), h->counts.as<int>(),
+                                         h->acc.as<int>(), accepted, h->modes.as<float>(), h->mode_counts.as<int>(),
+                                         k_modes));
+        HIP_TRY(hipStreamSynchronize(st));
+      }
+    }
+    const int k_old = k_modes;
+    k_modes += accepted;
+    // Coverage by the new modes, and the pool left to seed.
+    HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
+    HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), k_old, k_modes, thr, 0,
+                               h->uncovered.as<uint8_t>(), h->used.as<uint8_t>(), meta, nullptr, nullptr));
+    HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const bool left = h->hmeta[META_LEFT] > 0;
+    // Controller (Sec. 3.2.4).
+    bool go_on = false;
+    have_nmin = eq19_n_min(p->p_target, k_modes, r, &nmin);
+    if (left) {
+      if (!have_nmin || double(n_seeds) < p->big_l * nmin) {
+        n_seeds *= 2;
+        go_on = true;
+      }
+    }
+    if (!go_on) break;
+  }
+
+  // Labels (Alg. 2): most similar mode, lowest index on ties; count pixels
+  // farther than h from every mode.
+  HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
+  HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), 0, k_modes, thr, 1, nullptr,
+                             nullptr, meta, h->fg_idx.as<int>(), labels));
+  HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (k_modes > k_max) {
+    HIP_TRY(hipStreamSynchronize(st));
+    *n_modes = k_modes;
+    return FMS_ERR_CAPACITY;
+  }
+  HIP_TRY(fms::launch_copy_rows(st, h->modes.as<float>(), fr.dp, modes_out, dim, k_modes, dim));
+  if (mode_counts_out && k_modes > 0)
+    HIP_TRY(hipMemcpyAsync(mode_counts_out, h->mode_counts.p, size_t(k_modes) * sizeof(int), hipMemcpyDeviceToDevice,
+                           st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n_modes = k_modes;
+  sx.n_uncovered = h->hmeta[META_LEFT];
+  sx.n_min = have_nmin ? nmin : std::numeric_limits<double>::quiet_NaN();
+  int64_t next = n_seeds;
+  if (have_nmin && double(n_seeds) > p->big_h * nmin) next = n_seeds - int64_t(std::ceil(nmin));
+  sx.n_state_out = int32_t(std::min<int64_t>(next, std::numeric_limits<int32_t>::max()));
+  if (stats) *stats = sx;
+  return FMS_OK;
+}
+
+fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                           const uint8_t* mask, int32_t height, int32_t width, int32_t dim, const int32_t* seed_fg,
+                           int32_t n_seeds, const fms_params* p, float* endpoints, int32_t* iters, uint8_t* converged,
+                           int32_t* counts, fms_stats* stats) {
+  fms_status stt = check_frame_args(h, emb, pixel_stride, channel_stride, height, width, dim);
+  if (stt != FMS_OK) return stt;
+  stt = check_params(p);
+  if (stt != FMS_OK) return stt;
+  if (n_seeds < 0 || (n_seeds > 0 && (!seed_fg || !endpoints || !iters || !converged))) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fms_stats sx;
+  std::memset(&sx, 0, sizeof(sx));
+  sx.n_min = std::numeric_limits<double>::quiet_NaN();
+  Frame fr;
+  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim, fr);
+  if (stt != FMS_OK) return stt;
+  sx.n_fg = fr.n;
+  if (n_seeds == 0) {
+    if (stats) *stats = sx;
+    return FMS_OK;
+  }
+  if (fr.n == 0) return FMS_ERR_INVALID_ARG;
+  const int m = n_seeds;
+  stt = ensure_round(h, fr, m);
+  if (stt != FMS_OK) return stt;
+  int* meta = h->meta.as<int>();
+  HIP_TRY(hipMemsetAsync(meta + META_BADSEED, 0, sizeof(int), st));
+  HIP_TRY(fms::launch_init_seeds(st, seed_fg, m, fr.n, h->x32.as<float>(), fr.dp, h->y.as<float>(), meta));
+  HIP_TRY(hipMemcpyAsync(h->hmeta + META_BADSEED, meta + META_BADSEED, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h->hmeta[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
+  const float thr = float(1.0 - p->bandwidth);
+  const float tol = float(tol_of(p));
+  RoundOut ro;
+  stt = run_round(h, st, fr, m, p, thr, tol, ro);
+  if (stt != FMS_OK) return stt;
+  // Window counts of every slot (the output keeps them for converged seeds).
+  int* hid = static_cast<int*>(h->hstage);
+  for (int k = 0; k < m; ++k) hid[k] = k;
+  HIP_TRY(hipMemcpyAsync(h->ident.p, h->hstage, size_t(m) * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(fms::launch_count(st, fr.dp, fr.geom, h->x32.as<float>(), h->y.as<float>(), h->ident.as<int>(), m, thr,
+                            h->pcount.as<int>(), h->counts.as<int>()));
+  HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
+                                   h->counts.as<int>(), endpoints, iters, converged, counts));
+  HIP_TRY(hipStreamSynchronize(st));
+  sx.iterations_total = ro.steps;
+  sx.refine_steps = ro.refine_steps;
+  sx.seed_pixel_updates = ro.updates;
+  sx.refine_unconverged = ro.refine_bad;
+  sx.refine_updates = ro.refine_updates;
+  add_timing(sx, ro);
+  sx.seeds_used = m;
+  sx.n_discarded = m - int(ro.conv.size());
+  if (stats) *stats = sx;
+  return FMS_OK;
+}
+
+}  // extern "C"

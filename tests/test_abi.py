@@ -1,0 +1,79 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports
+every entry point that include/fms.h declares, and its struct layouts agree
+with the Python binding.  Nothing here launches GPU work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fms.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fms_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    from paper_2007_14283_amd import _binding as B
+    assert _declared() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2007_14283_amd import _binding as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    for name in _declared():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_default_params_and_status_strings():
+    import paper_2007_14283_amd as F
+    p = F.default_params()
+    assert (p.bandwidth, p.gamma, p.n_initial, p.big_l, p.big_h, p.p_target) == (0.1, 0.9, 128, 2.0, 8.0, 0.99)
+    assert (p.max_iter, p.max_rounds, p.precision, p.refine_iters, p.conv_tol) == (100, 32, 0, 3, 0.0)
+    lib = F.library()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.fms_status_string(code)
+    assert lib.fms_status_string(42) == b"unknown status"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2007_14283_amd import _binding as B
+    src = tmp_path / "layout.c"
+    fields_p = [f for f, _ in B.FmsParams._fields_]
+    fields_s = [f for f, _ in B.FmsStats._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fms.h"', "int main(void) {",
+             'printf("%zu %zu\\n", sizeof(fms_params), sizeof(fms_stats));']
+    lines += [f'printf("%zu\\n", offsetof(fms_params, {f}));' for f in fields_p]
+    lines += [f'printf("%zu\\n", offsetof(fms_stats, {f}));' for f in fields_s]
+    lines += ["return 0; }"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(B.FmsParams) and vals[1] == ctypes.sizeof(B.FmsStats)
+    want = [getattr(B.FmsParams, f).offset for f in fields_p] + [getattr(B.FmsStats, f).offset for f in fields_s]
+    assert vals[2:] == want
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2007_14283_amd import _binding as B
+    with pytest.raises(RuntimeError):
+        B.load.__wrapped__(str(tmp_path / "nope.so")) if hasattr(B.load, "__wrapped__") else \
+            _fresh_load(B, str(tmp_path / "nope.so"))
+
+
+def _fresh_load(B, path):
+    saved = B._lib
+    B._lib = None
+    try:
+        return B.load(path)
+    finally:
+        B._lib = saved

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded synthetic frames.
+
+Tolerances: mode error (1 - cos, FP64) <= 1e-5 for the FP32 form and <= 1e-3
+for BF16 + FP32 refine; labels exact outside the counted exempt sets
+(|best - (1 - h)| < 1e-4, |best - second| < 1e-4); integer outputs (seed
+order, iteration counts, window counts, round statistics) exact except where
+the oracle's own decision sits within rounding of its threshold (counted)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cluster as C
+from oracle import seed_order as so
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+BF16_TOL = 1e-3
+DELTA_BAND = 1e-7   # |delta - tol| below this: the freeze decision may differ by rounding
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2007_14283_amd as fms
+    fms.library()
+    return fms
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _dev(torch, frame):
+    emb = torch.from_numpy(frame.emb).cuda()
+    mask = torch.from_numpy(frame.mask).cuda()
+    return emb, mask
+
+
+_FRAMES = {}
+
+
+def _frame(spec):
+    if spec not in _FRAMES:
+        _FRAMES[spec] = synth.make_frame(spec)
+    return _FRAMES[spec]
+
+
+_ORACLE = {}
+
+
+def _oracle(spec, **kw):
+    key = (spec, tuple(sorted(kw.items())))
+    if key not in _ORACLE:
+        f = _frame(spec)
+        _ORACLE[key] = C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth, **kw))
+    return _ORACLE[key]
+
+
+# ------------------------------------------------------------------ seed order
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 5), (3, 1), (1000, 0), (8113, 0), (100187, 0), (65536, 77),
+                                    (318603, 0)])
+def test_seed_order_matches_oracle(F, n, seed):
+    _say("seed_order", n, seed)
+    got = F.seed_order(n, seed).cpu().numpy()
+    np.testing.assert_array_equal(got, so.seed_order(n, seed))
+
+
+# ------------------------------------------------------------------ lockstep
+
+def _lockstep_compare(F, torch, spec, seeds, precision, tol_mode):
+    f = _frame(spec)
+    emb, mask = _dev(torch, f)
+    prec = F.FP32 if precision == "fp32" else F.BF16_REFINE
+    _say("lockstep", spec, len(seeds), precision)
+    g = F.shift_seeds(emb, mask, seeds, bandwidth=f.bandwidth, precision=prec)
+    o = C.lockstep(f.emb, f.mask, seeds, C.Params(bandwidth=f.bandwidth))
+    ge = g["endpoints"].cpu().numpy().astype(np.float64)
+    gi = g["iters"].cpu().numpy()
+    gc = g["converged"].cpu().numpy().astype(bool)
+    gn = g["counts"].cpu().numpy()
+    risky = (o["margin"] < parity.BAND) | (o["tol_margin"] < DELTA_BAND)
+    both = gc & o["converged"]
+    err = C.mode_error(ge[both], o["endpoints"][both])
+    return f, g, o, ge, gi, gc, gn, risky, both, err
+
+
+@pytest.mark.parametrize("spec,m", [(synth.MID, 128), (synth.MID, 333), (synth.TINY, 200)])
+def test_lockstep_fp32(F, torch_mod, spec, m):
+    rng = np.random.Generator(np.random.PCG64(1000 + m))
+    n = _frame(spec).n_fg
+    seeds = rng.choice(n, size=m, replace=False).astype(np.int32)
+    f, g, o, ge, gi, gc, gn, risky, both, err = _lockstep_compare(F, torch_mod, spec, seeds, "fp32", FP32_TOL)
+    safe = ~risky
+    print(f"risky seeds {risky.sum()} / {m}; max err {err.max() if len(err) else 0:.3e}")
+    np.testing.assert_array_equal(gc[safe], o["converged"][safe])
+    np.testing.assert_array_equal(gi[safe], o["iters"][safe])
+    assert err.max() <= FP32_TOL
+    # Window counts at converged endpoints: exact unless a pixel sits in the band there.
+    cnt_ok = both & safe & (o["end_margin"] >= parity.BAND)
+    np.testing.assert_array_equal(gn[cnt_ok], o["counts"][cnt_ok])
+    assert np.all(gn[~gc] == -1)
+    st = g["stats"]
+    if not risky.any():
+        assert st["iterations_total"] == o["steps"]
+        assert st["seed_pixel_updates"] == o["updates"]
+
+
+def test_lockstep_bf16_refine(F, torch_mod):
+    spec = synth.MID
+    rng = np.random.Generator(np.random.PCG64(7))
+    seeds = rng.choice(_frame(spec).n_fg, size=256, replace=False).astype(np.int32)
+    f, g, o, ge, gi, gc, gn, risky, both, err = _lockstep_compare(F, torch_mod, spec, seeds, "bf16", BF16_TOL)
+    print(f"bf16: converged gpu {gc.sum()} oracle {o['converged'].sum()}, max err {err.max():.3e}, "
+          f"refine_unconverged {g['stats']['refine_unconverged']}")
+    assert both.sum() >= 0.8 * len(seeds)
+    assert err.max() <= BF16_TOL
+
+
+def test_lockstep_rejects_bad_seed_index(F, torch_mod):
+    f = _frame(synth.TINY)
+    emb, mask = _dev(torch_mod, f)
+    _say("lockstep bad seed")
+    with pytest.raises(F.FmsError) as ei:
+        F.shift_seeds(emb, mask, np.array([0, f.n_fg], np.int32), bandwidth=f.bandwidth)
+    assert ei.value.status == -1
+
+
+# ------------------------------------------------------------------ end to end
+
+def _cluster_compare(F, torch, spec, precision="fp32", layout="nhwc", **kw):
+    f = _frame(spec)
+    emb, mask = _dev(torch, f)
+    if layout == "nchw":
+        emb = emb.permute(2, 0, 1).contiguous()
+    prec = F.FP32 if precision == "fp32" else F.BF16_REFINE
+    _say("cluster", spec, precision, layout, kw)
+    modes, labels, st = F.cluster(emb, mask, f.bandwidth, layout=layout, precision=prec, **kw)
+    res = _oracle(spec, **kw)
+    mm = parity.match_modes(modes.cpu().numpy(), res.modes)
+    lc = parity.compare_labels(labels.cpu().numpy(), res, mm, 1.0 - f.bandwidth)
+    print(f"modes gpu {len(modes)} oracle {len(res.modes)} unmatched {mm.unmatched_gpu}/{mm.unmatched_oracle} "
+          f"max err {mm.max_error:.3e}; labels {lc}; stats gpu {st} oracle {res.stats}")
+    return f, modes, labels, st, res, mm, lc
+
+
+@pytest.mark.parametrize("spec,layout", [(synth.TINY, "nhwc"), (synth.MID, "nhwc"), (synth.MID, "nchw")])
+def test_cluster_fp32_matches_oracle(F, torch_mod, spec, layout):
+    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32", layout)
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+    assert mm.max_error <= FP32_TOL
+    assert lc.mismatched == 0
+    for k in ("rounds", "seeds_used", "iterations_total", "n_discarded", "n_state_out",
+              "seed_pixel_updates"):
+        assert st[k] == res.stats[k], k
+    assert abs(st["n_uncovered"] - res.stats["n_uncovered"]) <= lc.exempt_band
+    # Mode order is acceptance order: the matching is the identity.
+    np.testing.assert_array_equal(mm.pairs[:, 0], mm.pairs[:, 1])
+    np.testing.assert_array_equal(st["mode_counts"].cpu().numpy(), res.mode_counts)
+
+
+def test_cluster_bf16_refine_matches_oracle(F, torch_mod):
+    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, synth.MID, "bf16")
+    assert mm.max_error <= BF16_TOL
+    assert mm.unmatched_oracle <= max(1, len(res.modes) // 20)
+    assert st["refine_steps"] >= 3
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_cluster_full_512_frame(F, torch_mod, precision):
+    # The 512 x 512, D = 32, 100-cell frame the benchmark times.
+    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, synth.PLAIN512, precision)
+    if precision == "fp32":
+        assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+        assert mm.max_error <= FP32_TOL
+        assert lc.mismatched == 0
+        assert st["rounds"] == res.stats["rounds"]
+        assert st["seeds_used"] == res.stats["seeds_used"]
+    else:
+        assert mm.max_error <= BF16_TOL
+        assert mm.unmatched_oracle <= max(2, len(res.modes) // 20)
+
+
+def test_cluster_is_deterministic(F, torch_mod):
+    f = _frame(synth.MID)
+    emb, mask = _dev(torch_mod, f)
+    _say("determinism")
+    a = F.cluster(emb, mask, f.bandwidth)
+    b = F.cluster(emb, mask, f.bandwidth)
+    assert torch_mod.equal(a[0], b[0]) and torch_mod.equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ edges
+
+def test_empty_mask(F, torch_mod):
+    f = _frame(synth.TINY)
+    emb, _ = _dev(torch_mod, f)
+    _say("empty mask")
+    modes, labels, st = F.cluster(emb, torch_mod.zeros(f.mask.shape, dtype=torch_mod.uint8, device="cuda"), 0.1)
+    assert modes.shape[0] == 0 and bool((labels == -1).all())
+    assert st["n_fg"] == 0 and st["n_state_out"] == 128
+
+
+def test_single_pixel_and_identical_vectors(F, torch_mod):
+    torch = torch_mod
+    _say("single pixel")
+    emb = torch.randn(5, 7, 16, device="cuda")
+    mask = torch.zeros(5, 7, dtype=torch.uint8, device="cuda")
+    mask[2, 3] = 1
+    modes, labels, st = F.cluster(emb, mask, 0.1)
+    assert modes.shape[0] == 1 and int(labels[2, 3]) == 0 and int((labels >= 0).sum()) == 1
+    v = emb[2, 3] / emb[2, 3].norm()
+    assert float(1 - (modes[0] * v).sum()) < 1e-6
+    _say("identical vectors")
+    e2 = torch.ones(40, 40, 18, device="cuda") * 3.0
+    modes, labels, st = F.cluster(e2, None, 0.1)
+    assert modes.shape[0] == 1 and bool((labels == 0).all())
+    assert st["iterations_total"] == 1
+
+
+@pytest.mark.parametrize("dim", [2, 3, 16, 18, 33, 64, 100, 128])
+def test_cluster_dims(F, torch_mod, dim):
+    spec = synth.FrameSpec(64, 80, 8, 5, 12, dim, 0.02 if dim > 8 else 0.005, 0.05, dim)
+    f = synth.make_frame(spec)
+    _FRAMES[spec] = f
+    fr, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32")
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+    assert mm.max_error <= FP32_TOL
+    assert lc.mismatched == 0
+
+
+def test_small_n_below_initial_seeds(F, torch_mod):
+    spec = synth.FrameSpec(24, 24, 3, 2, 4, 32, 0.02, None, 5)
+    f = synth.make_frame(spec)
+    _FRAMES[spec] = f
+    assert f.n_fg < 128
+    fr, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32")
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+    assert st["seeds_used"] == res.stats["seeds_used"]
+
+
+def test_capacity_and_bad_input(F, torch_mod):
+    import ctypes
+    from paper_2007_14283_amd import _binding as B
+    torch = torch_mod
+    f = _frame(synth.TINY)
+    emb, mask = _dev(torch, f)
+    _say("capacity")
+    res = _oracle(synth.TINY)
+    modes, labels, st = F.cluster(emb, mask, f.bandwidth, k_max=2)  # binding retries with the needed size
+    assert modes.shape[0] == len(res.modes)
+    lib = F.library()
+    h = F._handle(0)
+    cp = F.Params(bandwidth=f.bandwidth).to_c()
+    out = torch.empty(2, 16, device="cuda")
+    lab = torch.empty(128, 128, dtype=torch.int32, device="cuda")
+    nm = ctypes.c_int32(0)
+    stt = lib.fms_cluster(h, None, ctypes.c_void_p(emb.data_ptr()), 16, 1, ctypes.c_void_p(mask.data_ptr()),
+                          128, 128, 16, ctypes.byref(cp), ctypes.c_void_p(out.data_ptr()), None, 2,
+                          ctypes.byref(nm), ctypes.c_void_p(lab.data_ptr()), None)
+    torch.cuda.synchronize()
+    assert stt == B.FMS_ERR_CAPACITY and nm.value == len(res.modes)
+    _say("bad input")
+    bad = emb.clone()
+    ys, xs = np.nonzero(f.mask)
+    bad[int(ys[5]), int(xs[5])] = 0.0
+    with pytest.raises(F.FmsError) as ei:
+        F.cluster(bad, mask, f.bandwidth)
+    assert ei.value.status == B.FMS_ERR_BAD_INPUT
+    bad[int(ys[5]), int(xs[5]), 3] = float("nan")
+    with pytest.raises(F.FmsError) as ei:
+        F.cluster(bad, mask, f.bandwidth)
+    assert ei.value.status == B.FMS_ERR_BAD_INPUT
+    # A zero row on the background is fine.
+    ok = emb.clone()
+    yb, xb = np.nonzero(f.mask == 0)
+    ok[int(yb[0]), int(xb[0])] = 0.0
+    F.cluster(ok, mask, f.bandwidth)
+    _say("invalid args")
+    for kw in ({"bandwidth": 0.0}, {"bandwidth": 2.5}, {"gamma": 1.5}, {"max_iter": 0}, {"precision": 7}):
+        with pytest.raises(F.FmsError) as ei:
+            F.cluster(emb, mask, **{"bandwidth": 0.1, **kw})
+        assert ei.value.status == B.FMS_ERR_INVALID_ARG
+    with pytest.raises(F.FmsError) as ei:
+        F.cluster(torch.randn(4, 4, 129, device="cuda"), None, 0.1)
+    assert ei.value.status == B.FMS_ERR_UNSUPPORTED
+
+
+def test_scale_invariance_gpu(F, torch_mod):
+    torch = torch_mod
+    f = _frame(synth.MID)
+    emb, mask = _dev(torch, f)
+    rng = np.random.Generator(np.random.PCG64(3))
+    scale = torch.from_numpy(np.ldexp(1.0, rng.integers(-6, 7, f.emb.shape[:2])).astype(np.float32))
+    _say("scale invariance")
+    a = F.cluster(emb, mask, f.bandwidth)
+    b = F.cluster(emb * scale.cuda()[..., None], mask, f.bandwidth)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_osop_state_carry(F, torch_mod):
+    f = _frame(synth.MID)
+    emb, mask = _dev(torch_mod, f)
+    _say("n_state_in")
+    modes, labels, st = F.cluster(emb, mask, f.bandwidth, n_state_in=512)
+    res = _oracle(synth.MID, n_state_in=512)
+    assert st["seeds_used"] == res.stats["seeds_used"]
+    assert st["n_state_out"] == res.stats["n_state_out"]
+    assert len(modes) == len(res.modes)
