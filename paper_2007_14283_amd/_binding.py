@@ -55,7 +55,7 @@ class FmsStats(ctypes.Structure):
         ("n_uncovered", ctypes.c_int32),
         ("n_state_out", ctypes.c_int32),
         ("refine_unconverged", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("refine_merged", ctypes.c_int32),
         ("refine_updates", ctypes.c_int64),
         ("step_ms", ctypes.c_double * 2),
         ("step_updates", ctypes.c_int64 * 2),

@@ -140,7 +140,7 @@ struct fms_handle_s {
   DevBuf bits, blocked, acc;
   // Modes found so far.
   DevBuf modes, mode_counts;
-  DevBuf meta;
+  DevBuf meta, meta64;
   // Event pairs for timing fused-step launches (created on first use).
   std::vector<hipEvent_t> events;
   hipError_t ensure_events(size_t count) {
@@ -213,7 +213,7 @@ fms_status check_frame_args(fms_handle h, const float* emb, int64_t ps, int64_t 
 
 // Compact the foreground, normalise it and write the four layouts.
 fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t ps, int64_t cs, const uint8_t* mask,
-                         int32_t height, int32_t width, int32_t dim, Frame& fr) {
+                         int32_t height, int32_t width, int32_t dim, bool bf16, Frame& fr) {
   const int64_t P = int64_t(height) * int64_t(width);
   const int nmb = int((P + fms::kMaskBlockPix - 1) / fms::kMaskBlockPix);
   fr.dp = pad_dim(dim);
@@ -234,24 +234,29 @@ fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t
   HIP_TRY(h->fg_idx.ensure(rows * sizeof(int)));
   HIP_TRY(h->x32.ensure(rows * dp * sizeof(float)));
   HIP_TRY(h->x32t.ensure(rows * dp * sizeof(float)));
-  HIP_TRY(h->x16.ensure(rows * dp * sizeof(uint16_t)));
-  HIP_TRY(h->x16t.ensure(rows * dp * sizeof(uint16_t)));
+  if (bf16) {
+    HIP_TRY(h->x16.ensure(rows * dp * sizeof(uint16_t)));
+    HIP_TRY(h->x16t.ensure(rows * dp * sizeof(uint16_t)));
+  }
   // Zero the last (possibly partial) block so padding rows contribute nothing.
   const size_t last = rows - fms::kBlockPix;
   HIP_TRY(hipMemsetAsync(h->x32.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
   HIP_TRY(hipMemsetAsync(h->x32t.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
-  HIP_TRY(hipMemsetAsync(h->x16.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
-  HIP_TRY(hipMemsetAsync(h->x16t.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
+  if (bf16) {
+    HIP_TRY(hipMemsetAsync(h->x16.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
+    HIP_TRY(hipMemsetAsync(h->x16t.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
+  }
   HIP_TRY(fms::launch_compact(st, fr.desc, h->blk.as<int>(), nmb, h->fg_idx.as<int>(), h->x32.as<float>(),
-                              h->x32t.as<float>(), h->x16.as<uint16_t>(), h->x16t.as<uint16_t>(),
-                              h->meta.as<int>()));
+                              h->x32t.as<float>(), bf16 ? h->x16.as<uint16_t>() : nullptr,
+                              bf16 ? h->x16t.as<uint16_t>() : nullptr, h->meta.as<int>()));
   HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   return FMS_OK;
 }
 
-fms_status ensure_round(fms_handle h, const Frame& fr, int m) {
+fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
+  HIP_TRY(h->stage(size_t(std::max(m, 1)) * sizeof(int) + 256));
   const size_t mm = size_t(std::max(m, 1));
   const size_t dp = size_t(fr.dp);
   HIP_TRY(h->y.ensure(mm * dp * sizeof(float)));
@@ -264,13 +269,53 @@ fms_status ensure_round(fms_handle h, const Frame& fr, int m) {
   HIP_TRY(h->ident.ensure(mm * sizeof(int)));
   HIP_TRY(h->cand.ensure(mm * sizeof(int)));
   HIP_TRY(h->counts.ensure(mm * sizeof(int)));
-  HIP_TRY(h->pcount.ensure(mm * size_t(std::max(fr.geom.n_chunks, 1)) * sizeof(int)));
-  HIP_TRY(h->partial.ensure(mm * size_t(std::max(fr.geom.n_chunks, 1)) * dp * sizeof(float)));
-  // Host staging for the whole round (conflict bits, counts, flags, lists),
-  // sized once so it is never reallocated while a copy is in flight.
-  const size_t words = (mm + 31) / 32;
-  HIP_TRY(h->stage(mm * words * sizeof(uint32_t) + mm * (2 * sizeof(int) + 1) + 256));
+  HIP_TRY(h->pcount.ensure(fms::count_partial_rows(fr.dp, int(mm)) * sizeof(int)));
+  const size_t rows = std::max(fms::shift_partial_rows(bf16, fr.dp, int(mm), fr.geom.n_blocks),
+                               fms::shift_partial_rows(false, fr.dp, int(mm), fr.geom.n_blocks));
+  HIP_TRY(h->partial.ensure(rows * dp * sizeof(float)));
   return FMS_OK;
+}
+
+// Device transfer area of one pruning pass (counts, candidate x candidate
+// bits, candidate x mode bits) and the host staging that receives it in one
+// copy.  Sized before any copy is enqueued, never reallocated mid-flight.
+struct Xfer {
+  int* counts;
+  uint32_t* bits_c;
+  uint32_t* bits_m;
+  int words_c, words_m;
+  size_t bytes;
+};
+
+fms_status ensure_xfer(fms_handle h, int nc, int k, Xfer& x) {
+  x.words_c = fms::simbits_words(nc);
+  x.words_m = fms::simbits_words(k);
+  const size_t nb_c = size_t(nc) * x.words_c * sizeof(uint32_t);
+  const size_t nb_m = size_t(nc) * x.words_m * sizeof(uint32_t);
+  const size_t nb_n = ((size_t(nc) * sizeof(int) + 255) / 256) * 256;
+  x.bytes = nb_n + nb_c + nb_m;
+  HIP_TRY(h->bits.ensure(x.bytes));
+  HIP_TRY(h->stage(x.bytes + 256));
+  uint8_t* base = static_cast<uint8_t*>(h->bits.p);
+  x.counts = reinterpret_cast<int*>(base);
+  x.bits_c = reinterpret_cast<uint32_t*>(base + nb_n);
+  x.bits_m = reinterpret_cast<uint32_t*>(base + nb_n + nb_c);
+  return FMS_OK;
+}
+
+// Host view of an Xfer after its copy.
+struct XferHost {
+  const int* counts;
+  const uint32_t* bits_c;
+  const uint32_t* bits_m;
+};
+
+XferHost xfer_host(fms_handle h, const Xfer& x, int nc) {
+  const uint8_t* hb = static_cast<const uint8_t*>(h->hstage);
+  const size_t nb_n = ((size_t(nc) * sizeof(int) + 255) / 256) * 256;
+  const size_t nb_c = size_t(nc) * x.words_c * sizeof(uint32_t);
+  return XferHost{reinterpret_cast<const int*>(hb), reinterpret_cast<const uint32_t*>(hb + nb_n),
+                  reinterpret_cast<const uint32_t*>(hb + nb_n + nb_c)};
 }
 
 struct RoundOut {
@@ -293,86 +338,168 @@ void add_timing(fms_stats& sx, const RoundOut& ro) {
   }
 }
 
-// Iterate the m seeds whose centres are in y[0..m) (Alg. 2, the parallel seed
-// loop) until more than gamma of them converged (Sec. 3.2.3), no seed is
-// active, or max_iter steps.  The BF16 form then runs refine_iters FP32 steps
-// on the converged seeds.  The converged slots end up in h->cand.
-fms_status run_round(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr, float tol,
-                     RoundOut& out) {
+// Iterate the seeds whose centres are in y[0..m) (Alg. 2, the parallel seed
+// loop) until more than gamma of them converged (Sec. 3.2.3), none is
+// active, or max_iter steps.  The active count, the early-stop test and the
+// done flag live on the device; the host enqueues iterations in batches and
+// reads the flag back between batches.  The converged slots end up in
+// out.conv (ascending) and in h->cand.
+fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr,
+                          float tol, RoundOut& out) {
   int* meta = h->meta.as<int>();
-  HIP_TRY(fms::launch_round_init(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>()));
-  HIP_TRY(hipMemsetAsync(meta + META_NCONV, 0, sizeof(int), st));
+  unsigned long long* meta64 = h->meta64.as<unsigned long long>();
   const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
-  const bool timing = p->timing != 0;
+  const int gs = fms::shift_group_seeds(bf16, fr.dp);
   const int pk = bf16 ? 1 : 0;
-  if (timing) HIP_TRY(h->ensure_events(2 * size_t(std::max(p->refine_iters, 1))));
-  int n_act = m;
-  int* act = h->active.as<int>();
-  int* nxt = h->next_active.as<int>();
-  for (int t = 0; t < p->max_iter && n_act > 0; ++t) {
-    HIP_TRY(hipMemsetAsync(meta + META_NNEXT, 0, sizeof(int), st));
-    if (timing) HIP_TRY(hipEventRecord(h->events[0], st));
-    HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom, xrm, xt, h->y.as<float>(), act, n_act, thr,
-                              h->partial.as<float>()));
-    if (timing) HIP_TRY(hipEventRecord(h->events[1], st));
-    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom, h->partial.as<float>(), n_act, act, h->y.as<float>(),
-                               h->state.as<uint8_t>(), h->iters.as<int>(), tol, 0, meta, nxt));
-    HIP_TRY(hipMemcpyAsync(h->hmeta + META_NCONV, meta + META_NCONV, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  const bool timing = p->timing != 0;
+  HIP_TRY(fms::launch_round_begin(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>(), meta,
+                                  meta64));
+  int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
+  int t = 0, batch = 3;
+  while (t < p->max_iter) {
+    const int nb = std::min(batch, p->max_iter - t);
+    if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
+    for (int i = 0; i < nb; ++i, ++t) {
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * i], st));
+      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom.n_blocks, xrm, xt, h->y.as<float>(), lists[t & 1], meta,
+                                fms::META_NACT, fms::META_DONE, m, thr, h->partial.as<float>()));
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * i + 1], st));
+      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), lists[t & 1],
+                                 h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1],
+                                 meta, meta64, fms::META_NACT, fms::META_DONE, m, fr.n, tol, p->gamma, 0));
+    }
+    HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (timing) {
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, h->events[0], h->events[1]));
-      out.step_ms[pk] += ms;
-      out.step_updates[pk] += int64_t(n_act) * int64_t(fr.n);
-      out.step_launches[pk] += 1;
+      for (int i = 0; i < nb; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * i], h->events[2 * i + 1]));
+        out.step_ms[pk] += ms;
+        out.step_launches[pk] += 1;
+      }
     }
-    out.steps += 1;
-    out.updates += int64_t(n_act) * int64_t(fr.n);
-    n_act = h->hmeta[META_NNEXT];
-    std::swap(act, nxt);
-    if (double(h->hmeta[META_NCONV]) > p->gamma * double(m)) break;
+    if (h->hmeta[fms::META_DONE]) break;
+    batch = std::min(2 * batch, 8);
   }
-  // Converged slots, in slot (= seed-order) order.
-  HIP_TRY(hipMemcpyAsync(h->hstage, h->state.p, size_t(m), hipMemcpyDeviceToHost, st));
+  out.steps = h->hmeta[fms::META_STEPS];
+  // Converged slots, in slot (= seed-order) order, and the update count.
+  uint8_t* hs = static_cast<uint8_t*>(h->hstage);
+  HIP_TRY(hipMemcpyAsync(hs, h->state.p, size_t(m), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hs + ((size_t(m) + 15) / 16) * 16, meta64, sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const uint8_t* stt = static_cast<const uint8_t*>(h->hstage);
+  unsigned long long upd = 0;
+  std::memcpy(&upd, hs + ((size_t(m) + 15) / 16) * 16, sizeof(upd));
+  out.updates = int64_t(upd);
+  if (timing) out.step_updates[pk] += out.updates;
   out.conv.clear();
   for (int k = 0; k < m; ++k)
-    if (stt[k] == 1) out.conv.push_back(k);
+    if (hs[k] == 1) out.conv.push_back(k);
   const int nc = int(out.conv.size());
   if (nc > 0) {
     std::memcpy(h->hstage, out.conv.data(), size_t(nc) * sizeof(int));
     HIP_TRY(hipMemcpyAsync(h->cand.p, h->hstage, size_t(nc) * sizeof(int), hipMemcpyHostToDevice, st));
-  }
-  if (bf16 && p->refine_iters > 0 && nc > 0) {
-    HIP_TRY(hipMemsetAsync(meta + META_REFINE_BAD, 0, sizeof(int), st));
-    for (int r = 0; r < p->refine_iters; ++r) {
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
-      HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom, h->x32.p, h->x32t.p, h->y.as<float>(), h->cand.as<int>(),
-                                nc, thr, h->partial.as<float>()));
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
-      out.refine_updates += int64_t(nc) * int64_t(fr.n);
-      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom, h->partial.as<float>(), nc, h->cand.as<int>(),
-                                 h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(), tol,
-                                 r + 1 == p->refine_iters ? 2 : 1, meta, nullptr));
-      out.refine_steps += 1;
-    }
-    HIP_TRY(hipMemcpyAsync(h->hmeta + META_REFINE_BAD, meta + META_REFINE_BAD, sizeof(int), hipMemcpyDeviceToHost,
-                           st));
     HIP_TRY(hipStreamSynchronize(st));
-    out.refine_bad = h->hmeta[META_REFINE_BAD];
+  }
+  return FMS_OK;
+}
+
+// FP32 refinement (BF16 form) of the `a` centres y[list[0..a)]: at least
+// `steps` steps; further steps in batches of four while any centre still
+// moves by >= tol, up to max_steps in total.  Counts the centres whose last
+// step moved >= tol.
+fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, const int* list, int a, int steps,
+                      int max_steps, float thr, float tol, bool timing, RoundOut& out) {
+  if (a <= 0 || steps <= 0) return FMS_OK;
+  int* meta = h->meta.as<int>();
+  const int gs = fms::shift_group_seeds(false, fr.dp);
+  h->hmeta[fms::META_NACC] = a;
+  HIP_TRY(hipMemcpyAsync(meta + fms::META_NACC, h->hmeta + fms::META_NACC, sizeof(int), hipMemcpyHostToDevice, st));
+  int done = 0, batch = steps;
+  while (true) {
+    const int nb = std::min(batch, std::max(max_steps - done, 1));
+    if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
+    HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
+    for (int r = 0; r < nb; ++r) {
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
+      HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, meta,
+                                fms::META_NACC, -1, a, thr, h->partial.as<float>()));
+      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
+      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), list, y,
+                                 h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, meta,
+                                 h->meta64.as<unsigned long long>(), fms::META_NACC, -1, a, fr.n, tol, 1.0,
+                                 r + 1 == nb ? 2 : 1));
+      out.refine_steps += 1;
+      out.refine_updates += int64_t(a) * int64_t(fr.n);
+    }
+    done += nb;
+    HIP_TRY(hipMemcpyAsync(h->hmeta + fms::META_REFINE_BAD, meta + fms::META_REFINE_BAD, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     if (timing) {
-      for (int r = 0; r < p->refine_iters; ++r) {
+      for (int r = 0; r < nb; ++r) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
         out.step_ms[0] += ms;
-        out.step_updates[0] += int64_t(nc) * int64_t(fr.n);
+        out.step_updates[0] += int64_t(a) * int64_t(fr.n);
         out.step_launches[0] += 1;
       }
     }
+    if (h->hmeta[fms::META_REFINE_BAD] == 0 || done >= max_steps) break;
+    batch = 4;
   }
+  out.refine_bad += h->hmeta[fms::META_REFINE_BAD];
+  return FMS_OK;
+}
+
+// Greedy pruning (Alg. 2): visit candidates in `order`, accept one when it is
+// not within the window of an existing mode (a nonzero row of bits_m) and not
+// within the window of a candidate accepted before it (bits_c).
+std::vector<int> greedy_accept(const std::vector<int>& order, const XferHost& xh, const Xfer& x, bool have_modes) {
+  std::vector<uint32_t> taken(size_t(std::max(x.words_c, 1)), 0u);
+  std::vector<int> acc;
+  for (int a : order) {
+    if (have_modes) {
+      const uint32_t* rm = xh.bits_m + size_t(a) * x.words_m;
+      bool blocked = false;
+      for (int w = 0; w < x.words_m && !blocked; ++w) blocked = rm[w] != 0;
+      if (blocked) continue;
+    }
+    const uint32_t* row = xh.bits_c + size_t(a) * x.words_c;
+    bool clash = false;
+    for (int w = 0; w < x.words_c && !clash; ++w) clash = (row[w] & taken[w]) != 0;
+    if (clash) continue;
+    taken[a >> 5] |= 1u << (a & 31);
+    acc.push_back(a);
+  }
+  return acc;
+}
+
+// Similarity bits of the nc centres y[list[..]] among themselves and against
+// modes[0..k), with their window counts when `counts` is requested, copied to
+// the host in one transfer.
+fms_status prune_inputs(fms_handle h, hipStream_t st, const Frame& fr, const float* y, const int* list, int nc, int k,
+                        float thr, bool with_counts, Xfer& x, XferHost& xh) {
+  fms_status stt = ensure_xfer(h, nc, k, x);
+  if (stt != FMS_OK) return stt;
+  if (with_counts)
+    HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), y, list, nc, thr,
+                              h->pcount.as<int>(), x.counts));
+  HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c));
+  if (k > 0) HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, nullptr, h->modes.as<float>(), k, thr, x.bits_m));
+  HIP_TRY(hipMemcpyAsync(h->hstage, h->bits.p, x.bytes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  xh = xfer_host(h, x, nc);
+  return FMS_OK;
+}
+
+fms_status grow_modes(fms_handle h, hipStream_t st, const Frame& fr, int k_modes, int extra) {
+  // The mode set persists across rounds: grow it without losing rows.
+  HIP_TRY(h->modes.grow_keep(size_t(k_modes + extra) * fr.dp * sizeof(float), size_t(k_modes) * fr.dp * sizeof(float),
+                             st));
+  HIP_TRY(h->mode_counts.grow_keep(size_t(k_modes + extra) * sizeof(int), size_t(k_modes) * sizeof(int), st));
   return FMS_OK;
 }
 
@@ -424,7 +551,8 @@ fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
   h->device = device_ordinal;
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), META_COUNT * sizeof(int), hipHostMallocDefault) !=
           hipSuccess ||
-      h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess) {
+      h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess ||
+      h->meta64.ensure(4 * sizeof(unsigned long long)) != hipSuccess) {
     fms_destroy(h);
     return FMS_ERR_HIP;
   }
@@ -439,7 +567,7 @@ fms_status fms_destroy(fms_handle h) {
   DevBuf* bufs[] = {&h->blk,   &h->fg_idx, &h->x32,     &h->x32t,        &h->x16,     &h->x16t,     &h->order,
                     &h->uncovered, &h->used, &h->y, &h->active, &h->next_active, &h->state, &h->iters,
                     &h->seed_pos, &h->seed_fg, &h->ident, &h->cand, &h->counts, &h->pcount, &h->partial,
-                    &h->bits, &h->blocked, &h->acc, &h->modes, &h->mode_counts, &h->meta};
+                    &h->bits, &h->blocked, &h->acc, &h->modes, &h->mode_counts, &h->meta, &h->meta64};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->hmeta) (void)hipHostFree(h->hmeta);
@@ -476,7 +604,8 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   int64_t n_seeds = p->n_state_in > 0 ? p->n_state_in : p->n_initial;
 
   Frame fr;
-  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim, fr);
+  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
+                      p->precision == FMS_PREC_BF16_REFINE, fr);
   if (stt != FMS_OK) return stt;
   sx.n_fg = fr.n;
   HIP_TRY(fms::launch_fill_i32(st, labels, P, -1));
@@ -512,7 +641,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     const int64_t want64 = std::min<int64_t>(n_seeds - n_used, n);
     if (want64 <= 0) break;
     const int want = int(want64);
-    stt = ensure_round(h, fr, want);
+    stt = ensure_round(h, fr, want, p->precision == FMS_PREC_BF16_REFINE);
     if (stt != FMS_OK) return stt;
     HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->uncovered.as<uint8_t>(), h->used.as<uint8_t>(), n, want,
                                meta, h->seed_pos.as<int>(), h->seed_fg.as<int>(), h->x32.as<float>(), fr.dp,
@@ -526,69 +655,74 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     sx.seeds_used += m;
 
     RoundOut ro;
-    stt = run_round(h, st, fr, m, p, thr, tol, ro);
+    const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
+    stt = run_iterations(h, st, fr, m, p, thr, tol, ro);
     if (stt != FMS_OK) return stt;
+    const int nc = int(ro.conv.size());
+    sx.n_discarded += m - nc;
+
+    // Prune (Alg. 2): window counts at the endpoints and similarity bits on
+    // the GPU, greedy acceptance on the host (count descending, then seed
+    // position).
+    int accepted = 0;
+    if (nc > 0) {
+      Xfer x;
+      XferHost xh;
+      stt = prune_inputs(h, st, fr, h->y.as<float>(), h->cand.as<int>(), nc, k_modes, thr, true, x, xh);
+      if (stt != FMS_OK) return stt;
+      std::vector<int> ord(nc);
+      for (int a = 0; a < nc; ++a) ord[a] = a;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return xh.counts[a] > xh.counts[b]; });
+      std::vector<int> acc = greedy_accept(ord, xh, x, k_modes > 0);
+      accepted = int(acc.size());
+      if (accepted > 0) {
+        stt = grow_modes(h, st, fr, k_modes, accepted);
+        if (stt != FMS_OK) return stt;
+        HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
+        int* hacc = reinterpret_cast<int*>(h->hstage);  // staging is free again after the sync above
+        for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
+        HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), x.counts, h->acc.as<int>(),
+                                         accepted, h->modes.as<float>(), h->mode_counts.as<int>(), k_modes));
+        HIP_TRY(hipStreamSynchronize(st));
+      }
+    }
+    if (bf16 && accepted > 0 && p->refine_iters > 0) {
+      // BF16 form: the accepted modes are refined in FP32 (at least
+      // refine_iters steps, then until they stop moving), recounted, and any
+      // that now fall inside the window of an earlier mode are dropped
+      // (acceptance order decides).
+      float* newm = h->modes.as<float>() + size_t(k_modes) * fr.dp;
+      HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), accepted));
+      stt = run_refine(h, st, fr, newm, h->ident.as<int>(), accepted, p->refine_iters, p->max_iter, thr, tol,
+                       p->timing != 0, ro);
+      if (stt != FMS_OK) return stt;
+      Xfer x;
+      XferHost xh;
+      stt = prune_inputs(h, st, fr, newm, h->ident.as<int>(), accepted, k_modes, thr, true, x, xh);
+      if (stt != FMS_OK) return stt;
+      std::vector<int> ord(accepted);
+      for (int a = 0; a < accepted; ++a) ord[a] = a;
+      std::vector<int> keep = greedy_accept(ord, xh, x, k_modes > 0);
+      // Rewrite the new rows through the (now free) centre buffer, keeping
+      // only the survivors, with their recounted windows.
+      HIP_TRY(fms::launch_copy_rows(st, newm, fr.dp, h->y.as<float>(), fr.dp, accepted, fr.dp));
+      HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
+      int* hk = reinterpret_cast<int*>(h->hstage);
+      for (size_t q = 0; q < keep.size(); ++q) hk[q] = keep[q];
+      HIP_TRY(hipMemcpyAsync(h->acc.p, hk, keep.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
+                                       int(keep.size()), h->modes.as<float>(), h->mode_counts.as<int>(), k_modes));
+      HIP_TRY(hipStreamSynchronize(st));
+      sx.refine_merged += accepted - int(keep.size());
+      accepted = int(keep.size());
+    }
     sx.iterations_total += ro.steps;
     sx.refine_steps += ro.refine_steps;
     sx.seed_pixel_updates += ro.updates;
     sx.refine_unconverged += ro.refine_bad;
     sx.refine_updates += ro.refine_updates;
     add_timing(sx, ro);
-    const int nc = int(ro.conv.size());
-    sx.n_discarded += m - nc;
-
-    // Prune (Alg. 2): window counts at the endpoints, conflicts on the GPU,
-    // greedy acceptance on the host.
-    int accepted = 0;
-    if (nc > 0) {
-      const int words = (nc + 31) / 32;
-      HIP_TRY(h->bits.ensure(size_t(nc) * words * sizeof(uint32_t)));
-      HIP_TRY(h->blocked.ensure(size_t(nc)));
-      HIP_TRY(h->acc.ensure(size_t(nc) * sizeof(int)));
-      HIP_TRY(fms::launch_count(st, fr.dp, fr.geom, h->x32.as<float>(), h->y.as<float>(), h->cand.as<int>(), nc, thr,
-                                h->pcount.as<int>(), h->counts.as<int>()));
-      HIP_TRY(fms::launch_conflicts(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->modes.as<float>(),
-                                    k_modes, thr, h->bits.as<uint32_t>(), words, h->blocked.as<uint8_t>()));
-      const size_t nb_bits = size_t(nc) * words * sizeof(uint32_t);
-      uint8_t* hs = static_cast<uint8_t*>(h->hstage);
-      uint32_t* hbits = reinterpret_cast<uint32_t*>(hs);
-      int* hcounts = reinterpret_cast<int*>(hs + nb_bits);
-      uint8_t* hblocked = hs + nb_bits + size_t(nc) * sizeof(int);
-      HIP_TRY(hipMemcpyAsync(hbits, h->bits.p, nb_bits, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(hcounts, h->counts.p, size_t(nc) * sizeof(int), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(hblocked, h->blocked.p, size_t(nc), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      std::vector<int> ord(nc);
-      for (int a = 0; a < nc; ++a) ord[a] = a;
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hcounts[a] > hcounts[b]; });
-      std::vector<uint32_t> taken(size_t(words), 0u);
-      std::vector<int> acc;
-      for (int a : ord) {
-        if (hblocked[a]) continue;
-        const uint32_t* row = hbits + size_t(a) * words;
-        bool clash = false;
-        for (int w = 0; w < words && !clash; ++w) clash = (row[w] & taken[w]) != 0;
-        if (clash) continue;
-        taken[a >> 5] |= 1u << (a & 31);
-        acc.push_back(a);
-      }
-      accepted = int(acc.size());
-      if (accepted > 0) {
-        // The mode set persists across rounds: grow it without losing rows.
-        HIP_TRY(h->modes.grow_keep(size_t(k_modes + accepted) * fr.dp * sizeof(float),
-                                   size_t(k_modes) * fr.dp * sizeof(float), st));
-        HIP_TRY(h->mode_counts.grow_keep(size_t(k_modes + accepted) * sizeof(int), size_t(k_modes) * sizeof(int),
-                                         st));
-        // acc holds candidate indices; translate to slots on the host.
-        int* hacc = reinterpret_cast<int*>(hs);  // staging is free again after the sync above
-        for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
-        HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
-        HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), h->counts.as<int>(),
-                                         h->acc.as<int>(), accepted, h->modes.as<float>(), h->mode_counts.as<int>(),
-                                         k_modes));
-        HIP_TRY(hipStreamSynchronize(st));
-      }
-    }
     const int k_old = k_modes;
     k_modes += accepted;
     // Coverage by the new modes, and the pool left to seed.
@@ -651,7 +785,8 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   std::memset(&sx, 0, sizeof(sx));
   sx.n_min = std::numeric_limits<double>::quiet_NaN();
   Frame fr;
-  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim, fr);
+  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
+                      p->precision == FMS_PREC_BF16_REFINE, fr);
   if (stt != FMS_OK) return stt;
   sx.n_fg = fr.n;
   if (n_seeds == 0) {
@@ -660,7 +795,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   }
   if (fr.n == 0) return FMS_ERR_INVALID_ARG;
   const int m = n_seeds;
-  stt = ensure_round(h, fr, m);
+  stt = ensure_round(h, fr, m, p->precision == FMS_PREC_BF16_REFINE);
   if (stt != FMS_OK) return stt;
   int* meta = h->meta.as<int>();
   HIP_TRY(hipMemsetAsync(meta + META_BADSEED, 0, sizeof(int), st));
@@ -671,14 +806,19 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   const float thr = float(1.0 - p->bandwidth);
   const float tol = float(tol_of(p));
   RoundOut ro;
-  stt = run_round(h, st, fr, m, p, thr, tol, ro);
+  h->hmeta[META_NSEL] = m;
+  HIP_TRY(hipMemcpyAsync(meta + META_NSEL, h->hmeta + META_NSEL, sizeof(int), hipMemcpyHostToDevice, st));
+  stt = run_iterations(h, st, fr, m, p, thr, tol, ro);
   if (stt != FMS_OK) return stt;
+  if (p->precision == FMS_PREC_BF16_REFINE && !ro.conv.empty()) {
+    stt = run_refine(h, st, fr, h->y.as<float>(), h->cand.as<int>(), int(ro.conv.size()), p->refine_iters,
+                     p->refine_iters, thr, tol, p->timing != 0, ro);
+    if (stt != FMS_OK) return stt;
+  }
   // Window counts of every slot (the output keeps them for converged seeds).
-  int* hid = static_cast<int*>(h->hstage);
-  for (int k = 0; k < m; ++k) hid[k] = k;
-  HIP_TRY(hipMemcpyAsync(h->ident.p, h->hstage, size_t(m) * sizeof(int), hipMemcpyHostToDevice, st));
-  HIP_TRY(fms::launch_count(st, fr.dp, fr.geom, h->x32.as<float>(), h->y.as<float>(), h->ident.as<int>(), m, thr,
-                            h->pcount.as<int>(), h->counts.as<int>()));
+  HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), m));
+  HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
+                            h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>()));
   HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
   HIP_TRY(hipStreamSynchronize(st));

@@ -19,7 +19,21 @@ enum MetaSlot {
   META_REFINE_BAD = 6, // refine steps whose move stayed >= tol
   META_LEFT = 7,       // foreground pixels neither covered nor used
   META_BADSEED = 8,    // seed indices outside [0, n)
+  META_NACT = 9,       // active seeds of the next iteration
+  META_DONE = 10,      // the round's iteration has stopped
+  META_BLKDONE = 11,   // finished work groups of the current reduce launch
+  META_STEPS = 12,     // iterations run this round
+  META_NACC = 13,      // modes being refined
   META_COUNT = 16
+};
+
+// Work decomposition of the fused step (see plan_chunks in kernels.hip).
+constexpr int kTargetItems = 1024;
+constexpr int kMaxChunks = 256;
+struct ChunkPlan {
+  int groups;
+  int n_chunks;
+  int chunk_blocks;
 };
 
 struct FrameDesc {
@@ -47,7 +61,8 @@ hipError_t launch_select(hipStream_t s, const int* order, const uint8_t* uncover
                          float* y);
 hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, const float* x32, int dp,
                              float* y, int* meta);
-hipError_t launch_round_init(hipStream_t s, int m, int* active, uint8_t* state, int* iters);
+hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
+                              unsigned long long* meta64);
 
 struct StepGeom {
   int n;             // foreground count
@@ -57,21 +72,29 @@ struct StepGeom {
 };
 StepGeom make_geom(int n);
 
-// One fused mean-shift step for the active seeds: partial window sums per chunk.
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const StepGeom& g, const void* xrm,
-                        const void* xt, const float* y, const int* active, int n_act, float thr,
-                        float* partial);
-// Sum partials, renormalise, convergence test, next active list.
-hipError_t launch_reduce(hipStream_t s, int dp, const StepGeom& g, const float* partial, int n_act,
-                         const int* active, float* y, uint8_t* state, int* iters, float tol, int mode,
-                         int* meta, int* next_active);
-// Window counts of the centres listed in `list`.
-hipError_t launch_count(hipStream_t s, int dp, const StepGeom& g, const float* x32, const float* y,
+// One fused mean-shift step for the active seeds (count in meta[nact_slot],
+// at most cap; skipped when done_slot >= 0 and meta[done_slot] is set):
+// partial window sums per pixel chunk.
+int shift_group_seeds(bool bf16, int dp);
+size_t shift_partial_rows(bool bf16, int dp, int cap, int n_blocks);
+hipError_t launch_shift(hipStream_t s, bool bf16, int dp, int n_blocks, const void* xrm, const void* xt,
+                        const float* y, const int* active, const int* meta, int nact_slot, int done_slot, int cap,
+                        float thr, float* partial);
+// Sum partials, renormalise, convergence test, next active list and (mode 0)
+// the early stop.
+hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, const float* partial,
+                         const int* active, float* y, uint8_t* state, int* iters, int* next_active, int* meta,
+                         unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
+                         double gamma, int mode);
+// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres (FP32 MFMA).
+size_t count_partial_rows(int dp, int cap);
+hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
                         const int* list, int m, float thr, int* pcount, int* counts);
-// Pairwise conflicts among candidates and against existing modes.
-hipError_t launch_conflicts(hipStream_t s, int dp, const float* y, const int* list, int m,
-                            const float* modes, int k, float thr, uint32_t* bits, int words,
-                            uint8_t* blocked);
+// Similarity bits between the rows y[rows[0..m)] and the columns y[cols[c]]
+// (or colmat[c]) for c < ncols: row stride simbits_words(ncols) words.
+int simbits_words(int ncols);
+hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
+                          const float* colmat, int ncols, float thr, uint32_t* bits);
 hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int* list, const int* counts,
                                const int* acc, int a, float* modes, int* mode_counts, int k0);
 // Coverage (mode = 0) or labels (mode = 1) against modes [k0, k1); both count
@@ -80,6 +103,7 @@ hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const f
                          int k1, float thr, int mode, uint8_t* uncovered, const uint8_t* used,
                          int* meta, const int* fg_idx, int* labels);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int64_t count, int value);
+hipError_t launch_iota(hipStream_t s, int* p, int count);
 hipError_t launch_copy_rows(hipStream_t s, const float* src, int src_stride, float* dst, int dst_stride,
                             int rows, int cols);
 hipError_t launch_lockstep_out(hipStream_t s, int m, int dp, int dim, const float* y, const uint8_t* state,

@@ -20,6 +20,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "fms_internal.h"
 
 namespace fms {
@@ -27,6 +30,10 @@ namespace fms {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Bit pattern of a float taken by value.  (Bit-casting an element of an
+// ext_vector_type in place reads the vector's first element instead.)
+__device__ __forceinline__ uint32_t fbits(float f) { return __builtin_bit_cast(uint32_t, f); }
 
 __device__ __forceinline__ uint16_t to_bf16_bits(float f) {
   return __builtin_bit_cast(uint16_t, (__bf16)f);
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(256) void k_compact(FrameDesc f, const int* __restr
     }
     fg_idx[ord] = (int)p;
     float* rowp = x32 + (int64_t)ord * DP;
-    uint16_t* row16 = x16 + (int64_t)ord * DP;
+    uint16_t* row16 = x16 ? x16 + (int64_t)ord * DP : nullptr;
     const int64_t blk = ord / kBlockPix, q = ord % kBlockPix;
     for (int d = 0; d < DP; d += 4) {
       float4 v4 = make_float4(vals[d] * inv, vals[d + 1] * inv, vals[d + 2] * inv, vals[d + 3] * inv);
@@ -173,6 +180,7 @@ __global__ __launch_bounds__(256) void k_compact(FrameDesc f, const int* __restr
       x32t[(blk * DP + d + 1) * kBlockPix + q] = v4.y;
       x32t[(blk * DP + d + 2) * kBlockPix + q] = v4.z;
       x32t[(blk * DP + d + 3) * kBlockPix + q] = v4.w;
+      if (!x16) continue;
       uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
                b3 = to_bf16_bits(v4.w);
       row16[d] = b0;
@@ -222,13 +230,15 @@ __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, u
 
 // One 1024-thread block: take the first `want` positions of the seed order
 // (from the cursor on) whose pixels are uncovered and unused, mark them used
-// and load their vectors as the round's starting centres.
+// and load their vectors as the round's starting centres.  Each pass looks at
+// 16 consecutive positions per thread (16384 per pass).
 __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order,
                                                  const uint8_t* __restrict__ uncovered,
                                                  uint8_t* __restrict__ used, int n, int want,
                                                  int* __restrict__ meta, int* __restrict__ seed_pos,
                                                  int* __restrict__ seed_fg, const float* __restrict__ x32,
                                                  int dp, float* __restrict__ y) {
+  constexpr int RUN = 16;
   __shared__ int sh[17];
   __shared__ int s_last;
   __shared__ int s_base;
@@ -238,18 +248,32 @@ __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order,
   int got = 0;
   int new_cursor = n;
   while (got < want && base < n) {
-    const int pos = base + (int)threadIdx.x;
-    int e = 0, o = -1;
-    if (pos < n) {
-      o = order[pos];
-      e = uncovered[o] && !used[o];
+    const int p0 = base + (int)threadIdx.x * RUN;
+    int ord[RUN];
+    uint32_t elig = 0;
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+      const int pos = p0 + k;
+      ord[k] = pos < n ? order[pos] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+      const int pos = p0 + k;
+      if (pos < n && uncovered[ord[k]] && !used[ord[k]]) elig |= 1u << k;
     }
     int tot;
-    int rank = block_exclusive_scan<1024>(e, &tot, sh);
-    if (e && got + rank < want) {
-      seed_pos[got + rank] = pos;
-      seed_fg[got + rank] = o;
-      if (got + rank == want - 1) s_last = pos;
+    int rank = block_exclusive_scan<1024>(__popc(elig), &tot, sh);
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+      if ((elig >> k) & 1u) {
+        const int q = got + rank;
+        if (q < want) {
+          seed_pos[q] = p0 + k;
+          seed_fg[q] = ord[k];
+          if (q == want - 1) s_last = p0 + k;
+        }
+        ++rank;
+      }
     }
     __syncthreads();
     if (got + tot >= want) {
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order,
       got = want;
     } else {
       got += tot;
-      base += 1024;
+      base += 1024 * RUN;
     }
     __syncthreads();
   }
@@ -289,383 +313,452 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
   y[k] = x32[(int64_t)o * dp + d];
 }
 
-__global__ __launch_bounds__(256) void k_round_init(int m, int* __restrict__ active, uint8_t* __restrict__ state,
-                                                    int* __restrict__ iters) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= m) return;
-  active[k] = k;
-  state[k] = 0;
-  iters[k] = 0;
-}
 
 // ------------------------------------------------------------------ fused step
 
-// FP32 form.  One wave = one work item (a group of ST x 16 seeds, one pixel
-// chunk).  v_mfma_f32_16x16x4_f32: lane (g, r) feeds A[r][g] and B[g][r].
-template <int DP, int ST>
-__global__ __launch_bounds__(64) void k_shift_f32(const float* __restrict__ x, const float* __restrict__ xt,
-                                                  const float* __restrict__ y, const int* __restrict__ active,
-                                                  int n_act, int n_blocks, int chunk_blocks, int n_chunks,
-                                                  float thr, float* __restrict__ partial) {
-  constexpr int KJ = DP / 4;    // dims per lane group = MFMA steps of S
-  constexpr int NDB = DP / 16;  // 16-dim blocks of V
-  const int lane = threadIdx.x;
-  const int g = lane >> 4, r = lane & 15;
-  const int grp = blockIdx.x / n_chunks;
-  const int chunk = blockIdx.x - grp * n_chunks;
-  const int a0 = grp * ST * 16;
-
-  float yb[ST][KJ];
-#pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    const int a = a0 + 16 * s + r;
-    if (a < n_act) {
-      const float4* yr = reinterpret_cast<const float4*>(y + (int64_t)active[a] * DP + g * KJ);
-#pragma unroll
-      for (int j = 0; j < KJ / 4; ++j) {
-        float4 v = yr[j];
-        yb[s][4 * j] = v.x;
-        yb[s][4 * j + 1] = v.y;
-        yb[s][4 * j + 2] = v.z;
-        yb[s][4 * j + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < KJ; ++j) yb[s][j] = 0.f;
-    }
-  }
-  f32x4 acc[ST][NDB];
-#pragma unroll
-  for (int s = 0; s < ST; ++s)
-#pragma unroll
-    for (int db = 0; db < NDB; ++db) acc[s][db] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const int b0 = chunk * chunk_blocks;
-  const int b1 = min(n_blocks, b0 + chunk_blocks);
-  const int rowsel0 = 8 * (r >> 2) + (r & 3);
-  for (int b = b0; b < b1; ++b) {
-    const float* xb = x + (int64_t)b * kBlockPix * DP;
-    float xa[2][KJ];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const float4* xr = reinterpret_cast<const float4*>(xb + (rowsel0 + 4 * t) * DP + g * KJ);
-#pragma unroll
-      for (int j = 0; j < KJ / 4; ++j) {
-        float4 v = xr[j];
-        xa[t][4 * j] = v.x;
-        xa[t][4 * j + 1] = v.y;
-        xa[t][4 * j + 2] = v.z;
-        xa[t][4 * j + 3] = v.w;
-      }
-    }
-    float xv[NDB][8];
-#pragma unroll
-    for (int db = 0; db < NDB; ++db) {
-      const float4* tp = reinterpret_cast<const float4*>(xt + ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
-      float4 u = tp[0], v = tp[1];
-      xv[db][0] = u.x; xv[db][1] = u.y; xv[db][2] = u.z; xv[db][3] = u.w;
-      xv[db][4] = v.x; xv[db][5] = v.y; xv[db][6] = v.z; xv[db][7] = v.w;
-    }
-#pragma unroll
-    for (int s = 0; s < ST; ++s) {
-      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int j = 0; j < KJ; ++j) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][j], yb[s][j], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[1][j], yb[s][j], s1, 0, 0, 0);
-      }
-      float w[8];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        w[i] = s0[i] >= thr ? 1.f : 0.f;
-        w[4 + i] = s1[i] >= thr ? 1.f : 0.f;
-      }
-#pragma unroll
-      for (int db = 0; db < NDB; ++db)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[db][e], w[e], acc[s][db], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    const int a = a0 + 16 * s + r;
-    if (a < n_act) {
-      float* dst = partial + ((int64_t)chunk * n_act + a) * DP + 4 * g;
-#pragma unroll
-      for (int db = 0; db < NDB; ++db) {
-        f32x4 v = acc[s][db];
-        *reinterpret_cast<float4*>(dst + 16 * db) = make_float4(v[0], v[1], v[2], v[3]);
-      }
-    }
-  }
+// Work plan of one fused step: seeds in groups of 16*ST, pixels in chunks of
+// whole 32-pixel blocks, about kTargetItems (group, chunk) items in total.
+// The kernels derive it from the active count held on the device; the host
+// uses the same function with upper bounds to size the partial buffer.
+__host__ __device__ inline ChunkPlan plan_chunks(int n_act, int group_seeds, int n_blocks) {
+  ChunkPlan cp;
+  const int groups = n_act > 0 ? (n_act + group_seeds - 1) / group_seeds : 1;
+  int want = (kTargetItems + groups - 1) / groups;
+  int lim = n_blocks < kMaxChunks ? n_blocks : kMaxChunks;
+  if (lim < 1) lim = 1;
+  int nc = want < 1 ? 1 : (want > lim ? lim : want);
+  const int cb = n_blocks > 0 ? (n_blocks + nc - 1) / nc : 1;
+  nc = n_blocks > 0 ? (n_blocks + cb - 1) / cb : 1;
+  cp.groups = groups;
+  cp.n_chunks = nc;
+  cp.chunk_blocks = cb;
+  return cp;
 }
 
-// BF16 form.  v_mfma_f32_16x16x32_bf16: lane (g, r) feeds A[r][8g..8g+7] and
-// B[8g..8g+7][r]; FP32 accumulate.  Centres are rounded to BF16 as they load.
-template <int DP, int ST>
-__global__ __launch_bounds__(64) void k_shift_bf16(const uint16_t* __restrict__ x, const uint16_t* __restrict__ xt,
-                                                   const float* __restrict__ y, const int* __restrict__ active,
-                                                   int n_act, int n_blocks, int chunk_blocks, int n_chunks,
-                                                   float thr, float* __restrict__ partial) {
-  constexpr int KS = DP / 32;   // MFMA steps of S (32 dims each)
-  constexpr int KJ = DP / 4;    // dims per lane group
-  constexpr int NDB = DP / 16;
-  const int lane = threadIdx.x;
+// The fused mean-shift step (Eq. 8, 10, 11) for the active seeds.
+//
+// Work group = 4 waves = one item: a group of 16*ST seeds and one pixel chunk.
+// The waves share the seeds and take every fourth block of the chunk; their
+// window sums are added in LDS in a fixed order and written as the item's
+// partial sum.  Items are spread over the XCDs so that the work groups of
+// one XCD walk through neighbouring items (same chunk, different seed groups)
+// and share that chunk in their L2.
+//
+// The MFMA accumulator of S^T starts at -thr, so S - thr comes out of the
+// matrix core and the window test is a sign test.  FP32 form:
+// v_mfma_f32_16x16x4_f32 (lane (g, r) feeds A[r][g], B[g][r]).  BF16 form:
+// v_mfma_f32_16x16x32_bf16 (lane (g, r) feeds A[r][8g..8g+7], B[8g..8g+7][r]),
+// FP32 accumulation; the 0/1 weights of two pixels are packed into one BF16
+// pair with one v_perm_b32 (sign bytes) and one bit-select.
+//
+// COUNT form (FP32 only): the same S^T tiles, no second product; each item
+// writes the per-seed number of its pixels inside the window (window counts
+// at the centres, used to rank candidate modes).
+template <bool BF16, bool COUNT, int DP, int ST>
+__global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, const void* __restrict__ xt_,
+                                               const float* __restrict__ y, const int* __restrict__ active,
+                                               const int* __restrict__ meta, int nact_slot, int done_slot,
+                                               int n_host, int n_blocks, int n_pix, float thr,
+                                               float* __restrict__ partial, int* __restrict__ pcount) {
+  constexpr int KJ = DP / 4;     // dimensions held per lane group
+  constexpr int KS = BF16 ? DP / 32 : DP / 4;  // MFMA steps of S per 16x16 tile
+  constexpr int NDB = DP / 16;   // 16-dimension blocks of V
+  typedef typename std::conditional<BF16, uint16_t, float>::type T;
+  typedef typename std::conditional<BF16, bf16x8, float>::type AOp;
+  const T* __restrict__ xrm = static_cast<const T*>(xrm_);
+  const T* __restrict__ xt = static_cast<const T*>(xt_);
+
+  static_assert(!(BF16 && COUNT), "window counts are taken in FP32");
+  if (done_slot >= 0 && meta[done_slot]) return;
+  const int n_act = nact_slot >= 0 ? meta[nact_slot] : n_host;
+  if (n_act <= 0) return;
+  const ChunkPlan cp = plan_chunks(n_act, 16 * ST, n_blocks);
+  const int items = cp.groups * cp.n_chunks;
+
+  __shared__ f32x4 red[COUNT ? 1 : 3][ST][COUNT ? 1 : NDB][64];
+  __shared__ int redc[COUNT ? 3 : 1][ST][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int grp = blockIdx.x / n_chunks;
-  const int chunk = blockIdx.x - grp * n_chunks;
-  const int a0 = grp * ST * 16;
-
-  bf16x8 yb[ST][KS];
-#pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    const int a = a0 + 16 * s + r;
-#pragma unroll
-    for (int j = 0; j < KS; ++j) {
-      if (a < n_act) {
-        const float4* yr = reinterpret_cast<const float4*>(y + (int64_t)active[a] * DP + g * KJ + 8 * j);
-        float4 u = yr[0], v = yr[1];
-        yb[s][j] = bf16x8{(__bf16)u.x, (__bf16)u.y, (__bf16)u.z, (__bf16)u.w,
-                          (__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
-      } else {
-        yb[s][j] = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
-                          (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-      }
-    }
-  }
-  f32x4 acc[ST][NDB];
-#pragma unroll
-  for (int s = 0; s < ST; ++s)
-#pragma unroll
-    for (int db = 0; db < NDB; ++db) acc[s][db] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-  const int b0 = chunk * chunk_blocks;
-  const int b1 = min(n_blocks, b0 + chunk_blocks);
   const int rowsel0 = 8 * (r >> 2) + (r & 3);
-  for (int b = b0; b < b1; ++b) {
-    const uint16_t* xb = x + (int64_t)b * kBlockPix * DP;
-    bf16x8 xa[2][KS];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int j = 0; j < KS; ++j)
-        xa[t][j] = *reinterpret_cast<const bf16x8*>(xb + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
-    bf16x8 xv[NDB];
-#pragma unroll
-    for (int db = 0; db < NDB; ++db)
-      xv[db] = *reinterpret_cast<const bf16x8*>(xt + ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+  const f32x4 cinit = {-thr, -thr, -thr, -thr};
+
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+  const int lo = (int)((int64_t)items * xcd / 8), hi = (int)((int64_t)items * (xcd + 1) / 8);
+  for (int it = lo + (int)(blockIdx.x >> 3); it < hi; it += per) {
+    const int chunk = it / cp.groups, grp = it - chunk * cp.groups;
+    const int a0 = grp * 16 * ST;
+    // Seed operands (B of S^T = X Y^T).
+    AOp yb[ST][KS];
 #pragma unroll
     for (int s = 0; s < ST; ++s) {
-      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+      const int a = a0 + 16 * s + r;
+      const float* yr = a < n_act ? y + (int64_t)active[a] * DP + g * KJ : nullptr;
+      if constexpr (BF16) {
 #pragma unroll
-      for (int j = 0; j < KS; ++j) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][j], yb[s][j], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][j], yb[s][j], s1, 0, 0, 0);
+        for (int j = 0; j < KS; ++j) {
+          float4 u = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+          float4 v = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          yb[s][j] = bf16x8{(__bf16)u.x, (__bf16)u.y, (__bf16)u.z, (__bf16)u.w,
+                            (__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < KJ / 4; ++j) {
+          float4 u = yr ? reinterpret_cast<const float4*>(yr)[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+          yb[s][4 * j] = u.x;
+          yb[s][4 * j + 1] = u.y;
+          yb[s][4 * j + 2] = u.z;
+          yb[s][4 * j + 3] = u.w;
+        }
       }
-      bf16x8 w;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        w[i] = s0[i] >= thr ? one : zero;
-        w[4 + i] = s1[i] >= thr ? one : zero;
-      }
-#pragma unroll
-      for (int db = 0; db < NDB; ++db)
-        acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[db], w, acc[s][db], 0, 0, 0);
     }
-  }
+    f32x4 acc[ST][NDB];
+    int cnt[ST];
 #pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    const int a = a0 + 16 * s + r;
-    if (a < n_act) {
-      float* dst = partial + ((int64_t)chunk * n_act + a) * DP + 4 * g;
+    for (int s = 0; s < ST; ++s) {
+      cnt[s] = 0;
 #pragma unroll
-      for (int db = 0; db < NDB; ++db) {
-        f32x4 v = acc[s][db];
-        *reinterpret_cast<float4*>(dst + 16 * db) = make_float4(v[0], v[1], v[2], v[3]);
+      for (int db = 0; db < NDB; ++db) acc[s][db] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    const int b0 = chunk * cp.chunk_blocks;
+    const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
+    // Register operands of one block: rows for S (two 16-pixel tiles) and the
+    // dimension-major copy for V.  Double-buffered: block b+4 loads while b
+    // computes.
+    AOp xa[2][2][KS];
+    AOp xv[2][NDB][BF16 ? 1 : 8];
+    auto load = [&](int buf, int b) {
+      if constexpr (BF16) {
+        const uint16_t* xb = reinterpret_cast<const uint16_t*>(xrm) + (int64_t)b * kBlockPix * DP;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int j = 0; j < KS; ++j)
+            xa[buf][t][j] = *reinterpret_cast<const bf16x8*>(xb + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
+#pragma unroll
+        for (int db = 0; db < NDB; ++db)
+          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) +
+                                                            ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+      } else {
+        const float* xb = reinterpret_cast<const float*>(xrm) + (int64_t)b * kBlockPix * DP;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const float4* xr = reinterpret_cast<const float4*>(xb + (rowsel0 + 4 * t) * DP + g * KJ);
+#pragma unroll
+          for (int j = 0; j < KJ / 4; ++j) {
+            float4 u = xr[j];
+            xa[buf][t][4 * j] = u.x;
+            xa[buf][t][4 * j + 1] = u.y;
+            xa[buf][t][4 * j + 2] = u.z;
+            xa[buf][t][4 * j + 3] = u.w;
+          }
+        }
+#pragma unroll
+        for (int db = 0; db < (COUNT ? 0 : NDB); ++db) {
+          const float4* tp = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(xt) +
+                                                             ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+          float4 u = tp[0], v = tp[1];
+          xv[buf][db][0] = u.x; xv[buf][db][1] = u.y; xv[buf][db][2] = u.z; xv[buf][db][3] = u.w;
+          xv[buf][db][4] = v.x; xv[buf][db][5] = v.y; xv[buf][db][6] = v.z; xv[buf][db][7] = v.w;
+        }
       }
+    };
+    auto compute = [&](int buf, int b) {
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        f32x4 s0 = cinit, s1 = cinit;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          if constexpr (BF16) {
+            s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][0][j], yb[s][j], s0, 0, 0, 0);
+            s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][1][j], yb[s][j], s1, 0, 0, 0);
+          } else {
+            s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[buf][0][j], yb[s][j], s0, 0, 0, 0);
+            s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[buf][1][j], yb[s][j], s1, 0, 0, 0);
+          }
+        }
+        if constexpr (BF16) {
+          // Pixels 8g..8g+3 come from tile 0, 8g+4..8g+7 from tile 1.
+          uint32_t m0 = __builtin_amdgcn_perm(fbits(s0[1]), fbits(s0[0]),
+                                              0x0B0B0909u);
+          uint32_t m1 = __builtin_amdgcn_perm(fbits(s0[3]), fbits(s0[2]),
+                                              0x0B0B0909u);
+          uint32_t m2 = __builtin_amdgcn_perm(fbits(s1[1]), fbits(s1[0]),
+                                              0x0B0B0909u);
+          uint32_t m3 = __builtin_amdgcn_perm(fbits(s1[3]), fbits(s1[2]),
+                                              0x0B0B0909u);
+          typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+          const uint32_t one2 = 0x3F803F80u;  // two BF16 ones
+          u32x4 wp = {~m0 & one2, ~m1 & one2, ~m2 & one2, ~m3 & one2};
+          const bf16x8 w = __builtin_bit_cast(bf16x8, wp);
+#pragma unroll
+          for (int db = 0; db < NDB; ++db)
+            acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[buf][db][0], w, acc[s][db], 0, 0, 0);
+        } else if constexpr (COUNT) {
+          const int pbase = b * kBlockPix + 8 * g;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            cnt[s] += ((fbits(s0[i]) >> 31) == 0u && pbase + i < n_pix) ? 1 : 0;
+            cnt[s] += ((fbits(s1[i]) >> 31) == 0u && pbase + 4 + i < n_pix) ? 1 : 0;
+          }
+        } else {
+          float w[8];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            w[i] = (fbits(s0[i]) >> 31) ? 0.f : 1.f;
+            w[4 + i] = (fbits(s1[i]) >> 31) ? 0.f : 1.f;
+          }
+#pragma unroll
+          for (int db = 0; db < NDB; ++db)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[buf][db][e], w[e], acc[s][db], 0, 0, 0);
+        }
+      }
+    };
+    int b = b0 + wave;
+    if (b < b1) load(0, b);
+    for (; b < b1; b += 8) {
+      if (b + 4 < b1) load(1, b + 4);
+      compute(0, b);
+      if (b + 4 >= b1) break;
+      if (b + 8 < b1) load(0, b + 8);
+      compute(1, b + 4);
+    }
+    if constexpr (COUNT) {
+      // Counts of seed r are spread over the four lane groups, then the waves.
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        int c = cnt[s];
+        c += __shfl_xor(c, 16, 64);
+        c += __shfl_xor(c, 32, 64);
+        if (wave > 0 && g == 0) redc[wave - 1][s][r] = c;
+        cnt[s] = c;
+      }
+      __syncthreads();
+      if (wave == 0 && g == 0) {
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          const int a = a0 + 16 * s + r;
+          if (a < n_act)
+            pcount[(int64_t)chunk * n_act + a] = cnt[s] + redc[0][s][r] + redc[1][s][r] + redc[2][s][r];
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    // Fixed-order sum of the four waves' window sums, then one partial per item.
+    if constexpr (!COUNT) {
+    if (wave > 0) {
+#pragma unroll
+      for (int s = 0; s < ST; ++s)
+#pragma unroll
+        for (int db = 0; db < NDB; ++db) red[wave - 1][s][db][lane] = acc[s][db];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        const int a = a0 + 16 * s + r;
+#pragma unroll
+        for (int db = 0; db < NDB; ++db) {
+          f32x4 v = acc[s][db];
+          v += red[0][s][db][lane];
+          v += red[1][s][db][lane];
+          v += red[2][s][db][lane];
+          if (a < n_act)
+            *reinterpret_cast<float4*>(partial + ((int64_t)chunk * n_act + a) * DP + 16 * db + 4 * g) =
+                make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
+    }
+    __syncthreads();
     }
   }
 }
 
 // Sum the chunk partials of each active seed in a fixed order, renormalise,
 // test convergence (Sec. 3.2.1: cosine distance between consecutive centres
-// below tol), and build the next active list.  One wave per seed.
-// mode 0: iterate (freeze converged seeds).  mode 1: refine step (no freezing;
-// counts moves >= tol).  mode 2: last refine step (same, and counts).
+// below tol), and build the next active list.  One work group per seed: the
+// 256 threads split the chunks into 256/DP phases, the phases are added in
+// order in LDS.
+//   mode 0: iterate, freezing converged seeds; the last work group to finish
+//           applies the early stop of Sec. 3.2.3 (more than gamma of the
+//           round's seeds converged, or none left active) by setting the
+//           done flag, and publishes the next active count.
+//   mode 1: refine step (no freezing).  mode 2: refine step that also counts
+//           the seeds whose move stayed >= tol.
 template <int DP>
-__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, int n_chunks, int n_act,
-                                                const int* __restrict__ active, float* __restrict__ y,
-                                                uint8_t* __restrict__ state, int* __restrict__ iters, float tol,
-                                                int mode, int* __restrict__ meta, int* __restrict__ next_active) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a = blockIdx.x * 4 + wave;
-  if (a >= n_act) return;
-  const int slot = active[a];
-  constexpr int DPL = DP > 64 ? DP / 64 : 1;  // dims per lane
-  float v[DPL];
-  int width;
-  if constexpr (DP == 32) {
-    const int d = lane & 31, ph = lane >> 5;
-    float acc = 0.f;
-    for (int c = ph; c < n_chunks; c += 2) acc += partial[((int64_t)c * n_act + a) * DP + d];
-    // Fixed pairing: even-chunk sum + odd-chunk sum, identical in both halves.
-    float other = __shfl_xor(acc, 32, 64);
-    v[0] = ph == 0 ? acc + other : other + acc;
-    width = 32;
-  } else {
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const int* __restrict__ active,
+                                                float* __restrict__ y, uint8_t* __restrict__ state,
+                                                int* __restrict__ iters, int* __restrict__ next_active,
+                                                int* __restrict__ meta, unsigned long long* __restrict__ meta64,
+                                                int nact_slot, int done_slot, int n_host, int n_blocks,
+                                                int group_seeds, int n_fg, float tol, double gamma, int mode) {
+  if (done_slot >= 0 && meta[done_slot]) return;
+  constexpr int P = 256 / DP;  // chunk phases
+  __shared__ float part[256];
+  __shared__ float wsum[4];
+  const int n_act = nact_slot >= 0 ? meta[nact_slot] : n_host;
+  const ChunkPlan cp = plan_chunks(n_act, group_seeds, n_blocks);
+  const int nc = cp.n_chunks;
+  const int a = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (a < n_act) {
+    const int slot = active[a];
+    {
+      const int d = tid % DP, ph = tid / DP;
+      const float* src = partial + (int64_t)a * DP + d;
+      const int64_t cstride = (int64_t)n_act * DP;
+      float accv = 0.f;
+      int c = ph;
+      for (; c + 7 * P < nc; c += 8 * P) {
+        float t[8];
 #pragma unroll
-    for (int q = 0; q < DPL; ++q) {
-      const int d = lane + 64 * q;
-      float acc = 0.f;
-      for (int c = 0; c < n_chunks; ++c) acc += partial[((int64_t)c * n_act + a) * DP + d];
-      v[q] = acc;
+        for (int u = 0; u < 8; ++u) t[u] = src[(int64_t)(c + u * P) * cstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) accv += t[u];
+      }
+      for (; c < nc; c += P) accv += src[(int64_t)c * cstride];
+      part[tid] = accv;
     }
-    width = 64;
-  }
-  float ss = 0.f;
+    __syncthreads();
+    // Threads 0..DP-1 own one dimension each.
+    float v = 0.f, yo = 0.f;
+    if (tid < DP) {
 #pragma unroll
-  for (int q = 0; q < DPL; ++q) ss = fmaf(v[q], v[q], ss);
-  ss = wave_sum_f(ss, width);
-  const float nv = sqrtf(ss);
-  const bool dead = !(nv > 0.f) || !__builtin_isfinite(nv);
-  const float inv = dead ? 0.f : 1.0f / nv;
-  float dd = 0.f;
-  float yn[DPL];
-#pragma unroll
-  for (int q = 0; q < DPL; ++q) {
-    const int d = (DP == 32) ? (lane & 31) : lane + 64 * q;
-    const float yo = y[(int64_t)slot * DP + d];
-    yn[q] = v[q] * inv;
-    const float df = yo - yn[q];
-    dd = fmaf(df, df, dd);
-  }
-  // 1 - y.y' = |y - y'|^2 / 2 for unit vectors, without cancellation.
-  const float delta = 0.5f * wave_sum_f(dd, width);
-  if (!dead) {
-#pragma unroll
-    for (int q = 0; q < DPL; ++q) {
-      const int d = (DP == 32) ? (lane & 31) : lane + 64 * q;
-      if (DP != 32 || lane < 32) y[(int64_t)slot * DP + d] = yn[q];
+      for (int q = 0; q < P; ++q) v += part[q * DP + tid];
+      yo = y[(int64_t)slot * DP + tid];
     }
-  }
-  if (lane == 0) {
-    if (mode == 0) {
-      iters[slot] += 1;
-      if (dead) {
-        state[slot] = 2;
-      } else if (delta < tol) {
-        state[slot] = 1;
-        atomicAdd(meta + META_NCONV, 1);
+    // |V|^2 over the first DP threads (one or two waves), fixed order.
+    float ss = wave_sum_f(v * v, 64);
+    if (lane == 0) wsum[wave] = ss;
+    __syncthreads();
+    ss = DP > 64 ? wsum[0] + wsum[1] : wsum[0];
+    const float nv = sqrtf(ss);
+    const bool dead = !(nv > 0.f) || !__builtin_isfinite(nv);
+    const float inv = dead ? 0.f : 1.0f / nv;
+    const float yn = v * inv;
+    const float df = tid < DP ? yo - yn : 0.f;
+    __syncthreads();
+    float dd = wave_sum_f(df * df, 64);
+    if (lane == 0) wsum[wave] = dd;
+    __syncthreads();
+    // 1 - y.y' = |y - y'|^2 / 2 for unit vectors, without cancellation.
+    const float delta = 0.5f * (DP > 64 ? wsum[0] + wsum[1] : wsum[0]);
+    if (!dead && tid < DP) y[(int64_t)slot * DP + tid] = yn;
+    if (tid == 0) {
+      if (mode == 0) {
+        iters[slot] += 1;
+        if (dead) {
+          state[slot] = 2;
+        } else if (delta < tol) {
+          state[slot] = 1;
+          atomicAdd(meta + META_NCONV, 1);
+        } else {
+          next_active[atomicAdd(meta + META_NNEXT, 1)] = slot;
+        }
       } else {
-        next_active[atomicAdd(meta + META_NNEXT, 1)] = slot;
-      }
-    } else {
-      if (dead) state[slot] = 2;
-      if (mode == 2 && (dead || !(delta < tol))) atomicAdd(meta + META_REFINE_BAD, 1);
-    }
-  }
-}
-
-// Window counts |{i : y . x_i >= thr}| for the centres in `list`, FP32 MFMA.
-template <int DP, int ST>
-__global__ __launch_bounds__(64) void k_count(const float* __restrict__ x, const float* __restrict__ y,
-                                              const int* __restrict__ list, int m, int n, int n_blocks,
-                                              int chunk_blocks, int n_chunks, float thr, int* __restrict__ pcount) {
-  constexpr int KJ = DP / 4;
-  const int lane = threadIdx.x;
-  const int g = lane >> 4, r = lane & 15;
-  const int grp = blockIdx.x / n_chunks;
-  const int chunk = blockIdx.x - grp * n_chunks;
-  const int a0 = grp * ST * 16;
-  float yb[ST][KJ];
-#pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    const int a = a0 + 16 * s + r;
-#pragma unroll
-    for (int j = 0; j < KJ; ++j) yb[s][j] = a < m ? y[(int64_t)list[a] * DP + g * KJ + j] : 0.f;
-  }
-  int cnt[ST];
-#pragma unroll
-  for (int s = 0; s < ST; ++s) cnt[s] = 0;
-  const int b0 = chunk * chunk_blocks;
-  const int b1 = min(n_blocks, b0 + chunk_blocks);
-  const int rowsel0 = 8 * (r >> 2) + (r & 3);
-  for (int b = b0; b < b1; ++b) {
-    const float* xb = x + (int64_t)b * kBlockPix * DP;
-    float xa[2][KJ];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int j = 0; j < KJ; ++j) xa[t][j] = xb[(rowsel0 + 4 * t) * DP + g * KJ + j];
-    const int pbase = b * kBlockPix + 8 * g;
-#pragma unroll
-    for (int s = 0; s < ST; ++s) {
-      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int j = 0; j < KJ; ++j) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][j], yb[s][j], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[1][j], yb[s][j], s1, 0, 0, 0);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        cnt[s] += (s0[i] >= thr && pbase + i < n) ? 1 : 0;
-        cnt[s] += (s1[i] >= thr && pbase + 4 + i < n) ? 1 : 0;
+        if (dead) state[slot] = 2;
+        if (mode == 2 && (dead || !(delta < tol))) atomicAdd(meta + META_REFINE_BAD, 1);
       }
     }
   }
-#pragma unroll
-  for (int s = 0; s < ST; ++s) {
-    int c = cnt[s];
-    c += __shfl_xor(c, 16, 64);
-    c += __shfl_xor(c, 32, 64);
-    const int a = a0 + 16 * s + r;
-    if (g == 0 && a < m) pcount[(int64_t)chunk * m + a] = c;
+  if (mode != 0) return;
+  __shared__ int s_last;
+  // The counter updates and list stores must be complete before the block
+  // reports itself done: the last block reads the counters next.
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(meta + META_BLKDONE, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();
+    const int n_next = atomicAdd(meta + META_NNEXT, 0);
+    const int n_conv = atomicAdd(meta + META_NCONV, 0);
+    const int m = meta[META_NSEL];
+    meta[META_STEPS] += 1;
+    meta64[0] += (unsigned long long)n_act * (unsigned long long)n_fg;
+    meta[nact_slot] = n_next;
+    meta[META_NNEXT] = 0;
+    meta[META_BLKDONE] = 0;
+    if ((double)n_conv > gamma * (double)m || n_next == 0) meta[done_slot] = 1;
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_counts(const int* __restrict__ pcount, int m, int n_chunks,
-                                                    int* __restrict__ counts) {
-  const int a = blockIdx.x * 256 + threadIdx.x;
+// Sum the per-chunk window counts of each centre (one wave per centre).
+__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_chunks,
+                                                       int* __restrict__ counts) {
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (a >= m) return;
   int c = 0;
-  for (int k = 0; k < n_chunks; ++k) c += pcount[(int64_t)k * m + a];
-  counts[a] = c;
+  for (int k = lane; k < n_chunks; k += 64) c += pcount[(int64_t)k * m + a];
+  c = wave_sum_i(c);
+  if (lane == 0) counts[a] = c;
 }
 
-// Conflict bits: bit k of row j is set when candidate j and candidate k are
-// inside each other's window; blocked[j] when an existing mode is.
+// Start of a round: the selected seeds become the active list.
+__global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ active, uint8_t* __restrict__ state,
+                                                     int* __restrict__ iters, int* __restrict__ meta,
+                                                     unsigned long long* __restrict__ meta64) {
+  const int m = meta[META_NSEL];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < m && k < cap) {
+    active[k] = k;
+    state[k] = 0;
+    iters[k] = 0;
+  }
+  if (k == 0) {
+    meta[META_NACT] = m;
+    meta[META_NCONV] = 0;
+    meta[META_NNEXT] = 0;
+    meta[META_BLKDONE] = 0;
+    meta[META_DONE] = m > 0 ? 0 : 1;
+    meta[META_STEPS] = 0;
+    meta64[0] = 0;
+  }
+}
+
+// Similarity bits: bit c of row j is set when row vector j and column
+// vector c are inside each other's window (dot >= thr).  Rows are
+// y[rows[j]]; columns are y[cols[c]] (cols != null) or the rows of `colmat`.
+// A wave owns 64 columns and 16 rows; each lane keeps its column vector in
+// registers and reads the (wave-uniform) row vectors.  Row stride: `words`
+// 32-bit words, a multiple of 2.
 template <int DP>
-__global__ __launch_bounds__(256) void k_conflicts(const float* __restrict__ y, const int* __restrict__ list, int m,
-                                                   const float* __restrict__ modes, int k, float thr,
-                                                   uint32_t* __restrict__ bits, int words,
-                                                   uint8_t* __restrict__ blocked) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t nbits = (int64_t)m * words;
-  if (t < nbits) {
-    const int j = (int)(t / words), w = (int)(t - (int64_t)j * words);
-    const float* yj = y + (int64_t)list[j] * DP;
-    uint32_t word = 0;
-    for (int b = 0; b < 32; ++b) {
-      const int c = 32 * w + b;
-      if (c >= m) break;
-      const float* yc = y + (int64_t)list[c] * DP;
-      float s = 0.f;
-      for (int d = 0; d < DP; ++d) s = fmaf(yj[d], yc[d], s);
-      if (s >= thr) word |= 1u << b;
+__global__ __launch_bounds__(256) void k_simbits(const float* __restrict__ y, const int* __restrict__ rows, int m,
+                                                 const int* __restrict__ cols, const float* __restrict__ colmat,
+                                                 int ncols, float thr, uint32_t* __restrict__ bits, int words) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col_tiles = words / 2;
+  const int ct = blockIdx.x % col_tiles, rt = blockIdx.x / col_tiles;
+  const int c = ct * 64 + lane;
+  float xc[DP];
+  if (c < ncols) {
+    const float* src = cols ? y + (int64_t)cols[c] * DP : colmat + (int64_t)c * DP;
+#pragma unroll
+    for (int d = 0; d < DP; d += 4) {
+      float4 u = *reinterpret_cast<const float4*>(src + d);
+      xc[d] = u.x; xc[d + 1] = u.y; xc[d + 2] = u.z; xc[d + 3] = u.w;
     }
-    bits[t] = word;
-  } else if (t < nbits + m) {
-    const int j = (int)(t - nbits);
-    const float* yj = y + (int64_t)list[j] * DP;
-    uint8_t bl = 0;
-    for (int q = 0; q < k && !bl; ++q) {
-      float s = 0.f;
-      for (int d = 0; d < DP; ++d) s = fmaf(yj[d], modes[(int64_t)q * DP + d], s);
-      if (s >= thr) bl = 1;
+  } else {
+#pragma unroll
+    for (int d = 0; d < DP; ++d) xc[d] = 0.f;
+  }
+  const int j0 = rt * 64 + wave * 16;
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = j0 + jj;
+    if (j >= m) break;
+    const float* rv = y + (int64_t)rows[j] * DP;
+    float dot = 0.f;
+#pragma unroll
+    for (int d = 0; d < DP; ++d) dot = fmaf(rv[d], xc[d], dot);
+    const unsigned long long bal = __ballot(c < ncols && dot >= thr);
+    if (lane == 0) {
+      bits[(int64_t)j * words + 2 * ct] = (uint32_t)bal;
+      bits[(int64_t)j * words + 2 * ct + 1] = (uint32_t)(bal >> 32);
     }
-    blocked[j] = bl;
   }
 }
 
@@ -737,6 +830,11 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int
     far = wave_sum_i(far);
     if ((threadIdx.x & 63) == 0 && far) atomicAdd(meta + META_LEFT, far);
   }
+}
+
+__global__ __launch_bounds__(256) void k_iota(int* __restrict__ p, int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = i;
 }
 
 __global__ __launch_bounds__(256) void k_fill_i32(int* __restrict__ p, int64_t count, int value) {
@@ -827,11 +925,6 @@ hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, co
   return hipGetLastError();
 }
 
-hipError_t launch_round_init(hipStream_t s, int m, int* active, uint8_t* state, int* iters) {
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_round_init, dim3(cdiv(m, 256)), dim3(256), 0, s, m, active, state, iters);
-  return hipGetLastError();
-}
 
 StepGeom make_geom(int n) {
   StepGeom g;
@@ -843,117 +936,121 @@ StepGeom make_geom(int n) {
   return g;
 }
 
-// Seed tiles per wave: enough work items to cover the chip, as few as that
-// allows (each wave re-reads its pixel chunk once per 16-seed tile group).
-static int pick_st(int n_act, int n_chunks, int dp) {
-  const int max_st = dp >= 128 ? 2 : 4;
-  for (int st = max_st; st > 1; st >>= 1) {
-    const int64_t items = (int64_t)cdiv(n_act, 16 * st) * n_chunks;
-    if (items >= 1024) return st;
-  }
-  return 1;
+// Seed tiles of 16 per wave in the fused step: enough seeds per pixel read to
+// keep the loads well below the matrix-core rate, few enough registers for
+// several waves per SIMD.
+int shift_group_seeds(bool bf16, int dp) {
+  int st;
+  if (bf16) st = dp <= 32 ? 4 : (dp <= 64 ? 2 : 1);
+  else st = dp <= 64 ? 2 : 1;
+  return 16 * st;
 }
 
-#define FMS_SHIFT_CASE(KERNEL, T, DPV, STV)                                                                   \
-  hipLaunchKernelGGL((KERNEL<DPV, STV>), dim3(items), dim3(64), 0, s, static_cast<const T*>(xrm),           \
-                     static_cast<const T*>(xt), y, active, n_act, g.n_blocks, g.chunk_blocks, g.n_chunks, thr, \
-                     partial)
+size_t shift_partial_rows(bool bf16, int dp, int cap, int n_blocks) {
+  const int64_t g = shift_group_seeds(bf16, dp);
+  const int64_t a = (int64_t)std::min<int64_t>((int64_t)kMaxChunks * cap, (int64_t)kTargetItems * g + cap);
+  (void)n_blocks;
+  return (size_t)std::max<int64_t>(a, 1);
+}
 
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const StepGeom& g, const void* xrm, const void* xt,
-                        const float* y, const int* active, int n_act, float thr, float* partial) {
-  if (n_act <= 0 || g.n_chunks <= 0) return hipSuccess;
-  const int st = pick_st(n_act, g.n_chunks, dp);
-  const unsigned items = cdiv(n_act, 16 * st) * g.n_chunks;
-  const int key = (bf16 ? 1000 : 0) + dp * 10 + st;
+static unsigned shift_grid(int cap, int group_seeds, int n_blocks) {
+  const ChunkPlan cp = plan_chunks(cap, group_seeds, n_blocks);
+  int64_t items = (int64_t)cp.groups * cp.n_chunks;
+  if (items > kTargetItems) items = kTargetItems;
+  unsigned grid = (unsigned)((items + 7) / 8 * 8);
+  return grid < 8 ? 8 : grid;
+}
+
+#define FMS_SHIFT_CASE(BFV, CNT, DPV, STV)                                                                       \
+  hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, xrm, xt, y, active, meta,          \
+                     nact_slot, done_slot, n_host, n_blocks, n_pix, thr, partial, pcount)
+
+static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, int n_blocks, int n_pix,
+                                 const void* xrm, const void* xt, const float* y, const int* active,
+                                 const int* meta, int nact_slot, int done_slot, int n_host, int cap, float thr,
+                                 float* partial, int* pcount) {
+  if (cap <= 0 || n_blocks <= 0) return hipSuccess;
+  const int gs = shift_group_seeds(bf16, dp);
+  const unsigned grid = shift_grid(cap, gs, n_blocks);
+  const int key = (bf16 ? 1000 : 0) + (count ? 5000 : 0) + dp * 10 + gs / 16;
   switch (key) {
-    case 321: FMS_SHIFT_CASE(k_shift_f32, float, 32, 1); break;
-    case 322: FMS_SHIFT_CASE(k_shift_f32, float, 32, 2); break;
-    case 324: FMS_SHIFT_CASE(k_shift_f32, float, 32, 4); break;
-    case 641: FMS_SHIFT_CASE(k_shift_f32, float, 64, 1); break;
-    case 642: FMS_SHIFT_CASE(k_shift_f32, float, 64, 2); break;
-    case 644: FMS_SHIFT_CASE(k_shift_f32, float, 64, 4); break;
-    case 1281: FMS_SHIFT_CASE(k_shift_f32, float, 128, 1); break;
-    case 1282: FMS_SHIFT_CASE(k_shift_f32, float, 128, 2); break;
-    case 1321: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 32, 1); break;
-    case 1322: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 32, 2); break;
-    case 1324: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 32, 4); break;
-    case 1641: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 64, 1); break;
-    case 1642: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 64, 2); break;
-    case 1644: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 64, 4); break;
-    case 2281: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 128, 1); break;
-    case 2282: FMS_SHIFT_CASE(k_shift_bf16, uint16_t, 128, 2); break;
+    case 322: FMS_SHIFT_CASE(false, false, 32, 2); break;
+    case 642: FMS_SHIFT_CASE(false, false, 64, 2); break;
+    case 1281: FMS_SHIFT_CASE(false, false, 128, 1); break;
+    case 1324: FMS_SHIFT_CASE(true, false, 32, 4); break;
+    case 1642: FMS_SHIFT_CASE(true, false, 64, 2); break;
+    case 2281: FMS_SHIFT_CASE(true, false, 128, 1); break;
+    case 5322: FMS_SHIFT_CASE(false, true, 32, 2); break;
+    case 5642: FMS_SHIFT_CASE(false, true, 64, 2); break;
+    case 6281: FMS_SHIFT_CASE(false, true, 128, 1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 #undef FMS_SHIFT_CASE
 
-hipError_t launch_reduce(hipStream_t s, int dp, const StepGeom& g, const float* partial, int n_act, const int* active,
-                         float* y, uint8_t* state, int* iters, float tol, int mode, int* meta, int* next_active) {
-  if (n_act <= 0) return hipSuccess;
-  const dim3 grid(cdiv(n_act, 4)), block(256);
+hipError_t launch_shift(hipStream_t s, bool bf16, int dp, int n_blocks, const void* xrm, const void* xt,
+                        const float* y, const int* active, const int* meta, int nact_slot, int done_slot, int cap,
+                        float thr, float* partial) {
+  return shift_dispatch(s, bf16, false, dp, n_blocks, 0, xrm, xt, y, active, meta, nact_slot, done_slot, cap, cap,
+                        thr, partial, nullptr);
+}
+
+hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, const float* partial,
+                         const int* active, float* y, uint8_t* state, int* iters, int* next_active, int* meta,
+                         unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
+                         double gamma, int mode) {
+  if (cap <= 0) return hipSuccess;
+  const dim3 grid(cap), block(256);
+#define FMS_REDUCE_CASE(DPV)                                                                                     \
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, meta, meta64, \
+                     nact_slot, done_slot, cap, n_blocks, group_seeds, n_fg, tol, gamma, mode)
   switch (dp) {
-    case 32:
-      hipLaunchKernelGGL(k_reduce<32>, grid, block, 0, s, partial, g.n_chunks, n_act, active, y, state, iters, tol,
-                         mode, meta, next_active);
-      break;
-    case 64:
-      hipLaunchKernelGGL(k_reduce<64>, grid, block, 0, s, partial, g.n_chunks, n_act, active, y, state, iters, tol,
-                         mode, meta, next_active);
-      break;
-    case 128:
-      hipLaunchKernelGGL(k_reduce<128>, grid, block, 0, s, partial, g.n_chunks, n_act, active, y, state, iters, tol,
-                         mode, meta, next_active);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 32: FMS_REDUCE_CASE(32); break;
+    case 64: FMS_REDUCE_CASE(64); break;
+    case 128: FMS_REDUCE_CASE(128); break;
+    default: return hipErrorInvalidValue;
   }
+#undef FMS_REDUCE_CASE
   return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t s, int dp, const StepGeom& g, const float* x32, const float* y, const int* list,
-                        int m, float thr, int* pcount, int* counts) {
-  if (m <= 0 || g.n_chunks <= 0) return hipSuccess;
-  const unsigned items = cdiv(m, 32) * g.n_chunks;
-  switch (dp) {
-    case 32:
-      hipLaunchKernelGGL((k_count<32, 2>), dim3(items), dim3(64), 0, s, x32, y, list, m, g.n, g.n_blocks,
-                         g.chunk_blocks, g.n_chunks, thr, pcount);
-      break;
-    case 64:
-      hipLaunchKernelGGL((k_count<64, 2>), dim3(items), dim3(64), 0, s, x32, y, list, m, g.n, g.n_blocks,
-                         g.chunk_blocks, g.n_chunks, thr, pcount);
-      break;
-    case 128:
-      hipLaunchKernelGGL((k_count<128, 2>), dim3(items), dim3(64), 0, s, x32, y, list, m, g.n, g.n_blocks,
-                         g.chunk_blocks, g.n_chunks, thr, pcount);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  hipError_t e = hipGetLastError();
+size_t count_partial_rows(int dp, int cap) { return shift_partial_rows(false, dp, cap, 0); }
+
+hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
+                        const int* list, int m, float thr, int* pcount, int* counts) {
+  if (m <= 0 || n_blocks <= 0) return hipSuccess;
+  hipError_t e = shift_dispatch(s, false, true, dp, n_blocks, n_pix, x32, nullptr, y, list, nullptr, -1, -1, m, m, thr,
+                                nullptr, pcount);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_counts, dim3(cdiv(m, 256)), dim3(256), 0, s, pcount, m, g.n_chunks, counts);
+  const ChunkPlan cp = plan_chunks(m, shift_group_seeds(false, dp), n_blocks);
+  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, cp.n_chunks, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_conflicts(hipStream_t s, int dp, const float* y, const int* list, int m, const float* modes, int k,
-                            float thr, uint32_t* bits, int words, uint8_t* blocked) {
+int simbits_words(int ncols) { return std::max(2, ((ncols + 63) / 64) * 2); }
+
+hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
+                          const float* colmat, int ncols, float thr, uint32_t* bits) {
   if (m <= 0) return hipSuccess;
-  const dim3 grid(cdiv((int64_t)m * words + m, 256)), block(256);
+  const int words = simbits_words(ncols);
+  const unsigned grid = (unsigned)((words / 2) * cdiv(m, 64));
+#define FMS_SIM_CASE(DPV)                                                                                        \
+  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid), dim3(256), 0, s, y, rows, m, cols, colmat, ncols, thr, bits, words)
   switch (dp) {
-    case 32:
-      hipLaunchKernelGGL(k_conflicts<32>, grid, block, 0, s, y, list, m, modes, k, thr, bits, words, blocked);
-      break;
-    case 64:
-      hipLaunchKernelGGL(k_conflicts<64>, grid, block, 0, s, y, list, m, modes, k, thr, bits, words, blocked);
-      break;
-    case 128:
-      hipLaunchKernelGGL(k_conflicts<128>, grid, block, 0, s, y, list, m, modes, k, thr, bits, words, blocked);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 32: FMS_SIM_CASE(32); break;
+    case 64: FMS_SIM_CASE(64); break;
+    case 128: FMS_SIM_CASE(128); break;
+    default: return hipErrorInvalidValue;
   }
+#undef FMS_SIM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
+                              unsigned long long* meta64) {
+  hipLaunchKernelGGL(k_round_begin, dim3(cdiv(std::max(cap, 1), 256)), dim3(256), 0, s, cap, active, state, iters,
+                     meta, meta64);
   return hipGetLastError();
 }
 
@@ -986,6 +1083,12 @@ hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const f
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(hipStream_t s, int* p, int count) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(cdiv(count, 256)), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 
