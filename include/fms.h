@@ -51,8 +51,10 @@ typedef enum {
 typedef enum {
   FMS_PREC_FP32 = 0,        /* every step's contractions on FP32 MFMA */
   FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) until the early stop; the
-                               pruned modes (fms_cluster) or the converged seeds
-                               (fms_shift_seeds) then take refine_iters FP32 steps */
+                               pruned modes (fms_cluster: refine_iters FP32 steps, then
+                               FP32 iteration under the same early stop) or the
+                               converged seeds (fms_shift_seeds: refine_iters steps)
+                               are refined in FP32 */
 } fms_precision;
 
 /* Clustering parameters.  fms_default_params fills the paper's values. */
@@ -92,8 +94,9 @@ typedef struct {
   int32_t n_discarded;        /* seeds dropped unconverged by the early stop */
   int32_t n_uncovered;        /* foreground pixels farther than h from every mode */
   int32_t n_state_out;        /* N to carry into the next frame (Sec. 3.2.4) */
-  int32_t refine_unconverged; /* BF16 form: modes (fms_cluster) or seeds (fms_shift_seeds)
-                                 whose last refine step moved >= tol */
+  int32_t refine_unconverged; /* BF16 form: fms_cluster: modes dropped because they were still
+                                 moving when the refinement's early stop ended it;
+                                 fms_shift_seeds: seeds whose last refine step moved >= tol */
   int32_t refine_merged;      /* BF16 form: modes dropped after refinement because they
                                  fell inside the window of an earlier mode */
   int64_t refine_updates;     /* (seeds) * n summed over FP32 refine steps */

@@ -134,10 +134,10 @@ struct DeviceGuard {
 struct fms_handle_s {
   int device = 0;
   // Frame data.
-  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, uncovered, used;
+  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig;
   // Round data.
   DevBuf y, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, pcount, partial;
-  DevBuf bits, blocked, acc;
+  DevBuf bits, blocked, acc, sorted, scount;
   // Modes found so far.
   DevBuf modes, mode_counts;
   DevBuf meta, meta64;
@@ -269,6 +269,8 @@ fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
   HIP_TRY(h->ident.ensure(mm * sizeof(int)));
   HIP_TRY(h->cand.ensure(mm * sizeof(int)));
   HIP_TRY(h->counts.ensure(mm * sizeof(int)));
+  HIP_TRY(h->sorted.ensure(mm * sizeof(int)));
+  HIP_TRY(h->scount.ensure(mm * sizeof(int)));
   HIP_TRY(h->pcount.ensure(fms::count_partial_rows(fr.dp, int(mm)) * sizeof(int)));
   const size_t rows = std::max(fms::shift_partial_rows(bf16, fr.dp, int(mm), fr.geom.n_blocks),
                                fms::shift_partial_rows(false, fr.dp, int(mm), fr.geom.n_blocks));
@@ -344,8 +346,9 @@ void add_timing(fms_stats& sx, const RoundOut& ro) {
 // done flag live on the device; the host enqueues iterations in batches and
 // reads the flag back between batches.  The converged slots end up in
 // out.conv (ascending) and in h->cand.
-fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr,
-                          float tol, RoundOut& out) {
+fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, float* ybuf, int cap,
+                             const fms_params* p, float thr, float tol, RoundOut& out, bool host_list) {
+  const int m = cap;  // upper bound; the round's seed count is meta[META_NSEL]
   int* meta = h->meta.as<int>();
   unsigned long long* meta64 = h->meta64.as<unsigned long long>();
   const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
@@ -363,11 +366,11 @@ fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, 
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
     for (int i = 0; i < nb; ++i, ++t) {
       if (timing) HIP_TRY(hipEventRecord(h->events[2 * i], st));
-      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom.n_blocks, xrm, xt, h->y.as<float>(), lists[t & 1], meta,
+      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom.n_blocks, xrm, xt, ybuf, lists[t & 1], meta,
                                 fms::META_NACT, fms::META_DONE, m, thr, h->partial.as<float>()));
       if (timing) HIP_TRY(hipEventRecord(h->events[2 * i + 1], st));
-      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), lists[t & 1],
-                                 h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1],
+      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), lists[t & 1], ybuf,
+                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1],
                                  meta, meta64, fms::META_NACT, fms::META_DONE, m, fr.n, tol, p->gamma, 0));
     }
     HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -384,9 +387,12 @@ fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, 
     batch = std::min(2 * batch, 8);
   }
   out.steps = h->hmeta[fms::META_STEPS];
+  out.conv.clear();
+  if (!host_list) return FMS_OK;  // the caller collects on the device and reads the counters later
   // Converged slots, in slot (= seed-order) order, and the update count.
+  const int msel = h->hmeta[fms::META_NSEL];
   uint8_t* hs = static_cast<uint8_t*>(h->hstage);
-  HIP_TRY(hipMemcpyAsync(hs, h->state.p, size_t(m), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hs, h->state.p, size_t(msel), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hs + ((size_t(m) + 15) / 16) * 16, meta64, sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -394,8 +400,7 @@ fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, 
   std::memcpy(&upd, hs + ((size_t(m) + 15) / 16) * 16, sizeof(upd));
   out.updates = int64_t(upd);
   if (timing) out.step_updates[pk] += out.updates;
-  out.conv.clear();
-  for (int k = 0; k < m; ++k)
+  for (int k = 0; k < msel; ++k)
     if (hs[k] == 1) out.conv.push_back(k);
   const int nc = int(out.conv.size());
   if (nc > 0) {
@@ -406,51 +411,80 @@ fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, 
   return FMS_OK;
 }
 
-// FP32 refinement (BF16 form) of the `a` centres y[list[0..a)]: at least
-// `steps` steps; further steps in batches of four while any centre still
-// moves by >= tol, up to max_steps in total.  Counts the centres whose last
-// step moved >= tol.
+fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr,
+                          float tol, RoundOut& out, bool host_list) {
+  return run_iterations_on(h, st, fr, h->y.as<float>(), m, p, thr, tol, out, host_list);
+}
+
+// FP32 refinement (BF16 form) of the `a` centres y[list[0..a)]: `steps`
+// steps without freezing.  With `early_stop`, the centres then keep iterating
+// with freezing under the early stop of Sec. 3.2.3 (until more than gamma of
+// them have converged, or max_steps in total); out_keep receives, per centre,
+// 1 when it converged and 0 when it was still moving and is dropped, like an
+// unconverged seed.  Without it, the centres whose last step moved >= tol
+// are counted.
 fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, const int* list, int a, int steps,
-                      int max_steps, float thr, float tol, bool timing, RoundOut& out) {
+                      int max_steps, float thr, float tol, double gamma, bool early_stop, bool timing,
+                      RoundOut& out, std::vector<uint8_t>* out_keep) {
   if (a <= 0 || steps <= 0) return FMS_OK;
   int* meta = h->meta.as<int>();
   const int gs = fms::shift_group_seeds(false, fr.dp);
   h->hmeta[fms::META_NACC] = a;
   HIP_TRY(hipMemcpyAsync(meta + fms::META_NACC, h->hmeta + fms::META_NACC, sizeof(int), hipMemcpyHostToDevice, st));
-  int done = 0, batch = steps;
-  while (true) {
-    const int nb = std::min(batch, std::max(max_steps - done, 1));
-    if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
-    HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
-    for (int r = 0; r < nb; ++r) {
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
-      HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, meta,
-                                fms::META_NACC, -1, a, thr, h->partial.as<float>()));
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
-      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), list, y,
-                                 h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, meta,
-                                 h->meta64.as<unsigned long long>(), fms::META_NACC, -1, a, fr.n, tol, 1.0,
-                                 r + 1 == nb ? 2 : 1));
-      out.refine_steps += 1;
-      out.refine_updates += int64_t(a) * int64_t(fr.n);
-    }
-    done += nb;
-    HIP_TRY(hipMemcpyAsync(h->hmeta + fms::META_REFINE_BAD, meta + fms::META_REFINE_BAD, sizeof(int),
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (timing) {
-      for (int r = 0; r < nb; ++r) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
-        out.step_ms[0] += ms;
-        out.step_updates[0] += int64_t(a) * int64_t(fr.n);
-        out.step_launches[0] += 1;
-      }
-    }
-    if (h->hmeta[fms::META_REFINE_BAD] == 0 || done >= max_steps) break;
-    batch = 4;
+  HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
+  if (timing) HIP_TRY(h->ensure_events(2 * size_t(steps)));
+  for (int r = 0; r < steps; ++r) {
+    if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
+    HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, meta, fms::META_NACC,
+                              -1, a, thr, h->partial.as<float>()));
+    if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
+    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), list, y,
+                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, meta,
+                               h->meta64.as<unsigned long long>(), fms::META_NACC, -1, a, fr.n, tol, 1.0,
+                               r + 1 == steps ? 2 : 1));
+    out.refine_steps += 1;
+    out.refine_updates += int64_t(a) * int64_t(fr.n);
   }
-  out.refine_bad += h->hmeta[fms::META_REFINE_BAD];
+  HIP_TRY(hipMemcpyAsync(h->hmeta + fms::META_REFINE_BAD, meta + fms::META_REFINE_BAD, sizeof(int),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (timing) {
+    for (int r = 0; r < steps; ++r) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
+      out.step_ms[0] += ms;
+      out.step_updates[0] += int64_t(a) * int64_t(fr.n);
+      out.step_launches[0] += 1;
+    }
+  }
+  const int moving = h->hmeta[fms::META_REFINE_BAD];
+  if (!early_stop) {
+    out.refine_bad += moving;
+    return FMS_OK;
+  }
+  out_keep->assign(size_t(a), 1);
+  if (moving == 0) return FMS_OK;
+  // Continue with freezing; the list maps iteration slots to the centres.
+  RoundOut ro;
+  h->hmeta[fms::META_NSEL] = a;
+  HIP_TRY(hipMemcpyAsync(meta + fms::META_NSEL, h->hmeta + fms::META_NSEL, sizeof(int), hipMemcpyHostToDevice, st));
+  fms_params q{};
+  q.gamma = gamma;
+  q.max_iter = std::max(max_steps - steps, 1);
+  q.precision = FMS_PREC_FP32;
+  q.timing = timing ? 1 : 0;
+  fms_status stt = run_iterations_on(h, st, fr, y, a, &q, thr, tol, ro, true);
+  if (stt != FMS_OK) return stt;
+  out.refine_steps += ro.steps;
+  out.refine_updates += ro.updates;
+  for (int k = 0; k < 2; ++k) {
+    out.step_ms[k] += ro.step_ms[k];
+    out.step_updates[k] += ro.step_updates[k];
+    out.step_launches[k] += ro.step_launches[k];
+  }
+  std::fill(out_keep->begin(), out_keep->end(), uint8_t(0));
+  for (int k : ro.conv) (*out_keep)[size_t(k)] = 1;
+  out.refine_bad += a - int(ro.conv.size());
   return FMS_OK;
 }
 
@@ -486,9 +520,11 @@ fms_status prune_inputs(fms_handle h, hipStream_t st, const Frame& fr, const flo
   if (stt != FMS_OK) return stt;
   if (with_counts)
     HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), y, list, nc, thr,
-                              h->pcount.as<int>(), x.counts));
-  HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c));
-  if (k > 0) HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, nullptr, h->modes.as<float>(), k, thr, x.bits_m));
+                              h->pcount.as<int>(), x.counts, nullptr, -1));
+  HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c, nullptr, -1, -1));
+  if (k > 0)
+    HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, nullptr, h->modes.as<float>(), k, thr, x.bits_m, nullptr, -1,
+                                -1));
   HIP_TRY(hipMemcpyAsync(h->hstage, h->bits.p, x.bytes, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   xh = xfer_host(h, x, nc);
@@ -549,7 +585,7 @@ fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
   fms_handle h = new (std::nothrow) fms_handle_s();
   if (!h) return FMS_ERR_HIP;
   h->device = device_ordinal;
-  if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), META_COUNT * sizeof(int), hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), (META_COUNT + 4) * sizeof(int), hipHostMallocDefault) !=
           hipSuccess ||
       h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess ||
       h->meta64.ensure(4 * sizeof(unsigned long long)) != hipSuccess) {
@@ -565,9 +601,9 @@ fms_status fms_destroy(fms_handle h) {
   DeviceGuard guard(h->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&h->blk,   &h->fg_idx, &h->x32,     &h->x32t,        &h->x16,     &h->x16t,     &h->order,
-                    &h->uncovered, &h->used, &h->y, &h->active, &h->next_active, &h->state, &h->iters,
+                    &h->rank, &h->elig, &h->y, &h->active, &h->next_active, &h->state, &h->iters,
                     &h->seed_pos, &h->seed_fg, &h->ident, &h->cand, &h->counts, &h->pcount, &h->partial,
-                    &h->bits, &h->blocked, &h->acc, &h->modes, &h->mode_counts, &h->meta, &h->meta64};
+                    &h->bits, &h->blocked, &h->acc, &h->sorted, &h->scount, &h->modes, &h->mode_counts, &h->meta, &h->meta64};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->hmeta) (void)hipHostFree(h->hmeta);
@@ -582,7 +618,7 @@ fms_status fms_seed_order(fms_handle h, void* stream, int32_t n, uint64_t seed, 
   DeviceGuard guard(h->device);
   uint64_t keys[4];
   round_keys(seed, keys);
-  HIP_TRY(fms::launch_seed_order(static_cast<hipStream_t>(stream), n, half_bits(n), keys, order));
+  HIP_TRY(fms::launch_seed_order(static_cast<hipStream_t>(stream), n, half_bits(n), keys, order, nullptr));
   return FMS_OK;
 }
 
@@ -624,13 +660,14 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
 
   // Seed order, coverage and use flags.
   HIP_TRY(h->order.ensure(size_t(n) * sizeof(int)));
-  HIP_TRY(h->uncovered.ensure(size_t(n)));
-  HIP_TRY(h->used.ensure(size_t(n)));
+  HIP_TRY(h->rank.ensure(size_t(n) * sizeof(int)));
+  const size_t elig_bytes = ((size_t(n) + 15) / 16) * 16 + 16;
+  HIP_TRY(h->elig.ensure(elig_bytes));
   uint64_t keys[4];
   round_keys(p->seed, keys);
-  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>()));
-  HIP_TRY(hipMemsetAsync(h->uncovered.p, 1, size_t(n), st));
-  HIP_TRY(hipMemsetAsync(h->used.p, 0, size_t(n), st));
+  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>(), h->rank.as<int>()));
+  HIP_TRY(hipMemsetAsync(h->elig.p, 0, elig_bytes, st));
+  HIP_TRY(hipMemsetAsync(h->elig.p, 1, size_t(n), st));
   HIP_TRY(hipMemsetAsync(meta + META_CURSOR, 0, sizeof(int), st));
 
   int64_t n_used = 0;
@@ -643,66 +680,98 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     const int want = int(want64);
     stt = ensure_round(h, fr, want, p->precision == FMS_PREC_BF16_REFINE);
     if (stt != FMS_OK) return stt;
-    HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->uncovered.as<uint8_t>(), h->used.as<uint8_t>(), n, want,
-                               meta, h->seed_pos.as<int>(), h->seed_fg.as<int>(), h->x32.as<float>(), fr.dp,
-                               h->y.as<float>()));
-    HIP_TRY(hipMemcpyAsync(h->hmeta + META_NSEL, meta + META_NSEL, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
+    // Room for every seed of the round to become a mode.
+    stt = grow_modes(h, st, fr, k_modes, want);
+    if (stt != FMS_OK) return stt;
+    HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->elig.as<uint8_t>(), n, want, meta, h->seed_pos.as<int>(),
+                               h->seed_fg.as<int>(), h->x32.as<float>(), fr.dp, h->y.as<float>()));
+    RoundOut ro;
+    const bool on_device = want <= fms::kRankMax;
+    stt = run_iterations(h, st, fr, want, p, thr, tol, ro, !on_device);
+    if (stt != FMS_OK) return stt;
     const int m = h->hmeta[META_NSEL];
     if (m == 0) break;
     n_used += m;
     sx.rounds += 1;
     sx.seeds_used += m;
 
-    RoundOut ro;
-    const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
-    stt = run_iterations(h, st, fr, m, p, thr, tol, ro);
-    if (stt != FMS_OK) return stt;
-    const int nc = int(ro.conv.size());
-    sx.n_discarded += m - nc;
-
-    // Prune (Alg. 2): window counts at the endpoints and similarity bits on
-    // the GPU, greedy acceptance on the host (count descending, then seed
-    // position).
+    // Prune (Alg. 2): window counts at the converged endpoints, ranking by
+    // count (descending) then seed position, greedy suppression against the
+    // modes kept so far and the candidates accepted before.
     int accepted = 0;
-    if (nc > 0) {
+    unsigned long long round_updates = 0;
+    int round_ncand = 0;
+    if (on_device) {
       Xfer x;
-      XferHost xh;
-      stt = prune_inputs(h, st, fr, h->y.as<float>(), h->cand.as<int>(), nc, k_modes, thr, true, x, xh);
+      stt = ensure_xfer(h, want, k_modes, x);
       if (stt != FMS_OK) return stt;
-      std::vector<int> ord(nc);
-      for (int a = 0; a < nc; ++a) ord[a] = a;
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return xh.counts[a] > xh.counts[b]; });
-      std::vector<int> acc = greedy_accept(ord, xh, x, k_modes > 0);
-      accepted = int(acc.size());
-      if (accepted > 0) {
-        stt = grow_modes(h, st, fr, k_modes, accepted);
-        if (stt != FMS_OK) return stt;
-        HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
-        int* hacc = reinterpret_cast<int*>(h->hstage);  // staging is free again after the sync above
-        for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
-        HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
-        HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), x.counts, h->acc.as<int>(),
-                                         accepted, h->modes.as<float>(), h->mode_counts.as<int>(), k_modes));
+      HIP_TRY(fms::launch_collect(st, h->state.as<uint8_t>(), h->cand.as<int>(), meta));
+      HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
+                                h->cand.as<int>(), m, thr, h->pcount.as<int>(), x.counts, meta, fms::META_NCAND));
+      HIP_TRY(fms::launch_rank(st, h->cand.as<int>(), x.counts, meta, h->sorted.as<int>(), h->scount.as<int>()));
+      HIP_TRY(fms::launch_simbits(st, fr.dp, h->y.as<float>(), h->sorted.as<int>(), want, h->sorted.as<int>(), nullptr,
+                                  want, thr, x.bits_c, meta, fms::META_NCAND, fms::META_NCAND));
+      if (k_modes > 0)
+        HIP_TRY(fms::launch_simbits(st, fr.dp, h->y.as<float>(), h->sorted.as<int>(), want, nullptr,
+                                    h->modes.as<float>(), k_modes, thr, x.bits_m, meta, fms::META_NCAND, -1));
+      HIP_TRY(fms::launch_greedy(st, x.bits_c, x.words_c, x.bits_m, x.words_m, k_modes, h->y.as<float>(),
+                                 h->sorted.as<int>(), h->scount.as<int>(), meta, fms::META_NCAND, fms::META_NACC,
+                                 fr.dp, h->modes.as<float>(), h->mode_counts.as<int>()));
+      if (bf16) {
+        // The refinement below reuses the iteration counters: read them now.
+        HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h->hmeta + META_COUNT, h->meta64.p, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        accepted = h->hmeta[fms::META_NACC];
+        std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
+        round_ncand = h->hmeta[fms::META_NCAND];
+      }
+    } else {
+      const int nc = int(ro.conv.size());
+      if (nc > 0) {
+        Xfer x;
+        XferHost xh;
+        stt = prune_inputs(h, st, fr, h->y.as<float>(), h->cand.as<int>(), nc, k_modes, thr, true, x, xh);
+        if (stt != FMS_OK) return stt;
+        std::vector<int> ord(nc);
+        for (int a = 0; a < nc; ++a) ord[a] = a;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return xh.counts[a] > xh.counts[b]; });
+        std::vector<int> acc = greedy_accept(ord, xh, x, k_modes > 0);
+        accepted = int(acc.size());
+        if (accepted > 0) {
+          HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
+          int* hacc = reinterpret_cast<int*>(h->hstage);  // staging is free again after the sync above
+          for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
+          HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
+          HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), x.counts,
+                                           h->acc.as<int>(), accepted, h->modes.as<float>(), h->mode_counts.as<int>(),
+                                           k_modes));
+          HIP_TRY(hipStreamSynchronize(st));
+        }
       }
     }
+    const bool acc_on_device = on_device && !bf16;
     if (bf16 && accepted > 0 && p->refine_iters > 0) {
-      // BF16 form: the accepted modes are refined in FP32 (at least
-      // refine_iters steps, then until they stop moving), recounted, and any
-      // that now fall inside the window of an earlier mode are dropped
-      // (acceptance order decides).
+      // BF16 form: the accepted modes are refined in FP32 (refine_iters steps,
+      // then FP32 iteration under the early stop), recounted, and any that now
+      // fall inside the window of an earlier mode are dropped (acceptance
+      // order decides).
       float* newm = h->modes.as<float>() + size_t(k_modes) * fr.dp;
       HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), accepted));
+      std::vector<uint8_t> settled;
       stt = run_refine(h, st, fr, newm, h->ident.as<int>(), accepted, p->refine_iters, p->max_iter, thr, tol,
-                       p->timing != 0, ro);
+                       p->gamma, true, p->timing != 0, ro, &settled);
       if (stt != FMS_OK) return stt;
+      HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), accepted));
       Xfer x;
       XferHost xh;
       stt = prune_inputs(h, st, fr, newm, h->ident.as<int>(), accepted, k_modes, thr, true, x, xh);
       if (stt != FMS_OK) return stt;
-      std::vector<int> ord(accepted);
-      for (int a = 0; a < accepted; ++a) ord[a] = a;
+      std::vector<int> ord;
+      for (int a = 0; a < accepted; ++a)
+        if (settled[size_t(a)]) ord.push_back(a);
       std::vector<int> keep = greedy_accept(ord, xh, x, k_modes > 0);
       // Rewrite the new rows through the (now free) centre buffer, keeping
       // only the survivors, with their recounted windows.
@@ -714,8 +783,30 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
                                        int(keep.size()), h->modes.as<float>(), h->mode_counts.as<int>(), k_modes));
       HIP_TRY(hipStreamSynchronize(st));
-      sx.refine_merged += accepted - int(keep.size());
+      sx.refine_merged += int(ord.size()) - int(keep.size());
       accepted = int(keep.size());
+    }
+    // Coverage by the new modes, and the pool left to seed; then one read of
+    // the round's counters.
+    HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
+    HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), k_modes,
+                               k_modes + (acc_on_device ? want : accepted), acc_on_device ? fms::META_NACC : -1, thr,
+                               0, h->elig.as<uint8_t>(), h->rank.as<int>(), meta, nullptr, nullptr));
+    HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h->hmeta + META_COUNT, h->meta64.p, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (acc_on_device) accepted = h->hmeta[fms::META_NACC];
+    if (on_device) {
+      if (!bf16) {
+        std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
+        round_ncand = h->hmeta[fms::META_NCAND];
+      }
+      ro.updates = int64_t(round_updates);
+      if (p->timing) ro.step_updates[bf16 ? 1 : 0] += ro.updates;
+      sx.n_discarded += m - round_ncand;
+    } else {
+      sx.n_discarded += m - int(ro.conv.size());
     }
     sx.iterations_total += ro.steps;
     sx.refine_steps += ro.refine_steps;
@@ -723,14 +814,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     sx.refine_unconverged += ro.refine_bad;
     sx.refine_updates += ro.refine_updates;
     add_timing(sx, ro);
-    const int k_old = k_modes;
     k_modes += accepted;
-    // Coverage by the new modes, and the pool left to seed.
-    HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
-    HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), k_old, k_modes, thr, 0,
-                               h->uncovered.as<uint8_t>(), h->used.as<uint8_t>(), meta, nullptr, nullptr));
-    HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
     const bool left = h->hmeta[META_LEFT] > 0;
     // Controller (Sec. 3.2.4).
     bool go_on = false;
@@ -747,7 +831,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   // Labels (Alg. 2): most similar mode, lowest index on ties; count pixels
   // farther than h from every mode.
   HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
-  HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), 0, k_modes, thr, 1, nullptr,
+  HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), 0, k_modes, -1, thr, 1, nullptr,
                              nullptr, meta, h->fg_idx.as<int>(), labels));
   HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
   if (k_modes > k_max) {
@@ -808,17 +892,17 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   RoundOut ro;
   h->hmeta[META_NSEL] = m;
   HIP_TRY(hipMemcpyAsync(meta + META_NSEL, h->hmeta + META_NSEL, sizeof(int), hipMemcpyHostToDevice, st));
-  stt = run_iterations(h, st, fr, m, p, thr, tol, ro);
+  stt = run_iterations(h, st, fr, m, p, thr, tol, ro, true);
   if (stt != FMS_OK) return stt;
   if (p->precision == FMS_PREC_BF16_REFINE && !ro.conv.empty()) {
     stt = run_refine(h, st, fr, h->y.as<float>(), h->cand.as<int>(), int(ro.conv.size()), p->refine_iters,
-                     p->refine_iters, thr, tol, p->timing != 0, ro);
+                     p->refine_iters, thr, tol, p->gamma, false, p->timing != 0, ro, nullptr);
     if (stt != FMS_OK) return stt;
   }
   // Window counts of every slot (the output keeps them for converged seeds).
   HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), m));
   HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
-                            h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>()));
+                            h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>(), nullptr, -1));
   HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
   HIP_TRY(hipStreamSynchronize(st));

@@ -17,15 +17,19 @@ enum MetaSlot {
   META_NCONV = 4,      // converged seeds this round
   META_NNEXT = 5,      // active seeds for the next iteration
   META_REFINE_BAD = 6, // refine steps whose move stayed >= tol
-  META_LEFT = 7,       // foreground pixels neither covered nor used
+  META_LEFT = 7,       // foreground pixels still eligible as seeds (coverage), or farther than h from every mode (labels)
   META_BADSEED = 8,    // seed indices outside [0, n)
   META_NACT = 9,       // active seeds of the next iteration
   META_DONE = 10,      // the round's iteration has stopped
   META_BLKDONE = 11,   // finished work groups of the current reduce launch
   META_STEPS = 12,     // iterations run this round
-  META_NACC = 13,      // modes being refined
+  META_NACC = 13,      // modes being refined / modes accepted by the last pruning pass
+  META_NCAND = 14,     // converged candidates of the round
   META_COUNT = 16
 };
+
+// Largest candidate set the single-block rank/greedy kernels take.
+constexpr int kRankMax = 8192;
 
 // Work decomposition of the fused step (see plan_chunks in kernels.hip).
 constexpr int kTargetItems = 1024;
@@ -54,11 +58,12 @@ hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_of
                           int* meta);
 constexpr int kMaskBlockPix = 1024;
 
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order);
+// order[j] = foreground ordinal at seed-order position j; rank = its inverse
+// (may be null).
+hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank);
 
-hipError_t launch_select(hipStream_t s, const int* order, const uint8_t* uncovered, uint8_t* used, int n,
-                         int want, int* meta, int* seed_pos, int* seed_fg, const float* x32, int dp,
-                         float* y);
+hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
+                         int* seed_fg, const float* x32, int dp, float* y);
 hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, const float* x32, int dp,
                              float* y, int* meta);
 hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
@@ -86,22 +91,32 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, c
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active, int* meta,
                          unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
                          double gamma, int mode);
-// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres (FP32 MFMA).
+// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres (FP32 MFMA);
+// with m_slot >= 0 the count is meta[m_slot] (m is then an upper bound).
 size_t count_partial_rows(int dp, int cap);
 hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
-                        const int* list, int m, float thr, int* pcount, int* counts);
+                        const int* list, int m, float thr, int* pcount, int* counts, const int* meta, int m_slot);
 // Similarity bits between the rows y[rows[0..m)] and the columns y[cols[c]]
-// (or colmat[c]) for c < ncols: row stride simbits_words(ncols) words.
+// (or colmat[c]) for c < ncols: row stride simbits_words(ncols) words.  With
+// rows_slot / cols_slot >= 0 the counts come from meta (m, ncols are then
+// upper bounds that size the grid and the row stride).
 int simbits_words(int ncols);
 hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
-                          const float* colmat, int ncols, float thr, uint32_t* bits);
+                          const float* colmat, int ncols, float thr, uint32_t* bits, const int* meta, int rows_slot,
+                          int cols_slot);
+// Pruning on the device: converged list, ranking, greedy suppression.
+hipError_t launch_collect(hipStream_t s, const uint8_t* state, int* cand, int* meta);
+hipError_t launch_rank(hipStream_t s, const int* cand, const int* counts, const int* meta, int* sorted, int* scount);
+hipError_t launch_greedy(hipStream_t s, const uint32_t* bits_c, int words_c, const uint32_t* bits_m, int words_m,
+                         int k0, const float* y, const int* sorted, const int* scount, int* meta, int ncand_slot,
+                         int acc_slot, int dp, float* modes, int* mode_counts);
 hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int* list, const int* counts,
                                const int* acc, int a, float* modes, int* mode_counts, int k0);
 // Coverage (mode = 0) or labels (mode = 1) against modes [k0, k1); both count
 // into meta[META_LEFT] (pixels left to seed, resp. farther than h from every mode).
 hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const float* modes, int k0,
-                         int k1, float thr, int mode, uint8_t* uncovered, const uint8_t* used,
-                         int* meta, const int* fg_idx, int* labels);
+                         int k1, int k1_slot, float thr, int mode, uint8_t* elig, const int* rank, int* meta,
+                         const int* fg_idx, int* labels);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int64_t count, int value);
 hipError_t launch_iota(hipStream_t s, int* p, int count);
 hipError_t launch_copy_rows(hipStream_t s, const float* src, int src_stride, float* dst, int dst_stride,

@@ -206,7 +206,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, uint64_t k1, uint64_t k2,
-                                                    uint64_t k3, int* __restrict__ order) {
+                                                    uint64_t k3, int* __restrict__ order, int* __restrict__ rank) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   const uint64_t mask = (1ull << b) - 1;
@@ -224,55 +224,53 @@ __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, u
     y = (left << b) | right;
   } while (y >= (uint64_t)n);
   order[j] = (int)y;
+  if (rank) rank[y] = j;
 }
 
 // ------------------------------------------------------------------ seeds
 
 // One 1024-thread block: take the first `want` positions of the seed order
-// (from the cursor on) whose pixels are uncovered and unused, mark them used
-// and load their vectors as the round's starting centres.  Each pass looks at
-// 16 consecutive positions per thread (16384 per pass).
-__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order,
-                                                 const uint8_t* __restrict__ uncovered,
-                                                 uint8_t* __restrict__ used, int n, int want,
-                                                 int* __restrict__ meta, int* __restrict__ seed_pos,
-                                                 int* __restrict__ seed_fg, const float* __restrict__ x32,
-                                                 int dp, float* __restrict__ y) {
+// (from the cursor on) that are still eligible (elig[pos] = 1: the pixel is
+// neither covered by a mode nor used as a seed), clear them, and load their
+// vectors as the round's starting centres.  Each pass reads 16 consecutive
+// eligibility bytes per thread with one 16-byte load (16384 positions per
+// pass).  Positions before the cursor are all ineligible, so a pass may start
+// at the cursor rounded down to 16; `elig` is zero-padded to a multiple of 16.
+__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order, uint8_t* __restrict__ elig, int n,
+                                                 int want, int* __restrict__ meta, int* __restrict__ seed_pos,
+                                                 int* __restrict__ seed_fg, const float* __restrict__ x32, int dp,
+                                                 float* __restrict__ y) {
   constexpr int RUN = 16;
   __shared__ int sh[17];
   __shared__ int s_last;
   __shared__ int s_base;
-  if (threadIdx.x == 0) s_base = meta[META_CURSOR];
+  if (threadIdx.x == 0) s_base = meta[META_CURSOR] & ~(RUN - 1);
   __syncthreads();
   int base = s_base;
   int got = 0;
   int new_cursor = n;
   while (got < want && base < n) {
     const int p0 = base + (int)threadIdx.x * RUN;
-    int ord[RUN];
-    uint32_t elig = 0;
-#pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-      const int pos = p0 + k;
-      ord[k] = pos < n ? order[pos] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-      const int pos = p0 + k;
-      if (pos < n && uncovered[ord[k]] && !used[ord[k]]) elig |= 1u << k;
-    }
+    uint4 e4 = make_uint4(0u, 0u, 0u, 0u);
+    if (p0 < n) e4 = *reinterpret_cast<const uint4*>(elig + p0);
+    const uint32_t ew[4] = {e4.x, e4.y, e4.z, e4.w};
+    const int cnt = __popc(e4.x) + __popc(e4.y) + __popc(e4.z) + __popc(e4.w);
     int tot;
-    int rank = block_exclusive_scan<1024>(__popc(elig), &tot, sh);
+    int rank = block_exclusive_scan<1024>(cnt, &tot, sh);
+    if (cnt && got + rank < want) {
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-      if ((elig >> k) & 1u) {
-        const int q = got + rank;
-        if (q < want) {
-          seed_pos[q] = p0 + k;
-          seed_fg[q] = ord[k];
-          if (q == want - 1) s_last = p0 + k;
+      for (int k = 0; k < RUN; ++k) {
+        if ((ew[k >> 2] >> (8 * (k & 3))) & 1u) {
+          const int q = got + rank;
+          if (q < want) {
+            const int pos = p0 + k;
+            seed_pos[q] = pos;
+            seed_fg[q] = order[pos];
+            elig[pos] = 0;
+            if (q == want - 1) s_last = pos;
+          }
+          ++rank;
         }
-        ++rank;
       }
     }
     __syncthreads();
@@ -285,12 +283,10 @@ __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order,
     }
     __syncthreads();
   }
-  // Mark used and load starting centres.
+  // Load the starting centres.
   for (int k = threadIdx.x; k < got * dp; k += 1024) {
     int s = k / dp, d = k - s * dp;
-    int o = seed_fg[s];
-    y[(int64_t)s * dp + d] = x32[(int64_t)o * dp + d];
-    if (d == 0) used[o] = 1;
+    y[(int64_t)s * dp + d] = x32[(int64_t)seed_fg[s] * dp + d];
   }
   if (threadIdx.x == 0) {
     meta[META_NSEL] = got;
@@ -580,9 +576,13 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
 
 // Sum the chunk partials of each active seed in a fixed order, renormalise,
 // test convergence (Sec. 3.2.1: cosine distance between consecutive centres
-// below tol), and build the next active list.  One work group per seed: the
-// 256 threads split the chunks into 256/DP phases, the phases are added in
-// order in LDS.
+// below tol), and build the next active list.
+//
+// Threads are laid out (seed, phase, 4-dimension slice): a seed's DP/4 slices
+// times P phases, P the smallest power of two with at most 8 chunks per
+// phase, so every thread issues at most 8 float4 loads at once.  Phases are
+// added in order in LDS; norms and moves are reduced over the seed's slice
+// lanes with a fixed butterfly.  Work groups loop over tiles of seeds.
 //   mode 0: iterate, freezing converged seeds; the last work group to finish
 //           applies the early stop of Sec. 3.2.3 (more than gamma of the
 //           round's seeds converged, or none left active) by setting the
@@ -597,78 +597,100 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
                                                 int nact_slot, int done_slot, int n_host, int n_blocks,
                                                 int group_seeds, int n_fg, float tol, double gamma, int mode) {
   if (done_slot >= 0 && meta[done_slot]) return;
-  constexpr int P = 256 / DP;  // chunk phases
-  __shared__ float part[256];
-  __shared__ float wsum[4];
+  constexpr int Q = DP / 4;  // float4 slices per row
+  __shared__ float4 part[256];
+  __shared__ int s_conv;
   const int n_act = nact_slot >= 0 ? meta[nact_slot] : n_host;
   const ChunkPlan cp = plan_chunks(n_act, group_seeds, n_blocks);
   const int nc = cp.n_chunks;
-  const int a = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (a < n_act) {
-    const int slot = active[a];
-    {
-      const int d = tid % DP, ph = tid / DP;
-      const float* src = partial + (int64_t)a * DP + d;
-      const int64_t cstride = (int64_t)n_act * DP;
-      float accv = 0.f;
-      int c = ph;
-      for (; c + 7 * P < nc; c += 8 * P) {
-        float t[8];
+  int P = 1;
+  while (P * 8 < nc && Q * P * 2 <= 256) P <<= 1;
+  const int tpr = Q * P;       // threads per seed
+  const int spw = 256 / tpr;   // seeds per work group tile
+  const int tiles = (n_act + spw - 1) / spw;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int sl = tid / tpr, rest = tid - sl * tpr, q = rest % Q, ph = rest / Q;
+  if (tid == 0) s_conv = 0;
+  const int64_t cstride = (int64_t)n_act * DP;
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int a = tile * spw + sl;
+    const bool live_seed = a < n_act && sl < spw;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live_seed) {
+      const float4* src = reinterpret_cast<const float4*>(partial + (int64_t)a * DP + 4 * q);
+      for (int c0 = ph; c0 < nc; c0 += 8 * P) {
+        float4 t[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = src[(int64_t)(c + u * P) * cstride];
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + u * P;
+          t[u] = c < nc ? src[(int64_t)c * (cstride / 4)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) accv += t[u];
+        for (int u = 0; u < 8; ++u) {
+          acc.x += t[u].x;
+          acc.y += t[u].y;
+          acc.z += t[u].z;
+          acc.w += t[u].w;
+        }
       }
-      for (; c < nc; c += P) accv += src[(int64_t)c * cstride];
-      part[tid] = accv;
     }
+    part[tid] = acc;
     __syncthreads();
-    // Threads 0..DP-1 own one dimension each.
-    float v = 0.f, yo = 0.f;
-    if (tid < DP) {
-#pragma unroll
-      for (int q = 0; q < P; ++q) v += part[q * DP + tid];
-      yo = y[(int64_t)slot * DP + tid];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool owner = live_seed && ph == 0;
+    if (owner) {
+      for (int pp = 0; pp < P; ++pp) {
+        const float4 u = part[sl * tpr + pp * Q + q];
+        v.x += u.x;
+        v.y += u.y;
+        v.z += u.z;
+        v.w += u.w;
+      }
     }
-    // |V|^2 over the first DP threads (one or two waves), fixed order.
-    float ss = wave_sum_f(v * v, 64);
-    if (lane == 0) wsum[wave] = ss;
-    __syncthreads();
-    ss = DP > 64 ? wsum[0] + wsum[1] : wsum[0];
+    // The Q owner lanes of a seed are consecutive and aligned within a wave.
+    float ss = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+    for (int m = Q / 2; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
     const float nv = sqrtf(ss);
     const bool dead = !(nv > 0.f) || !__builtin_isfinite(nv);
     const float inv = dead ? 0.f : 1.0f / nv;
-    const float yn = v * inv;
-    const float df = tid < DP ? yo - yn : 0.f;
-    __syncthreads();
-    float dd = wave_sum_f(df * df, 64);
-    if (lane == 0) wsum[wave] = dd;
-    __syncthreads();
+    const int slot = owner ? active[a] : 0;
+    float4 yo = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (owner) yo = *reinterpret_cast<const float4*>(y + (int64_t)slot * DP + 4 * q);
+    const float4 yn = make_float4(v.x * inv, v.y * inv, v.z * inv, v.w * inv);
+    float dd = (yo.x - yn.x) * (yo.x - yn.x) + (yo.y - yn.y) * (yo.y - yn.y) + (yo.z - yn.z) * (yo.z - yn.z) +
+               (yo.w - yn.w) * (yo.w - yn.w);
+    for (int m = Q / 2; m >= 1; m >>= 1) dd += __shfl_xor(dd, m, 64);
     // 1 - y.y' = |y - y'|^2 / 2 for unit vectors, without cancellation.
-    const float delta = 0.5f * (DP > 64 ? wsum[0] + wsum[1] : wsum[0]);
-    if (!dead && tid < DP) y[(int64_t)slot * DP + tid] = yn;
-    if (tid == 0) {
-      if (mode == 0) {
+    const float delta = 0.5f * dd;
+    if (owner && !dead) *reinterpret_cast<float4*>(y + (int64_t)slot * DP + 4 * q) = yn;
+    const bool head = owner && q == 0;
+    if (mode == 0) {
+      const bool conv = head && !dead && delta < tol;
+      const bool next = head && !dead && !(delta < tol);
+      if (head) {
         iters[slot] += 1;
-        if (dead) {
-          state[slot] = 2;
-        } else if (delta < tol) {
-          state[slot] = 1;
-          atomicAdd(meta + META_NCONV, 1);
-        } else {
-          next_active[atomicAdd(meta + META_NNEXT, 1)] = slot;
-        }
-      } else {
         if (dead) state[slot] = 2;
-        if (mode == 2 && (dead || !(delta < tol))) atomicAdd(meta + META_REFINE_BAD, 1);
+        if (conv) state[slot] = 1;
       }
+      // Wave-aggregated list append and converged count.
+      const unsigned long long bn = __ballot(next);
+      const unsigned long long bc = __ballot(conv);
+      int base = 0;
+      if (lane == 0 && bn) base = atomicAdd(meta + META_NNEXT, __popcll(bn));
+      base = __shfl(base, 0, 64);
+      if (next) next_active[base + __popcll(bn & ((1ull << lane) - 1ull))] = slot;
+      if (lane == 0 && bc) atomicAdd(&s_conv, __popcll(bc));
+    } else if (head) {
+      if (dead) state[slot] = 2;
+      if (mode == 2 && (dead || !(delta < tol))) atomicAdd(meta + META_REFINE_BAD, 1);
     }
+    __syncthreads();
   }
   if (mode != 0) return;
   __shared__ int s_last;
   // The counter updates and list stores must be complete before the block
   // reports itself done: the last block reads the counters next.
+  if (tid == 0 && s_conv) atomicAdd(meta + META_NCONV, s_conv);
   __threadfence();
   __syncthreads();
   if (tid == 0) s_last = atomicAdd(meta + META_BLKDONE, 1) == (int)gridDim.x - 1;
@@ -688,8 +710,11 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
 }
 
 // Sum the per-chunk window counts of each centre (one wave per centre).
-__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_chunks,
+__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_blocks,
+                                                       int group_seeds, const int* __restrict__ meta, int m_slot,
                                                        int* __restrict__ counts) {
+  if (m_slot >= 0) m = meta[m_slot];
+  const int n_chunks = plan_chunks(m, group_seeds, n_blocks).n_chunks;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (a >= m) return;
   int c = 0;
@@ -729,8 +754,11 @@ __global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ 
 template <int DP>
 __global__ __launch_bounds__(256) void k_simbits(const float* __restrict__ y, const int* __restrict__ rows, int m,
                                                  const int* __restrict__ cols, const float* __restrict__ colmat,
-                                                 int ncols, float thr, uint32_t* __restrict__ bits, int words) {
+                                                 int ncols, float thr, uint32_t* __restrict__ bits, int words,
+                                                 const int* __restrict__ meta, int rows_slot, int cols_slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (rows_slot >= 0) m = meta[rows_slot];
+  if (cols_slot >= 0) ncols = meta[cols_slot];
   const int col_tiles = words / 2;
   const int ct = blockIdx.x % col_tiles, rt = blockIdx.x / col_tiles;
   const int c = ct * 64 + lane;
@@ -762,6 +790,149 @@ __global__ __launch_bounds__(256) void k_simbits(const float* __restrict__ y, co
   }
 }
 
+// ------------------------------------------------------------------ pruning on the device
+
+// Converged slots of the round, ascending (= seed-order order), and their
+// number in meta[META_NCAND].  One 1024-thread block.
+__global__ __launch_bounds__(1024) void k_collect(const uint8_t* __restrict__ state, int* __restrict__ cand,
+                                                  int* __restrict__ meta) {
+  __shared__ int sh[17];
+  const int m = meta[META_NSEL];
+  int base = 0;
+  for (int k0 = 0; k0 < m; k0 += 1024) {
+    const int k = k0 + (int)threadIdx.x;
+    const int c = (k < m && state[k] == 1) ? 1 : 0;
+    int tot;
+    const int r = block_exclusive_scan<1024>(c, &tot, sh);
+    if (c) cand[base + r] = k;
+    base += tot;
+  }
+  if (threadIdx.x == 0) meta[META_NCAND] = base;
+}
+
+// Rank the nc candidates by window count (descending), then by index
+// (ascending, = seed position): sorted[r] = cand[a_r], scount[r] = count.
+// Bitonic sort of 64-bit keys in LDS; nc <= kRankMax.
+__global__ __launch_bounds__(1024) void k_rank(const int* __restrict__ cand, const int* __restrict__ counts,
+                                               const int* __restrict__ meta, int* __restrict__ sorted,
+                                               int* __restrict__ scount) {
+  __shared__ unsigned long long key[kRankMax];
+  const int nc = meta[META_NCAND];
+  int np = 1;
+  while (np < nc) np <<= 1;
+  for (int i = threadIdx.x; i < np; i += 1024) {
+    key[i] = i < nc ? ((unsigned long long)(uint32_t)(0x7FFFFFFF - counts[i]) << 32) | (uint32_t)i
+                    : ~0ull;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < np; i += 1024) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long a = key[i], b = key[j];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = threadIdx.x; r < nc; r += 1024) {
+    const int a = (int)(key[r] & 0xFFFFFFFFull);
+    sorted[r] = cand[a];
+    scount[r] = counts[a];
+  }
+}
+
+// Greedy suppression (Alg. 2 "Prune modes") over candidates already in rank
+// order: candidate r is accepted when no existing mode is within its window
+// (row r of bits_m is empty) and no accepted candidate r' < r is (bit r' of
+// row r of bits_c).  Decided in parallel passes: an undecided r is rejected
+// as soon as an earlier accepted candidate conflicts with it and accepted
+// once every earlier conflicting candidate is rejected; each pass decides at
+// least the first undecided candidate, and every decision equals the
+// sequential one whatever order the passes observe.  The accepted rows are
+// appended to the mode set at k0; their number goes to meta[acc_slot].
+__global__ __launch_bounds__(1024) void k_greedy(const uint32_t* __restrict__ bits_c, int words_c,
+                                                 const uint32_t* __restrict__ bits_m, int words_m, int k0,
+                                                 const float* __restrict__ y, const int* __restrict__ sorted,
+                                                 const int* __restrict__ scount, int* __restrict__ meta,
+                                                 int ncand_slot, int acc_slot, int dp, float* __restrict__ modes,
+                                                 int* __restrict__ mode_counts) {
+  __shared__ uint8_t st[kRankMax];
+  __shared__ int s_open;
+  __shared__ int sh[17];
+  const int nc = meta[ncand_slot];
+  for (int r = threadIdx.x; r < nc; r += 1024) {
+    uint8_t v = 0;
+    if (k0 > 0) {
+      const uint32_t* rm = bits_m + (int64_t)r * words_m;
+      for (int w = 0; w < words_m; ++w)
+        if (rm[w]) {
+          v = 2;
+          break;
+        }
+    }
+    st[r] = v;
+  }
+  __syncthreads();
+  for (;;) {
+    if (threadIdx.x == 0) s_open = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nc; r += 1024) {
+      if (reinterpret_cast<volatile uint8_t*>(st)[r] != 0) continue;
+      const uint32_t* row = bits_c + (int64_t)r * words_c;
+      bool rejected = false, waiting = false;
+      const int wend = r >> 5;
+      for (int w = 0; w <= wend && !rejected; ++w) {
+        uint32_t b = row[w];
+        if (w == wend) b &= (r & 31) ? ((1u << (r & 31)) - 1u) : 0u;
+        while (b) {
+          const int k = (w << 5) + __ffs(b) - 1;
+          b &= b - 1;
+          const uint8_t sk = reinterpret_cast<volatile uint8_t*>(st)[k];
+          if (sk == 1) {
+            rejected = true;
+            break;
+          }
+          if (sk == 0) waiting = true;
+        }
+      }
+      if (rejected) {
+        reinterpret_cast<volatile uint8_t*>(st)[r] = 2;
+      } else if (!waiting) {
+        reinterpret_cast<volatile uint8_t*>(st)[r] = 1;
+      } else {
+        atomicAdd(&s_open, 1);
+      }
+    }
+    __syncthreads();
+    const int open = s_open;
+    __syncthreads();
+    if (open == 0) break;
+  }
+  // Append the accepted candidates in rank order.
+  int base = 0;
+  for (int r0 = 0; r0 < nc; r0 += 1024) {
+    const int r = r0 + (int)threadIdx.x;
+    const int acc = (r < nc && st[r] == 1) ? 1 : 0;
+    int tot;
+    const int q = base + block_exclusive_scan<1024>(acc, &tot, sh);
+    if (acc) {
+      const float* src = y + (int64_t)sorted[r] * dp;
+      float* dst = modes + (int64_t)(k0 + q) * dp;
+      for (int d = 0; d < dp; ++d) dst[d] = src[d];
+      mode_counts[k0 + q] = scount[r];
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) meta[acc_slot] = base;
+}
+
 // Append accepted candidates (indices into `list`) to the mode set.
 __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __restrict__ y,
                                                       const int* __restrict__ list, const int* __restrict__ counts,
@@ -775,15 +946,17 @@ __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __res
   if (d == 0) mode_counts[k0 + q] = counts[cand];
 }
 
-// Coverage (mode 0): clear `uncovered` for pixels within h of a mode in
-// [k0, k1) and count pixels still uncovered and unused.  Labels (mode 1):
+// Coverage (mode 0): pixels within h of a mode in [k0, k1) stop being
+// eligible seeds (elig[rank[i]] = 0); count the pixels still eligible.  Labels (mode 1):
 // most similar mode in [k0, k1), lowest index on ties.
 template <int DP>
 __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int n, const float* __restrict__ modes,
-                                                int k0, int k1, float thr, int mode, uint8_t* __restrict__ uncovered,
-                                                const uint8_t* __restrict__ used, int* __restrict__ meta,
-                                                const int* __restrict__ fg_idx, int* __restrict__ labels) {
+                                                int k0, int k1, int k1_slot, float thr, int mode,
+                                                uint8_t* __restrict__ elig, const int* __restrict__ rank,
+                                                int* __restrict__ meta, const int* __restrict__ fg_idx,
+                                                int* __restrict__ labels) {
   constexpr int KT = 64;
+  if (k1_slot >= 0) k1 = k0 + meta[k1_slot];
   __shared__ float sm[KT * DP];
   const int i = blockIdx.x * 256 + threadIdx.x;
   float xi[DP];
@@ -812,12 +985,13 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int
   if (mode == 0) {
     int left = 0;
     if (i < n) {
-      uint8_t u = uncovered[i];
-      if (u && best >= thr) {
-        uncovered[i] = 0;
-        u = 0;
+      const int pos = rank[i];
+      uint8_t e = elig[pos];
+      if (e && best >= thr) {
+        elig[pos] = 0;
+        e = 0;
       }
-      left = (u && !used[i]) ? 1 : 0;
+      left = e ? 1 : 0;
     }
     left = wave_sum_i(left);
     if ((threadIdx.x & 63) == 0 && left) atomicAdd(meta + META_LEFT, left);
@@ -903,17 +1077,16 @@ hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_of
   return hipGetLastError();
 }
 
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order) {
+hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_seed_order, dim3(cdiv(n, 256)), dim3(256), 0, s, n, half_bits, keys[0], keys[1], keys[2],
-                     keys[3], order);
+                     keys[3], order, rank);
   return hipGetLastError();
 }
 
-hipError_t launch_select(hipStream_t s, const int* order, const uint8_t* uncovered, uint8_t* used, int n, int want,
-                         int* meta, int* seed_pos, int* seed_fg, const float* x32, int dp, float* y) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, order, uncovered, used, n, want, meta, seed_pos, seed_fg,
-                     x32, dp, y);
+hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
+                         int* seed_fg, const float* x32, int dp, float* y) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, order, elig, n, want, meta, seed_pos, seed_fg, x32, dp, y);
   return hipGetLastError();
 }
 
@@ -1001,7 +1174,13 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, c
                          unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
                          double gamma, int mode) {
   if (cap <= 0) return hipSuccess;
-  const dim3 grid(cap), block(256);
+  // Enough work groups for the seed tiles of the largest active count; they
+  // loop when the active count shrinks and tiles get smaller.
+  const ChunkPlan cp = plan_chunks(cap, group_seeds, n_blocks);
+  int P = 1;
+  while (P * 8 < cp.n_chunks && (dp / 4) * P * 2 <= 256) P <<= 1;
+  const int spw = std::max(1, 256 / ((dp / 4) * P));
+  const dim3 grid(cdiv(cap, spw)), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                     \
   hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, meta, meta64, \
                      nact_slot, done_slot, cap, n_blocks, group_seeds, n_fg, tol, gamma, mode)
@@ -1018,25 +1197,45 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, c
 size_t count_partial_rows(int dp, int cap) { return shift_partial_rows(false, dp, cap, 0); }
 
 hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
-                        const int* list, int m, float thr, int* pcount, int* counts) {
+                        const int* list, int m, float thr, int* pcount, int* counts, const int* meta, int m_slot) {
   if (m <= 0 || n_blocks <= 0) return hipSuccess;
-  hipError_t e = shift_dispatch(s, false, true, dp, n_blocks, n_pix, x32, nullptr, y, list, nullptr, -1, -1, m, m, thr,
-                                nullptr, pcount);
+  hipError_t e = shift_dispatch(s, false, true, dp, n_blocks, n_pix, x32, nullptr, y, list, meta, m_slot, -1, m, m,
+                                thr, nullptr, pcount);
   if (e != hipSuccess) return e;
-  const ChunkPlan cp = plan_chunks(m, shift_group_seeds(false, dp), n_blocks);
-  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, cp.n_chunks, counts);
+  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, n_blocks,
+                     shift_group_seeds(false, dp), meta, m_slot, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect(hipStream_t s, const uint8_t* state, int* cand, int* meta) {
+  hipLaunchKernelGGL(k_collect, dim3(1), dim3(1024), 0, s, state, cand, meta);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank(hipStream_t s, const int* cand, const int* counts, const int* meta, int* sorted, int* scount) {
+  hipLaunchKernelGGL(k_rank, dim3(1), dim3(1024), 0, s, cand, counts, meta, sorted, scount);
+  return hipGetLastError();
+}
+
+hipError_t launch_greedy(hipStream_t s, const uint32_t* bits_c, int words_c, const uint32_t* bits_m, int words_m,
+                         int k0, const float* y, const int* sorted, const int* scount, int* meta, int ncand_slot,
+                         int acc_slot, int dp, float* modes, int* mode_counts) {
+  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(1024), 0, s, bits_c, words_c, bits_m, words_m, k0, y, sorted, scount,
+                     meta, ncand_slot, acc_slot, dp, modes, mode_counts);
   return hipGetLastError();
 }
 
 int simbits_words(int ncols) { return std::max(2, ((ncols + 63) / 64) * 2); }
 
 hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
-                          const float* colmat, int ncols, float thr, uint32_t* bits) {
-  if (m <= 0) return hipSuccess;
+                          const float* colmat, int ncols, float thr, uint32_t* bits, const int* meta, int rows_slot,
+                          int cols_slot) {
+  if (m <= 0 || ncols <= 0) return hipSuccess;
   const int words = simbits_words(ncols);
   const unsigned grid = (unsigned)((words / 2) * cdiv(m, 64));
 #define FMS_SIM_CASE(DPV)                                                                                        \
-  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid), dim3(256), 0, s, y, rows, m, cols, colmat, ncols, thr, bits, words)
+  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid), dim3(256), 0, s, y, rows, m, cols, colmat, ncols, thr, bits, words, \
+                     meta, rows_slot, cols_slot)
   switch (dp) {
     case 32: FMS_SIM_CASE(32); break;
     case 64: FMS_SIM_CASE(64); break;
@@ -1062,22 +1261,22 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
   return hipGetLastError();
 }
 
-hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const float* modes, int k0, int k1, float thr,
-                         int mode, uint8_t* uncovered, const uint8_t* used, int* meta, const int* fg_idx,
+hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const float* modes, int k0, int k1, int k1_slot, float thr,
+                         int mode, uint8_t* elig, const int* rank, int* meta, const int* fg_idx,
                          int* labels) {
   if (n <= 0) return hipSuccess;
   const dim3 grid(cdiv(n, 256)), block(256);
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, x32, n, modes, k0, k1, thr, mode, uncovered, used, meta,
+      hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
                          fg_idx, labels);
       break;
     case 64:
-      hipLaunchKernelGGL(k_assign<64>, grid, block, 0, s, x32, n, modes, k0, k1, thr, mode, uncovered, used, meta,
+      hipLaunchKernelGGL(k_assign<64>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
                          fg_idx, labels);
       break;
     case 128:
-      hipLaunchKernelGGL(k_assign<128>, grid, block, 0, s, x32, n, modes, k0, k1, thr, mode, uncovered, used, meta,
+      hipLaunchKernelGGL(k_assign<128>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
                          fg_idx, labels);
       break;
     default:
