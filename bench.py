@@ -32,7 +32,31 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
+                         "reference), then --steps frames of each form; prints a short summary only")
     return ap.parse_args()
+
+
+def _profile_run(a):
+    import torch
+
+    import paper_2007_14283_amd as fms
+    import synth
+    ref = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(ref)
+    ref.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(ref)  # reads and writes exactly 256 MiB
+    torch.cuda.synchronize()
+    frame = synth.make_frame(synth.PLAIN512)
+    emb = torch.from_numpy(frame.emb).cuda()
+    mask = torch.from_numpy(frame.mask).cuda()
+    for prec in (fms.FP32, fms.BF16_REFINE):
+        for _ in range(a.steps):
+            modes, _, st = fms.cluster(emb, mask, frame.bandwidth, precision=prec)
+    torch.cuda.synchronize()
+    print(f"profile run: copy 256 MiB, {a.steps} frames per form, {len(modes)} modes", flush=True)
 
 
 def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
@@ -83,6 +107,9 @@ def _cpu_threads():
 
 def main():
     a = _args()
+    if a.profile_run:
+        _profile_run(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -50,11 +50,13 @@ typedef enum {
 
 typedef enum {
   FMS_PREC_FP32 = 0,        /* every step's contractions on FP32 MFMA */
-  FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) until the early stop; the
-                               pruned modes (fms_cluster: refine_iters FP32 steps, then
-                               FP32 iteration under the same early stop) or the
-                               converged seeds (fms_shift_seeds: refine_iters steps)
-                               are refined in FP32 */
+  FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) for every round's
+                               iteration; then fms_cluster refines the frame's modes
+                               once, after the last round (refine_iters FP32 steps,
+                               then FP32 iteration under the same early stop), and
+                               fms_shift_seeds refines the converged seeds
+                               (refine_iters steps).  Coverage and the seed-count
+                               controller see the BF16 endpoints. */
 } fms_precision;
 
 /* Clustering parameters.  fms_default_params fills the paper's values. */
@@ -76,10 +78,17 @@ typedef struct {
   int32_t max_iter;   /* cap on iterations per round (not in the paper); 100. */
   int32_t max_rounds; /* cap on seed rounds per frame (not in the paper); 32. */
   int32_t precision;  /* fms_precision. */
-  int32_t refine_iters; /* FP32 steps after a BF16 round; 3. */
+  int32_t refine_iters; /* FP32 steps that start the refinement of the BF16 form; 3. */
   int32_t timing;     /* nonzero: time every fused-step launch with HIP events on
                          `stream` and report the totals in fms_stats. */
-  int32_t reserved;
+  /* Work decomposition of the fused step (0 = the library's choice): seeds per
+   * group (16, 32, 64 or 128; rounded down to a size compiled for the
+   * precision and D), target number of (seed group, pixel chunk) items per
+   * step, and cap on pixel chunks.  They change speed only: every result is
+   * the same up to the order of FP32 additions. */
+  int32_t tile_seeds;
+  int32_t tile_items;
+  int32_t tile_chunks;
 } fms_params;
 
 /* Per-call statistics (host struct). */

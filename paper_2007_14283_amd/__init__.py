@@ -50,6 +50,9 @@ class Params:
     precision: int = FP32
     refine_iters: int = 3
     timing: int = 0
+    tile_seeds: int = 0
+    tile_items: int = 0
+    tile_chunks: int = 0
 
     def to_c(self) -> B.FmsParams:
         c = B.FmsParams()

@@ -38,7 +38,9 @@ class FmsParams(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("refine_iters", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile_seeds", ctypes.c_int32),
+        ("tile_items", ctypes.c_int32),
+        ("tile_chunks", ctypes.c_int32),
     ]
 
 

@@ -24,7 +24,6 @@ using fms::META_CURSOR;
 using fms::META_LEFT;
 using fms::META_N;
 using fms::META_NCONV;
-using fms::META_NNEXT;
 using fms::META_NSEL;
 using fms::META_REFINE_BAD;
 
@@ -187,6 +186,8 @@ struct Frame {
   int dp = 32;
   int n_pad = 0;
   fms::StepGeom geom{};
+  fms::Tiling tile{};       // the precision of the call
+  fms::Tiling tile_fp32{};  // FP32 steps (refinement) and window counts
 };
 
 fms_status check_params(const fms_params* p) {
@@ -198,6 +199,7 @@ fms_status check_params(const fms_params* p) {
   if (!std::isfinite(p->conv_tol)) return FMS_ERR_INVALID_ARG;
   if (p->n_initial < 1 || p->max_iter < 1 || p->max_rounds < 1 || p->refine_iters < 0) return FMS_ERR_INVALID_ARG;
   if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE) return FMS_ERR_INVALID_ARG;
+  if (p->tile_seeds < 0 || p->tile_items < 0 || p->tile_chunks < 0) return FMS_ERR_INVALID_ARG;
   return FMS_OK;
 }
 
@@ -255,6 +257,12 @@ fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t
   return FMS_OK;
 }
 
+void set_tiling(Frame& fr, const fms_params* p) {
+  const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
+  fr.tile = fms::make_tiling(bf16, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+  fr.tile_fp32 = fms::make_tiling(false, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+}
+
 fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
   HIP_TRY(h->stage(size_t(std::max(m, 1)) * sizeof(int) + 256));
   const size_t mm = size_t(std::max(m, 1));
@@ -271,9 +279,9 @@ fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
   HIP_TRY(h->counts.ensure(mm * sizeof(int)));
   HIP_TRY(h->sorted.ensure(mm * sizeof(int)));
   HIP_TRY(h->scount.ensure(mm * sizeof(int)));
-  HIP_TRY(h->pcount.ensure(fms::count_partial_rows(fr.dp, int(mm)) * sizeof(int)));
-  const size_t rows = std::max(fms::shift_partial_rows(bf16, fr.dp, int(mm), fr.geom.n_blocks),
-                               fms::shift_partial_rows(false, fr.dp, int(mm), fr.geom.n_blocks));
+  (void)bf16;
+  HIP_TRY(h->pcount.ensure(fms::shift_partial_rows(fr.tile_fp32, int(mm)) * sizeof(int)));
+  const size_t rows = std::max(fms::shift_partial_rows(fr.tile, int(mm)), fms::shift_partial_rows(fr.tile_fp32, int(mm)));
   HIP_TRY(h->partial.ensure(rows * dp * sizeof(float)));
   return FMS_OK;
 }
@@ -354,7 +362,7 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
   const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
-  const int gs = fms::shift_group_seeds(bf16, fr.dp);
+  const fms::Tiling& tl = bf16 ? fr.tile : fr.tile_fp32;
   const int pk = bf16 ? 1 : 0;
   const bool timing = p->timing != 0;
   HIP_TRY(fms::launch_round_begin(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>(), meta,
@@ -365,13 +373,12 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
     const int nb = std::min(batch, p->max_iter - t);
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
     for (int i = 0; i < nb; ++i, ++t) {
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * i], st));
-      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, fr.geom.n_blocks, xrm, xt, ybuf, lists[t & 1], meta,
-                                fms::META_NACT, fms::META_DONE, m, thr, h->partial.as<float>()));
-      if (timing) HIP_TRY(hipEventRecord(h->events[2 * i + 1], st));
-      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), lists[t & 1], ybuf,
-                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1],
-                                 meta, meta64, fms::META_NACT, fms::META_DONE, m, fr.n, tol, p->gamma, 0));
+      const fms::IterCtl ctl{meta, meta64, -1, t, fr.n, p->gamma};
+      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, tl, fr.geom.n_blocks, xrm, xt, ybuf, lists[t & 1], ctl, m, thr,
+                                h->partial.as<float>(), timing ? h->events[2 * i] : nullptr,
+                                timing ? h->events[2 * i + 1] : nullptr));
+      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), lists[t & 1], ybuf,
+                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1], ctl, m, tol, 0));
     }
     HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -383,7 +390,11 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
         out.step_launches[pk] += 1;
       }
     }
-    if (h->hmeta[fms::META_DONE]) break;
+    // The early stop of the next iteration, as its step kernel would take it.
+    const int* hm = h->hmeta;
+    if (hm[fms::META_DONE] || hm[fms::META_ACT + (t & 1)] <= 0 ||
+        (double)hm[fms::META_NCONV] > p->gamma * (double)hm[fms::META_NSEL])
+      break;
     batch = std::min(2 * batch, 8);
   }
   out.steps = h->hmeta[fms::META_STEPS];
@@ -428,19 +439,18 @@ fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, c
                       RoundOut& out, std::vector<uint8_t>* out_keep) {
   if (a <= 0 || steps <= 0) return FMS_OK;
   int* meta = h->meta.as<int>();
-  const int gs = fms::shift_group_seeds(false, fr.dp);
+  const fms::Tiling& tl = fr.tile_fp32;
   h->hmeta[fms::META_NACC] = a;
   HIP_TRY(hipMemcpyAsync(meta + fms::META_NACC, h->hmeta + fms::META_NACC, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
   if (timing) HIP_TRY(h->ensure_events(2 * size_t(steps)));
   for (int r = 0; r < steps; ++r) {
-    if (timing) HIP_TRY(hipEventRecord(h->events[2 * r], st));
-    HIP_TRY(fms::launch_shift(st, false, fr.dp, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, meta, fms::META_NACC,
-                              -1, a, thr, h->partial.as<float>()));
-    if (timing) HIP_TRY(hipEventRecord(h->events[2 * r + 1], st));
-    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, gs, h->partial.as<float>(), list, y,
-                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, meta,
-                               h->meta64.as<unsigned long long>(), fms::META_NACC, -1, a, fr.n, tol, 1.0,
+    const fms::IterCtl ctl{meta, nullptr, fms::META_NACC, -1, fr.n, 1.0};
+    HIP_TRY(fms::launch_shift(st, false, fr.dp, tl, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, ctl, a, thr,
+                              h->partial.as<float>(), timing ? h->events[2 * r] : nullptr,
+                              timing ? h->events[2 * r + 1] : nullptr));
+    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), list, y,
+                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, ctl, a, tol,
                                r + 1 == steps ? 2 : 1));
     out.refine_steps += 1;
     out.refine_updates += int64_t(a) * int64_t(fr.n);
@@ -473,6 +483,9 @@ fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, c
   q.max_iter = std::max(max_steps - steps, 1);
   q.precision = FMS_PREC_FP32;
   q.timing = timing ? 1 : 0;
+  q.tile_seeds = tl.group_seeds;
+  q.tile_items = tl.target_items;
+  q.tile_chunks = tl.max_chunks;
   fms_status stt = run_iterations_on(h, st, fr, y, a, &q, thr, tol, ro, true);
   if (stt != FMS_OK) return stt;
   out.refine_steps += ro.steps;
@@ -519,7 +532,7 @@ fms_status prune_inputs(fms_handle h, hipStream_t st, const Frame& fr, const flo
   fms_status stt = ensure_xfer(h, nc, k, x);
   if (stt != FMS_OK) return stt;
   if (with_counts)
-    HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), y, list, nc, thr,
+    HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(), y, list, nc, thr,
                               h->pcount.as<int>(), x.counts, nullptr, -1));
   HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c, nullptr, -1, -1));
   if (k > 0)
@@ -643,6 +656,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
                       p->precision == FMS_PREC_BF16_REFINE, fr);
   if (stt != FMS_OK) return stt;
+  set_tiling(fr, p);
   sx.n_fg = fr.n;
   HIP_TRY(fms::launch_fill_i32(st, labels, P, -1));
   if (fr.n == 0) {
@@ -707,8 +721,9 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       stt = ensure_xfer(h, want, k_modes, x);
       if (stt != FMS_OK) return stt;
       HIP_TRY(fms::launch_collect(st, h->state.as<uint8_t>(), h->cand.as<int>(), meta));
-      HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
-                                h->cand.as<int>(), m, thr, h->pcount.as<int>(), x.counts, meta, fms::META_NCAND));
+      HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(),
+                                h->y.as<float>(), h->cand.as<int>(), m, thr, h->pcount.as<int>(), x.counts, meta,
+                                fms::META_NCAND));
       HIP_TRY(fms::launch_rank(st, h->cand.as<int>(), x.counts, meta, h->sorted.as<int>(), h->scount.as<int>()));
       HIP_TRY(fms::launch_simbits(st, fr.dp, h->y.as<float>(), h->sorted.as<int>(), want, h->sorted.as<int>(), nullptr,
                                   want, thr, x.bits_c, meta, fms::META_NCAND, fms::META_NCAND));
@@ -718,16 +733,6 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       HIP_TRY(fms::launch_greedy(st, x.bits_c, x.words_c, x.bits_m, x.words_m, k_modes, h->y.as<float>(),
                                  h->sorted.as<int>(), h->scount.as<int>(), meta, fms::META_NCAND, fms::META_NACC,
                                  fr.dp, h->modes.as<float>(), h->mode_counts.as<int>()));
-      if (bf16) {
-        // The refinement below reuses the iteration counters: read them now.
-        HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(h->hmeta + META_COUNT, h->meta64.p, sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        accepted = h->hmeta[fms::META_NACC];
-        std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
-        round_ncand = h->hmeta[fms::META_NCAND];
-      }
     } else {
       const int nc = int(ro.conv.size());
       if (nc > 0) {
@@ -752,40 +757,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
         }
       }
     }
-    const bool acc_on_device = on_device && !bf16;
-    if (bf16 && accepted > 0 && p->refine_iters > 0) {
-      // BF16 form: the accepted modes are refined in FP32 (refine_iters steps,
-      // then FP32 iteration under the early stop), recounted, and any that now
-      // fall inside the window of an earlier mode are dropped (acceptance
-      // order decides).
-      float* newm = h->modes.as<float>() + size_t(k_modes) * fr.dp;
-      HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), accepted));
-      std::vector<uint8_t> settled;
-      stt = run_refine(h, st, fr, newm, h->ident.as<int>(), accepted, p->refine_iters, p->max_iter, thr, tol,
-                       p->gamma, true, p->timing != 0, ro, &settled);
-      if (stt != FMS_OK) return stt;
-      HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), accepted));
-      Xfer x;
-      XferHost xh;
-      stt = prune_inputs(h, st, fr, newm, h->ident.as<int>(), accepted, k_modes, thr, true, x, xh);
-      if (stt != FMS_OK) return stt;
-      std::vector<int> ord;
-      for (int a = 0; a < accepted; ++a)
-        if (settled[size_t(a)]) ord.push_back(a);
-      std::vector<int> keep = greedy_accept(ord, xh, x, k_modes > 0);
-      // Rewrite the new rows through the (now free) centre buffer, keeping
-      // only the survivors, with their recounted windows.
-      HIP_TRY(fms::launch_copy_rows(st, newm, fr.dp, h->y.as<float>(), fr.dp, accepted, fr.dp));
-      HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
-      int* hk = reinterpret_cast<int*>(h->hstage);
-      for (size_t q = 0; q < keep.size(); ++q) hk[q] = keep[q];
-      HIP_TRY(hipMemcpyAsync(h->acc.p, hk, keep.size() * sizeof(int), hipMemcpyHostToDevice, st));
-      HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
-                                       int(keep.size()), h->modes.as<float>(), h->mode_counts.as<int>(), k_modes));
-      HIP_TRY(hipStreamSynchronize(st));
-      sx.refine_merged += int(ord.size()) - int(keep.size());
-      accepted = int(keep.size());
-    }
+    const bool acc_on_device = on_device;
     // Coverage by the new modes, and the pool left to seed; then one read of
     // the round's counters.
     HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
@@ -798,10 +770,8 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     HIP_TRY(hipStreamSynchronize(st));
     if (acc_on_device) accepted = h->hmeta[fms::META_NACC];
     if (on_device) {
-      if (!bf16) {
-        std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
-        round_ncand = h->hmeta[fms::META_NCAND];
-      }
+      std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
+      round_ncand = h->hmeta[fms::META_NCAND];
       ro.updates = int64_t(round_updates);
       if (p->timing) ro.step_updates[bf16 ? 1 : 0] += ro.updates;
       sx.n_discarded += m - round_ncand;
@@ -826,6 +796,48 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       }
     }
     if (!go_on) break;
+  }
+
+  if (p->precision == FMS_PREC_BF16_REFINE && k_modes > 0 && p->refine_iters > 0) {
+    // BF16 form: the frame's modes are refined in FP32 (refine_iters steps,
+    // then FP32 iteration under the early stop; modes still moving at the
+    // stop are dropped), recounted, and a mode that now falls inside the
+    // window of an earlier kept mode is dropped (acceptance order decides).
+    stt = ensure_round(h, fr, k_modes, true);
+    if (stt != FMS_OK) return stt;
+    RoundOut ro;
+    float* mrows = h->modes.as<float>();
+    HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), k_modes));
+    std::vector<uint8_t> settled;
+    stt = run_refine(h, st, fr, mrows, h->ident.as<int>(), k_modes, p->refine_iters, p->max_iter, thr, tol, p->gamma,
+                     true, p->timing != 0, ro, &settled);
+    if (stt != FMS_OK) return stt;
+    HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), k_modes));
+    Xfer x;
+    XferHost xh;
+    stt = prune_inputs(h, st, fr, mrows, h->ident.as<int>(), k_modes, 0, thr, true, x, xh);
+    if (stt != FMS_OK) return stt;
+    std::vector<int> ord;
+    for (int a = 0; a < k_modes; ++a)
+      if (settled[size_t(a)]) ord.push_back(a);
+    std::vector<int> keep = greedy_accept(ord, xh, x, false);
+    // Rewrite the rows through the (now free) centre buffer, keeping only the
+    // survivors, with their recounted windows.
+    HIP_TRY(fms::launch_copy_rows(st, mrows, fr.dp, h->y.as<float>(), fr.dp, k_modes, fr.dp));
+    HIP_TRY(h->acc.ensure(size_t(k_modes) * sizeof(int)));
+    int* hk = reinterpret_cast<int*>(h->hstage);
+    for (size_t q = 0; q < keep.size(); ++q) hk[q] = keep[q];
+    if (!keep.empty())
+      HIP_TRY(hipMemcpyAsync(h->acc.p, hk, keep.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
+                                     int(keep.size()), mrows, h->mode_counts.as<int>(), 0));
+    HIP_TRY(hipStreamSynchronize(st));
+    sx.refine_merged += int(ord.size()) - int(keep.size());
+    sx.refine_steps += ro.refine_steps;
+    sx.refine_unconverged += ro.refine_bad;
+    sx.refine_updates += ro.refine_updates;
+    add_timing(sx, ro);
+    k_modes = int(keep.size());
   }
 
   // Labels (Alg. 2): most similar mode, lowest index on ties; count pixels
@@ -872,6 +884,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
                       p->precision == FMS_PREC_BF16_REFINE, fr);
   if (stt != FMS_OK) return stt;
+  set_tiling(fr, p);
   sx.n_fg = fr.n;
   if (n_seeds == 0) {
     if (stats) *stats = sx;
@@ -901,7 +914,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   }
   // Window counts of every slot (the output keeps them for converged seeds).
   HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(st, fr.dp, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
+  HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
                             h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>(), nullptr, -1));
   HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));

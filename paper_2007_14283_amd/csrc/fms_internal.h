@@ -15,25 +15,34 @@ enum MetaSlot {
   META_NSEL = 2,       // seeds selected this round
   META_CURSOR = 3,     // seed-order cursor (every earlier position is used or covered)
   META_NCONV = 4,      // converged seeds this round
-  META_NNEXT = 5,      // active seeds for the next iteration
   META_REFINE_BAD = 6, // refine steps whose move stayed >= tol
   META_LEFT = 7,       // foreground pixels still eligible as seeds (coverage), or farther than h from every mode (labels)
   META_BADSEED = 8,    // seed indices outside [0, n)
-  META_NACT = 9,       // active seeds of the next iteration
   META_DONE = 10,      // the round's iteration has stopped
-  META_BLKDONE = 11,   // finished work groups of the current reduce launch
   META_STEPS = 12,     // iterations run this round
   META_NACC = 13,      // modes being refined / modes accepted by the last pruning pass
   META_NCAND = 14,     // converged candidates of the round
-  META_COUNT = 16
+  META_ACT = 16,       // two slots (16, 17): active seeds of the even / odd iterations
+  META_COUNT = 24
 };
 
 // Largest candidate set the single-block rank/greedy kernels take.
 constexpr int kRankMax = 8192;
 
-// Work decomposition of the fused step (see plan_chunks in kernels.hip).
-constexpr int kTargetItems = 1024;
+// Work decomposition of the fused step (see plan_chunks in kernels.hip):
+// seeds in groups of `group_seeds`, pixels in chunks of whole 32-pixel
+// blocks, about `target_items` (group, chunk) items, at most `max_chunks`
+// chunks.  Defaults below; fms_params can override them.
+constexpr int kTargetItems = 512;
 constexpr int kMaxChunks = 256;
+struct Tiling {
+  int group_seeds;
+  int target_items;
+  int max_chunks;
+};
+// The tiling used for a (precision, padded D) pair given the caller's
+// requests (0 = default); group sizes round down to a compiled one.
+Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks);
 struct ChunkPlan {
   int groups;
   int n_chunks;
@@ -68,7 +77,6 @@ hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, co
                              float* y, int* meta);
 hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
                               unsigned long long* meta64);
-
 struct StepGeom {
   int n;             // foreground count
   int n_blocks;      // ceil(n / 32)
@@ -77,25 +85,39 @@ struct StepGeom {
 };
 StepGeom make_geom(int n);
 
-// One fused mean-shift step for the active seeds (count in meta[nact_slot],
-// at most cap; skipped when done_slot >= 0 and meta[done_slot] is set):
-// partial window sums per pixel chunk.
-int shift_group_seeds(bool bf16, int dp);
-size_t shift_partial_rows(bool bf16, int dp, int cap, int n_blocks);
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, int n_blocks, const void* xrm, const void* xt,
-                        const float* y, const int* active, const int* meta, int nact_slot, int done_slot, int cap,
-                        float thr, float* partial);
-// Sum partials, renormalise, convergence test, next active list and (mode 0)
-// the early stop.
-hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, const float* partial,
-                         const int* active, float* y, uint8_t* state, int* iters, int* next_active, int* meta,
-                         unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
-                         double gamma, int mode);
+// Control of the iterate loop on the device.  Iteration `iter` reads its
+// active count from meta[META_ACT + iter % 2] and appends the next one to
+// the other slot.  The step kernel applies the early stop of Sec. 3.2.3
+// first (more than gamma of the round's seeds converged, or none left
+// active): it sets meta[META_DONE] and skips the iteration, and the reduce
+// kernel of that iteration sees the flag.  Otherwise its first work group
+// clears the other slot and counts the iteration (META_STEPS, meta64[0]).
+// iter < 0: a plain step whose count is meta[nact_slot] (or the host count).
+struct IterCtl {
+  int* meta;
+  unsigned long long* meta64;
+  int nact_slot;
+  int iter;
+  int n_fg;
+  double gamma;
+};
+// One fused mean-shift step for the active seeds (at most cap): partial
+// window sums per pixel chunk.  ev0/ev1 (may be null) receive the start and
+// end of the kernel itself (hipExtLaunchKernel), not of the launch call.
+size_t shift_partial_rows(const Tiling& t, int cap);
+hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, const void* xrm,
+                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap, float thr,
+                        float* partial, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Sum partials, renormalise, convergence test and (mode 0) the next active
+// list and converged count.
+hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
+                         const int* active, float* y, uint8_t* state, int* iters, int* next_active,
+                         const IterCtl& ctl, int cap, float tol, int mode);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of m centres (FP32 MFMA);
 // with m_slot >= 0 the count is meta[m_slot] (m is then an upper bound).
-size_t count_partial_rows(int dp, int cap);
-hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
-                        const int* list, int m, float thr, int* pcount, int* counts, const int* meta, int m_slot);
+hipError_t launch_count(hipStream_t s, int dp, const Tiling& t, int n_blocks, int n_pix, const float* x32,
+                        const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
+                        int m_slot);
 // Similarity bits between the rows y[rows[0..m)] and the columns y[cols[c]]
 // (or colmat[c]) for c < ncols: row stride simbits_words(ncols) words.  With
 // rows_slot / cols_slot >= 0 the counts come from meta (m, ncols are then

@@ -17,6 +17,7 @@
 // are ordered so that k-slot 8g+e of lane group g is pixel 8g+e; the first
 // product therefore reads pixel sigma_t(r) = 8(r/4) + 4t + r%4 as row r of
 // tile t.  S is never written to memory.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -316,11 +317,11 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
 // whole 32-pixel blocks, about kTargetItems (group, chunk) items in total.
 // The kernels derive it from the active count held on the device; the host
 // uses the same function with upper bounds to size the partial buffer.
-__host__ __device__ inline ChunkPlan plan_chunks(int n_act, int group_seeds, int n_blocks) {
+__host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int n_blocks) {
   ChunkPlan cp;
-  const int groups = n_act > 0 ? (n_act + group_seeds - 1) / group_seeds : 1;
-  int want = (kTargetItems + groups - 1) / groups;
-  int lim = n_blocks < kMaxChunks ? n_blocks : kMaxChunks;
+  const int groups = n_act > 0 ? (n_act + t.group_seeds - 1) / t.group_seeds : 1;
+  int want = (t.target_items + groups - 1) / groups;
+  int lim = n_blocks < t.max_chunks ? n_blocks : t.max_chunks;
   if (lim < 1) lim = 1;
   int nc = want < 1 ? 1 : (want > lim ? lim : want);
   const int cb = n_blocks > 0 ? (n_blocks + nc - 1) / nc : 1;
@@ -351,11 +352,10 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, int group_seeds, int
 // writes the per-seed number of its pixels inside the window (window counts
 // at the centres, used to rank candidate modes).
 template <bool BF16, bool COUNT, int DP, int ST>
-__global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, const void* __restrict__ xt_,
-                                               const float* __restrict__ y, const int* __restrict__ active,
-                                               const int* __restrict__ meta, int nact_slot, int done_slot,
-                                               int n_host, int n_blocks, int n_pix, float thr,
-                                               float* __restrict__ partial, int* __restrict__ pcount) {
+__device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
+                                           const float* __restrict__ y, const int* __restrict__ active, int n_act,
+                                           const Tiling& tl, int n_blocks, int n_pix, float thr,
+                                           float* __restrict__ partial, int* __restrict__ pcount, int wg, int nwg) {
   constexpr int KJ = DP / 4;     // dimensions held per lane group
   constexpr int KS = BF16 ? DP / 32 : DP / 4;  // MFMA steps of S per 16x16 tile
   constexpr int NDB = DP / 16;   // 16-dimension blocks of V
@@ -365,10 +365,7 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
   const T* __restrict__ xt = static_cast<const T*>(xt_);
 
   static_assert(!(BF16 && COUNT), "window counts are taken in FP32");
-  if (done_slot >= 0 && meta[done_slot]) return;
-  const int n_act = nact_slot >= 0 ? meta[nact_slot] : n_host;
-  if (n_act <= 0) return;
-  const ChunkPlan cp = plan_chunks(n_act, 16 * ST, n_blocks);
+  const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int items = cp.groups * cp.n_chunks;
 
   __shared__ f32x4 red[COUNT ? 1 : 3][ST][COUNT ? 1 : NDB][64];
@@ -378,9 +375,11 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
   const int rowsel0 = 8 * (r >> 2) + (r & 3);
   const f32x4 cinit = {-thr, -thr, -thr, -thr};
 
-  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+  // nwg is a multiple of 8: work group wg runs on XCD wg % 8 (round-robin
+  // dispatch), and each XCD owns one contiguous eighth of the items.
+  const int xcd = wg & 7, per = nwg >> 3;
   const int lo = (int)((int64_t)items * xcd / 8), hi = (int)((int64_t)items * (xcd + 1) / 8);
-  for (int it = lo + (int)(blockIdx.x >> 3); it < hi; it += per) {
+  for (int it = lo + (wg >> 3); it < hi; it += per) {
     const int chunk = it / cp.groups, grp = it - chunk * cp.groups;
     const int a0 = grp * 16 * ST;
     // Seed operands (B of S^T = X Y^T).
@@ -574,6 +573,36 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
   }
 }
 
+template <bool BF16, bool COUNT, int DP, int ST>
+__global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, const void* __restrict__ xt_,
+                                               const float* __restrict__ y, const int* __restrict__ active,
+                                               IterCtl ctl, int n_host, Tiling tl, int n_blocks, int n_pix,
+                                               float thr, float* __restrict__ partial, int* __restrict__ pcount) {
+  int* meta = ctl.meta;
+  int n_act;
+  if (ctl.iter >= 0) {
+    if (meta[META_DONE]) return;
+    n_act = meta[META_ACT + (ctl.iter & 1)];
+    const int n_conv = meta[META_NCONV];
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    // Same test, in the same precision, as the host's between batches.
+    if (n_act <= 0 || (double)n_conv > ctl.gamma * (double)meta[META_NSEL]) {
+      if (first) meta[META_DONE] = 1;
+      return;
+    }
+    if (first) {
+      meta[META_ACT + ((ctl.iter + 1) & 1)] = 0;
+      meta[META_STEPS] += 1;
+      ctl.meta64[0] += (unsigned long long)n_act * (unsigned long long)ctl.n_fg;
+    }
+  } else {
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : n_host;
+  }
+  if (n_act <= 0) return;
+  shift_body<BF16, COUNT, DP, ST>(xrm_, xt_, y, active, n_act, tl, n_blocks, n_pix, thr, partial, pcount,
+                                  (int)blockIdx.x, (int)gridDim.x);
+}
+
 // Sum the chunk partials of each active seed in a fixed order, renormalise,
 // test convergence (Sec. 3.2.1: cosine distance between consecutive centres
 // below tol), and build the next active list.
@@ -583,25 +612,23 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
 // phase, so every thread issues at most 8 float4 loads at once.  Phases are
 // added in order in LDS; norms and moves are reduced over the seed's slice
 // lanes with a fixed butterfly.  Work groups loop over tiles of seeds.
-//   mode 0: iterate, freezing converged seeds; the last work group to finish
-//           applies the early stop of Sec. 3.2.3 (more than gamma of the
-//           round's seeds converged, or none left active) by setting the
-//           done flag, and publishes the next active count.
+//   mode 0: iterate, freezing converged seeds: next active list and
+//           converged count (the early stop is taken by the next step).
 //   mode 1: refine step (no freezing).  mode 2: refine step that also counts
 //           the seeds whose move stayed >= tol.
+// Reduce/renormalise/converge the active seeds' tiles owned by work group wg
+// of nwg.  Returns (in every thread) this group's number of newly converged
+// seeds (mode 0).  next_ctr receives the appends to next_active.
 template <int DP>
-__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const int* __restrict__ active,
-                                                float* __restrict__ y, uint8_t* __restrict__ state,
-                                                int* __restrict__ iters, int* __restrict__ next_active,
-                                                int* __restrict__ meta, unsigned long long* __restrict__ meta64,
-                                                int nact_slot, int done_slot, int n_host, int n_blocks,
-                                                int group_seeds, int n_fg, float tol, double gamma, int mode) {
-  if (done_slot >= 0 && meta[done_slot]) return;
+__device__ __forceinline__ int reduce_body(const float* __restrict__ partial, const int* __restrict__ active,
+                                           float* __restrict__ y, uint8_t* __restrict__ state,
+                                           int* __restrict__ iters, int* __restrict__ next_active,
+                                           int* __restrict__ next_ctr, int* __restrict__ refine_bad, int n_act,
+                                           const Tiling& tl, int n_blocks, float tol, int mode, int wg, int nwg) {
   constexpr int Q = DP / 4;  // float4 slices per row
   __shared__ float4 part[256];
   __shared__ int s_conv;
-  const int n_act = nact_slot >= 0 ? meta[nact_slot] : n_host;
-  const ChunkPlan cp = plan_chunks(n_act, group_seeds, n_blocks);
+  const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int nc = cp.n_chunks;
   int P = 1;
   while (P * 8 < nc && Q * P * 2 <= 256) P <<= 1;
@@ -611,8 +638,9 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
   const int tid = threadIdx.x, lane = tid & 63;
   const int sl = tid / tpr, rest = tid - sl * tpr, q = rest % Q, ph = rest / Q;
   if (tid == 0) s_conv = 0;
+  __syncthreads();
   const int64_t cstride = (int64_t)n_act * DP;
-  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  for (int tile = wg; tile < tiles; tile += nwg) {
     const int a = tile * spw + sl;
     const bool live_seed = a < n_act && sl < spw;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -676,45 +704,45 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
       const unsigned long long bn = __ballot(next);
       const unsigned long long bc = __ballot(conv);
       int base = 0;
-      if (lane == 0 && bn) base = atomicAdd(meta + META_NNEXT, __popcll(bn));
+      if (lane == 0 && bn) base = atomicAdd(next_ctr, __popcll(bn));
       base = __shfl(base, 0, 64);
       if (next) next_active[base + __popcll(bn & ((1ull << lane) - 1ull))] = slot;
       if (lane == 0 && bc) atomicAdd(&s_conv, __popcll(bc));
     } else if (head) {
       if (dead) state[slot] = 2;
-      if (mode == 2 && (dead || !(delta < tol))) atomicAdd(meta + META_REFINE_BAD, 1);
+      if (mode == 2 && (dead || !(delta < tol))) atomicAdd(refine_bad, 1);
     }
     __syncthreads();
   }
-  if (mode != 0) return;
-  __shared__ int s_last;
-  // The counter updates and list stores must be complete before the block
-  // reports itself done: the last block reads the counters next.
-  if (tid == 0 && s_conv) atomicAdd(meta + META_NCONV, s_conv);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(meta + META_BLKDONE, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (s_last && tid == 0) {
-    __threadfence();
-    const int n_next = atomicAdd(meta + META_NNEXT, 0);
-    const int n_conv = atomicAdd(meta + META_NCONV, 0);
-    const int m = meta[META_NSEL];
-    meta[META_STEPS] += 1;
-    meta64[0] += (unsigned long long)n_act * (unsigned long long)n_fg;
-    meta[nact_slot] = n_next;
-    meta[META_NNEXT] = 0;
-    meta[META_BLKDONE] = 0;
-    if ((double)n_conv > gamma * (double)m || n_next == 0) meta[done_slot] = 1;
+  return s_conv;
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const int* __restrict__ active,
+                                                float* __restrict__ y, uint8_t* __restrict__ state,
+                                                int* __restrict__ iters, int* __restrict__ next_active, IterCtl ctl,
+                                                int n_host, int n_blocks, Tiling tl, float tol, int mode) {
+  int* meta = ctl.meta;
+  int n_act;
+  int* next_ctr = nullptr;
+  if (ctl.iter >= 0) {
+    if (meta[META_DONE]) return;
+    n_act = meta[META_ACT + (ctl.iter & 1)];
+    next_ctr = meta + META_ACT + ((ctl.iter + 1) & 1);
+  } else {
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : n_host;
   }
+  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, next_ctr, meta + META_REFINE_BAD,
+                                   n_act, tl, n_blocks, tol, mode, (int)blockIdx.x, (int)gridDim.x);
+  if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
 }
 
 // Sum the per-chunk window counts of each centre (one wave per centre).
-__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_blocks,
-                                                       int group_seeds, const int* __restrict__ meta, int m_slot,
+__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_blocks, Tiling tl,
+                                                       const int* __restrict__ meta, int m_slot,
                                                        int* __restrict__ counts) {
   if (m_slot >= 0) m = meta[m_slot];
-  const int n_chunks = plan_chunks(m, group_seeds, n_blocks).n_chunks;
+  const int n_chunks = plan_chunks(m, tl, n_blocks).n_chunks;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (a >= m) return;
   int c = 0;
@@ -735,10 +763,9 @@ __global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ 
     iters[k] = 0;
   }
   if (k == 0) {
-    meta[META_NACT] = m;
+    meta[META_ACT] = m;
+    meta[META_ACT + 1] = 0;
     meta[META_NCONV] = 0;
-    meta[META_NNEXT] = 0;
-    meta[META_BLKDONE] = 0;
     meta[META_DONE] = m > 0 ? 0 : 1;
     meta[META_STEPS] = 0;
     meta64[0] = 0;
@@ -1109,81 +1136,108 @@ StepGeom make_geom(int n) {
   return g;
 }
 
-// Seed tiles of 16 per wave in the fused step: enough seeds per pixel read to
-// keep the loads well below the matrix-core rate, few enough registers for
-// several waves per SIMD.
-int shift_group_seeds(bool bf16, int dp) {
-  int st;
-  if (bf16) st = dp <= 32 ? 4 : (dp <= 64 ? 2 : 1);
-  else st = dp <= 64 ? 2 : 1;
-  return 16 * st;
+// Seed groups of the fused step: enough seeds per pixel read to keep the loads
+// well below the matrix-core rate, few enough registers for several waves per
+// SIMD.  Compiled group sizes per (precision, padded D):
+//   FP32: D 32 -> 16, 32, 64; D 64 -> 16, 32; D 128 -> 16.
+//   BF16: D 32 -> 32, 64, 128; D 64 -> 16, 32, 64; D 128 -> 16, 32.
+static int max_group(bool bf16, int dp) {
+  if (bf16) return dp <= 32 ? 128 : (dp <= 64 ? 64 : 32);
+  return dp <= 32 ? 64 : (dp <= 64 ? 32 : 16);
+}
+static int min_group(bool bf16, int dp) { return (bf16 && dp <= 32) ? 32 : 16; }
+
+Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks) {
+  Tiling t;
+  // Defaults from a sweep on the 512x512, D = 32 workload (32 seeds, ~512
+  // items, <= 256 chunks was fastest for both precisions).
+  int def = dp <= 64 ? 32 : 16;
+  int g = want_seeds > 0 ? want_seeds : def;
+  int gs = min_group(bf16, dp);
+  while (gs * 2 <= g && gs * 2 <= max_group(bf16, dp)) gs *= 2;
+  t.group_seeds = gs;
+  t.target_items = want_items > 0 ? std::max(8, std::min(want_items, 1 << 16)) : kTargetItems;
+  t.max_chunks = want_chunks > 0 ? std::max(1, std::min(want_chunks, 4096)) : kMaxChunks;
+  return t;
 }
 
-size_t shift_partial_rows(bool bf16, int dp, int cap, int n_blocks) {
-  const int64_t g = shift_group_seeds(bf16, dp);
-  const int64_t a = (int64_t)std::min<int64_t>((int64_t)kMaxChunks * cap, (int64_t)kTargetItems * g + cap);
-  (void)n_blocks;
+size_t shift_partial_rows(const Tiling& t, int cap) {
+  const int64_t a = std::min<int64_t>((int64_t)t.max_chunks * cap, (int64_t)t.target_items * t.group_seeds + cap);
   return (size_t)std::max<int64_t>(a, 1);
 }
 
-static unsigned shift_grid(int cap, int group_seeds, int n_blocks) {
-  const ChunkPlan cp = plan_chunks(cap, group_seeds, n_blocks);
+static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
+  const ChunkPlan cp = plan_chunks(cap, t, n_blocks);
   int64_t items = (int64_t)cp.groups * cp.n_chunks;
-  if (items > kTargetItems) items = kTargetItems;
+  if (items > t.target_items) items = t.target_items;
   unsigned grid = (unsigned)((items + 7) / 8 * 8);
   return grid < 8 ? 8 : grid;
 }
 
 #define FMS_SHIFT_CASE(BFV, CNT, DPV, STV)                                                                       \
-  hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, xrm, xt, y, active, meta,          \
-                     nact_slot, done_slot, n_host, n_blocks, n_pix, thr, partial, pcount)
+  hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, ev0, ev1, 0, xrm, xt, y, active, \
+                        ctl, n_host, t, n_blocks, n_pix, thr, partial, pcount)
 
-static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, int n_blocks, int n_pix,
-                                 const void* xrm, const void* xt, const float* y, const int* active,
-                                 const int* meta, int nact_slot, int done_slot, int n_host, int cap, float thr,
-                                 float* partial, int* pcount) {
-  if (cap <= 0 || n_blocks <= 0) return hipSuccess;
-  const int gs = shift_group_seeds(bf16, dp);
-  const unsigned grid = shift_grid(cap, gs, n_blocks);
-  const int key = (bf16 ? 1000 : 0) + (count ? 5000 : 0) + dp * 10 + gs / 16;
+static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, const Tiling& t, int n_blocks,
+                                 int n_pix, const void* xrm, const void* xt, const float* y, const int* active,
+                                 const IterCtl& ctl, int n_host, int cap, float thr, float* partial, int* pcount,
+                                 hipEvent_t ev0, hipEvent_t ev1) {
+  if (cap <= 0 || n_blocks <= 0) {
+    // Nothing to launch; the events still mark this point of the stream.
+    hipError_t e = ev0 ? hipEventRecord(ev0, s) : hipSuccess;
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    return e;
+  }
+  const unsigned grid = shift_grid(cap, t, n_blocks);
+  const int key = (bf16 ? 1000000 : 0) + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
   switch (key) {
-    case 322: FMS_SHIFT_CASE(false, false, 32, 2); break;
-    case 642: FMS_SHIFT_CASE(false, false, 64, 2); break;
-    case 1281: FMS_SHIFT_CASE(false, false, 128, 1); break;
-    case 1324: FMS_SHIFT_CASE(true, false, 32, 4); break;
-    case 1642: FMS_SHIFT_CASE(true, false, 64, 2); break;
-    case 2281: FMS_SHIFT_CASE(true, false, 128, 1); break;
-    case 5322: FMS_SHIFT_CASE(false, true, 32, 2); break;
-    case 5642: FMS_SHIFT_CASE(false, true, 64, 2); break;
-    case 6281: FMS_SHIFT_CASE(false, true, 128, 1); break;
+    case 3201: FMS_SHIFT_CASE(false, false, 32, 1); break;
+    case 3202: FMS_SHIFT_CASE(false, false, 32, 2); break;
+    case 3204: FMS_SHIFT_CASE(false, false, 32, 4); break;
+    case 6401: FMS_SHIFT_CASE(false, false, 64, 1); break;
+    case 6402: FMS_SHIFT_CASE(false, false, 64, 2); break;
+    case 12801: FMS_SHIFT_CASE(false, false, 128, 1); break;
+    case 103201: FMS_SHIFT_CASE(false, true, 32, 1); break;
+    case 103202: FMS_SHIFT_CASE(false, true, 32, 2); break;
+    case 103204: FMS_SHIFT_CASE(false, true, 32, 4); break;
+    case 106401: FMS_SHIFT_CASE(false, true, 64, 1); break;
+    case 106402: FMS_SHIFT_CASE(false, true, 64, 2); break;
+    case 112801: FMS_SHIFT_CASE(false, true, 128, 1); break;
+    case 1003202: FMS_SHIFT_CASE(true, false, 32, 2); break;
+    case 1003204: FMS_SHIFT_CASE(true, false, 32, 4); break;
+    case 1003208: FMS_SHIFT_CASE(true, false, 32, 8); break;
+    case 1006401: FMS_SHIFT_CASE(true, false, 64, 1); break;
+    case 1006402: FMS_SHIFT_CASE(true, false, 64, 2); break;
+    case 1006404: FMS_SHIFT_CASE(true, false, 64, 4); break;
+    case 1012801: FMS_SHIFT_CASE(true, false, 128, 1); break;
+    case 1012802: FMS_SHIFT_CASE(true, false, 128, 2); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 #undef FMS_SHIFT_CASE
 
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, int n_blocks, const void* xrm, const void* xt,
-                        const float* y, const int* active, const int* meta, int nact_slot, int done_slot, int cap,
-                        float thr, float* partial) {
-  return shift_dispatch(s, bf16, false, dp, n_blocks, 0, xrm, xt, y, active, meta, nact_slot, done_slot, cap, cap,
-                        thr, partial, nullptr);
+hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, const void* xrm,
+                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap, float thr,
+                        float* partial, hipEvent_t ev0, hipEvent_t ev1) {
+  return shift_dispatch(s, bf16, false, dp, t, n_blocks, 0, xrm, xt, y, active, ctl, cap, cap, thr, partial, nullptr,
+                        ev0, ev1);
 }
 
-hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, const float* partial,
-                         const int* active, float* y, uint8_t* state, int* iters, int* next_active, int* meta,
-                         unsigned long long* meta64, int nact_slot, int done_slot, int cap, int n_fg, float tol,
-                         double gamma, int mode) {
+hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
+                         const int* active, float* y, uint8_t* state, int* iters, int* next_active,
+                         const IterCtl& ctl, int cap, float tol, int mode) {
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
-  const ChunkPlan cp = plan_chunks(cap, group_seeds, n_blocks);
+  const ChunkPlan cp = plan_chunks(cap, t, n_blocks);
   int P = 1;
   while (P * 8 < cp.n_chunks && (dp / 4) * P * 2 <= 256) P <<= 1;
   const int spw = std::max(1, 256 / ((dp / 4) * P));
   const dim3 grid(cdiv(cap, spw)), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                     \
-  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, meta, meta64, \
-                     nact_slot, done_slot, cap, n_blocks, group_seeds, n_fg, tol, gamma, mode)
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, ctl, cap,    \
+                     n_blocks, t, tol, mode)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
@@ -1194,16 +1248,16 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, int group_seeds, c
   return hipGetLastError();
 }
 
-size_t count_partial_rows(int dp, int cap) { return shift_partial_rows(false, dp, cap, 0); }
-
-hipError_t launch_count(hipStream_t s, int dp, int n_blocks, int n_pix, const float* x32, const float* y,
-                        const int* list, int m, float thr, int* pcount, int* counts, const int* meta, int m_slot) {
+hipError_t launch_count(hipStream_t s, int dp, const Tiling& t, int n_blocks, int n_pix, const float* x32,
+                        const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
+                        int m_slot) {
   if (m <= 0 || n_blocks <= 0) return hipSuccess;
-  hipError_t e = shift_dispatch(s, false, true, dp, n_blocks, n_pix, x32, nullptr, y, list, meta, m_slot, -1, m, m,
-                                thr, nullptr, pcount);
+  const IterCtl ctl{const_cast<int*>(meta), nullptr, m_slot, -1, 0, 0.0};
+  hipError_t e = shift_dispatch(s, false, true, dp, t, n_blocks, n_pix, x32, nullptr, y, list, ctl, m, m, thr, nullptr,
+                                pcount, nullptr, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, n_blocks,
-                     shift_group_seeds(false, dp), meta, m_slot, counts);
+  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, n_blocks, t, meta, m_slot,
+                     counts);
   return hipGetLastError();
 }
 
