@@ -81,7 +81,30 @@ def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
     return dt, agg, last
 
 
-def _roofline(agg, dim):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_shift_512x512_d32_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_14283_amd", "csrc", "kernels.hip")
+
+
+def _measured_traffic(dtype):
+    """HBM bytes per launch of the fused step from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"kernels_sha256: {src}" not in text:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == dtype:
+            return float(f[2])
+    return None
+
+
+def _roofline(agg, dim, n_fg):
     # Dominant kernel: the fused-step form with the larger summed duration.
     k = 1 if agg["step_ms"][1] >= agg["step_ms"][0] else 0
     dtype = "bf16" if k == 1 else "fp32"
@@ -90,8 +113,14 @@ def _roofline(agg, dim):
     launches = max(1, agg["step_launches"][k])
     achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     peak = PEAK_TFLOPS[dtype]
+    # Algorithmic bytes per launch: the pixels once (n x D x b) plus the
+    # active centres in and out (2 x N_act x D x 4), averaged over launches.
+    b = 2 if dtype == "bf16" else 4
+    seeds = agg["step_updates"][k] / max(1, n_fg)
+    alg_bytes = n_fg * dim * b + 8.0 * dim * seeds / launches
     return {"kernel": "k_shift_" + dtype, "bound": "mfma", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": _measured_traffic(dtype),
+            "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": ms * 1e3 / launches, "launches": agg["step_launches"][k],
             "flops_per_launch": flops / launches}
 
@@ -156,10 +185,10 @@ def main():
         "updates_per_s": upd_b,
         "modes": int(len(last_b[0])),
         "fp32": {"frames_per_s": fps_f, "ms_per_frame": 1e3 * dt_f / a.steps, "updates_per_s": upd_f,
-                 "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim),
+                 "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim, frame.n_fg),
                  "kernel_ms_per_frame": agg_f["step_ms"][0] / a.steps},
         "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
-        "roofline": _roofline(agg_b, spec.dim),
+        "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
     }
 
     if not a.no_cpu:
