@@ -135,7 +135,7 @@ struct fms_handle_s {
   // Frame data.
   DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig;
   // Round data.
-  DevBuf y, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, pcount, partial;
+  DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, pcount, partial;
   DevBuf bits, blocked, acc, sorted, scount;
   // Modes found so far.
   DevBuf modes, mode_counts;
@@ -150,6 +150,13 @@ struct fms_handle_s {
       events.push_back(e);
     }
     return hipSuccess;
+  }
+  // Host waits go through an event without timing (cheaper to wait on than
+  // a whole-stream synchronisation).
+  hipEvent_t sync_ev = nullptr;
+  hipError_t wait(hipStream_t st) {
+    hipError_t e = hipEventRecord(sync_ev, st);
+    return e == hipSuccess ? hipEventSynchronize(sync_ev) : e;
   }
   // Pinned host staging.
   int* hmeta = nullptr;
@@ -180,6 +187,12 @@ namespace {
     if (_e != hipSuccess) return FMS_ERR_HIP; \
   } while (0)
 
+// Launches with at least kBigGroupMin centres use seed groups of kBigGroup
+// (where compiled): on the 512x512, D = 32 workload a 64-seed group is about
+// 20% faster than a 32-seed one from 1,024 centres on, and no slower at 256.
+constexpr int kBigGroup = 64;
+constexpr int kBigGroupMin = 512;
+
 struct Frame {
   fms::FrameDesc desc;
   int n = 0;
@@ -188,6 +201,10 @@ struct Frame {
   fms::StepGeom geom{};
   fms::Tiling tile{};       // the precision of the call
   fms::Tiling tile_fp32{};  // FP32 steps (refinement) and window counts
+  // The same with larger seed groups, for launches with many centres (fewer
+  // re-reads of the pixels per centre).
+  fms::Tiling tile_big{};
+  fms::Tiling tile_fp32_big{};
 };
 
 fms_status check_params(const fms_params* p) {
@@ -226,7 +243,7 @@ fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t
   HIP_TRY(fms::launch_mask_count(st, mask, P, h->blk.as<int>(), nmb));
   HIP_TRY(fms::launch_scan_blocks(st, h->blk.as<int>(), nmb, h->meta.as<int>()));
   HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   fr.n = h->hmeta[META_N];
   fr.n_pad = ((fr.n + fms::kBlockPix - 1) / fms::kBlockPix) * fms::kBlockPix;
   fr.geom = fms::make_geom(fr.n);
@@ -240,20 +257,12 @@ fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t
     HIP_TRY(h->x16.ensure(rows * dp * sizeof(uint16_t)));
     HIP_TRY(h->x16t.ensure(rows * dp * sizeof(uint16_t)));
   }
-  // Zero the last (possibly partial) block so padding rows contribute nothing.
-  const size_t last = rows - fms::kBlockPix;
-  HIP_TRY(hipMemsetAsync(h->x32.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
-  HIP_TRY(hipMemsetAsync(h->x32t.as<float>() + last * dp, 0, fms::kBlockPix * dp * sizeof(float), st));
-  if (bf16) {
-    HIP_TRY(hipMemsetAsync(h->x16.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
-    HIP_TRY(hipMemsetAsync(h->x16t.as<uint16_t>() + last * dp, 0, fms::kBlockPix * dp * sizeof(uint16_t), st));
-  }
   HIP_TRY(fms::launch_compact(st, fr.desc, h->blk.as<int>(), nmb, h->fg_idx.as<int>(), h->x32.as<float>(),
                               h->x32t.as<float>(), bf16 ? h->x16.as<uint16_t>() : nullptr,
                               bf16 ? h->x16t.as<uint16_t>() : nullptr, h->meta.as<int>()));
-  HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  // meta[META_BAD] counts zero or non-finite rows.  The caller checks it at
+  // its next read of the counters (no kernel indexes by embedding values, so
+  // the work enqueued meanwhile is merely wasted).
   return FMS_OK;
 }
 
@@ -261,6 +270,16 @@ void set_tiling(Frame& fr, const fms_params* p) {
   const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
   fr.tile = fms::make_tiling(bf16, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
   fr.tile_fp32 = fms::make_tiling(false, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+  // A caller-fixed group size holds for every launch.
+  const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
+  fr.tile_big = fms::make_tiling(bf16, fr.dp, big, p->tile_items, p->tile_chunks);
+  fr.tile_fp32_big = fms::make_tiling(false, fr.dp, big, p->tile_items, p->tile_chunks);
+}
+
+// Tiling of a fused-step launch with at most `bound` centres.
+const fms::Tiling& pick_tiling(const Frame& fr, bool bf16, int bound) {
+  if (bound >= kBigGroupMin) return bf16 ? fr.tile_big : fr.tile_fp32_big;
+  return bf16 ? fr.tile : fr.tile_fp32;
 }
 
 fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
@@ -268,6 +287,8 @@ fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
   const size_t mm = size_t(std::max(m, 1));
   const size_t dp = size_t(fr.dp);
   HIP_TRY(h->y.ensure(mm * dp * sizeof(float)));
+  HIP_TRY(h->yc0.ensure(mm * dp * sizeof(float)));
+  HIP_TRY(h->yc1.ensure(mm * dp * sizeof(float)));
   HIP_TRY(h->active.ensure(mm * sizeof(int)));
   HIP_TRY(h->next_active.ensure(mm * sizeof(int)));
   HIP_TRY(h->state.ensure(mm));
@@ -280,8 +301,10 @@ fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
   HIP_TRY(h->sorted.ensure(mm * sizeof(int)));
   HIP_TRY(h->scount.ensure(mm * sizeof(int)));
   (void)bf16;
-  HIP_TRY(h->pcount.ensure(fms::shift_partial_rows(fr.tile_fp32, int(mm)) * sizeof(int)));
-  const size_t rows = std::max(fms::shift_partial_rows(fr.tile, int(mm)), fms::shift_partial_rows(fr.tile_fp32, int(mm)));
+  const int im = int(mm);
+  const size_t rows = std::max({fms::shift_partial_rows(fr.tile, im), fms::shift_partial_rows(fr.tile_fp32, im),
+                                fms::shift_partial_rows(fr.tile_big, im), fms::shift_partial_rows(fr.tile_fp32_big, im)});
+  HIP_TRY(h->pcount.ensure(rows * sizeof(int)));
   HIP_TRY(h->partial.ensure(rows * dp * sizeof(float)));
   return FMS_OK;
 }
@@ -350,38 +373,55 @@ void add_timing(fms_stats& sx, const RoundOut& ro) {
 
 // Iterate the seeds whose centres are in y[0..m) (Alg. 2, the parallel seed
 // loop) until more than gamma of them converged (Sec. 3.2.3), none is
-// active, or max_iter steps.  The active count, the early-stop test and the
-// done flag live on the device; the host enqueues iterations in batches and
-// reads the flag back between batches.  The converged slots end up in
-// out.conv (ascending) and in h->cand.
+// active, or max_iter steps.  With seed_fg the centres first load from those
+// pixel rows.  The active count, the early-stop test and the done flag live
+// on the device; the host enqueues iterations in batches and reads the flag
+// back between batches.  The converged slots end up in out.conv (ascending)
+// and in h->cand.
 fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, float* ybuf, int cap,
-                             const fms_params* p, float thr, float tol, RoundOut& out, bool host_list) {
+                             const fms_params* p, float thr, float tol, RoundOut& out, bool host_list,
+                             const int* seed_fg = nullptr) {
   const int m = cap;  // upper bound; the round's seed count is meta[META_NSEL]
   int* meta = h->meta.as<int>();
   unsigned long long* meta64 = h->meta64.as<unsigned long long>();
   const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
-  const fms::Tiling& tl = bf16 ? fr.tile : fr.tile_fp32;
   const int pk = bf16 ? 1 : 0;
   const bool timing = p->timing != 0;
   HIP_TRY(fms::launch_round_begin(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>(), meta,
-                                  meta64));
+                                  meta64, seed_fg, h->x32.as<float>(), fr.dp, ybuf));
   int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
-  int t = 0, batch = 3;
+  float* yc[2] = {h->yc0.as<float>(), h->yc1.as<float>()};
+  // Iterations go out in batches; the host reads the counters back after
+  // each batch and stops enqueueing at the early stop.  Launches queued past
+  // the stop find the done flag and return at once.
+  // Batch sizes: most rounds of the 512x512 workload stop within 3 to 9
+  // iterations; 3, 6, 8 measured best among the schedules tried.
+  static constexpr int kSched[] = {3, 6, 8};
+  int t = 0, nbatch = 0;
+  int bound = m;  // active centres of the next iteration, at most
   while (t < p->max_iter) {
-    const int nb = std::min(batch, p->max_iter - t);
+    const int want_nb = kSched[std::min(nbatch, 2)];
+    ++nbatch;
+    const int nb = std::min(want_nb, p->max_iter - t);
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
+    const fms::Tiling& tl = pick_tiling(fr, bf16, bound);
     for (int i = 0; i < nb; ++i, ++t) {
       const fms::IterCtl ctl{meta, meta64, -1, t, fr.n, p->gamma};
-      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, tl, fr.geom.n_blocks, xrm, xt, ybuf, lists[t & 1], ctl, m, thr,
+      // Iteration 0 reads the centres in place (the active list is the
+      // identity); later iterations read the rows the previous reduce
+      // compacted in active-list order.
+      const float* yin = t == 0 ? ybuf : yc[t & 1];
+      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, tl, fr.geom.n_blocks, xrm, xt, yin, nullptr, ctl, m, thr,
                                 h->partial.as<float>(), timing ? h->events[2 * i] : nullptr,
                                 timing ? h->events[2 * i + 1] : nullptr));
       HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), lists[t & 1], ybuf,
-                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1], ctl, m, tol, 0));
+                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1], yc[(t + 1) & 1],
+                                 ctl, m, tol, 0));
     }
     HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
     if (timing) {
       for (int i = 0; i < nb; ++i) {
         float ms = 0.f;
@@ -390,12 +430,11 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
         out.step_launches[pk] += 1;
       }
     }
-    // The early stop of the next iteration, as its step kernel would take it.
+    // The early stop of the next iteration, as its step kernel takes it.
     const int* hm = h->hmeta;
-    if (hm[fms::META_DONE] || hm[fms::META_ACT + (t & 1)] <= 0 ||
-        (double)hm[fms::META_NCONV] > p->gamma * (double)hm[fms::META_NSEL])
+    bound = hm[fms::META_ACT + (t & 1)];
+    if (hm[fms::META_DONE] || bound <= 0 || (double)hm[fms::META_NCONV] > p->gamma * (double)hm[fms::META_NSEL])
       break;
-    batch = std::min(2 * batch, 8);
   }
   out.steps = h->hmeta[fms::META_STEPS];
   out.conv.clear();
@@ -406,7 +445,7 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
   HIP_TRY(hipMemcpyAsync(hs, h->state.p, size_t(msel), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hs + ((size_t(m) + 15) / 16) * 16, meta64, sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   unsigned long long upd = 0;
   std::memcpy(&upd, hs + ((size_t(m) + 15) / 16) * 16, sizeof(upd));
   out.updates = int64_t(upd);
@@ -417,14 +456,14 @@ fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, floa
   if (nc > 0) {
     std::memcpy(h->hstage, out.conv.data(), size_t(nc) * sizeof(int));
     HIP_TRY(hipMemcpyAsync(h->cand.p, h->hstage, size_t(nc) * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
   }
   return FMS_OK;
 }
 
 fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr,
-                          float tol, RoundOut& out, bool host_list) {
-  return run_iterations_on(h, st, fr, h->y.as<float>(), m, p, thr, tol, out, host_list);
+                          float tol, RoundOut& out, bool host_list, const int* seed_fg = nullptr) {
+  return run_iterations_on(h, st, fr, h->y.as<float>(), m, p, thr, tol, out, host_list, seed_fg);
 }
 
 // FP32 refinement (BF16 form) of the `a` centres y[list[0..a)]: `steps`
@@ -439,7 +478,7 @@ fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, c
                       RoundOut& out, std::vector<uint8_t>* out_keep) {
   if (a <= 0 || steps <= 0) return FMS_OK;
   int* meta = h->meta.as<int>();
-  const fms::Tiling& tl = fr.tile_fp32;
+  const fms::Tiling& tl = pick_tiling(fr, false, a);
   h->hmeta[fms::META_NACC] = a;
   HIP_TRY(hipMemcpyAsync(meta + fms::META_NACC, h->hmeta + fms::META_NACC, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
@@ -450,14 +489,14 @@ fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, c
                               h->partial.as<float>(), timing ? h->events[2 * r] : nullptr,
                               timing ? h->events[2 * r + 1] : nullptr));
     HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), list, y,
-                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, ctl, a, tol,
+                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, nullptr, ctl, a, tol,
                                r + 1 == steps ? 2 : 1));
     out.refine_steps += 1;
     out.refine_updates += int64_t(a) * int64_t(fr.n);
   }
   HIP_TRY(hipMemcpyAsync(h->hmeta + fms::META_REFINE_BAD, meta + fms::META_REFINE_BAD, sizeof(int),
                          hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   if (timing) {
     for (int r = 0; r < steps; ++r) {
       float ms = 0.f;
@@ -532,14 +571,15 @@ fms_status prune_inputs(fms_handle h, hipStream_t st, const Frame& fr, const flo
   fms_status stt = ensure_xfer(h, nc, k, x);
   if (stt != FMS_OK) return stt;
   if (with_counts)
-    HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(), y, list, nc, thr,
+    HIP_TRY(fms::launch_count(st, false, fr.dp, pick_tiling(fr, false, nc), fr.geom.n_blocks, fr.n, h->x32.p, y,
+                              list, nc, thr,
                               h->pcount.as<int>(), x.counts, nullptr, -1));
   HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c, nullptr, -1, -1));
   if (k > 0)
     HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, nullptr, h->modes.as<float>(), k, thr, x.bits_m, nullptr, -1,
                                 -1));
   HIP_TRY(hipMemcpyAsync(h->hstage, h->bits.p, x.bytes, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   xh = xfer_host(h, x, nc);
   return FMS_OK;
 }
@@ -600,6 +640,8 @@ fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
   h->device = device_ordinal;
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), (META_COUNT + 4) * sizeof(int), hipHostMallocDefault) !=
           hipSuccess ||
+      hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess ||
+
       h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess ||
       h->meta64.ensure(4 * sizeof(unsigned long long)) != hipSuccess) {
     fms_destroy(h);
@@ -614,12 +656,13 @@ fms_status fms_destroy(fms_handle h) {
   DeviceGuard guard(h->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&h->blk,   &h->fg_idx, &h->x32,     &h->x32t,        &h->x16,     &h->x16t,     &h->order,
-                    &h->rank, &h->elig, &h->y, &h->active, &h->next_active, &h->state, &h->iters,
+                    &h->rank, &h->elig, &h->y, &h->yc0, &h->yc1, &h->active, &h->next_active, &h->state, &h->iters,
                     &h->seed_pos, &h->seed_fg, &h->ident, &h->cand, &h->counts, &h->pcount, &h->partial,
                     &h->bits, &h->blocked, &h->acc, &h->sorted, &h->scount, &h->modes, &h->mode_counts, &h->meta, &h->meta64};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->hmeta) (void)hipHostFree(h->hmeta);
+  if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
   if (h->hstage) (void)hipHostFree(h->hstage);
   delete h;
   return FMS_OK;
@@ -660,7 +703,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   sx.n_fg = fr.n;
   HIP_TRY(fms::launch_fill_i32(st, labels, P, -1));
   if (fr.n == 0) {
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
     *n_modes = 0;
     sx.n_state_out = int32_t(std::min<int64_t>(n_seeds, std::numeric_limits<int32_t>::max()));
     if (stats) *stats = sx;
@@ -679,10 +722,8 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   HIP_TRY(h->elig.ensure(elig_bytes));
   uint64_t keys[4];
   round_keys(p->seed, keys);
-  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>(), h->rank.as<int>()));
-  HIP_TRY(hipMemsetAsync(h->elig.p, 0, elig_bytes, st));
-  HIP_TRY(hipMemsetAsync(h->elig.p, 1, size_t(n), st));
-  HIP_TRY(hipMemsetAsync(meta + META_CURSOR, 0, sizeof(int), st));
+  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>(), h->rank.as<int>(),
+                                 h->elig.as<uint8_t>(), int(elig_bytes), meta));
 
   int64_t n_used = 0;
   int k_modes = 0;
@@ -699,11 +740,12 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
     stt = grow_modes(h, st, fr, k_modes, want);
     if (stt != FMS_OK) return stt;
     HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->elig.as<uint8_t>(), n, want, meta, h->seed_pos.as<int>(),
-                               h->seed_fg.as<int>(), h->x32.as<float>(), fr.dp, h->y.as<float>()));
+                               h->seed_fg.as<int>()));
     RoundOut ro;
     const bool on_device = want <= fms::kRankMax;
-    stt = run_iterations(h, st, fr, want, p, thr, tol, ro, !on_device);
+    stt = run_iterations(h, st, fr, want, p, thr, tol, ro, !on_device, h->seed_fg.as<int>());
     if (stt != FMS_OK) return stt;
+    if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
     const int m = h->hmeta[META_NSEL];
     if (m == 0) break;
     n_used += m;
@@ -721,7 +763,10 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       stt = ensure_xfer(h, want, k_modes, x);
       if (stt != FMS_OK) return stt;
       HIP_TRY(fms::launch_collect(st, h->state.as<uint8_t>(), h->cand.as<int>(), meta));
-      HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(),
+      // Ranking counts in the precision of the iteration (the BF16 form
+      // recounts its refined modes in FP32 at the end of the frame).
+      HIP_TRY(fms::launch_count(st, bf16, fr.dp, pick_tiling(fr, bf16, want), fr.geom.n_blocks, fr.n,
+                                bf16 ? h->x16.p : h->x32.p,
                                 h->y.as<float>(), h->cand.as<int>(), m, thr, h->pcount.as<int>(), x.counts, meta,
                                 fms::META_NCAND));
       HIP_TRY(fms::launch_rank(st, h->cand.as<int>(), x.counts, meta, h->sorted.as<int>(), h->scount.as<int>()));
@@ -753,21 +798,20 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
           HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), x.counts,
                                            h->acc.as<int>(), accepted, h->modes.as<float>(), h->mode_counts.as<int>(),
                                            k_modes));
-          HIP_TRY(hipStreamSynchronize(st));
+          HIP_TRY(h->wait(st));
         }
       }
     }
     const bool acc_on_device = on_device;
     // Coverage by the new modes, and the pool left to seed; then one read of
     // the round's counters.
-    HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
     HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), k_modes,
                                k_modes + (acc_on_device ? want : accepted), acc_on_device ? fms::META_NACC : -1, thr,
                                0, h->elig.as<uint8_t>(), h->rank.as<int>(), meta, nullptr, nullptr));
     HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(h->hmeta + META_COUNT, h->meta64.p, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
     if (acc_on_device) accepted = h->hmeta[fms::META_NACC];
     if (on_device) {
       std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
@@ -831,7 +875,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
       HIP_TRY(hipMemcpyAsync(h->acc.p, hk, keep.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
                                      int(keep.size()), mrows, h->mode_counts.as<int>(), 0));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
     sx.refine_merged += int(ord.size()) - int(keep.size());
     sx.refine_steps += ro.refine_steps;
     sx.refine_unconverged += ro.refine_bad;
@@ -847,7 +891,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
                              nullptr, meta, h->fg_idx.as<int>(), labels));
   HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
   if (k_modes > k_max) {
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(h->wait(st));
     *n_modes = k_modes;
     return FMS_ERR_CAPACITY;
   }
@@ -855,7 +899,7 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
   if (mode_counts_out && k_modes > 0)
     HIP_TRY(hipMemcpyAsync(mode_counts_out, h->mode_counts.p, size_t(k_modes) * sizeof(int), hipMemcpyDeviceToDevice,
                            st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   *n_modes = k_modes;
   sx.n_uncovered = h->hmeta[META_LEFT];
   sx.n_min = have_nmin ? nmin : std::numeric_limits<double>::quiet_NaN();
@@ -897,8 +941,9 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   int* meta = h->meta.as<int>();
   HIP_TRY(hipMemsetAsync(meta + META_BADSEED, 0, sizeof(int), st));
   HIP_TRY(fms::launch_init_seeds(st, seed_fg, m, fr.n, h->x32.as<float>(), fr.dp, h->y.as<float>(), meta));
-  HIP_TRY(hipMemcpyAsync(h->hmeta + META_BADSEED, meta + META_BADSEED, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(h->wait(st));
+  if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   if (h->hmeta[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
   const float thr = float(1.0 - p->bandwidth);
   const float tol = float(tol_of(p));
@@ -914,11 +959,12 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   }
   // Window counts of every slot (the output keeps them for converged seeds).
   HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(st, fr.dp, fr.tile_fp32, fr.geom.n_blocks, fr.n, h->x32.as<float>(), h->y.as<float>(),
+  HIP_TRY(fms::launch_count(st, false, fr.dp, pick_tiling(fr, false, m), fr.geom.n_blocks, fr.n, h->x32.p,
+                            h->y.as<float>(),
                             h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>(), nullptr, -1));
   HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(h->wait(st));
   sx.iterations_total = ro.steps;
   sx.refine_steps = ro.refine_steps;
   sx.seed_pixel_updates = ro.updates;

@@ -62,21 +62,26 @@ struct FrameDesc {
 hipError_t launch_mask_count(hipStream_t s, const uint8_t* mask, int64_t n_pixels, int* block_counts,
                              int n_mask_blocks);
 hipError_t launch_scan_blocks(hipStream_t s, int* block_counts, int n_mask_blocks, int* meta);
+// Also zeroes the padding rows [n, n_pad) of every layout (n = meta[META_N]).
 hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_offsets, int n_mask_blocks,
                           int* fg_idx, float* x32, float* x32t, uint16_t* x16, uint16_t* x16t,
                           int* meta);
 constexpr int kMaskBlockPix = 1024;
 
 // order[j] = foreground ordinal at seed-order position j; rank = its inverse
-// (may be null).
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank);
+// (may be null).  With elig (may be null): elig[j] = 1 for j < n and 0 up to
+// elig_len, and meta[META_CURSOR] = 0.
+hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank,
+                             uint8_t* elig = nullptr, int elig_len = 0, int* meta = nullptr);
 
 hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
-                         int* seed_fg, const float* x32, int dp, float* y);
+                         int* seed_fg);
 hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, const float* x32, int dp,
                              float* y, int* meta);
+// Start of a round's iteration (identity active list, counters); with
+// seed_fg (may be null) the centres are also loaded from the pixel rows.
 hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
-                              unsigned long long* meta64);
+                              unsigned long long* meta64, const int* seed_fg, const float* x32, int dp, float* y);
 struct StepGeom {
   int n;             // foreground count
   int n_blocks;      // ceil(n / 32)
@@ -102,20 +107,25 @@ struct IterCtl {
   double gamma;
 };
 // One fused mean-shift step for the active seeds (at most cap): partial
-// window sums per pixel chunk.  ev0/ev1 (may be null) receive the start and
-// end of the kernel itself (hipExtLaunchKernel), not of the launch call.
+// window sums per pixel chunk.  Centre a is y[active[a]], or y[a] when
+// active is null (rows already compacted).  ev0/ev1 (may be null) receive
+// the start and end of the kernel itself (hipExtLaunchKernel), not of the
+// launch call.
 size_t shift_partial_rows(const Tiling& t, int cap);
 hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, const void* xrm,
                         const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap, float thr,
                         float* partial, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Sum partials, renormalise, convergence test and (mode 0) the next active
-// list and converged count.
+// list and converged count.  yc_next (mode 0, may be null) receives the new
+// rows of the seeds that stay active, in next-list order.
 hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         const IterCtl& ctl, int cap, float tol, int mode);
-// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres (FP32 MFMA);
-// with m_slot >= 0 the count is meta[m_slot] (m is then an upper bound).
-hipError_t launch_count(hipStream_t s, int dp, const Tiling& t, int n_blocks, int n_pix, const float* x32,
+                         float* yc_next, const IterCtl& ctl, int cap, float tol, int mode);
+// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres, on FP32 MFMA
+// (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the BF16 rows; the centres
+// are rounded to BF16); with m_slot >= 0 the count is meta[m_slot] (m is
+// then an upper bound).
+hipError_t launch_count(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, int n_pix, const void* xrm,
                         const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
                         int m_slot);
 // Similarity bits between the rows y[rows[0..m)] and the columns y[cols[c]]

@@ -196,6 +196,22 @@ __global__ __launch_bounds__(256) void k_compact(FrameDesc f, const int* __restr
     ++ord;
   }
   if (bad) atomicAdd(meta + META_BAD, bad);
+  // The rows from n up to the next multiple of 32 are padding: zero in every
+  // layout, so they add nothing to any sum.
+  if (blockIdx.x == 0) {
+    const int n = meta[META_N];
+    const int pad = (kBlockPix - n % kBlockPix) % kBlockPix;
+    for (int e = threadIdx.x; e < pad * DP; e += 256) {
+      const int64_t row = n + e / DP, d = e % DP;
+      const int64_t blk = row / kBlockPix, q = row % kBlockPix;
+      x32[row * DP + d] = 0.f;
+      x32t[(blk * DP + d) * kBlockPix + q] = 0.f;
+      if (x16) {
+        x16[row * DP + d] = 0;
+        x16t[(blk * DP + d) * kBlockPix + q] = 0;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ seed order
@@ -207,8 +223,14 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, uint64_t k1, uint64_t k2,
-                                                    uint64_t k3, int* __restrict__ order, int* __restrict__ rank) {
+                                                    uint64_t k3, int* __restrict__ order, int* __restrict__ rank,
+                                                    uint8_t* __restrict__ elig, int elig_len,
+                                                    int* __restrict__ meta) {
   const int j = blockIdx.x * 256 + threadIdx.x;
+  // Start of a frame's seeding: every position eligible, the tail padding
+  // not, the cursor at 0.
+  if (elig && j < elig_len) elig[j] = j < n ? 1 : 0;
+  if (meta && j == 0) meta[META_CURSOR] = 0;
   if (j >= n) return;
   const uint64_t mask = (1ull << b) - 1;
   const uint64_t keys[4] = {k0, k1, k2, k3};
@@ -232,15 +254,14 @@ __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, u
 
 // One 1024-thread block: take the first `want` positions of the seed order
 // (from the cursor on) that are still eligible (elig[pos] = 1: the pixel is
-// neither covered by a mode nor used as a seed), clear them, and load their
-// vectors as the round's starting centres.  Each pass reads 16 consecutive
+// neither covered by a mode nor used as a seed) and clear them; their
+// vectors are loaded by the round's first kernel.  Each pass reads 16 consecutive
 // eligibility bytes per thread with one 16-byte load (16384 positions per
 // pass).  Positions before the cursor are all ineligible, so a pass may start
 // at the cursor rounded down to 16; `elig` is zero-padded to a multiple of 16.
 __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order, uint8_t* __restrict__ elig, int n,
                                                  int want, int* __restrict__ meta, int* __restrict__ seed_pos,
-                                                 int* __restrict__ seed_fg, const float* __restrict__ x32, int dp,
-                                                 float* __restrict__ y) {
+                                                 int* __restrict__ seed_fg) {
   constexpr int RUN = 16;
   __shared__ int sh[17];
   __shared__ int s_last;
@@ -283,11 +304,6 @@ __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order, 
       base += 1024 * RUN;
     }
     __syncthreads();
-  }
-  // Load the starting centres.
-  for (int k = threadIdx.x; k < got * dp; k += 1024) {
-    int s = k / dp, d = k - s * dp;
-    y[(int64_t)s * dp + d] = x32[(int64_t)seed_fg[s] * dp + d];
   }
   if (threadIdx.x == 0) {
     meta[META_NSEL] = got;
@@ -348,9 +364,9 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 // FP32 accumulation; the 0/1 weights of two pixels are packed into one BF16
 // pair with one v_perm_b32 (sign bytes) and one bit-select.
 //
-// COUNT form (FP32 only): the same S^T tiles, no second product; each item
-// writes the per-seed number of its pixels inside the window (window counts
-// at the centres, used to rank candidate modes).
+// COUNT form: the same S^T tiles, no second product; each item writes the
+// per-seed number of its pixels inside the window (window counts at the
+// centres, used to rank candidate modes).
 template <bool BF16, bool COUNT, int DP, int ST>
 __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
                                            const float* __restrict__ y, const int* __restrict__ active, int n_act,
@@ -364,7 +380,6 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   const T* __restrict__ xrm = static_cast<const T*>(xrm_);
   const T* __restrict__ xt = static_cast<const T*>(xt_);
 
-  static_assert(!(BF16 && COUNT), "window counts are taken in FP32");
   const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int items = cp.groups * cp.n_chunks;
 
@@ -381,13 +396,61 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   const int lo = (int)((int64_t)items * xcd / 8), hi = (int)((int64_t)items * (xcd + 1) / 8);
   for (int it = lo + (wg >> 3); it < hi; it += per) {
     const int chunk = it / cp.groups, grp = it - chunk * cp.groups;
+    const int b0 = chunk * cp.chunk_blocks;
+    const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
+    // Register operands of one block: rows for S (two 16-pixel tiles) and the
+    // dimension-major copy for V.  Double-buffered: block b+4 loads while b
+    // computes.
+    AOp xa[2][2][KS];
+    AOp xv[2][NDB][BF16 ? 1 : 8];
+    auto load = [&](int buf, int b) {
+      if constexpr (BF16) {
+        const uint16_t* xb = reinterpret_cast<const uint16_t*>(xrm) + (int64_t)b * kBlockPix * DP;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int j = 0; j < KS; ++j)
+            xa[buf][t][j] = *reinterpret_cast<const bf16x8*>(xb + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
+#pragma unroll
+        for (int db = 0; db < (COUNT ? 0 : NDB); ++db)
+          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) +
+                                                            ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+      } else {
+        const float* xb = reinterpret_cast<const float*>(xrm) + (int64_t)b * kBlockPix * DP;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const float4* xr = reinterpret_cast<const float4*>(xb + (rowsel0 + 4 * t) * DP + g * KJ);
+#pragma unroll
+          for (int j = 0; j < KJ / 4; ++j) {
+            float4 u = xr[j];
+            xa[buf][t][4 * j] = u.x;
+            xa[buf][t][4 * j + 1] = u.y;
+            xa[buf][t][4 * j + 2] = u.z;
+            xa[buf][t][4 * j + 3] = u.w;
+          }
+        }
+#pragma unroll
+        for (int db = 0; db < (COUNT ? 0 : NDB); ++db) {
+          const float4* tp = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(xt) +
+                                                             ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+          float4 u = tp[0], v = tp[1];
+          xv[buf][db][0] = u.x; xv[buf][db][1] = u.y; xv[buf][db][2] = u.z; xv[buf][db][3] = u.w;
+          xv[buf][db][4] = v.x; xv[buf][db][5] = v.y; xv[buf][db][6] = v.z; xv[buf][db][7] = v.w;
+        }
+      }
+    };
+    // The first pixel block is requested before the seeds: the two loads
+    // overlap instead of queueing behind each other.
+    int b = b0 + wave;
+    if (b < b1) load(0, b);
     const int a0 = grp * 16 * ST;
     // Seed operands (B of S^T = X Y^T).
     AOp yb[ST][KS];
 #pragma unroll
     for (int s = 0; s < ST; ++s) {
       const int a = a0 + 16 * s + r;
-      const float* yr = a < n_act ? y + (int64_t)active[a] * DP + g * KJ : nullptr;
+      const float* yr =
+          a < n_act ? y + (int64_t)(active ? active[a] : a) * DP + g * KJ : nullptr;
       if constexpr (BF16) {
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
@@ -416,49 +479,6 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
       for (int db = 0; db < NDB; ++db) acc[s][db] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 
-    const int b0 = chunk * cp.chunk_blocks;
-    const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
-    // Register operands of one block: rows for S (two 16-pixel tiles) and the
-    // dimension-major copy for V.  Double-buffered: block b+4 loads while b
-    // computes.
-    AOp xa[2][2][KS];
-    AOp xv[2][NDB][BF16 ? 1 : 8];
-    auto load = [&](int buf, int b) {
-      if constexpr (BF16) {
-        const uint16_t* xb = reinterpret_cast<const uint16_t*>(xrm) + (int64_t)b * kBlockPix * DP;
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int j = 0; j < KS; ++j)
-            xa[buf][t][j] = *reinterpret_cast<const bf16x8*>(xb + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
-#pragma unroll
-        for (int db = 0; db < NDB; ++db)
-          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) +
-                                                            ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
-      } else {
-        const float* xb = reinterpret_cast<const float*>(xrm) + (int64_t)b * kBlockPix * DP;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const float4* xr = reinterpret_cast<const float4*>(xb + (rowsel0 + 4 * t) * DP + g * KJ);
-#pragma unroll
-          for (int j = 0; j < KJ / 4; ++j) {
-            float4 u = xr[j];
-            xa[buf][t][4 * j] = u.x;
-            xa[buf][t][4 * j + 1] = u.y;
-            xa[buf][t][4 * j + 2] = u.z;
-            xa[buf][t][4 * j + 3] = u.w;
-          }
-        }
-#pragma unroll
-        for (int db = 0; db < (COUNT ? 0 : NDB); ++db) {
-          const float4* tp = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(xt) +
-                                                             ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
-          float4 u = tp[0], v = tp[1];
-          xv[buf][db][0] = u.x; xv[buf][db][1] = u.y; xv[buf][db][2] = u.z; xv[buf][db][3] = u.w;
-          xv[buf][db][4] = v.x; xv[buf][db][5] = v.y; xv[buf][db][6] = v.z; xv[buf][db][7] = v.w;
-        }
-      }
-    };
     auto compute = [&](int buf, int b) {
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
@@ -473,7 +493,14 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
             s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[buf][1][j], yb[s][j], s1, 0, 0, 0);
           }
         }
-        if constexpr (BF16) {
+        if constexpr (COUNT) {
+          const int pbase = b * kBlockPix + 8 * g;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            cnt[s] += ((fbits(s0[i]) >> 31) == 0u && pbase + i < n_pix) ? 1 : 0;
+            cnt[s] += ((fbits(s1[i]) >> 31) == 0u && pbase + 4 + i < n_pix) ? 1 : 0;
+          }
+        } else if constexpr (BF16) {
           // Pixels 8g..8g+3 come from tile 0, 8g+4..8g+7 from tile 1.
           uint32_t m0 = __builtin_amdgcn_perm(fbits(s0[1]), fbits(s0[0]),
                                               0x0B0B0909u);
@@ -490,13 +517,6 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 #pragma unroll
           for (int db = 0; db < NDB; ++db)
             acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[buf][db][0], w, acc[s][db], 0, 0, 0);
-        } else if constexpr (COUNT) {
-          const int pbase = b * kBlockPix + 8 * g;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            cnt[s] += ((fbits(s0[i]) >> 31) == 0u && pbase + i < n_pix) ? 1 : 0;
-            cnt[s] += ((fbits(s1[i]) >> 31) == 0u && pbase + 4 + i < n_pix) ? 1 : 0;
-          }
         } else {
           float w[8];
 #pragma unroll
@@ -512,8 +532,6 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    int b = b0 + wave;
-    if (b < b1) load(0, b);
     for (; b < b1; b += 8) {
       if (b + 4 < b1) load(1, b + 4);
       compute(0, b);
@@ -623,8 +641,9 @@ template <int DP>
 __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, const int* __restrict__ active,
                                            float* __restrict__ y, uint8_t* __restrict__ state,
                                            int* __restrict__ iters, int* __restrict__ next_active,
-                                           int* __restrict__ next_ctr, int* __restrict__ refine_bad, int n_act,
-                                           const Tiling& tl, int n_blocks, float tol, int mode, int wg, int nwg) {
+                                           float* __restrict__ yc_next, int* __restrict__ next_ctr,
+                                           int* __restrict__ refine_bad, int n_act, const Tiling& tl, int n_blocks,
+                                           float tol, int mode, int wg, int nwg) {
   constexpr int Q = DP / 4;  // float4 slices per row
   __shared__ float4 part[256];
   __shared__ int s_conv;
@@ -643,6 +662,12 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
   for (int tile = wg; tile < tiles; tile += nwg) {
     const int a = tile * spw + sl;
     const bool live_seed = a < n_act && sl < spw;
+    const bool owner = live_seed && ph == 0;
+    // The centre's slot and its current row do not depend on the partials:
+    // request them first.
+    const int slot = owner ? active[a] : 0;
+    float4 yo = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (owner) yo = *reinterpret_cast<const float4*>(y + (int64_t)slot * DP + 4 * q);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live_seed) {
       const float4* src = reinterpret_cast<const float4*>(partial + (int64_t)a * DP + 4 * q);
@@ -665,7 +690,6 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     part[tid] = acc;
     __syncthreads();
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    const bool owner = live_seed && ph == 0;
     if (owner) {
       for (int pp = 0; pp < P; ++pp) {
         const float4 u = part[sl * tpr + pp * Q + q];
@@ -681,9 +705,6 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     const float nv = sqrtf(ss);
     const bool dead = !(nv > 0.f) || !__builtin_isfinite(nv);
     const float inv = dead ? 0.f : 1.0f / nv;
-    const int slot = owner ? active[a] : 0;
-    float4 yo = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (owner) yo = *reinterpret_cast<const float4*>(y + (int64_t)slot * DP + 4 * q);
     const float4 yn = make_float4(v.x * inv, v.y * inv, v.z * inv, v.w * inv);
     float dd = (yo.x - yn.x) * (yo.x - yn.x) + (yo.y - yn.y) * (yo.y - yn.y) + (yo.z - yn.z) * (yo.z - yn.z) +
                (yo.w - yn.w) * (yo.w - yn.w);
@@ -706,7 +727,15 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
       int base = 0;
       if (lane == 0 && bn) base = atomicAdd(next_ctr, __popcll(bn));
       base = __shfl(base, 0, 64);
-      if (next) next_active[base + __popcll(bn & ((1ull << lane) - 1ull))] = slot;
+      const int pos = base + __popcll(bn & ((1ull << lane) - 1ull));
+      if (next) next_active[pos] = slot;
+      if (yc_next) {
+        // The seed's owner lanes copy its new row to its place in the
+        // compacted rows of the next iteration (position from the head lane).
+        const int hpos = __shfl(pos, lane - q, 64);
+        const int hnext = __shfl(next ? 1 : 0, lane - q, 64);
+        if (owner && hnext) *reinterpret_cast<float4*>(yc_next + (int64_t)hpos * DP + 4 * q) = yn;
+      }
       if (lane == 0 && bc) atomicAdd(&s_conv, __popcll(bc));
     } else if (head) {
       if (dead) state[slot] = 2;
@@ -720,8 +749,9 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
 template <int DP>
 __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const int* __restrict__ active,
                                                 float* __restrict__ y, uint8_t* __restrict__ state,
-                                                int* __restrict__ iters, int* __restrict__ next_active, IterCtl ctl,
-                                                int n_host, int n_blocks, Tiling tl, float tol, int mode) {
+                                                int* __restrict__ iters, int* __restrict__ next_active,
+                                                float* __restrict__ yc_next, IterCtl ctl, int n_host, int n_blocks,
+                                                Tiling tl, float tol, int mode) {
   int* meta = ctl.meta;
   int n_act;
   int* next_ctr = nullptr;
@@ -732,8 +762,9 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
   } else {
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : n_host;
   }
-  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, next_ctr, meta + META_REFINE_BAD,
-                                   n_act, tl, n_blocks, tol, mode, (int)blockIdx.x, (int)gridDim.x);
+  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, yc_next, next_ctr,
+                                   meta + META_REFINE_BAD, n_act, tl, n_blocks, tol, mode, (int)blockIdx.x,
+                                   (int)gridDim.x);
   if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
 }
 
@@ -751,21 +782,32 @@ __global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ p
   if (lane == 0) counts[a] = c;
 }
 
-// Start of a round: the selected seeds become the active list.
+// Start of a round: the selected seeds become the active list.  With
+// seed_fg, centre k also starts at pixel row seed_fg[k] of x32.
+template <int DP>
 __global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ active, uint8_t* __restrict__ state,
                                                      int* __restrict__ iters, int* __restrict__ meta,
-                                                     unsigned long long* __restrict__ meta64) {
+                                                     unsigned long long* __restrict__ meta64,
+                                                     const int* __restrict__ seed_fg, const float* __restrict__ x32,
+                                                     float* __restrict__ y) {
   const int m = meta[META_NSEL];
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < m && k < cap) {
     active[k] = k;
     state[k] = 0;
     iters[k] = 0;
+    if (seed_fg) {
+      const float4* src = reinterpret_cast<const float4*>(x32 + (int64_t)seed_fg[k] * DP);
+      float4* dst = reinterpret_cast<float4*>(y + (int64_t)k * DP);
+#pragma unroll
+      for (int q = 0; q < DP / 4; ++q) dst[q] = src[q];
+    }
   }
   if (k == 0) {
     meta[META_ACT] = m;
     meta[META_ACT + 1] = 0;
     meta[META_NCONV] = 0;
+    meta[META_LEFT] = 0;  // the round's coverage counts the pixels left to seed
     meta[META_DONE] = m > 0 ? 0 : 1;
     meta[META_STEPS] = 0;
     meta64[0] = 0;
@@ -1104,16 +1146,18 @@ hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_of
   return hipGetLastError();
 }
 
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank) {
+hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank,
+                             uint8_t* elig, int elig_len, int* meta) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_seed_order, dim3(cdiv(n, 256)), dim3(256), 0, s, n, half_bits, keys[0], keys[1], keys[2],
-                     keys[3], order, rank);
+  const int span = std::max(n, elig ? elig_len : 0);
+  hipLaunchKernelGGL(k_seed_order, dim3(cdiv(span, 256)), dim3(256), 0, s, n, half_bits, keys[0], keys[1], keys[2],
+                     keys[3], order, rank, elig, elig_len, meta);
   return hipGetLastError();
 }
 
 hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
-                         int* seed_fg, const float* x32, int dp, float* y) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, order, elig, n, want, meta, seed_pos, seed_fg, x32, dp, y);
+                         int* seed_fg) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, order, elig, n, want, meta, seed_pos, seed_fg);
   return hipGetLastError();
 }
 
@@ -1175,8 +1219,12 @@ static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
 }
 
 #define FMS_SHIFT_CASE(BFV, CNT, DPV, STV)                                                                       \
-  hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, ev0, ev1, 0, xrm, xt, y, active, \
-                        ctl, n_host, t, n_blocks, n_pix, thr, partial, pcount)
+  if (ev0 || ev1)                                                                                            \
+    hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, ev0, ev1, 0, xrm, xt, y,    \
+                          active, ctl, n_host, t, n_blocks, n_pix, thr, partial, pcount);                       \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, xrm, xt, y, active, ctl, n_host, \
+                       t, n_blocks, n_pix, thr, partial, pcount)
 
 static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, const Tiling& t, int n_blocks,
                                  int n_pix, const void* xrm, const void* xt, const float* y, const int* active,
@@ -1203,6 +1251,12 @@ static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, c
     case 106401: FMS_SHIFT_CASE(false, true, 64, 1); break;
     case 106402: FMS_SHIFT_CASE(false, true, 64, 2); break;
     case 112801: FMS_SHIFT_CASE(false, true, 128, 1); break;
+    case 1103202: FMS_SHIFT_CASE(true, true, 32, 2); break;
+    case 1103204: FMS_SHIFT_CASE(true, true, 32, 4); break;
+    case 1106402: FMS_SHIFT_CASE(true, true, 64, 2); break;
+    case 1106404: FMS_SHIFT_CASE(true, true, 64, 4); break;
+    case 1112801: FMS_SHIFT_CASE(true, true, 128, 1); break;
+    case 1112802: FMS_SHIFT_CASE(true, true, 128, 2); break;
     case 1003202: FMS_SHIFT_CASE(true, false, 32, 2); break;
     case 1003204: FMS_SHIFT_CASE(true, false, 32, 4); break;
     case 1003208: FMS_SHIFT_CASE(true, false, 32, 8); break;
@@ -1226,7 +1280,7 @@ hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n
 
 hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         const IterCtl& ctl, int cap, float tol, int mode) {
+                         float* yc_next, const IterCtl& ctl, int cap, float tol, int mode) {
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
@@ -1236,8 +1290,8 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, c
   const int spw = std::max(1, 256 / ((dp / 4) * P));
   const dim3 grid(cdiv(cap, spw)), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                     \
-  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, ctl, cap,    \
-                     n_blocks, t, tol, mode)
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, yc_next,   \
+                     ctl, cap, n_blocks, t, tol, mode)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
@@ -1248,12 +1302,12 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, c
   return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t s, int dp, const Tiling& t, int n_blocks, int n_pix, const float* x32,
+hipError_t launch_count(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, int n_pix, const void* xrm,
                         const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
                         int m_slot) {
   if (m <= 0 || n_blocks <= 0) return hipSuccess;
   const IterCtl ctl{const_cast<int*>(meta), nullptr, m_slot, -1, 0, 0.0};
-  hipError_t e = shift_dispatch(s, false, true, dp, t, n_blocks, n_pix, x32, nullptr, y, list, ctl, m, m, thr, nullptr,
+  hipError_t e = shift_dispatch(s, bf16, true, dp, t, n_blocks, n_pix, xrm, nullptr, y, list, ctl, m, m, thr, nullptr,
                                 pcount, nullptr, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, n_blocks, t, meta, m_slot,
@@ -1301,9 +1355,22 @@ hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows
 }
 
 hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
-                              unsigned long long* meta64) {
-  hipLaunchKernelGGL(k_round_begin, dim3(cdiv(std::max(cap, 1), 256)), dim3(256), 0, s, cap, active, state, iters,
-                     meta, meta64);
+                              unsigned long long* meta64, const int* seed_fg, const float* x32, int dp, float* y) {
+  const dim3 grid(cdiv(std::max(cap, 1), 256)), block(256);
+  switch (dp) {
+    case 32:
+      hipLaunchKernelGGL(k_round_begin<32>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32, y);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_round_begin<64>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32, y);
+      break;
+    case 128:
+      hipLaunchKernelGGL(k_round_begin<128>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32,
+                         y);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
