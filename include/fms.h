@@ -152,6 +152,47 @@ fms_status fms_cluster(fms_handle h, void* stream,
                        float* modes, int32_t* mode_counts, int32_t k_max, int32_t* n_modes,
                        int32_t* labels, fms_stats* stats);
 
+/* One frame of a batch (host struct; the pointers are device pointers). */
+typedef struct {
+  const float* emb;          /* device, FP32, (pixel p, channel c) at
+                                emb[p*pixel_stride + c*channel_stride] */
+  int64_t pixel_stride;
+  int64_t channel_stride;
+  const uint8_t* mask;       /* device, height*width bytes (nonzero = foreground),
+                                or NULL = all pixels */
+  int32_t height, width;     /* >= 1 each */
+  double bandwidth;          /* this frame's h, 0 < h < 2 */
+  int32_t n_state_in;        /* this frame's N carried over from its previous
+                                frame; <= 0: fms_params.n_initial */
+  int32_t* labels;           /* device, height*width int32 output: -1 on
+                                background, else the index of the most similar
+                                of this frame's modes (lowest on ties) */
+} fms_frame;
+
+/* Cluster a batch of frames of one embedding width (Alg. 2 under the online
+ * seed optimisation policy, each frame on its own).  Every launch covers all
+ * frames, so many small frames cost little more than one; each frame's
+ * result is the one fms_cluster returns for it alone.
+ *
+ *  n_frames       >= 1; frames: host array of n_frames entries.
+ *  dim            D (1..128), shared by the frames.
+ *  p              host; every field but bandwidth and n_state_in (taken per
+ *                 frame) applies to all frames.
+ *  modes          device, k_max*dim FP32: the frames' modes, packed: frame
+ *                 f's are rows mode_offsets[f] .. mode_offsets[f+1]-1, in
+ *                 acceptance order.
+ *  mode_counts    device, k_max int32 window counts of the modes, or NULL.
+ *  mode_offsets   host, n_frames+1 int32 (output); on CAPACITY
+ *                 mode_offsets[n_frames] is the required total.
+ *  stats          host, n_frames entries, or NULL.  The kernel-timing fields
+ *                 describe the whole call and are filled in stats[0] only.
+ * A round that needs more than 8192 seeds in one frame is UNSUPPORTED in a
+ * batch of two or more frames.
+ * Errors: INVALID_ARG, UNSUPPORTED, BAD_INPUT, CAPACITY, HIP. */
+fms_status fms_cluster_batch(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames,
+                             int32_t dim, const fms_params* p, float* modes, int32_t* mode_counts,
+                             int32_t k_max, int32_t* mode_offsets, fms_stats* stats);
+
 /* One round of the parallel seed iteration (Alg. 2, the loop over seeds, with
  * the early stop of Sec. 3.2.3) on an explicit seed list, for lockstep checks
  * and benchmarking of the hot loop.

@@ -20,7 +20,8 @@ from typing import Dict, Optional
 
 from . import _binding as B
 
-__all__ = ["Params", "FmsError", "cluster", "shift_seeds", "seed_order", "default_params", "library"]
+__all__ = ["Params", "FmsError", "cluster", "cluster_batch", "shift_seeds", "seed_order", "default_params",
+           "library"]
 
 FP32 = B.FMS_PREC_FP32
 BF16_REFINE = B.FMS_PREC_BF16_REFINE
@@ -167,6 +168,68 @@ def cluster(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str = 
     out = stats.as_dict()
     out["mode_counts"] = counts[:k]
     return modes[:k], labels, out
+
+
+def cluster_batch(frames, *, layout: str = "nhwc", params: Optional[Params] = None, k_max: int = 0, **kw):
+    """Cluster a batch of frames of one embedding width D in one call
+    (fms_cluster_batch).  ``frames``: sequence of dicts with ``emb`` (GPU
+    float32, (H, W, D) or (D, H, W) per ``layout``), ``mask`` (GPU (H, W) or
+    None), ``bandwidth`` and optionally ``n_state_in``.  Returns a list of
+    (modes [K_f, D], labels [H, W], stats dict with ``mode_counts``) per frame."""
+    import torch
+    p = _params(params, kw)
+    frames = list(frames)
+    if not frames:
+        return []
+    lib = library()
+    cframes = (B.FmsFrame * len(frames))()
+    keep = []
+    dev = None
+    d0 = None
+    outs = []
+    for i, fr in enumerate(frames):
+        emb, h, w, d, ps, cs = _frame_args(fr["emb"], layout)
+        if d0 is None:
+            d0, dev = d, emb.device
+        elif d != d0 or emb.device != dev:
+            raise ValueError("every frame of a batch needs the same D and device")
+        m, mptr = _mask_arg(fr.get("mask"), h, w, dev)
+        labels = torch.empty((h, w), dtype=torch.int32, device=dev)
+        keep += [emb, m, labels]
+        cf = cframes[i]
+        cf.emb = emb.data_ptr()
+        cf.pixel_stride, cf.channel_stride = ps, cs
+        cf.mask = mptr if mptr else None
+        cf.height, cf.width = h, w
+        cf.bandwidth = float(fr["bandwidth"])
+        cf.n_state_in = int(fr.get("n_state_in", 0))
+        cf.labels = labels.data_ptr()
+        outs.append(labels)
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    cp = p.to_c()
+    n = len(frames)
+    k_max = max(k_max, 256 * n)
+    while True:
+        modes = torch.empty((k_max, d0), dtype=torch.float32, device=dev)
+        counts = torch.empty((k_max,), dtype=torch.int32, device=dev)
+        offs = (ctypes.c_int32 * (n + 1))()
+        stats = (B.FmsStats * n)()
+        st = lib.fms_cluster_batch(hdl, _stream_ptr(dev), n, cframes, d0, ctypes.byref(cp),
+                                   ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()), k_max,
+                                   offs, stats)
+        if st == B.FMS_ERR_CAPACITY and offs[n] > k_max:
+            k_max = offs[n]
+            continue
+        if st != B.FMS_OK:
+            raise FmsError(st, "fms_cluster_batch")
+        break
+    res = []
+    for i in range(n):
+        a, b = offs[i], offs[i + 1]
+        sd = stats[i].as_dict()
+        sd["mode_counts"] = counts[a:b]
+        res.append((modes[a:b], outs[i], sd))
+    return res
 
 
 def shift_seeds(emb, mask, seeds, *, layout: str = "nhwc", params: Optional[Params] = None, **kw):

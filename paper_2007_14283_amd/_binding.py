@@ -18,8 +18,8 @@ FMS_PREC_FP32 = 0
 FMS_PREC_BF16_REFINE = 1
 
 # Every entry point declared in include/fms.h.
-EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_shift_seeds",
-           "fms_seed_order", "fms_status_string")
+EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",
+           "fms_shift_seeds", "fms_seed_order", "fms_status_string")
 
 
 class FmsParams(ctypes.Structure):
@@ -41,6 +41,20 @@ class FmsParams(ctypes.Structure):
         ("tile_seeds", ctypes.c_int32),
         ("tile_items", ctypes.c_int32),
         ("tile_chunks", ctypes.c_int32),
+    ]
+
+
+class FmsFrame(ctypes.Structure):
+    _fields_ = [
+        ("emb", ctypes.c_void_p),
+        ("pixel_stride", ctypes.c_int64),
+        ("channel_stride", ctypes.c_int64),
+        ("mask", ctypes.c_void_p),
+        ("height", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("bandwidth", ctypes.c_double),
+        ("n_state_in", ctypes.c_int32),
+        ("labels", ctypes.c_void_p),
     ]
 
 
@@ -97,6 +111,9 @@ def load(path: str = LIB_PATH):
     lib.fms_cluster.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, ctypes.POINTER(FmsParams),
                                 vp, vp, i32, ctypes.POINTER(i32), vp, ctypes.POINTER(FmsStats)]
     lib.fms_cluster.restype = ctypes.c_int
+    lib.fms_cluster_batch.argtypes = [vp, vp, i32, ctypes.POINTER(FmsFrame), i32, ctypes.POINTER(FmsParams),
+                                      vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(FmsStats)]
+    lib.fms_cluster_batch.restype = ctypes.c_int
     lib.fms_shift_seeds.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, vp, i32,
                                     ctypes.POINTER(FmsParams), vp, vp, vp, vp, ctypes.POINTER(FmsStats)]
     lib.fms_shift_seeds.restype = ctypes.c_int

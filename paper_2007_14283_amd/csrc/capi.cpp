@@ -3,8 +3,12 @@
 // (Sec. 3.2.2-3.2.4) and the C ABI declared in include/fms.h.
 //
 // The CPU steers the seed count and the GPU iterates the seeds (Fig. 3): the
-// host reads a few counters back after each GPU step (iteration, round) and
-// decides what to launch next.
+// host reads a few counters back after each batch of GPU steps and after
+// each round, and decides what to launch next.  Every call works on a batch
+// of F >= 1 frames: each launch covers all of them (the frame is the second
+// grid dimension), each frame keeps its own counters and OSOP state, and the
+// rounds of the frames run in lockstep.  A single-frame call is a batch of
+// one.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -17,15 +21,18 @@
 
 namespace {
 
+using fms::kMeta64;
 using fms::META_BAD;
 using fms::META_BADSEED;
 using fms::META_COUNT;
-using fms::META_CURSOR;
 using fms::META_LEFT;
 using fms::META_N;
+using fms::META_NACC;
+using fms::META_NCAND;
 using fms::META_NCONV;
 using fms::META_NSEL;
 using fms::META_REFINE_BAD;
+using fms::META_STEPS;
 
 struct DevBuf {
   void* p = nullptr;
@@ -47,29 +54,37 @@ struct DevBuf {
     cap = want;
     return hipSuccess;
   }
-  // Grow like ensure(), keeping the first `keep` bytes (the old buffer is
-  // copied on `st` and freed once the copy has finished).
-  hipError_t grow_keep(size_t bytes, size_t keep, hipStream_t st) {
-    if (bytes <= cap) return hipSuccess;
-    size_t want = std::max<size_t>(bytes + bytes / 2, 4096);
-    void* np = nullptr;
-    hipError_t e = hipMalloc(&np, want);
-    if (e != hipSuccess) return e;
-    if (p && keep > 0) {
-      e = hipMemcpyAsync(np, p, std::min(keep, cap), hipMemcpyDeviceToDevice, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) {
-        (void)hipFree(np);
-        return e;
-      }
-    }
+  void release() {
     if (p) (void)hipFree(p);
-    p = np;
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Pinned host buffer that grows on demand (contents are not kept).
+struct PinBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
     cap = want;
     return hipSuccess;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
   }
@@ -128,18 +143,29 @@ struct DeviceGuard {
   }
 };
 
+// Launches with at least kBigGroupMin centres per frame use seed groups of
+// kBigGroup (where compiled): on the 512x512, D = 32 workload a 64-seed group
+// is about 20% faster than a 32-seed one from 1,024 centres on, and no
+// slower at 256.
+constexpr int kBigGroup = 64;
+constexpr int kBigGroupMin = 512;
+
 }  // namespace
 
 struct fms_handle_s {
   int device = 0;
-  // Frame data.
+  // Pixel data of the call's frames; every row-indexed buffer holds frame f
+  // from row geo[f].row0 on.
   DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig;
-  // Round data.
-  DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, pcount, partial;
-  DevBuf bits, blocked, acc, sorted, scount;
-  // Modes found so far.
+  // Centres of a round, their lists and flags, window counts and ranking.
+  DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, sorted, scount;
+  DevBuf pcount, partial;
+  // Similarity bits of the pruning passes (all frames), accepted list.
+  DevBuf bits, acc;
+  // Modes found so far (rows of frame f from geo[f].row0 on).
   DevBuf modes, mode_counts;
-  DevBuf meta, meta64;
+  // Per-frame counters and tables.
+  DevBuf meta, meta64, geo, rt, out_off;
   // Event pairs for timing fused-step launches (created on first use).
   std::vector<hipEvent_t> events;
   hipError_t ensure_events(size_t count) {
@@ -151,65 +177,77 @@ struct fms_handle_s {
     }
     return hipSuccess;
   }
-  // Host waits go through an event without timing (cheaper to wait on than
-  // a whole-stream synchronisation).
+  // Host waits go through an event without timing (cheaper to wait on than a
+  // whole-stream synchronisation).  A wait also frees the pinned tables for
+  // the next upload.
   hipEvent_t sync_ev = nullptr;
+  bool uploads_in_flight = false;
   hipError_t wait(hipStream_t st) {
     hipError_t e = hipEventRecord(sync_ev, st);
-    return e == hipSuccess ? hipEventSynchronize(sync_ev) : e;
+    if (e == hipSuccess) e = hipEventSynchronize(sync_ev);
+    if (e == hipSuccess) uploads_in_flight = false;
+    return e;
   }
-  // Pinned host staging.
-  int* hmeta = nullptr;
-  void* hstage = nullptr;
-  size_t hstage_cap = 0;
-
-  hipError_t stage(size_t bytes) {
-    if (bytes <= hstage_cap) return hipSuccess;
-    if (hstage) (void)hipHostFree(hstage);
-    hstage = nullptr;
-    hstage_cap = 0;
-    size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 16);
-    hipError_t e = hipHostMalloc(&hstage, want, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      hstage = nullptr;
-      return e;
-    }
-    hstage_cap = want;
-    return hipSuccess;
+  // Pinned host staging: counters (F * META_COUNT ints, then F * kMeta64
+  // 64-bit words), frame tables, output offsets, a general area.
+  PinBuf hmeta, hgeo, hrt, hoff, hstage;
+  const int* hm(int f) const { return hmeta.as<int>() + size_t(f) * META_COUNT; }
+  unsigned long long hm64(int f, int F) const {
+    const unsigned long long* q =
+        reinterpret_cast<const unsigned long long*>(hmeta.as<int>() + size_t(F) * META_COUNT);
+    return q[size_t(f) * kMeta64];
   }
 };
 
 namespace {
 
-#define HIP_TRY(expr)                       \
-  do {                                      \
-    hipError_t _e = (expr);                 \
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t _e = (expr);                   \
     if (_e != hipSuccess) return FMS_ERR_HIP; \
   } while (0)
 
-// Launches with at least kBigGroupMin centres use seed groups of kBigGroup
-// (where compiled): on the 512x512, D = 32 workload a 64-seed group is about
-// 20% faster than a 32-seed one from 1,024 centres on, and no slower at 256.
-constexpr int kBigGroup = 64;
-constexpr int kBigGroupMin = 512;
+#define FMS_TRY(expr)                    \
+  do {                                   \
+    fms_status _s = (expr);              \
+    if (_s != FMS_OK) return _s;         \
+  } while (0)
 
-struct Frame {
-  fms::FrameDesc desc;
-  int n = 0;
-  int dp = 32;
+// Host state of one frame of a call.
+struct FrameHost {
+  fms::FrameGeo g{};  // what the kernels see
   int n_pad = 0;
-  fms::StepGeom geom{};
-  fms::Tiling tile{};       // the precision of the call
-  fms::Tiling tile_fp32{};  // FP32 steps (refinement) and window counts
-  // The same with larger seed groups, for launches with many centres (fewer
-  // re-reads of the pixels per centre).
-  fms::Tiling tile_big{};
-  fms::Tiling tile_fp32_big{};
+  double r = 0.0;     // foreground fraction n / (H*W)
+  // OSOP state (Sec. 3.2.4).
+  int64_t n_seeds = 0, n_used = 0;
+  int k_modes = 0;
+  bool live = false;
+  bool have_nmin = false;
+  double nmin = 0.0;
+  fms::RoundTab rt{};
+  fms_stats sx{};
+};
+
+// Fused-step launches of a call, timed with kernel-bound events.
+struct Timing {
+  double step_ms[2] = {0.0, 0.0};
+  int64_t step_updates[2] = {0, 0};
+  int step_launches[2] = {0, 0};
+};
+
+struct Call {
+  hipStream_t st = nullptr;
+  int F = 0, dim = 0, dp = 32;
+  bool bf16 = false;
+  std::vector<FrameHost> fr;
+  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{};
+  fms::Batch b{};
+  int64_t max_pixels = 0;
+  Timing tm;
 };
 
 fms_status check_params(const fms_params* p) {
   if (!p) return FMS_ERR_INVALID_ARG;
-  if (!(p->bandwidth > 0.0 && p->bandwidth < 2.0)) return FMS_ERR_INVALID_ARG;
   if (!(p->gamma >= 0.0 && p->gamma <= 1.0)) return FMS_ERR_INVALID_ARG;
   if (!(p->big_l > 0.0) || !(p->big_h > 0.0)) return FMS_ERR_INVALID_ARG;
   if (!(p->p_target > 0.0 && p->p_target < 1.0)) return FMS_ERR_INVALID_ARG;
@@ -220,342 +258,340 @@ fms_status check_params(const fms_params* p) {
   return FMS_OK;
 }
 
-fms_status check_frame_args(fms_handle h, const float* emb, int64_t ps, int64_t cs, int32_t height, int32_t width,
-                            int32_t dim) {
-  if (!h || !emb) return FMS_ERR_INVALID_ARG;
-  if (height < 1 || width < 1 || ps < 0 || cs < 0) return FMS_ERR_INVALID_ARG;
+fms_status check_frame(const fms_frame& f, int32_t dim) {
+  if (!f.emb || f.height < 1 || f.width < 1 || f.pixel_stride < 0 || f.channel_stride < 0)
+    return FMS_ERR_INVALID_ARG;
   if (dim < 1) return FMS_ERR_INVALID_ARG;
   if (dim > 128) return FMS_ERR_UNSUPPORTED;
-  if (int64_t(height) * int64_t(width) > int64_t(std::numeric_limits<int32_t>::max())) return FMS_ERR_UNSUPPORTED;
+  if (int64_t(f.height) * int64_t(f.width) > int64_t(std::numeric_limits<int32_t>::max())) return FMS_ERR_UNSUPPORTED;
+  if (!(f.bandwidth > 0.0 && f.bandwidth < 2.0)) return FMS_ERR_INVALID_ARG;
   return FMS_OK;
 }
 
-// Compact the foreground, normalise it and write the four layouts.
-fms_status prepare_frame(fms_handle h, hipStream_t st, const float* emb, int64_t ps, int64_t cs, const uint8_t* mask,
-                         int32_t height, int32_t width, int32_t dim, bool bf16, Frame& fr) {
-  const int64_t P = int64_t(height) * int64_t(width);
-  const int nmb = int((P + fms::kMaskBlockPix - 1) / fms::kMaskBlockPix);
-  fr.dp = pad_dim(dim);
-  fr.desc = fms::FrameDesc{emb, ps, cs, mask, P, dim, fr.dp};
-  HIP_TRY(h->blk.ensure(size_t(nmb) * sizeof(int)));
-  HIP_TRY(h->meta.ensure(META_COUNT * sizeof(int)));
-  HIP_TRY(hipMemsetAsync(h->meta.p, 0, META_COUNT * sizeof(int), st));
-  HIP_TRY(fms::launch_mask_count(st, mask, P, h->blk.as<int>(), nmb));
-  HIP_TRY(fms::launch_scan_blocks(st, h->blk.as<int>(), nmb, h->meta.as<int>()));
-  HIP_TRY(hipMemcpyAsync(h->hmeta, h->meta.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(h->wait(st));
-  fr.n = h->hmeta[META_N];
-  fr.n_pad = ((fr.n + fms::kBlockPix - 1) / fms::kBlockPix) * fms::kBlockPix;
-  fr.geom = fms::make_geom(fr.n);
-  if (fr.n == 0) return FMS_OK;
-  const size_t rows = size_t(fr.n_pad);
-  const size_t dp = size_t(fr.dp);
-  HIP_TRY(h->fg_idx.ensure(rows * sizeof(int)));
-  HIP_TRY(h->x32.ensure(rows * dp * sizeof(float)));
-  HIP_TRY(h->x32t.ensure(rows * dp * sizeof(float)));
-  if (bf16) {
-    HIP_TRY(h->x16.ensure(rows * dp * sizeof(uint16_t)));
-    HIP_TRY(h->x16t.ensure(rows * dp * sizeof(uint16_t)));
-  }
-  HIP_TRY(fms::launch_compact(st, fr.desc, h->blk.as<int>(), nmb, h->fg_idx.as<int>(), h->x32.as<float>(),
-                              h->x32t.as<float>(), bf16 ? h->x16.as<uint16_t>() : nullptr,
-                              bf16 ? h->x16t.as<uint16_t>() : nullptr, h->meta.as<int>()));
-  // meta[META_BAD] counts zero or non-finite rows.  The caller checks it at
-  // its next read of the counters (no kernel indexes by embedding values, so
-  // the work enqueued meanwhile is merely wasted).
-  return FMS_OK;
+double tol_of(const fms_params* p, double h) { return p->conv_tol > 0.0 ? p->conv_tol : h / 1000.0; }
+
+// Tiling of a fused-step launch with at most `bound` centres per frame.
+const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
+  if (bound >= kBigGroupMin) return bf16 ? c.tile_big : c.tile_fp32_big;
+  return bf16 ? c.tile : c.tile_fp32;
 }
 
-void set_tiling(Frame& fr, const fms_params* p) {
-  const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
-  fr.tile = fms::make_tiling(bf16, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
-  fr.tile_fp32 = fms::make_tiling(false, fr.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+void set_tiling(Call& c, const fms_params* p) {
+  c.tile = fms::make_tiling(c.bf16, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+  c.tile_fp32 = fms::make_tiling(false, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
   // A caller-fixed group size holds for every launch.
   const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
-  fr.tile_big = fms::make_tiling(bf16, fr.dp, big, p->tile_items, p->tile_chunks);
-  fr.tile_fp32_big = fms::make_tiling(false, fr.dp, big, p->tile_items, p->tile_chunks);
+  c.tile_big = fms::make_tiling(c.bf16, c.dp, big, p->tile_items, p->tile_chunks);
+  c.tile_fp32_big = fms::make_tiling(false, c.dp, big, p->tile_items, p->tile_chunks);
 }
 
-// Tiling of a fused-step launch with at most `bound` centres.
-const fms::Tiling& pick_tiling(const Frame& fr, bool bf16, int bound) {
-  if (bound >= kBigGroupMin) return bf16 ? fr.tile_big : fr.tile_fp32_big;
-  return bf16 ? fr.tile : fr.tile_fp32;
+// Chunk-partial rows a frame of `cap` centres needs under any tiling.
+int64_t partial_rows(const Call& c, int cap) {
+  return (int64_t)std::max({fms::shift_partial_rows(c.tile, cap), fms::shift_partial_rows(c.tile_fp32, cap),
+                            fms::shift_partial_rows(c.tile_big, cap), fms::shift_partial_rows(c.tile_fp32_big, cap)});
 }
 
-fms_status ensure_round(fms_handle h, const Frame& fr, int m, bool bf16) {
-  HIP_TRY(h->stage(size_t(std::max(m, 1)) * sizeof(int) + 256));
-  const size_t mm = size_t(std::max(m, 1));
-  const size_t dp = size_t(fr.dp);
-  HIP_TRY(h->y.ensure(mm * dp * sizeof(float)));
-  HIP_TRY(h->yc0.ensure(mm * dp * sizeof(float)));
-  HIP_TRY(h->yc1.ensure(mm * dp * sizeof(float)));
-  HIP_TRY(h->active.ensure(mm * sizeof(int)));
-  HIP_TRY(h->next_active.ensure(mm * sizeof(int)));
-  HIP_TRY(h->state.ensure(mm));
-  HIP_TRY(h->iters.ensure(mm * sizeof(int)));
-  HIP_TRY(h->seed_pos.ensure(mm * sizeof(int)));
-  HIP_TRY(h->seed_fg.ensure(mm * sizeof(int)));
-  HIP_TRY(h->ident.ensure(mm * sizeof(int)));
-  HIP_TRY(h->cand.ensure(mm * sizeof(int)));
-  HIP_TRY(h->counts.ensure(mm * sizeof(int)));
-  HIP_TRY(h->sorted.ensure(mm * sizeof(int)));
-  HIP_TRY(h->scount.ensure(mm * sizeof(int)));
-  (void)bf16;
-  const int im = int(mm);
-  const size_t rows = std::max({fms::shift_partial_rows(fr.tile, im), fms::shift_partial_rows(fr.tile_fp32, im),
-                                fms::shift_partial_rows(fr.tile_big, im), fms::shift_partial_rows(fr.tile_fp32_big, im)});
-  HIP_TRY(h->pcount.ensure(rows * sizeof(int)));
-  HIP_TRY(h->partial.ensure(rows * dp * sizeof(float)));
+// Upload the frame tables.  The pinned copy is rewritten only after the
+// previous upload has completed.
+fms_status upload_geo(fms_handle h, Call& c) {
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  fms::FrameGeo* hg = h->hgeo.as<fms::FrameGeo>();
+  for (int f = 0; f < c.F; ++f) hg[f] = c.fr[f].g;
+  HIP_TRY(hipMemcpyAsync(h->geo.p, hg, size_t(c.F) * sizeof(fms::FrameGeo), hipMemcpyHostToDevice, c.st));
+  h->uploads_in_flight = true;
   return FMS_OK;
 }
 
-// Device transfer area of one pruning pass (counts, candidate x candidate
-// bits, candidate x mode bits) and the host staging that receives it in one
-// copy.  Sized before any copy is enqueued, never reallocated mid-flight.
-struct Xfer {
-  int* counts;
-  uint32_t* bits_c;
-  uint32_t* bits_m;
-  int words_c, words_m;
-  size_t bytes;
-};
-
-fms_status ensure_xfer(fms_handle h, int nc, int k, Xfer& x) {
-  x.words_c = fms::simbits_words(nc);
-  x.words_m = fms::simbits_words(k);
-  const size_t nb_c = size_t(nc) * x.words_c * sizeof(uint32_t);
-  const size_t nb_m = size_t(nc) * x.words_m * sizeof(uint32_t);
-  const size_t nb_n = ((size_t(nc) * sizeof(int) + 255) / 256) * 256;
-  x.bytes = nb_n + nb_c + nb_m;
-  HIP_TRY(h->bits.ensure(x.bytes));
-  HIP_TRY(h->stage(x.bytes + 256));
-  uint8_t* base = static_cast<uint8_t*>(h->bits.p);
-  x.counts = reinterpret_cast<int*>(base);
-  x.bits_c = reinterpret_cast<uint32_t*>(base + nb_n);
-  x.bits_m = reinterpret_cast<uint32_t*>(base + nb_n + nb_c);
+fms_status upload_rt(fms_handle h, Call& c) {
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  fms::RoundTab* hr = h->hrt.as<fms::RoundTab>();
+  for (int f = 0; f < c.F; ++f) hr[f] = c.fr[f].rt;
+  HIP_TRY(hipMemcpyAsync(h->rt.p, hr, size_t(c.F) * sizeof(fms::RoundTab), hipMemcpyHostToDevice, c.st));
+  h->uploads_in_flight = true;
   return FMS_OK;
 }
 
-// Host view of an Xfer after its copy.
-struct XferHost {
-  const int* counts;
-  const uint32_t* bits_c;
-  const uint32_t* bits_m;
-};
-
-XferHost xfer_host(fms_handle h, const Xfer& x, int nc) {
-  const uint8_t* hb = static_cast<const uint8_t*>(h->hstage);
-  const size_t nb_n = ((size_t(nc) * sizeof(int) + 255) / 256) * 256;
-  const size_t nb_c = size_t(nc) * x.words_c * sizeof(uint32_t);
-  return XferHost{reinterpret_cast<const int*>(hb), reinterpret_cast<const uint32_t*>(hb + nb_n),
-                  reinterpret_cast<const uint32_t*>(hb + nb_n + nb_c)};
+// Staging upload of n ints to device memory (waits for earlier uploads first).
+fms_status upload_ints(fms_handle h, Call& c, void* dst, const int* src, size_t n) {
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  HIP_TRY(h->hstage.ensure(n * sizeof(int) + 256));
+  std::memcpy(h->hstage.p, src, n * sizeof(int));
+  HIP_TRY(hipMemcpyAsync(dst, h->hstage.p, n * sizeof(int), hipMemcpyHostToDevice, c.st));
+  h->uploads_in_flight = true;
+  return FMS_OK;
 }
 
-struct RoundOut {
-  int steps = 0;
-  int64_t updates = 0;
-  int refine_steps = 0;
-  int refine_bad = 0;
-  int64_t refine_updates = 0;
-  double step_ms[2] = {0.0, 0.0};
-  int64_t step_updates[2] = {0, 0};
-  int step_launches[2] = {0, 0};
-  std::vector<int> conv;  // converged slots, ascending
-};
+// All frames' counters (and 64-bit counters) to the host; waits.
+fms_status read_meta(fms_handle h, Call& c) {
+  HIP_TRY(hipMemcpyAsync(h->hmeta.p, h->meta.p, size_t(c.F) * META_COUNT * sizeof(int), hipMemcpyDeviceToHost,
+                         c.st));
+  HIP_TRY(hipMemcpyAsync(h->hmeta.as<int>() + size_t(c.F) * META_COUNT, h->meta64.p,
+                         size_t(c.F) * kMeta64 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(h->wait(c.st));
+  return FMS_OK;
+}
 
-void add_timing(fms_stats& sx, const RoundOut& ro) {
-  for (int k = 0; k < 2; ++k) {
-    sx.step_ms[k] += ro.step_ms[k];
-    sx.step_updates[k] += ro.step_updates[k];
-    sx.step_launches[k] += ro.step_launches[k];
+// Compact the foreground of every frame, normalise it and write the layouts;
+// set every frame's label map to -1.  The frames' n, rows and tables are
+// set; the caller checks META_BAD at its next read of the counters (no
+// kernel indexes by embedding values, so the work enqueued meanwhile is
+// merely wasted).
+fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_params* p) {
+  const int F = c.F;
+  HIP_TRY(h->geo.ensure(size_t(F) * sizeof(fms::FrameGeo)));
+  HIP_TRY(h->rt.ensure(size_t(F) * sizeof(fms::RoundTab)));
+  HIP_TRY(h->out_off.ensure(size_t(F + 1) * sizeof(int)));
+  HIP_TRY(h->meta.ensure(size_t(F) * META_COUNT * sizeof(int)));
+  HIP_TRY(h->meta64.ensure(size_t(F) * kMeta64 * sizeof(unsigned long long)));
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  HIP_TRY(h->hmeta.ensure(size_t(F) * (META_COUNT * sizeof(int) + kMeta64 * sizeof(unsigned long long))));
+  HIP_TRY(h->hgeo.ensure(size_t(F) * sizeof(fms::FrameGeo)));
+  HIP_TRY(h->hrt.ensure(size_t(F) * sizeof(fms::RoundTab)));
+  HIP_TRY(h->hoff.ensure(size_t(F + 1) * sizeof(int)));
+  c.fr.assign(size_t(F), FrameHost{});
+  c.b = fms::Batch{};
+  c.b.F = F;
+  c.b.geo = h->geo.as<fms::FrameGeo>();
+  c.b.rt = h->rt.as<fms::RoundTab>();
+  c.b.meta = h->meta.as<int>();
+  c.b.meta64 = h->meta64.as<unsigned long long>();
+  int64_t mblk = 0;
+  for (int f = 0; f < F; ++f) {
+    const fms_frame& in = frames[f];
+    FrameHost& fh = c.fr[f];
+    const int64_t P = int64_t(in.height) * int64_t(in.width);
+    fh.g.desc = fms::FrameDesc{in.emb, in.pixel_stride, in.channel_stride, in.mask, P, c.dim, c.dp};
+    fh.g.mblk0 = mblk;
+    fh.g.labels = in.labels;
+    fh.g.thr = float(1.0 - in.bandwidth);
+    fh.g.tol = float(tol_of(p, in.bandwidth));
+    const int64_t nmb = (P + fms::kMaskBlockPix - 1) / fms::kMaskBlockPix;
+    mblk += nmb;
+    c.b.max_mblk = std::max(c.b.max_mblk, nmb);
+    c.max_pixels = std::max(c.max_pixels, P);
+    fh.sx.n_min = std::numeric_limits<double>::quiet_NaN();
+    fh.n_seeds = in.n_state_in > 0 ? in.n_state_in : p->n_initial;
   }
+  HIP_TRY(h->blk.ensure(size_t(std::max<int64_t>(mblk, 1)) * sizeof(int)));
+  FMS_TRY(upload_geo(h, c));
+  HIP_TRY(hipMemsetAsync(h->meta.p, 0, size_t(F) * META_COUNT * sizeof(int), c.st));
+  HIP_TRY(hipMemsetAsync(h->meta64.p, 0, size_t(F) * kMeta64 * sizeof(unsigned long long), c.st));
+  HIP_TRY(fms::launch_mask_count(c.st, c.b, h->blk.as<int>()));
+  HIP_TRY(fms::launch_scan_blocks(c.st, c.b, h->blk.as<int>()));
+  FMS_TRY(read_meta(h, c));
+  // Frame regions: rows (pixels, centres, modes), chunk partials, flags.
+  int64_t rows = 0, part = 0, elig = 0;
+  for (int f = 0; f < F; ++f) {
+    FrameHost& fh = c.fr[f];
+    const int n = h->hm(f)[META_N];
+    fh.g.n = n;
+    fh.n_pad = ((n + fms::kBlockPix - 1) / fms::kBlockPix) * fms::kBlockPix;
+    fh.g.n_blocks = fh.n_pad / fms::kBlockPix;
+    fh.g.half_bits = half_bits(n);
+    fh.g.row0 = rows;
+    fh.g.part0 = part;
+    fh.g.elig0 = elig;
+    fh.r = double(n) / double(fh.g.desc.n_pixels);
+    fh.sx.n_fg = n;
+    rows += fh.n_pad;
+    part += n > 0 ? partial_rows(c, n) : 0;
+    elig += fms::elig_len(n);
+    c.b.max_n = std::max(c.b.max_n, n);
+    c.b.max_blocks = std::max(c.b.max_blocks, fh.g.n_blocks);
+  }
+  const size_t R = size_t(std::max<int64_t>(rows, fms::kBlockPix)), dp = size_t(c.dp);
+  HIP_TRY(h->fg_idx.ensure(R * sizeof(int)));
+  HIP_TRY(h->x32.ensure(R * dp * sizeof(float)));
+  HIP_TRY(h->x32t.ensure(R * dp * sizeof(float)));
+  if (c.bf16) {
+    HIP_TRY(h->x16.ensure(R * dp * sizeof(uint16_t)));
+    HIP_TRY(h->x16t.ensure(R * dp * sizeof(uint16_t)));
+  }
+  for (DevBuf* b : {&h->y, &h->yc0, &h->yc1, &h->modes}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
+  for (DevBuf* b : {&h->order, &h->rank, &h->active, &h->next_active, &h->iters, &h->seed_pos, &h->seed_fg,
+                    &h->ident, &h->cand, &h->counts, &h->sorted, &h->scount, &h->mode_counts})
+    HIP_TRY(b->ensure(R * sizeof(int)));
+  HIP_TRY(h->state.ensure(R));
+  HIP_TRY(h->elig.ensure(size_t(std::max<int64_t>(elig, 16))));
+  const size_t PR = size_t(std::max<int64_t>(part, 1));
+  HIP_TRY(h->pcount.ensure(PR * sizeof(int)));
+  HIP_TRY(h->partial.ensure(PR * dp * sizeof(float)));
+  FMS_TRY(upload_geo(h, c));
+  HIP_TRY(fms::launch_fill_labels(c.st, c.b, c.max_pixels));
+  if (c.b.max_n > 0)
+    HIP_TRY(fms::launch_compact(c.st, c.b, c.dp, h->blk.as<int>(), h->fg_idx.as<int>(), h->x32.as<float>(),
+                                h->x32t.as<float>(), c.bf16 ? h->x16.as<uint16_t>() : nullptr,
+                                c.bf16 ? h->x16t.as<uint16_t>() : nullptr));
+  return FMS_OK;
 }
 
-// Iterate the seeds whose centres are in y[0..m) (Alg. 2, the parallel seed
-// loop) until more than gamma of them converged (Sec. 3.2.3), none is
-// active, or max_iter steps.  With seed_fg the centres first load from those
-// pixel rows.  The active count, the early-stop test and the done flag live
-// on the device; the host enqueues iterations in batches and reads the flag
-// back between batches.  The converged slots end up in out.conv (ascending)
-// and in h->cand.
-fms_status run_iterations_on(fms_handle h, hipStream_t st, const Frame& fr, float* ybuf, int cap,
-                             const fms_params* p, float thr, float tol, RoundOut& out, bool host_list,
-                             const int* seed_fg = nullptr) {
-  const int m = cap;  // upper bound; the round's seed count is meta[META_NSEL]
-  int* meta = h->meta.as<int>();
-  unsigned long long* meta64 = h->meta64.as<unsigned long long>();
-  const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
+// Iterate every frame's centres y[row0 .. row0 + NSEL) (Alg. 2, the parallel
+// seed loop) until more than gamma of them converged (Sec. 3.2.3), none is
+// active, or max_iter steps; each frame stops on its own counters.  With
+// seed_fg the centres first load from those pixel rows; with nsel_from_rt a
+// frame's centre count is rt.nact.  The active count, the early-stop test and
+// the done flag live on the device; the host enqueues iterations in batches
+// and reads the counters back between batches.  cap: most centres of any
+// frame.  On return h->hm(f) holds every frame's counters.
+fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double gamma, int max_iter, bool bf16,
+                          bool timing, const int* seed_fg, bool nsel_from_rt) {
+  const fms::Batch& b = c.b;
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
   const int pk = bf16 ? 1 : 0;
-  const bool timing = p->timing != 0;
-  HIP_TRY(fms::launch_round_begin(st, m, h->active.as<int>(), h->state.as<uint8_t>(), h->iters.as<int>(), meta,
-                                  meta64, seed_fg, h->x32.as<float>(), fr.dp, ybuf));
+  HIP_TRY(fms::launch_round_begin(c.st, b, cap, nsel_from_rt, h->active.as<int>(), h->state.as<uint8_t>(),
+                                  h->iters.as<int>(), seed_fg, h->x32.as<float>(), c.dp, ybuf));
   int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
   float* yc[2] = {h->yc0.as<float>(), h->yc1.as<float>()};
-  // Iterations go out in batches; the host reads the counters back after
-  // each batch and stops enqueueing at the early stop.  Launches queued past
-  // the stop find the done flag and return at once.
   // Batch sizes: most rounds of the 512x512 workload stop within 3 to 9
   // iterations; 3, 6, 8 measured best among the schedules tried.
   static constexpr int kSched[] = {3, 6, 8};
   int t = 0, nbatch = 0;
-  int bound = m;  // active centres of the next iteration, at most
-  while (t < p->max_iter) {
-    const int want_nb = kSched[std::min(nbatch, 2)];
+  int bound = cap;  // active centres of any frame in the next iteration, at most
+  while (t < max_iter) {
+    const int nb = std::min(kSched[std::min(nbatch, 2)], max_iter - t);
     ++nbatch;
-    const int nb = std::min(want_nb, p->max_iter - t);
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
-    const fms::Tiling& tl = pick_tiling(fr, bf16, bound);
+    const fms::Tiling& tl = pick_tiling(c, bf16, bound);
     for (int i = 0; i < nb; ++i, ++t) {
-      const fms::IterCtl ctl{meta, meta64, -1, t, fr.n, p->gamma};
+      const fms::IterCtl ctl{-1, t, gamma};
       // Iteration 0 reads the centres in place (the active list is the
       // identity); later iterations read the rows the previous reduce
       // compacted in active-list order.
       const float* yin = t == 0 ? ybuf : yc[t & 1];
-      HIP_TRY(fms::launch_shift(st, bf16, fr.dp, tl, fr.geom.n_blocks, xrm, xt, yin, nullptr, ctl, m, thr,
-                                h->partial.as<float>(), timing ? h->events[2 * i] : nullptr,
-                                timing ? h->events[2 * i + 1] : nullptr));
-      HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), lists[t & 1], ybuf,
+      HIP_TRY(fms::launch_shift(c.st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap, h->partial.as<float>(),
+                                timing ? h->events[2 * i] : nullptr, timing ? h->events[2 * i + 1] : nullptr));
+      HIP_TRY(fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[t & 1], ybuf,
                                  h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1], yc[(t + 1) & 1],
-                                 ctl, m, tol, 0));
+                                 ctl, cap, 0));
     }
-    HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(h->wait(st));
+    FMS_TRY(read_meta(h, c));
     if (timing) {
       for (int i = 0; i < nb; ++i) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * i], h->events[2 * i + 1]));
-        out.step_ms[pk] += ms;
-        out.step_launches[pk] += 1;
+        c.tm.step_ms[pk] += ms;
+        c.tm.step_launches[pk] += 1;
       }
     }
-    // The early stop of the next iteration, as its step kernel takes it.
-    const int* hm = h->hmeta;
-    bound = hm[fms::META_ACT + (t & 1)];
-    if (hm[fms::META_DONE] || bound <= 0 || (double)hm[fms::META_NCONV] > p->gamma * (double)hm[fms::META_NSEL])
-      break;
+    // The early stop of each frame's next iteration, as its step kernel
+    // takes it.
+    bool all_done = true;
+    bound = 0;
+    for (int f = 0; f < c.F; ++f) {
+      const int* hm = h->hm(f);
+      const int act = hm[fms::META_ACT + (t & 1)];
+      const bool done = hm[fms::META_DONE] || act <= 0 || (double)hm[META_NCONV] > gamma * (double)hm[META_NSEL];
+      if (!done) {
+        all_done = false;
+        bound = std::max(bound, act);
+      }
+    }
+    if (all_done) break;
   }
-  out.steps = h->hmeta[fms::META_STEPS];
-  out.conv.clear();
-  if (!host_list) return FMS_OK;  // the caller collects on the device and reads the counters later
-  // Converged slots, in slot (= seed-order) order, and the update count.
-  const int msel = h->hmeta[fms::META_NSEL];
-  uint8_t* hs = static_cast<uint8_t*>(h->hstage);
-  HIP_TRY(hipMemcpyAsync(hs, h->state.p, size_t(msel), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(hs + ((size_t(m) + 15) / 16) * 16, meta64, sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(h->wait(st));
-  unsigned long long upd = 0;
-  std::memcpy(&upd, hs + ((size_t(m) + 15) / 16) * 16, sizeof(upd));
-  out.updates = int64_t(upd);
-  if (timing) out.step_updates[pk] += out.updates;
-  for (int k = 0; k < msel; ++k)
-    if (hs[k] == 1) out.conv.push_back(k);
-  const int nc = int(out.conv.size());
-  if (nc > 0) {
-    std::memcpy(h->hstage, out.conv.data(), size_t(nc) * sizeof(int));
-    HIP_TRY(hipMemcpyAsync(h->cand.p, h->hstage, size_t(nc) * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(h->wait(st));
-  }
+  if (timing)
+    for (int f = 0; f < c.F; ++f) c.tm.step_updates[pk] += int64_t(h->hm64(f, c.F));
   return FMS_OK;
 }
 
-fms_status run_iterations(fms_handle h, hipStream_t st, const Frame& fr, int m, const fms_params* p, float thr,
-                          float tol, RoundOut& out, bool host_list, const int* seed_fg = nullptr) {
-  return run_iterations_on(h, st, fr, h->y.as<float>(), m, p, thr, tol, out, host_list, seed_fg);
-}
-
-// FP32 refinement (BF16 form) of the `a` centres y[list[0..a)]: `steps`
-// steps without freezing.  With `early_stop`, the centres then keep iterating
-// with freezing under the early stop of Sec. 3.2.3 (until more than gamma of
-// them have converged, or max_steps in total); out_keep receives, per centre,
-// 1 when it converged and 0 when it was still moving and is dropped, like an
-// unconverged seed.  Without it, the centres whose last step moved >= tol
-// are counted.
-fms_status run_refine(fms_handle h, hipStream_t st, const Frame& fr, float* y, const int* list, int a, int steps,
-                      int max_steps, float thr, float tol, double gamma, bool early_stop, bool timing,
-                      RoundOut& out, std::vector<uint8_t>* out_keep) {
-  if (a <= 0 || steps <= 0) return FMS_OK;
-  int* meta = h->meta.as<int>();
-  const fms::Tiling& tl = pick_tiling(fr, false, a);
-  h->hmeta[fms::META_NACC] = a;
-  HIP_TRY(hipMemcpyAsync(meta + fms::META_NACC, h->hmeta + fms::META_NACC, sizeof(int), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemsetAsync(meta + fms::META_REFINE_BAD, 0, sizeof(int), st));
+// FP32 refinement of every frame's rt.nact centres y[row0 + list[..]] (rt
+// uploaded): `steps` steps without freezing; the last one counts the centres
+// still moving, and with `cont` also sets each centre's state.  With `cont`,
+// the frames with moving centres then keep iterating the same centres (list
+// = identity) in FP32 with freezing under the early stop, up to max_steps in
+// total; their state ends 1 for converged centres and 0 for the ones still
+// moving.  rt is uploaded again unchanged on return.
+fms_status run_refine(fms_handle h, Call& c, float* y, const int* list, int cap, int steps, int max_steps,
+                      double gamma, bool cont, bool timing) {
+  if (cap <= 0 || steps <= 0) return FMS_OK;
+  const fms::Tiling& tl = pick_tiling(c, false, cap);
+  HIP_TRY(fms::launch_set_slot(c.st, c.b, META_REFINE_BAD, false, 0));
   if (timing) HIP_TRY(h->ensure_events(2 * size_t(steps)));
   for (int r = 0; r < steps; ++r) {
-    const fms::IterCtl ctl{meta, nullptr, fms::META_NACC, -1, fr.n, 1.0};
-    HIP_TRY(fms::launch_shift(st, false, fr.dp, tl, fr.geom.n_blocks, h->x32.p, h->x32t.p, y, list, ctl, a, thr,
+    const fms::IterCtl ctl{-1, -1, 1.0};
+    HIP_TRY(fms::launch_shift(c.st, c.b, false, c.dp, tl, h->x32.p, h->x32t.p, y, list, ctl, cap,
                               h->partial.as<float>(), timing ? h->events[2 * r] : nullptr,
                               timing ? h->events[2 * r + 1] : nullptr));
-    HIP_TRY(fms::launch_reduce(st, fr.dp, fr.geom.n_blocks, tl, h->partial.as<float>(), list, y,
-                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, nullptr, ctl, a, tol,
-                               r + 1 == steps ? 2 : 1));
-    out.refine_steps += 1;
-    out.refine_updates += int64_t(a) * int64_t(fr.n);
+    HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, tl, h->partial.as<float>(), list, y, h->state.as<uint8_t>(),
+                               h->iters.as<int>(), nullptr, nullptr, ctl, cap, r + 1 < steps ? 1 : (cont ? 3 : 2)));
   }
-  HIP_TRY(hipMemcpyAsync(h->hmeta + fms::META_REFINE_BAD, meta + fms::META_REFINE_BAD, sizeof(int),
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(h->wait(st));
+  FMS_TRY(read_meta(h, c));
   if (timing) {
     for (int r = 0; r < steps; ++r) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
-      out.step_ms[0] += ms;
-      out.step_updates[0] += int64_t(a) * int64_t(fr.n);
-      out.step_launches[0] += 1;
+      c.tm.step_ms[0] += ms;
+      c.tm.step_launches[0] += 1;
     }
   }
-  const int moving = h->hmeta[fms::META_REFINE_BAD];
-  if (!early_stop) {
-    out.refine_bad += moving;
+  for (FrameHost& fh : c.fr) {
+    const int64_t upd = int64_t(fh.rt.nact) * steps * int64_t(fh.g.n);
+    if (fh.rt.nact > 0) fh.sx.refine_steps += steps;
+    fh.sx.refine_updates += upd;
+    if (timing) c.tm.step_updates[0] += upd;
+  }
+  if (!cont) {
+    for (int f = 0; f < c.F; ++f) c.fr[f].sx.refine_unconverged += h->hm(f)[META_REFINE_BAD];
     return FMS_OK;
   }
-  out_keep->assign(size_t(a), 1);
-  if (moving == 0) return FMS_OK;
-  // Continue with freezing; the list maps iteration slots to the centres.
-  RoundOut ro;
-  h->hmeta[fms::META_NSEL] = a;
-  HIP_TRY(hipMemcpyAsync(meta + fms::META_NSEL, h->hmeta + fms::META_NSEL, sizeof(int), hipMemcpyHostToDevice, st));
-  fms_params q{};
-  q.gamma = gamma;
-  q.max_iter = std::max(max_steps - steps, 1);
-  q.precision = FMS_PREC_FP32;
-  q.timing = timing ? 1 : 0;
-  q.tile_seeds = tl.group_seeds;
-  q.tile_items = tl.target_items;
-  q.tile_chunks = tl.max_chunks;
-  fms_status stt = run_iterations_on(h, st, fr, y, a, &q, thr, tol, ro, true);
-  if (stt != FMS_OK) return stt;
-  out.refine_steps += ro.steps;
-  out.refine_updates += ro.updates;
-  for (int k = 0; k < 2; ++k) {
-    out.step_ms[k] += ro.step_ms[k];
-    out.step_updates[k] += ro.step_updates[k];
-    out.step_launches[k] += ro.step_launches[k];
+  // Continue, with freezing, the frames whose centres still move.
+  std::vector<int> nact(static_cast<size_t>(c.F));
+  bool any = false;
+  for (int f = 0; f < c.F; ++f) {
+    nact[f] = c.fr[f].rt.nact;
+    if (h->hm(f)[META_REFINE_BAD] == 0) c.fr[f].rt.nact = 0;
+    any = any || c.fr[f].rt.nact > 0;
   }
-  std::fill(out_keep->begin(), out_keep->end(), uint8_t(0));
-  for (int k : ro.conv) (*out_keep)[size_t(k)] = 1;
-  out.refine_bad += a - int(ro.conv.size());
-  return FMS_OK;
+  if (!any) return FMS_OK;
+  FMS_TRY(upload_rt(h, c));
+  FMS_TRY(run_iterations(h, c, y, cap, gamma, std::max(max_steps - steps, 1), false, timing, nullptr, true));
+  for (int f = 0; f < c.F; ++f) {
+    FrameHost& fh = c.fr[f];
+    if (fh.rt.nact > 0) {
+      fh.sx.refine_steps += h->hm(f)[META_STEPS];
+      fh.sx.refine_updates += int64_t(h->hm64(f, c.F));
+    }
+    fh.rt.nact = nact[f];
+  }
+  return upload_rt(h, c);
 }
 
-// Greedy pruning (Alg. 2): visit candidates in `order`, accept one when it is
-// not within the window of an existing mode (a nonzero row of bits_m) and not
-// within the window of a candidate accepted before it (bits_c).
-std::vector<int> greedy_accept(const std::vector<int>& order, const XferHost& xh, const Xfer& x, bool have_modes) {
-  std::vector<uint32_t> taken(size_t(std::max(x.words_c, 1)), 0u);
+// Bit-matrix layout of a device pruning pass: frame f's candidate x
+// candidate rows (rt.want rows of simbits_words(rt.want) words) and, with
+// modes, candidate x mode rows (simbits_words(rt.k_modes) words).  Returns
+// the words needed.
+int64_t layout_bits(Call& c, bool with_modes) {
+  int64_t w = 0;
+  for (FrameHost& fh : c.fr) {
+    const int m = fh.rt.want;
+    fh.rt.words_c = fms::simbits_words(m);
+    fh.rt.words_m = with_modes ? fms::simbits_words(fh.rt.k_modes) : 0;
+    fh.rt.bits_c0 = w;
+    w += int64_t(m) * fh.rt.words_c;
+    fh.rt.bits_m0 = w;
+    w += int64_t(m) * fh.rt.words_m;
+  }
+  return std::max<int64_t>(w, 2);
+}
+
+// Greedy pruning (Alg. 2) on the host: visit candidates in `order`, accept
+// one when it is not within the window of an existing mode (a nonzero row of
+// bits_m) and not within the window of a candidate accepted before it.
+std::vector<int> greedy_accept(const std::vector<int>& order, const int* counts, const uint32_t* bits_c, int words_c,
+                               const uint32_t* bits_m, int words_m) {
+  (void)counts;
+  std::vector<uint32_t> taken(size_t(std::max(words_c, 1)), 0u);
   std::vector<int> acc;
   for (int a : order) {
-    if (have_modes) {
-      const uint32_t* rm = xh.bits_m + size_t(a) * x.words_m;
+    if (bits_m) {
+      const uint32_t* rm = bits_m + size_t(a) * words_m;
       bool blocked = false;
-      for (int w = 0; w < x.words_m && !blocked; ++w) blocked = rm[w] != 0;
+      for (int w = 0; w < words_m && !blocked; ++w) blocked = rm[w] != 0;
       if (blocked) continue;
     }
-    const uint32_t* row = xh.bits_c + size_t(a) * x.words_c;
+    const uint32_t* row = bits_c + size_t(a) * words_c;
     bool clash = false;
-    for (int w = 0; w < x.words_c && !clash; ++w) clash = (row[w] & taken[w]) != 0;
+    for (int w = 0; w < words_c && !clash; ++w) clash = (row[w] & taken[w]) != 0;
     if (clash) continue;
     taken[a >> 5] |= 1u << (a & 31);
     acc.push_back(a);
@@ -563,36 +599,299 @@ std::vector<int> greedy_accept(const std::vector<int>& order, const XferHost& xh
   return acc;
 }
 
-// Similarity bits of the nc centres y[list[..]] among themselves and against
-// modes[0..k), with their window counts when `counts` is requested, copied to
-// the host in one transfer.
-fms_status prune_inputs(fms_handle h, hipStream_t st, const Frame& fr, const float* y, const int* list, int nc, int k,
-                        float thr, bool with_counts, Xfer& x, XferHost& xh) {
-  fms_status stt = ensure_xfer(h, nc, k, x);
-  if (stt != FMS_OK) return stt;
-  if (with_counts)
-    HIP_TRY(fms::launch_count(st, false, fr.dp, pick_tiling(fr, false, nc), fr.geom.n_blocks, fr.n, h->x32.p, y,
-                              list, nc, thr,
-                              h->pcount.as<int>(), x.counts, nullptr, -1));
-  HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, list, nullptr, nc, thr, x.bits_c, nullptr, -1, -1));
+// Converged slots of a single frame's round, ascending (state == 1).
+fms_status host_converged(fms_handle h, Call& c, std::vector<int>& conv) {
+  const int msel = h->hm(0)[META_NSEL];
+  conv.clear();
+  if (msel <= 0) return FMS_OK;
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  HIP_TRY(h->hstage.ensure(size_t(msel) + 256));
+  HIP_TRY(hipMemcpyAsync(h->hstage.p, h->state.p, size_t(msel), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(h->wait(c.st));
+  const uint8_t* hs = h->hstage.as<uint8_t>();
+  for (int k = 0; k < msel; ++k)
+    if (hs[k] == 1) conv.push_back(k);
+  return FMS_OK;
+}
+
+// Single frame with more candidates than the device ranking takes: window
+// counts and similarity bits of the converged candidates against each other
+// and the modes kept so far go to the host in one copy; greedy acceptance
+// on the host by (count desc, slot asc); the accepted rows are appended to
+// the modes and their number put in META_NACC.
+fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
+  FrameHost& fh = c.fr[0];
+  const int nc = int(conv.size());
+  if (nc == 0) {
+    HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NACC, false, 0));
+    return FMS_OK;
+  }
+  const int k = fh.k_modes;
+  fh.rt.want = nc;
+  fh.rt.k_modes = k;
+  const int64_t words = layout_bits(c, k > 0);
+  const size_t nb_n = ((size_t(nc) * sizeof(int) + 255) / 256) * 256;
+  const size_t bytes = nb_n + size_t(words) * sizeof(uint32_t);
+  HIP_TRY(h->bits.ensure(bytes));
+  FMS_TRY(upload_ints(h, c, h->cand.p, conv.data(), size_t(nc)));
+  FMS_TRY(upload_rt(h, c));
+  HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NCAND, false, nc));
+  int* counts = h->bits.as<int>();
+  uint32_t* bits = reinterpret_cast<uint32_t*>(h->bits.as<uint8_t>() + nb_n);
+  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, nc), h->x32.p, h->y.as<float>(),
+                            h->cand.as<int>(), nc, h->pcount.as<int>(), counts, META_NCAND));
+  HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nullptr,
+                              nc, bits, false, META_NCAND, META_NCAND));
   if (k > 0)
-    HIP_TRY(fms::launch_simbits(st, fr.dp, y, list, nc, nullptr, h->modes.as<float>(), k, thr, x.bits_m, nullptr, -1,
-                                -1));
-  HIP_TRY(hipMemcpyAsync(h->hstage, h->bits.p, x.bytes, hipMemcpyDeviceToHost, st));
-  HIP_TRY(h->wait(st));
-  xh = xfer_host(h, x, nc);
+    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, nullptr,
+                                h->modes.as<float>(), k, bits, true, META_NCAND, -1));
+  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  HIP_TRY(h->hstage.ensure(bytes + 256));
+  HIP_TRY(hipMemcpyAsync(h->hstage.p, h->bits.p, bytes, hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(h->wait(c.st));
+  const int* hc = h->hstage.as<int>();
+  const uint32_t* hb = reinterpret_cast<const uint32_t*>(h->hstage.as<uint8_t>() + nb_n);
+  std::vector<int> ord(static_cast<size_t>(nc));
+  for (int a = 0; a < nc; ++a) ord[a] = a;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hc[a] > hc[b]; });
+  std::vector<int> acc = greedy_accept(ord, hc, hb + fh.rt.bits_c0, fh.rt.words_c,
+                                       k > 0 ? hb + fh.rt.bits_m0 : nullptr, fh.rt.words_m);
+  const int na = int(acc.size());
+  if (na > 0) {
+    HIP_TRY(h->acc.ensure(size_t(na) * sizeof(int)));
+    FMS_TRY(upload_ints(h, c, h->acc.p, acc.data(), size_t(na)));
+    HIP_TRY(fms::launch_append_modes(c.st, c.dp, h->y.as<float>(), h->cand.as<int>(), counts, h->acc.as<int>(), na,
+                                     h->modes.as<float>(), h->mode_counts.as<int>(), k));
+  }
+  HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NACC, false, na));
   return FMS_OK;
 }
 
-fms_status grow_modes(fms_handle h, hipStream_t st, const Frame& fr, int k_modes, int extra) {
-  // The mode set persists across rounds: grow it without losing rows.
-  HIP_TRY(h->modes.grow_keep(size_t(k_modes + extra) * fr.dp * sizeof(float), size_t(k_modes) * fr.dp * sizeof(float),
-                             st));
-  HIP_TRY(h->mode_counts.grow_keep(size_t(k_modes + extra) * sizeof(int), size_t(k_modes) * sizeof(int), st));
+// The OSOP round loop (Sec. 3.2.4) over the frames of a call, then the BF16
+// refinement and the labels.  Modes stay in h->modes; on return rt.k_modes
+// of every frame (uploaded) is its final mode count.
+fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p) {
+  const int F = c.F;
+  const bool timing = p->timing != 0;
+  if (c.b.max_n > 0) {
+    uint64_t keys[4];
+    round_keys(p->seed, keys);
+    HIP_TRY(
+        fms::launch_seed_order(c.st, c.b, keys, h->order.as<int>(), h->rank.as<int>(), h->elig.as<uint8_t>()));
+  }
+  for (FrameHost& fh : c.fr) fh.live = fh.g.n > 0;
+  bool checked_bad = false;
+  for (int round = 0; round < p->max_rounds; ++round) {
+    // Seeds of this round per frame: N - N_used fresh ones.
+    int cap = 0;
+    for (FrameHost& fh : c.fr) {
+      fh.rt = fms::RoundTab{};
+      fh.rt.k_modes = fh.k_modes;
+      if (!fh.live) continue;
+      const int64_t want64 = std::min<int64_t>(fh.n_seeds - fh.n_used, fh.g.n);
+      if (want64 <= 0) {
+        fh.live = false;
+        continue;
+      }
+      fh.rt.want = int(want64);
+      cap = std::max(cap, fh.rt.want);
+    }
+    if (cap == 0) break;
+    const bool on_device = cap <= fms::kRankMax;
+    if (!on_device && F > 1) return FMS_ERR_UNSUPPORTED;
+    if (on_device) HIP_TRY(h->bits.ensure(size_t(layout_bits(c, true)) * sizeof(uint32_t)));
+    FMS_TRY(upload_rt(h, c));
+    HIP_TRY(fms::launch_select(c.st, c.b, h->order.as<int>(), h->elig.as<uint8_t>(), h->seed_pos.as<int>(),
+                               h->seed_fg.as<int>()));
+    FMS_TRY(run_iterations(h, c, h->y.as<float>(), cap, p->gamma, p->max_iter, c.bf16, timing, h->seed_fg.as<int>(),
+                           false));
+    if (!checked_bad) {
+      for (int f = 0; f < F; ++f)
+        if (h->hm(f)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+      checked_bad = true;
+    }
+    std::vector<int> msel(static_cast<size_t>(F)), steps(static_cast<size_t>(F));
+    std::vector<unsigned long long> upd(static_cast<size_t>(F));
+    for (int f = 0; f < F; ++f) {
+      msel[f] = h->hm(f)[META_NSEL];
+      steps[f] = h->hm(f)[META_STEPS];
+      upd[f] = h->hm64(f, F);
+    }
+    int host_cand = 0;
+    if (on_device) {
+      // Prune (Alg. 2): window counts at the converged endpoints (in the
+      // precision of the iteration; the BF16 form recounts its refined modes
+      // in FP32 at the end), ranking by count (descending) then seed
+      // position, greedy suppression against the modes kept so far and the
+      // candidates accepted before.
+      HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
+      HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, pick_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
+                                h->y.as<float>(), h->cand.as<int>(), cap, h->pcount.as<int>(), h->counts.as<int>(),
+                                META_NCAND));
+      HIP_TRY(fms::launch_rank(c.st, c.b, h->cand.as<int>(), h->counts.as<int>(), h->sorted.as<int>(),
+                               h->scount.as<int>()));
+      HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, h->sorted.as<int>(),
+                                  nullptr, cap, h->bits.as<uint32_t>(), false, META_NCAND, META_NCAND));
+      int kmax = 0;
+      for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.rt.want > 0 ? fh.k_modes : 0);
+      if (kmax > 0)
+        HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, nullptr,
+                                    h->modes.as<float>(), kmax, h->bits.as<uint32_t>(), true, META_NCAND, -1));
+      HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->sorted.as<int>(),
+                                 h->scount.as<int>(), META_NCAND, META_NACC, c.dp, h->modes.as<float>(),
+                                 h->mode_counts.as<int>()));
+    } else {
+      std::vector<int> conv;
+      FMS_TRY(host_converged(h, c, conv));
+      FMS_TRY(host_prune(h, c, conv));
+      host_cand = int(conv.size());
+    }
+    // Coverage by the new modes, and the pool left to seed; then one read of
+    // the counters.
+    HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, h->x32.as<float>(), h->modes.as<float>(), META_NACC, 0,
+                               h->elig.as<uint8_t>(), h->rank.as<int>(), nullptr));
+    FMS_TRY(read_meta(h, c));
+    for (int f = 0; f < F; ++f) {
+      FrameHost& fh = c.fr[f];
+      if (!fh.live) continue;
+      const int* hm = h->hm(f);
+      const int m = msel[f];
+      if (m == 0) {
+        fh.live = false;
+        continue;
+      }
+      fh.n_used += m;
+      fh.sx.rounds += 1;
+      fh.sx.seeds_used += m;
+      fh.sx.iterations_total += steps[f];
+      fh.sx.seed_pixel_updates += int64_t(upd[f]);
+      fh.sx.n_discarded += m - (on_device ? hm[META_NCAND] : host_cand);
+      fh.k_modes += hm[META_NACC];
+      const bool left = hm[META_LEFT] > 0;
+      // Controller (Sec. 3.2.4).
+      bool go_on = false;
+      fh.have_nmin = eq19_n_min(p->p_target, fh.k_modes, fh.r, &fh.nmin);
+      if (left && (!fh.have_nmin || double(fh.n_seeds) < p->big_l * fh.nmin)) {
+        fh.n_seeds *= 2;
+        go_on = true;
+      }
+      fh.live = go_on;
+    }
+  }
+
+  int kmax = 0;
+  for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.k_modes);
+  if (c.bf16 && p->refine_iters > 0 && kmax > 0) {
+    // BF16 form: every frame's modes are refined in FP32 (refine_iters steps,
+    // then FP32 iteration under the early stop; modes still moving at the
+    // stop are dropped), recounted, and a mode that now falls inside the
+    // window of an earlier kept mode is dropped (acceptance order decides).
+    if (kmax > fms::kRankMax) return FMS_ERR_UNSUPPORTED;
+    for (FrameHost& fh : c.fr) {
+      fh.rt = fms::RoundTab{};
+      fh.rt.nact = fh.k_modes;
+      fh.rt.want = fh.k_modes;
+    }
+    HIP_TRY(h->bits.ensure(size_t(layout_bits(c, false)) * sizeof(uint32_t)));
+    FMS_TRY(upload_rt(h, c));
+    float* mrows = h->modes.as<float>();
+    HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), kmax));
+    FMS_TRY(run_refine(h, c, mrows, h->ident.as<int>(), kmax, p->refine_iters, p->max_iter, p->gamma, true, timing));
+    // The refined rows move to the (now free) centre buffer; the settled ones
+    // are recounted in FP32 and pruned in index order back into the mode
+    // rows.
+    HIP_TRY(fms::launch_copy_rows(c.st, c.b, mrows, h->y.as<float>(), c.dp, kmax));
+    HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NSEL, true, 0));
+    HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
+    HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, kmax), h->x32.p, h->y.as<float>(),
+                              h->cand.as<int>(), kmax, h->pcount.as<int>(), h->counts.as<int>(), META_NCAND));
+    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), kmax, h->cand.as<int>(),
+                                nullptr, kmax, h->bits.as<uint32_t>(), false, META_NCAND, META_NCAND));
+    HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->cand.as<int>(),
+                               h->counts.as<int>(), META_NCAND, META_NACC, c.dp, mrows, h->mode_counts.as<int>()));
+    FMS_TRY(read_meta(h, c));
+    for (int f = 0; f < F; ++f) {
+      FrameHost& fh = c.fr[f];
+      const int settled = h->hm(f)[META_NCAND], kept = h->hm(f)[META_NACC];
+      fh.sx.refine_unconverged += fh.k_modes - settled;
+      fh.sx.refine_merged += settled - kept;
+      fh.k_modes = kept;
+    }
+  }
+
+  // Labels (Alg. 2): most similar mode, lowest index on ties; count pixels
+  // farther than h from every mode.
+  for (FrameHost& fh : c.fr) {
+    fh.rt = fms::RoundTab{};
+    fh.rt.k_modes = fh.k_modes;
+  }
+  FMS_TRY(upload_rt(h, c));
+  HIP_TRY(fms::launch_set_slot(c.st, c.b, META_LEFT, false, 0));
+  HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, h->x32.as<float>(), h->modes.as<float>(), -1, 1, nullptr, nullptr,
+                             h->fg_idx.as<int>()));
+  FMS_TRY(read_meta(h, c));
+  for (int f = 0; f < F; ++f) {
+    FrameHost& fh = c.fr[f];
+    fh.sx.n_uncovered = fh.g.n > 0 ? h->hm(f)[META_LEFT] : 0;
+    fh.sx.n_min = fh.have_nmin ? fh.nmin : std::numeric_limits<double>::quiet_NaN();
+    int64_t next = fh.n_seeds;
+    if (fh.have_nmin && double(fh.n_seeds) > p->big_h * fh.nmin) next = fh.n_seeds - int64_t(std::ceil(fh.nmin));
+    fh.sx.n_state_out = int32_t(std::min<int64_t>(next, std::numeric_limits<int32_t>::max()));
+  }
   return FMS_OK;
 }
 
-double tol_of(const fms_params* p) { return p->conv_tol > 0.0 ? p->conv_tol : p->bandwidth / 1000.0; }
+// Every frame's modes (rt.k_modes uploaded) to the packed outputs at rows
+// off[f].
+fms_status write_modes(fms_handle h, Call& c, float* modes_out, int32_t* counts_out, const int* off) {
+  int kmax = 0;
+  for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.k_modes);
+  if (kmax == 0) return FMS_OK;
+  FMS_TRY(upload_ints(h, c, h->out_off.p, off, size_t(c.F)));
+  HIP_TRY(fms::launch_modes_out(c.st, c.b, h->modes.as<float>(), h->mode_counts.as<int>(), c.dp, c.dim,
+                                h->out_off.as<int>(), modes_out, counts_out, kmax));
+  return FMS_OK;
+}
+
+void fill_stats(const Call& c, fms_stats* stats) {
+  if (!stats) return;
+  for (int f = 0; f < c.F; ++f) stats[f] = c.fr[f].sx;
+  // Kernel timing covers the whole call; it is reported with the first frame.
+  for (int k = 0; k < 2; ++k) {
+    stats[0].step_ms[k] = c.tm.step_ms[k];
+    stats[0].step_updates[k] = c.tm.step_updates[k];
+    stats[0].step_launches[k] = c.tm.step_launches[k];
+  }
+}
+
+fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames, int32_t dim,
+                      const fms_params* p, Call& c) {
+  if (!h || n_frames < 1 || !frames) return FMS_ERR_INVALID_ARG;
+  for (int f = 0; f < n_frames; ++f) FMS_TRY(check_frame(frames[f], dim));
+  FMS_TRY(check_params(p));
+  c.st = static_cast<hipStream_t>(stream);
+  c.F = n_frames;
+  c.dim = dim;
+  c.dp = pad_dim(dim);
+  c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
+  set_tiling(c, p);
+  return setup_call(h, c, frames, p);
+}
+
+fms_frame frame_of(const float* emb, int64_t ps, int64_t cs, const uint8_t* mask, int32_t height, int32_t width,
+                   double bandwidth, int32_t n_state_in, int32_t* labels) {
+  fms_frame f;
+  f.emb = emb;
+  f.pixel_stride = ps;
+  f.channel_stride = cs;
+  f.mask = mask;
+  f.height = height;
+  f.width = width;
+  f.bandwidth = bandwidth;
+  f.n_state_in = n_state_in;
+  f.labels = labels;
+  return f;
+}
 
 }  // namespace
 
@@ -638,12 +937,7 @@ fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
   fms_handle h = new (std::nothrow) fms_handle_s();
   if (!h) return FMS_ERR_HIP;
   h->device = device_ordinal;
-  if (hipHostMalloc(reinterpret_cast<void**>(&h->hmeta), (META_COUNT + 4) * sizeof(int), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess ||
-
-      h->meta.ensure(META_COUNT * sizeof(int)) != hipSuccess ||
-      h->meta64.ensure(4 * sizeof(unsigned long long)) != hipSuccess) {
+  if (hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
     fms_destroy(h);
     return FMS_ERR_HIP;
   }
@@ -655,15 +949,16 @@ fms_status fms_destroy(fms_handle h) {
   if (!h) return FMS_OK;
   DeviceGuard guard(h->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&h->blk,   &h->fg_idx, &h->x32,     &h->x32t,        &h->x16,     &h->x16t,     &h->order,
-                    &h->rank, &h->elig, &h->y, &h->yc0, &h->yc1, &h->active, &h->next_active, &h->state, &h->iters,
-                    &h->seed_pos, &h->seed_fg, &h->ident, &h->cand, &h->counts, &h->pcount, &h->partial,
-                    &h->bits, &h->blocked, &h->acc, &h->sorted, &h->scount, &h->modes, &h->mode_counts, &h->meta, &h->meta64};
+  DevBuf* bufs[] = {&h->blk,    &h->fg_idx,  &h->x32,        &h->x32t,    &h->x16,         &h->x16t,
+                    &h->order,  &h->rank,    &h->elig,       &h->y,       &h->yc0,         &h->yc1,
+                    &h->active, &h->next_active, &h->state,  &h->iters,   &h->seed_pos,    &h->seed_fg,
+                    &h->ident,  &h->cand,    &h->counts,     &h->sorted,  &h->scount,      &h->pcount,
+                    &h->partial, &h->bits,   &h->acc,        &h->modes,   &h->mode_counts, &h->meta,
+                    &h->meta64, &h->geo,     &h->rt,         &h->out_off};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
-  if (h->hmeta) (void)hipHostFree(h->hmeta);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
-  if (h->hstage) (void)hipHostFree(h->hstage);
+  for (PinBuf* b : {&h->hmeta, &h->hgeo, &h->hrt, &h->hoff, &h->hstage}) b->release();
   delete h;
   return FMS_OK;
 }
@@ -674,7 +969,36 @@ fms_status fms_seed_order(fms_handle h, void* stream, int32_t n, uint64_t seed, 
   DeviceGuard guard(h->device);
   uint64_t keys[4];
   round_keys(seed, keys);
-  HIP_TRY(fms::launch_seed_order(static_cast<hipStream_t>(stream), n, half_bits(n), keys, order, nullptr));
+  HIP_TRY(fms::launch_seed_order_plain(static_cast<hipStream_t>(stream), n, half_bits(n), keys, order));
+  return FMS_OK;
+}
+
+fms_status fms_cluster_batch(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames, int32_t dim,
+                             const fms_params* p, float* modes, int32_t* mode_counts, int32_t k_max,
+                             int32_t* mode_offsets, fms_stats* stats) {
+  if (!h || !frames || n_frames < 1 || !mode_offsets || k_max < 0 || (k_max > 0 && !modes))
+    return FMS_ERR_INVALID_ARG;
+  for (int f = 0; f < n_frames; ++f)
+    if (!frames[f].labels) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  Call c;
+  FMS_TRY(begin_call(h, stream, n_frames, frames, dim, p, c));
+  FMS_TRY(cluster_frames(h, c, p));
+  int64_t total = 0;
+  std::vector<int> off(static_cast<size_t>(c.F));
+  for (int f = 0; f < c.F; ++f) {
+    off[f] = int(total);
+    mode_offsets[f] = int32_t(total);
+    total += c.fr[f].k_modes;
+  }
+  mode_offsets[c.F] = int32_t(std::min<int64_t>(total, std::numeric_limits<int32_t>::max()));
+  fill_stats(c, stats);
+  if (total > k_max) {
+    HIP_TRY(h->wait(c.st));
+    return FMS_ERR_CAPACITY;
+  }
+  FMS_TRY(write_modes(h, c, modes, mode_counts, off.data()));
+  HIP_TRY(h->wait(c.st));
   return FMS_OK;
 }
 
@@ -682,298 +1006,81 @@ fms_status fms_cluster(fms_handle h, void* stream, const float* emb, int64_t pix
                        const uint8_t* mask, int32_t height, int32_t width, int32_t dim, const fms_params* p,
                        float* modes_out, int32_t* mode_counts_out, int32_t k_max, int32_t* n_modes, int32_t* labels,
                        fms_stats* stats) {
-  fms_status stt = check_frame_args(h, emb, pixel_stride, channel_stride, height, width, dim);
-  if (stt != FMS_OK) return stt;
-  stt = check_params(p);
-  if (stt != FMS_OK) return stt;
-  if (!n_modes || !labels || k_max < 0 || (k_max > 0 && !modes_out)) return FMS_ERR_INVALID_ARG;
-  DeviceGuard guard(h->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t P = int64_t(height) * int64_t(width);
-  fms_stats sx;
-  std::memset(&sx, 0, sizeof(sx));
-  sx.n_min = std::numeric_limits<double>::quiet_NaN();
-  int64_t n_seeds = p->n_state_in > 0 ? p->n_state_in : p->n_initial;
-
-  Frame fr;
-  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
-                      p->precision == FMS_PREC_BF16_REFINE, fr);
-  if (stt != FMS_OK) return stt;
-  set_tiling(fr, p);
-  sx.n_fg = fr.n;
-  HIP_TRY(fms::launch_fill_i32(st, labels, P, -1));
-  if (fr.n == 0) {
-    HIP_TRY(h->wait(st));
-    *n_modes = 0;
-    sx.n_state_out = int32_t(std::min<int64_t>(n_seeds, std::numeric_limits<int32_t>::max()));
-    if (stats) *stats = sx;
-    return FMS_OK;
-  }
-  const int n = fr.n;
-  const float thr = float(1.0 - p->bandwidth);
-  const float tol = float(tol_of(p));
-  const double r = double(n) / double(P);
-  int* meta = h->meta.as<int>();
-
-  // Seed order, coverage and use flags.
-  HIP_TRY(h->order.ensure(size_t(n) * sizeof(int)));
-  HIP_TRY(h->rank.ensure(size_t(n) * sizeof(int)));
-  const size_t elig_bytes = ((size_t(n) + 15) / 16) * 16 + 16;
-  HIP_TRY(h->elig.ensure(elig_bytes));
-  uint64_t keys[4];
-  round_keys(p->seed, keys);
-  HIP_TRY(fms::launch_seed_order(st, n, half_bits(n), keys, h->order.as<int>(), h->rank.as<int>(),
-                                 h->elig.as<uint8_t>(), int(elig_bytes), meta));
-
-  int64_t n_used = 0;
-  int k_modes = 0;
-  bool have_nmin = false;
-  double nmin = 0.0;
-  for (int round = 0; round < p->max_rounds; ++round) {
-    const int64_t want64 = std::min<int64_t>(n_seeds - n_used, n);
-    if (want64 <= 0) break;
-    const int want = int(want64);
-    stt = ensure_round(h, fr, want, p->precision == FMS_PREC_BF16_REFINE);
-    if (stt != FMS_OK) return stt;
-    const bool bf16 = p->precision == FMS_PREC_BF16_REFINE;
-    // Room for every seed of the round to become a mode.
-    stt = grow_modes(h, st, fr, k_modes, want);
-    if (stt != FMS_OK) return stt;
-    HIP_TRY(fms::launch_select(st, h->order.as<int>(), h->elig.as<uint8_t>(), n, want, meta, h->seed_pos.as<int>(),
-                               h->seed_fg.as<int>()));
-    RoundOut ro;
-    const bool on_device = want <= fms::kRankMax;
-    stt = run_iterations(h, st, fr, want, p, thr, tol, ro, !on_device, h->seed_fg.as<int>());
-    if (stt != FMS_OK) return stt;
-    if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
-    const int m = h->hmeta[META_NSEL];
-    if (m == 0) break;
-    n_used += m;
-    sx.rounds += 1;
-    sx.seeds_used += m;
-
-    // Prune (Alg. 2): window counts at the converged endpoints, ranking by
-    // count (descending) then seed position, greedy suppression against the
-    // modes kept so far and the candidates accepted before.
-    int accepted = 0;
-    unsigned long long round_updates = 0;
-    int round_ncand = 0;
-    if (on_device) {
-      Xfer x;
-      stt = ensure_xfer(h, want, k_modes, x);
-      if (stt != FMS_OK) return stt;
-      HIP_TRY(fms::launch_collect(st, h->state.as<uint8_t>(), h->cand.as<int>(), meta));
-      // Ranking counts in the precision of the iteration (the BF16 form
-      // recounts its refined modes in FP32 at the end of the frame).
-      HIP_TRY(fms::launch_count(st, bf16, fr.dp, pick_tiling(fr, bf16, want), fr.geom.n_blocks, fr.n,
-                                bf16 ? h->x16.p : h->x32.p,
-                                h->y.as<float>(), h->cand.as<int>(), m, thr, h->pcount.as<int>(), x.counts, meta,
-                                fms::META_NCAND));
-      HIP_TRY(fms::launch_rank(st, h->cand.as<int>(), x.counts, meta, h->sorted.as<int>(), h->scount.as<int>()));
-      HIP_TRY(fms::launch_simbits(st, fr.dp, h->y.as<float>(), h->sorted.as<int>(), want, h->sorted.as<int>(), nullptr,
-                                  want, thr, x.bits_c, meta, fms::META_NCAND, fms::META_NCAND));
-      if (k_modes > 0)
-        HIP_TRY(fms::launch_simbits(st, fr.dp, h->y.as<float>(), h->sorted.as<int>(), want, nullptr,
-                                    h->modes.as<float>(), k_modes, thr, x.bits_m, meta, fms::META_NCAND, -1));
-      HIP_TRY(fms::launch_greedy(st, x.bits_c, x.words_c, x.bits_m, x.words_m, k_modes, h->y.as<float>(),
-                                 h->sorted.as<int>(), h->scount.as<int>(), meta, fms::META_NCAND, fms::META_NACC,
-                                 fr.dp, h->modes.as<float>(), h->mode_counts.as<int>()));
-    } else {
-      const int nc = int(ro.conv.size());
-      if (nc > 0) {
-        Xfer x;
-        XferHost xh;
-        stt = prune_inputs(h, st, fr, h->y.as<float>(), h->cand.as<int>(), nc, k_modes, thr, true, x, xh);
-        if (stt != FMS_OK) return stt;
-        std::vector<int> ord(nc);
-        for (int a = 0; a < nc; ++a) ord[a] = a;
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return xh.counts[a] > xh.counts[b]; });
-        std::vector<int> acc = greedy_accept(ord, xh, x, k_modes > 0);
-        accepted = int(acc.size());
-        if (accepted > 0) {
-          HIP_TRY(h->acc.ensure(size_t(accepted) * sizeof(int)));
-          int* hacc = reinterpret_cast<int*>(h->hstage);  // staging is free again after the sync above
-          for (int q = 0; q < accepted; ++q) hacc[q] = acc[q];
-          HIP_TRY(hipMemcpyAsync(h->acc.p, hacc, size_t(accepted) * sizeof(int), hipMemcpyHostToDevice, st));
-          HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->cand.as<int>(), x.counts,
-                                           h->acc.as<int>(), accepted, h->modes.as<float>(), h->mode_counts.as<int>(),
-                                           k_modes));
-          HIP_TRY(h->wait(st));
-        }
-      }
-    }
-    const bool acc_on_device = on_device;
-    // Coverage by the new modes, and the pool left to seed; then one read of
-    // the round's counters.
-    HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), k_modes,
-                               k_modes + (acc_on_device ? want : accepted), acc_on_device ? fms::META_NACC : -1, thr,
-                               0, h->elig.as<uint8_t>(), h->rank.as<int>(), meta, nullptr, nullptr));
-    HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(h->hmeta + META_COUNT, h->meta64.p, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                           st));
-    HIP_TRY(h->wait(st));
-    if (acc_on_device) accepted = h->hmeta[fms::META_NACC];
-    if (on_device) {
-      std::memcpy(&round_updates, h->hmeta + META_COUNT, sizeof(round_updates));
-      round_ncand = h->hmeta[fms::META_NCAND];
-      ro.updates = int64_t(round_updates);
-      if (p->timing) ro.step_updates[bf16 ? 1 : 0] += ro.updates;
-      sx.n_discarded += m - round_ncand;
-    } else {
-      sx.n_discarded += m - int(ro.conv.size());
-    }
-    sx.iterations_total += ro.steps;
-    sx.refine_steps += ro.refine_steps;
-    sx.seed_pixel_updates += ro.updates;
-    sx.refine_unconverged += ro.refine_bad;
-    sx.refine_updates += ro.refine_updates;
-    add_timing(sx, ro);
-    k_modes += accepted;
-    const bool left = h->hmeta[META_LEFT] > 0;
-    // Controller (Sec. 3.2.4).
-    bool go_on = false;
-    have_nmin = eq19_n_min(p->p_target, k_modes, r, &nmin);
-    if (left) {
-      if (!have_nmin || double(n_seeds) < p->big_l * nmin) {
-        n_seeds *= 2;
-        go_on = true;
-      }
-    }
-    if (!go_on) break;
-  }
-
-  if (p->precision == FMS_PREC_BF16_REFINE && k_modes > 0 && p->refine_iters > 0) {
-    // BF16 form: the frame's modes are refined in FP32 (refine_iters steps,
-    // then FP32 iteration under the early stop; modes still moving at the
-    // stop are dropped), recounted, and a mode that now falls inside the
-    // window of an earlier kept mode is dropped (acceptance order decides).
-    stt = ensure_round(h, fr, k_modes, true);
-    if (stt != FMS_OK) return stt;
-    RoundOut ro;
-    float* mrows = h->modes.as<float>();
-    HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), k_modes));
-    std::vector<uint8_t> settled;
-    stt = run_refine(h, st, fr, mrows, h->ident.as<int>(), k_modes, p->refine_iters, p->max_iter, thr, tol, p->gamma,
-                     true, p->timing != 0, ro, &settled);
-    if (stt != FMS_OK) return stt;
-    HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), k_modes));
-    Xfer x;
-    XferHost xh;
-    stt = prune_inputs(h, st, fr, mrows, h->ident.as<int>(), k_modes, 0, thr, true, x, xh);
-    if (stt != FMS_OK) return stt;
-    std::vector<int> ord;
-    for (int a = 0; a < k_modes; ++a)
-      if (settled[size_t(a)]) ord.push_back(a);
-    std::vector<int> keep = greedy_accept(ord, xh, x, false);
-    // Rewrite the rows through the (now free) centre buffer, keeping only the
-    // survivors, with their recounted windows.
-    HIP_TRY(fms::launch_copy_rows(st, mrows, fr.dp, h->y.as<float>(), fr.dp, k_modes, fr.dp));
-    HIP_TRY(h->acc.ensure(size_t(k_modes) * sizeof(int)));
-    int* hk = reinterpret_cast<int*>(h->hstage);
-    for (size_t q = 0; q < keep.size(); ++q) hk[q] = keep[q];
-    if (!keep.empty())
-      HIP_TRY(hipMemcpyAsync(h->acc.p, hk, keep.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(fms::launch_append_modes(st, fr.dp, h->y.as<float>(), h->ident.as<int>(), x.counts, h->acc.as<int>(),
-                                     int(keep.size()), mrows, h->mode_counts.as<int>(), 0));
-    HIP_TRY(h->wait(st));
-    sx.refine_merged += int(ord.size()) - int(keep.size());
-    sx.refine_steps += ro.refine_steps;
-    sx.refine_unconverged += ro.refine_bad;
-    sx.refine_updates += ro.refine_updates;
-    add_timing(sx, ro);
-    k_modes = int(keep.size());
-  }
-
-  // Labels (Alg. 2): most similar mode, lowest index on ties; count pixels
-  // farther than h from every mode.
-  HIP_TRY(hipMemsetAsync(meta + META_LEFT, 0, sizeof(int), st));
-  HIP_TRY(fms::launch_assign(st, fr.dp, h->x32.as<float>(), n, h->modes.as<float>(), 0, k_modes, -1, thr, 1, nullptr,
-                             nullptr, meta, h->fg_idx.as<int>(), labels));
-  HIP_TRY(hipMemcpyAsync(h->hmeta + META_LEFT, meta + META_LEFT, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (k_modes > k_max) {
-    HIP_TRY(h->wait(st));
-    *n_modes = k_modes;
-    return FMS_ERR_CAPACITY;
-  }
-  HIP_TRY(fms::launch_copy_rows(st, h->modes.as<float>(), fr.dp, modes_out, dim, k_modes, dim));
-  if (mode_counts_out && k_modes > 0)
-    HIP_TRY(hipMemcpyAsync(mode_counts_out, h->mode_counts.p, size_t(k_modes) * sizeof(int), hipMemcpyDeviceToDevice,
-                           st));
-  HIP_TRY(h->wait(st));
-  *n_modes = k_modes;
-  sx.n_uncovered = h->hmeta[META_LEFT];
-  sx.n_min = have_nmin ? nmin : std::numeric_limits<double>::quiet_NaN();
-  int64_t next = n_seeds;
-  if (have_nmin && double(n_seeds) > p->big_h * nmin) next = n_seeds - int64_t(std::ceil(nmin));
-  sx.n_state_out = int32_t(std::min<int64_t>(next, std::numeric_limits<int32_t>::max()));
-  if (stats) *stats = sx;
-  return FMS_OK;
+  if (!h || !p || !n_modes || !labels || k_max < 0 || (k_max > 0 && !modes_out)) return FMS_ERR_INVALID_ARG;
+  const fms_frame fr =
+      frame_of(emb, pixel_stride, channel_stride, mask, height, width, p->bandwidth, p->n_state_in, labels);
+  int32_t off[2] = {0, 0};
+  const fms_status stt = fms_cluster_batch(h, stream, 1, &fr, dim, p, modes_out, mode_counts_out, k_max, off, stats);
+  if (stt == FMS_OK || stt == FMS_ERR_CAPACITY) *n_modes = off[1];
+  return stt;
 }
 
 fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t pixel_stride, int64_t channel_stride,
                            const uint8_t* mask, int32_t height, int32_t width, int32_t dim, const int32_t* seed_fg,
                            int32_t n_seeds, const fms_params* p, float* endpoints, int32_t* iters, uint8_t* converged,
                            int32_t* counts, fms_stats* stats) {
-  fms_status stt = check_frame_args(h, emb, pixel_stride, channel_stride, height, width, dim);
-  if (stt != FMS_OK) return stt;
-  stt = check_params(p);
-  if (stt != FMS_OK) return stt;
+  if (!h || !p) return FMS_ERR_INVALID_ARG;
   if (n_seeds < 0 || (n_seeds > 0 && (!seed_fg || !endpoints || !iters || !converged))) return FMS_ERR_INVALID_ARG;
   DeviceGuard guard(h->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  fms_stats sx;
-  std::memset(&sx, 0, sizeof(sx));
-  sx.n_min = std::numeric_limits<double>::quiet_NaN();
-  Frame fr;
-  stt = prepare_frame(h, st, emb, pixel_stride, channel_stride, mask, height, width, dim,
-                      p->precision == FMS_PREC_BF16_REFINE, fr);
-  if (stt != FMS_OK) return stt;
-  set_tiling(fr, p);
-  sx.n_fg = fr.n;
+  const fms_frame fr = frame_of(emb, pixel_stride, channel_stride, mask, height, width, p->bandwidth, 0, nullptr);
+  Call c;
+  FMS_TRY(begin_call(h, stream, 1, &fr, dim, p, c));
+  FrameHost& fh = c.fr[0];
   if (n_seeds == 0) {
-    if (stats) *stats = sx;
+    HIP_TRY(h->wait(c.st));
+    fill_stats(c, stats);
     return FMS_OK;
   }
-  if (fr.n == 0) return FMS_ERR_INVALID_ARG;
+  if (fh.g.n == 0) return FMS_ERR_INVALID_ARG;
   const int m = n_seeds;
-  stt = ensure_round(h, fr, m, p->precision == FMS_PREC_BF16_REFINE);
-  if (stt != FMS_OK) return stt;
-  int* meta = h->meta.as<int>();
-  HIP_TRY(hipMemsetAsync(meta + META_BADSEED, 0, sizeof(int), st));
-  HIP_TRY(fms::launch_init_seeds(st, seed_fg, m, fr.n, h->x32.as<float>(), fr.dp, h->y.as<float>(), meta));
-  HIP_TRY(hipMemcpyAsync(h->hmeta, meta, META_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(h->wait(st));
-  if (h->hmeta[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
-  if (h->hmeta[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
-  const float thr = float(1.0 - p->bandwidth);
-  const float tol = float(tol_of(p));
-  RoundOut ro;
-  h->hmeta[META_NSEL] = m;
-  HIP_TRY(hipMemcpyAsync(meta + META_NSEL, h->hmeta + META_NSEL, sizeof(int), hipMemcpyHostToDevice, st));
-  stt = run_iterations(h, st, fr, m, p, thr, tol, ro, true);
-  if (stt != FMS_OK) return stt;
-  if (p->precision == FMS_PREC_BF16_REFINE && !ro.conv.empty()) {
-    stt = run_refine(h, st, fr, h->y.as<float>(), h->cand.as<int>(), int(ro.conv.size()), p->refine_iters,
-                     p->refine_iters, thr, tol, p->gamma, false, p->timing != 0, ro, nullptr);
-    if (stt != FMS_OK) return stt;
+  if (m > fh.g.n) {
+    // More seeds than foreground pixels: widen the (single) frame's centre
+    // region and its chunk partials.
+    const size_t R = size_t(m) + fms::kBlockPix, dp = size_t(c.dp);
+    for (DevBuf* b : {&h->y, &h->yc0, &h->yc1}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
+    for (DevBuf* b : {&h->active, &h->next_active, &h->iters, &h->ident, &h->cand, &h->counts})
+      HIP_TRY(b->ensure(R * sizeof(int)));
+    HIP_TRY(h->state.ensure(R));
+    const size_t PR = size_t(partial_rows(c, m));
+    HIP_TRY(h->pcount.ensure(PR * sizeof(int)));
+    HIP_TRY(h->partial.ensure(PR * dp * sizeof(float)));
+  }
+  HIP_TRY(fms::launch_init_seeds(c.st, seed_fg, m, fh.g.n, h->x32.as<float>(), c.dp, h->y.as<float>(),
+                                 h->meta.as<int>()));
+  fh.rt = fms::RoundTab{};
+  fh.rt.nact = m;
+  FMS_TRY(upload_rt(h, c));
+  FMS_TRY(read_meta(h, c));
+  if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  if (h->hm(0)[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
+  const bool timing = p->timing != 0;
+  FMS_TRY(run_iterations(h, c, h->y.as<float>(), m, p->gamma, p->max_iter, c.bf16, timing, nullptr, true));
+  fh.sx.iterations_total = h->hm(0)[META_STEPS];
+  fh.sx.seed_pixel_updates = int64_t(h->hm64(0, 1));
+  std::vector<int> conv;
+  FMS_TRY(host_converged(h, c, conv));
+  const int nc = int(conv.size());
+  if (c.bf16 && nc > 0 && p->refine_iters > 0) {
+    // The converged seeds take refine_iters FP32 steps; the output keeps the
+    // iteration's converged flags.
+    FMS_TRY(upload_ints(h, c, h->cand.p, conv.data(), size_t(nc)));
+    fh.rt.nact = nc;
+    FMS_TRY(upload_rt(h, c));
+    FMS_TRY(run_refine(h, c, h->y.as<float>(), h->cand.as<int>(), nc, p->refine_iters, p->refine_iters, p->gamma,
+                       false, timing));
   }
   // Window counts of every slot (the output keeps them for converged seeds).
-  HIP_TRY(fms::launch_iota(st, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(st, false, fr.dp, pick_tiling(fr, false, m), fr.geom.n_blocks, fr.n, h->x32.p,
-                            h->y.as<float>(),
-                            h->ident.as<int>(), m, thr, h->pcount.as<int>(), h->counts.as<int>(), nullptr, -1));
-  HIP_TRY(fms::launch_lockstep_out(st, m, fr.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
+  fh.rt.nact = m;
+  FMS_TRY(upload_rt(h, c));
+  HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), m));
+  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, m), h->x32.p, h->y.as<float>(),
+                            h->ident.as<int>(), m, h->pcount.as<int>(), h->counts.as<int>(), -1));
+  HIP_TRY(fms::launch_lockstep_out(c.st, m, c.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
-  HIP_TRY(h->wait(st));
-  sx.iterations_total = ro.steps;
-  sx.refine_steps = ro.refine_steps;
-  sx.seed_pixel_updates = ro.updates;
-  sx.refine_unconverged = ro.refine_bad;
-  sx.refine_updates = ro.refine_updates;
-  add_timing(sx, ro);
-  sx.seeds_used = m;
-  sx.n_discarded = m - int(ro.conv.size());
-  if (stats) *stats = sx;
+  HIP_TRY(h->wait(c.st));
+  fh.sx.seeds_used = m;
+  fh.sx.n_discarded = m - nc;
+  fill_stats(c, stats);
   return FMS_OK;
 }
 

@@ -58,30 +58,83 @@ struct FrameDesc {
   int dp;            // D padded to 32, 64 or 128
 };
 
-// Compaction and normalisation of the foreground (one pass each).
-hipError_t launch_mask_count(hipStream_t s, const uint8_t* mask, int64_t n_pixels, int* block_counts,
-                             int n_mask_blocks);
-hipError_t launch_scan_blocks(hipStream_t s, int* block_counts, int n_mask_blocks, int* meta);
-// Also zeroes the padding rows [n, n_pad) of every layout (n = meta[META_N]).
-hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_offsets, int n_mask_blocks,
-                          int* fg_idx, float* x32, float* x32t, uint16_t* x16, uint16_t* x16t,
-                          int* meta);
+// ------------------------------------------------------------------ batches
+// A call works on F >= 1 frames at once.  Every row-indexed buffer
+// (compacted pixels and their transposed blocks, centres and their
+// compacted rows, lists, flags, counts, modes) holds frame f's rows from
+// geo[f].row0 on; a frame never needs more rows there than its padded
+// foreground count.  Frame f's counters are meta + f * META_COUNT and
+// meta64 + f * kMeta64.  Kernels with many work groups per frame take the
+// frame from blockIdx.y; kernels with one work group per frame from
+// blockIdx.x.
+constexpr int kMeta64 = 4;
+struct FrameGeo {
+  FrameDesc desc;  // source embeddings and mask
+  int64_t mblk0;   // first mask block of the frame (compaction scan)
+  int64_t row0;    // first row in every row-indexed buffer (a multiple of 32)
+  int64_t part0;   // first row of the chunk partials and partial counts
+  int64_t elig0;   // first byte of the eligibility flags (a multiple of 16)
+  int* labels;     // the frame's label map (H*W), or null
+  int n;           // foreground pixels
+  int n_blocks;    // 32-pixel blocks, ceil(n / 32)
+  int half_bits;   // half width of the seed-order Feistel network
+  float thr;       // 1 - h in FP32
+  float tol;       // convergence threshold on the cosine distance
+};
+// Per-frame values the host sets for one round or pass.
+struct RoundTab {
+  int want;          // seeds to select (0: the frame sits the round out)
+  int k_modes;       // modes kept before the pass; new modes start there
+  int nact;          // centre count of a plain (refinement) step or list
+  int words_c;       // row stride of the candidate x candidate bits
+  int words_m;       // row stride of the candidate x mode bits
+  int64_t bits_c0;   // first word of the frame's candidate x candidate bits
+  int64_t bits_m0;   // first word of the frame's candidate x mode bits
+};
+// Device view of a call.  The maxima size the grids; work groups past a
+// frame's own extent return.
+struct Batch {
+  int F;
+  const FrameGeo* geo;
+  const RoundTab* rt;
+  int* meta;
+  unsigned long long* meta64;
+  int max_n;           // largest foreground count
+  int max_blocks;      // largest 32-pixel block count
+  int64_t max_mblk;    // largest mask block count
+};
 constexpr int kMaskBlockPix = 1024;
+// Eligibility bytes a frame of n foreground pixels needs (whole 16-byte
+// words plus one word of zero padding).
+__host__ __device__ inline int64_t elig_len(int n) { return ((int64_t)n + 15) / 16 * 16 + 16; }
 
-// order[j] = foreground ordinal at seed-order position j; rank = its inverse
-// (may be null).  With elig (may be null): elig[j] = 1 for j < n and 0 up to
-// elig_len, and meta[META_CURSOR] = 0.
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank,
-                             uint8_t* elig = nullptr, int elig_len = 0, int* meta = nullptr);
+// Compaction and normalisation of the foreground.  Also zeroes the padding
+// rows [n, n_pad) of every layout (n = meta[META_N] of the frame).
+hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts);
+hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts);
+hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
+                          float* x32t, uint16_t* x16, uint16_t* x16t);
 
-hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
+// order[j] = foreground ordinal at seed-order position j; rank = its
+// inverse.  Also sets every eligibility flag of the frame (1 for j < n, 0
+// for the padding) and the seed cursor to 0.
+hipError_t launch_seed_order(hipStream_t s, const Batch& b, const uint64_t keys[4], int* order, int* rank,
+                             uint8_t* elig);
+// The seed order of a single foreground of n pixels (no flags, no rank).
+hipError_t launch_seed_order_plain(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order);
+
+// Each frame takes its round's rt.want seeds (one work group per frame).
+hipError_t launch_select(hipStream_t s, const Batch& b, const int* order, uint8_t* elig, int* seed_pos,
                          int* seed_fg);
+// Single frame: the given seeds' rows as the starting centres.
 hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, const float* x32, int dp,
                              float* y, int* meta);
-// Start of a round's iteration (identity active list, counters); with
-// seed_fg (may be null) the centres are also loaded from the pixel rows.
-hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
-                              unsigned long long* meta64, const int* seed_fg, const float* x32, int dp, float* y);
+// Start of a round's iteration (identity active list, counters) for at most
+// cap centres per frame.  With nsel_from_rt the frame's centre count is
+// rt.nact (and is written to META_NSEL), else META_NSEL.  With seed_fg (may
+// be null) the centres are also loaded from the pixel rows.
+hipError_t launch_round_begin(hipStream_t s, const Batch& b, int cap, bool nsel_from_rt, int* active,
+                              uint8_t* state, int* iters, const int* seed_fg, const float* x32, int dp, float* y);
 struct StepGeom {
   int n;             // foreground count
   int n_blocks;      // ceil(n / 32)
@@ -97,62 +150,74 @@ StepGeom make_geom(int n);
 // active): it sets meta[META_DONE] and skips the iteration, and the reduce
 // kernel of that iteration sees the flag.  Otherwise its first work group
 // clears the other slot and counts the iteration (META_STEPS, meta64[0]).
-// iter < 0: a plain step whose count is meta[nact_slot] (or the host count).
+// iter < 0: a plain step whose count is meta[nact_slot], or rt.nact when
+// nact_slot < 0.
 struct IterCtl {
-  int* meta;
-  unsigned long long* meta64;
   int nact_slot;
   int iter;
-  int n_fg;
   double gamma;
 };
-// One fused mean-shift step for the active seeds (at most cap): partial
-// window sums per pixel chunk.  Centre a is y[active[a]], or y[a] when
-// active is null (rows already compacted).  ev0/ev1 (may be null) receive
-// the start and end of the kernel itself (hipExtLaunchKernel), not of the
-// launch call.
+// One fused mean-shift step for the active seeds (at most cap per frame):
+// partial window sums per pixel chunk.  Centre a is y[active[a]], or y[a]
+// when active is null (rows already compacted).  ev0/ev1 (may be null)
+// receive the start and end of the kernel itself (hipExtLaunchKernel), not
+// of the launch call.
 size_t shift_partial_rows(const Tiling& t, int cap);
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, const void* xrm,
-                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap, float thr,
+hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
+                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap,
                         float* partial, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Sum partials, renormalise, convergence test and (mode 0) the next active
 // list and converged count.  yc_next (mode 0, may be null) receives the new
-// rows of the seeds that stay active, in next-list order.
-hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
+// rows of the seeds that stay active, in next-list order.  Modes 1-3 are
+// plain (refinement) steps; mode 2 also counts the centres that moved at
+// least tol (or lost their window) in META_REFINE_BAD, and mode 3 besides
+// sets each centre's state (1: its move was below tol, 0: it moved, 2: its
+// window was empty).
+hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, float tol, int mode);
-// Window counts |{i : y[list[a]] . x_i >= thr}| of m centres, on FP32 MFMA
-// (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the BF16 rows; the centres
-// are rounded to BF16); with m_slot >= 0 the count is meta[m_slot] (m is
-// then an upper bound).
-hipError_t launch_count(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, int n_pix, const void* xrm,
-                        const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
-                        int m_slot);
-// Similarity bits between the rows y[rows[0..m)] and the columns y[cols[c]]
-// (or colmat[c]) for c < ncols: row stride simbits_words(ncols) words.  With
-// rows_slot / cols_slot >= 0 the counts come from meta (m, ncols are then
-// upper bounds that size the grid and the row stride).
+                         float* yc_next, const IterCtl& ctl, int cap, int mode);
+// Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
+// frame, on FP32 MFMA (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the
+// BF16 rows; the centres are rounded to BF16).  The frame's count is
+// meta[m_slot], or rt.nact when m_slot < 0.
+hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
+                        const float* y, const int* list, int m, int* pcount, int* counts, int m_slot);
+// Similarity bits between the rows y[rows[0..m)] and either the columns
+// y[cols[c]], c < meta[cols_slot] (mode_cols false; bits at rt.bits_c0, row
+// stride rt.words_c) or the frame's modes before the pass, c < rt.k_modes
+// (mode_cols true; bits at rt.bits_m0, stride rt.words_m).  The row count is
+// meta[rows_slot]; m and ncols bound the grid.
 int simbits_words(int ncols);
-hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
-                          const float* colmat, int ncols, float thr, uint32_t* bits, const int* meta, int rows_slot,
-                          int cols_slot);
-// Pruning on the device: converged list, ranking, greedy suppression.
-hipError_t launch_collect(hipStream_t s, const uint8_t* state, int* cand, int* meta);
-hipError_t launch_rank(hipStream_t s, const int* cand, const int* counts, const int* meta, int* sorted, int* scount);
-hipError_t launch_greedy(hipStream_t s, const uint32_t* bits_c, int words_c, const uint32_t* bits_m, int words_m,
-                         int k0, const float* y, const int* sorted, const int* scount, int* meta, int ncand_slot,
-                         int acc_slot, int dp, float* modes, int* mode_counts);
+hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
+                          const int* cols, const float* modes, int ncols, uint32_t* bits, bool mode_cols,
+                          int rows_slot, int cols_slot);
+// Pruning on the device (one work group per frame): converged list, ranking,
+// greedy suppression.
+hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand);
+hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount);
+hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, const float* y, const int* sorted,
+                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts);
+// Single frame: append accepted candidates (indices into list) at k0.
 hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int* list, const int* counts,
                                const int* acc, int a, float* modes, int* mode_counts, int k0);
-// Coverage (mode = 0) or labels (mode = 1) against modes [k0, k1); both count
-// into meta[META_LEFT] (pixels left to seed, resp. farther than h from every mode).
-hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const float* modes, int k0,
-                         int k1, int k1_slot, float thr, int mode, uint8_t* elig, const int* rank, int* meta,
-                         const int* fg_idx, int* labels);
-hipError_t launch_fill_i32(hipStream_t s, int* p, int64_t count, int value);
-hipError_t launch_iota(hipStream_t s, int* p, int count);
-hipError_t launch_copy_rows(hipStream_t s, const float* src, int src_stride, float* dst, int dst_stride,
-                            int rows, int cols);
+// Coverage (mode 0: against the frame's new modes [rt.k_modes, rt.k_modes +
+// meta[k1_slot])) or labels (mode 1: against modes [0, rt.k_modes)); both
+// count into META_LEFT (pixels left to seed, resp. farther than h from
+// every mode).
+hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
+                         int mode, uint8_t* elig, const int* rank, const int* fg_idx);
+// meta[slot] of every frame to rt.nact (from_rt) or to value.
+hipError_t launch_set_slot(hipStream_t s, const Batch& b, int slot, bool from_rt, int value);
+// Every frame's label map to -1.
+hipError_t launch_fill_labels(hipStream_t s, const Batch& b, int64_t max_pixels);
+// p[row0 + k] = k for k < rt.nact of each frame (max_count bounds the grid).
+hipError_t launch_iota(hipStream_t s, const Batch& b, int* p, int max_count);
+// rt.nact rows of each frame from src to dst (both row-indexed by frame).
+hipError_t launch_copy_rows(hipStream_t s, const Batch& b, const float* src, float* dst, int dp, int max_rows);
+// Frame f's rt.k_modes modes (first dim columns) and counts to the packed
+// outputs at row out_off[f] (device array).
+hipError_t launch_modes_out(hipStream_t s, const Batch& b, const float* modes, const int* mode_counts, int dp,
+                            int dim, const int* out_off, float* out, int* out_counts, int max_rows);
 hipError_t launch_lockstep_out(hipStream_t s, int m, int dp, int dim, const float* y, const uint8_t* state,
                                const int* iters, const int* counts_in, float* endpoints, int* iters_out,
                                uint8_t* conv_out, int* counts_out);

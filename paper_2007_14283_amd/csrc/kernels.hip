@@ -79,9 +79,13 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total, int* sh /
 
 // ------------------------------------------------------------------ compaction
 
-__global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ mask, int64_t n_pixels,
-                                                    int* __restrict__ block_counts) {
+__global__ __launch_bounds__(256) void k_mask_count(const FrameGeo* __restrict__ geo, int* __restrict__ block_counts) {
   __shared__ int red[4];
+  const FrameGeo& g = geo[blockIdx.y];
+  const uint8_t* mask = g.desc.mask;
+  const int64_t n_pixels = g.desc.n_pixels;
+  if ((int64_t)blockIdx.x * kMaskBlockPix >= n_pixels) return;
+  block_counts += g.mblk0;
   const int64_t base = (int64_t)blockIdx.x * kMaskBlockPix + threadIdx.x * 4;
   int c = 0;
   for (int e = 0; e < 4; ++e) {
@@ -94,9 +98,15 @@ __global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ 
   if (threadIdx.x == 0) block_counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Exclusive scan of the per-block counts in place; total into meta[META_N].
-__global__ __launch_bounds__(1024) void k_scan_blocks(int* __restrict__ counts, int nb, int* __restrict__ meta) {
+// Exclusive scan of a frame's per-block counts in place; total into
+// meta[META_N] (one work group per frame).
+__global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict__ geo, int* __restrict__ counts,
+                                                      int* __restrict__ meta) {
   __shared__ int sh[17];
+  const FrameGeo& g = geo[blockIdx.x];
+  const int nb = (int)((g.desc.n_pixels + kMaskBlockPix - 1) / kMaskBlockPix);
+  counts += g.mblk0;
+  meta += (int64_t)blockIdx.x * META_COUNT;
   int carry = 0;
   for (int base = 0; base < nb; base += 1024) {
     int i = base + threadIdx.x;
@@ -115,11 +125,24 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int* __restrict__ counts, 
 // Gather the foreground rows in raster order, normalise them and write the
 // four layouts.  Each thread owns 4 consecutive pixels.
 template <int DP>
-__global__ __launch_bounds__(256) void k_compact(FrameDesc f, const int* __restrict__ block_offsets,
-                                                 int* __restrict__ fg_idx, float* __restrict__ x32,
-                                                 float* __restrict__ x32t, uint16_t* __restrict__ x16,
-                                                 uint16_t* __restrict__ x16t, int* __restrict__ meta) {
+__global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ geo,
+                                                 const int* __restrict__ block_offsets, int* __restrict__ fg_idx,
+                                                 float* __restrict__ x32, float* __restrict__ x32t,
+                                                 uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
+                                                 int* __restrict__ meta) {
   __shared__ int sh[5];
+  const FrameGeo& gf = geo[blockIdx.y];
+  const FrameDesc f = gf.desc;
+  if ((int64_t)blockIdx.x * kMaskBlockPix >= f.n_pixels) return;
+  block_offsets += gf.mblk0;
+  fg_idx += gf.row0;
+  x32 += gf.row0 * DP;
+  x32t += gf.row0 * DP;
+  if (x16) {
+    x16 += gf.row0 * DP;
+    x16t += gf.row0 * DP;
+  }
+  meta += (int64_t)blockIdx.y * META_COUNT;
   const int64_t base = (int64_t)blockIdx.x * kMaskBlockPix + threadIdx.x * 4;
   int flags = 0, c = 0;
   for (int e = 0; e < 4; ++e) {
@@ -222,15 +245,24 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, uint64_t k1, uint64_t k2,
-                                                    uint64_t k3, int* __restrict__ order, int* __restrict__ rank,
-                                                    uint8_t* __restrict__ elig, int elig_len,
+__global__ __launch_bounds__(256) void k_seed_order(const FrameGeo* __restrict__ geo, int n, int b, uint64_t k0,
+                                                    uint64_t k1, uint64_t k2, uint64_t k3, int* __restrict__ order,
+                                                    int* __restrict__ rank, uint8_t* __restrict__ elig,
                                                     int* __restrict__ meta) {
   const int j = blockIdx.x * 256 + threadIdx.x;
-  // Start of a frame's seeding: every position eligible, the tail padding
-  // not, the cursor at 0.
-  if (elig && j < elig_len) elig[j] = j < n ? 1 : 0;
-  if (meta && j == 0) meta[META_CURSOR] = 0;
+  if (geo) {
+    // Start of a frame's seeding: every position eligible, the tail padding
+    // not, the cursor at 0.
+    const FrameGeo& g = geo[blockIdx.y];
+    n = g.n;
+    b = g.half_bits;
+    order += g.row0;
+    rank += g.row0;
+    elig += g.elig0;
+    meta += (int64_t)blockIdx.y * META_COUNT;
+    if (j < elig_len(n)) elig[j] = j < n ? 1 : 0;
+    if (j == 0) meta[META_CURSOR] = 0;
+  }
   if (j >= n) return;
   const uint64_t mask = (1ull << b) - 1;
   const uint64_t keys[4] = {k0, k1, k2, k3};
@@ -247,7 +279,7 @@ __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, u
     y = (left << b) | right;
   } while (y >= (uint64_t)n);
   order[j] = (int)y;
-  if (rank) rank[y] = j;
+  if (geo) rank[y] = j;
 }
 
 // ------------------------------------------------------------------ seeds
@@ -259,13 +291,21 @@ __global__ __launch_bounds__(256) void k_seed_order(int n, int b, uint64_t k0, u
 // eligibility bytes per thread with one 16-byte load (16384 positions per
 // pass).  Positions before the cursor are all ineligible, so a pass may start
 // at the cursor rounded down to 16; `elig` is zero-padded to a multiple of 16.
-__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ order, uint8_t* __restrict__ elig, int n,
-                                                 int want, int* __restrict__ meta, int* __restrict__ seed_pos,
+__global__ __launch_bounds__(1024) void k_select(const FrameGeo* __restrict__ geo, const RoundTab* __restrict__ rt,
+                                                 const int* __restrict__ order, uint8_t* __restrict__ elig,
+                                                 int* __restrict__ meta, int* __restrict__ seed_pos,
                                                  int* __restrict__ seed_fg) {
   constexpr int RUN = 16;
   __shared__ int sh[17];
   __shared__ int s_last;
   __shared__ int s_base;
+  const FrameGeo& g = geo[blockIdx.x];
+  const int n = g.n, want = rt[blockIdx.x].want;
+  order += g.row0;
+  elig += g.elig0;
+  seed_pos += g.row0;
+  seed_fg += g.row0;
+  meta += (int64_t)blockIdx.x * META_COUNT;
   if (threadIdx.x == 0) s_base = meta[META_CURSOR] & ~(RUN - 1);
   __syncthreads();
   int base = s_base;
@@ -592,11 +632,20 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 }
 
 template <bool BF16, bool COUNT, int DP, int ST>
-__global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, const void* __restrict__ xt_,
+__global__ __launch_bounds__(256) void k_shift(Batch bt, const void* __restrict__ xrm_, const void* __restrict__ xt_,
                                                const float* __restrict__ y, const int* __restrict__ active,
-                                               IterCtl ctl, int n_host, Tiling tl, int n_blocks, int n_pix,
-                                               float thr, float* __restrict__ partial, int* __restrict__ pcount) {
-  int* meta = ctl.meta;
+                                               IterCtl ctl, Tiling tl, float* __restrict__ partial,
+                                               int* __restrict__ pcount) {
+  typedef typename std::conditional<BF16, uint16_t, float>::type T;
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
+  const T* xrm = static_cast<const T*>(xrm_) + g.row0 * DP;
+  const T* xt = xt_ ? static_cast<const T*>(xt_) + g.row0 * DP : nullptr;
+  y += g.row0 * DP;
+  if (active) active += g.row0;
+  if (partial) partial += g.part0 * DP;
+  if (pcount) pcount += g.part0;
   int n_act;
   if (ctl.iter >= 0) {
     if (meta[META_DONE]) return;
@@ -611,13 +660,13 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
     if (first) {
       meta[META_ACT + ((ctl.iter + 1) & 1)] = 0;
       meta[META_STEPS] += 1;
-      ctl.meta64[0] += (unsigned long long)n_act * (unsigned long long)ctl.n_fg;
+      bt.meta64[(int64_t)f * kMeta64] += (unsigned long long)n_act * (unsigned long long)g.n;
     }
   } else {
-    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : n_host;
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   if (n_act <= 0) return;
-  shift_body<BF16, COUNT, DP, ST>(xrm_, xt_, y, active, n_act, tl, n_blocks, n_pix, thr, partial, pcount,
+  shift_body<BF16, COUNT, DP, ST>(xrm, xt, y, active, n_act, tl, g.n_blocks, g.n, g.thr, partial, pcount,
                                   (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -633,7 +682,8 @@ __global__ __launch_bounds__(256) void k_shift(const void* __restrict__ xrm_, co
 //   mode 0: iterate, freezing converged seeds: next active list and
 //           converged count (the early stop is taken by the next step).
 //   mode 1: refine step (no freezing).  mode 2: refine step that also counts
-//           the seeds whose move stayed >= tol.
+//           the seeds whose move stayed >= tol.  mode 3: as mode 2, and it
+//           sets each seed's state to its last-move test.
 // Reduce/renormalise/converge the active seeds' tiles owned by work group wg
 // of nwg.  Returns (in every thread) this group's number of newly converged
 // seeds (mode 0).  next_ctr receives the appends to next_active.
@@ -739,7 +789,10 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
       if (lane == 0 && bc) atomicAdd(&s_conv, __popcll(bc));
     } else if (head) {
       if (dead) state[slot] = 2;
-      if (mode == 2 && (dead || !(delta < tol))) atomicAdd(refine_bad, 1);
+      if (mode >= 2) {
+        if (mode == 3 && !dead) state[slot] = delta < tol ? 1 : 0;
+        if (dead || !(delta < tol)) atomicAdd(refine_bad, 1);
+      }
     }
     __syncthreads();
   }
@@ -747,12 +800,21 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
 }
 
 template <int DP>
-__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const int* __restrict__ active,
-                                                float* __restrict__ y, uint8_t* __restrict__ state,
-                                                int* __restrict__ iters, int* __restrict__ next_active,
-                                                float* __restrict__ yc_next, IterCtl ctl, int n_host, int n_blocks,
-                                                Tiling tl, float tol, int mode) {
-  int* meta = ctl.meta;
+__global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restrict__ partial,
+                                                const int* __restrict__ active, float* __restrict__ y,
+                                                uint8_t* __restrict__ state, int* __restrict__ iters,
+                                                int* __restrict__ next_active, float* __restrict__ yc_next,
+                                                IterCtl ctl, Tiling tl, int mode) {
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
+  partial += g.part0 * DP;
+  active += g.row0;
+  y += g.row0 * DP;
+  state += g.row0;
+  iters += g.row0;
+  if (next_active) next_active += g.row0;
+  if (yc_next) yc_next += g.row0 * DP;
   int n_act;
   int* next_ctr = nullptr;
   if (ctl.iter >= 0) {
@@ -760,20 +822,23 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     n_act = meta[META_ACT + (ctl.iter & 1)];
     next_ctr = meta + META_ACT + ((ctl.iter + 1) & 1);
   } else {
-    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : n_host;
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, yc_next, next_ctr,
-                                   meta + META_REFINE_BAD, n_act, tl, n_blocks, tol, mode, (int)blockIdx.x,
+                                   meta + META_REFINE_BAD, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
                                    (int)gridDim.x);
   if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
 }
 
 // Sum the per-chunk window counts of each centre (one wave per centre).
-__global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ pcount, int m, int n_blocks, Tiling tl,
-                                                       const int* __restrict__ meta, int m_slot,
+__global__ __launch_bounds__(256) void k_reduce_counts(Batch bt, const int* __restrict__ pcount, Tiling tl, int m_slot,
                                                        int* __restrict__ counts) {
-  if (m_slot >= 0) m = meta[m_slot];
-  const int n_chunks = plan_chunks(m, tl, n_blocks).n_chunks;
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  const int m = m_slot >= 0 ? bt.meta[(int64_t)f * META_COUNT + m_slot] : bt.rt[f].nact;
+  pcount += g.part0;
+  counts += g.row0;
+  const int n_chunks = plan_chunks(m, tl, g.n_blocks).n_chunks;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (a >= m) return;
   int c = 0;
@@ -785,12 +850,21 @@ __global__ __launch_bounds__(256) void k_reduce_counts(const int* __restrict__ p
 // Start of a round: the selected seeds become the active list.  With
 // seed_fg, centre k also starts at pixel row seed_fg[k] of x32.
 template <int DP>
-__global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ active, uint8_t* __restrict__ state,
-                                                     int* __restrict__ iters, int* __restrict__ meta,
-                                                     unsigned long long* __restrict__ meta64,
+__global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel_from_rt, int* __restrict__ active,
+                                                     uint8_t* __restrict__ state, int* __restrict__ iters,
                                                      const int* __restrict__ seed_fg, const float* __restrict__ x32,
                                                      float* __restrict__ y) {
-  const int m = meta[META_NSEL];
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
+  unsigned long long* meta64 = bt.meta64 + (int64_t)f * kMeta64;
+  active += g.row0;
+  state += g.row0;
+  iters += g.row0;
+  y += g.row0 * DP;
+  x32 += g.row0 * DP;
+  if (seed_fg) seed_fg += g.row0;
+  const int m = nsel_from_rt ? bt.rt[f].nact : meta[META_NSEL];
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < m && k < cap) {
     active[k] = k;
@@ -804,6 +878,7 @@ __global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ 
     }
   }
   if (k == 0) {
+    if (nsel_from_rt) meta[META_NSEL] = m;
     meta[META_ACT] = m;
     meta[META_ACT + 1] = 0;
     meta[META_NCONV] = 0;
@@ -816,19 +891,30 @@ __global__ __launch_bounds__(256) void k_round_begin(int cap, int* __restrict__ 
 
 // Similarity bits: bit c of row j is set when row vector j and column
 // vector c are inside each other's window (dot >= thr).  Rows are
-// y[rows[j]]; columns are y[cols[c]] (cols != null) or the rows of `colmat`.
+// y[rows[j]]; columns are y[cols[c]] (cols != null) or the frame's modes.
 // A wave owns 64 columns and 16 rows; each lane keeps its column vector in
 // registers and reads the (wave-uniform) row vectors.  Row stride: `words`
 // 32-bit words, a multiple of 2.
 template <int DP>
-__global__ __launch_bounds__(256) void k_simbits(const float* __restrict__ y, const int* __restrict__ rows, int m,
+__global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restrict__ y, const int* __restrict__ rows,
                                                  const int* __restrict__ cols, const float* __restrict__ colmat,
-                                                 int ncols, float thr, uint32_t* __restrict__ bits, int words,
-                                                 const int* __restrict__ meta, int rows_slot, int cols_slot) {
+                                                 uint32_t* __restrict__ bits, int rows_slot, int cols_slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (rows_slot >= 0) m = meta[rows_slot];
-  if (cols_slot >= 0) ncols = meta[cols_slot];
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  const RoundTab& tab = bt.rt[f];
+  const int* meta = bt.meta + (int64_t)f * META_COUNT;
+  const int m = meta[rows_slot];
+  const int ncols = cols ? meta[cols_slot] : tab.k_modes;
+  const int words = cols ? tab.words_c : tab.words_m;
+  const float thr = g.thr;
+  y += g.row0 * DP;
+  rows += g.row0;
+  if (cols) cols += g.row0;
+  if (colmat) colmat += g.row0 * DP;
+  bits += cols ? tab.bits_c0 : tab.bits_m0;
   const int col_tiles = words / 2;
+  if (col_tiles == 0 || (int)blockIdx.x >= col_tiles * ((m + 63) / 64)) return;
   const int ct = blockIdx.x % col_tiles, rt = blockIdx.x / col_tiles;
   const int c = ct * 64 + lane;
   float xc[DP];
@@ -863,9 +949,13 @@ __global__ __launch_bounds__(256) void k_simbits(const float* __restrict__ y, co
 
 // Converged slots of the round, ascending (= seed-order order), and their
 // number in meta[META_NCAND].  One 1024-thread block.
-__global__ __launch_bounds__(1024) void k_collect(const uint8_t* __restrict__ state, int* __restrict__ cand,
-                                                  int* __restrict__ meta) {
+__global__ __launch_bounds__(1024) void k_collect(Batch bt, const uint8_t* __restrict__ state,
+                                                  int* __restrict__ cand) {
   __shared__ int sh[17];
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
+  state += g.row0;
+  cand += g.row0;
   const int m = meta[META_NSEL];
   int base = 0;
   for (int k0 = 0; k0 < m; k0 += 1024) {
@@ -882,11 +972,15 @@ __global__ __launch_bounds__(1024) void k_collect(const uint8_t* __restrict__ st
 // Rank the nc candidates by window count (descending), then by index
 // (ascending, = seed position): sorted[r] = cand[a_r], scount[r] = count.
 // Bitonic sort of 64-bit keys in LDS; nc <= kRankMax.
-__global__ __launch_bounds__(1024) void k_rank(const int* __restrict__ cand, const int* __restrict__ counts,
-                                               const int* __restrict__ meta, int* __restrict__ sorted,
-                                               int* __restrict__ scount) {
+__global__ __launch_bounds__(1024) void k_rank(Batch bt, const int* __restrict__ cand, const int* __restrict__ counts,
+                                               int* __restrict__ sorted, int* __restrict__ scount) {
   __shared__ unsigned long long key[kRankMax];
-  const int nc = meta[META_NCAND];
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  cand += g.row0;
+  counts += g.row0;
+  sorted += g.row0;
+  scount += g.row0;
+  const int nc = bt.meta[(int64_t)blockIdx.x * META_COUNT + META_NCAND];
   int np = 1;
   while (np < nc) np <<= 1;
   for (int i = threadIdx.x; i < np; i += 1024) {
@@ -926,15 +1020,24 @@ __global__ __launch_bounds__(1024) void k_rank(const int* __restrict__ cand, con
 // least the first undecided candidate, and every decision equals the
 // sequential one whatever order the passes observe.  The accepted rows are
 // appended to the mode set at k0; their number goes to meta[acc_slot].
-__global__ __launch_bounds__(1024) void k_greedy(const uint32_t* __restrict__ bits_c, int words_c,
-                                                 const uint32_t* __restrict__ bits_m, int words_m, int k0,
+__global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __restrict__ bits,
                                                  const float* __restrict__ y, const int* __restrict__ sorted,
-                                                 const int* __restrict__ scount, int* __restrict__ meta,
-                                                 int ncand_slot, int acc_slot, int dp, float* __restrict__ modes,
-                                                 int* __restrict__ mode_counts) {
+                                                 const int* __restrict__ scount, int ncand_slot, int acc_slot, int dp,
+                                                 float* __restrict__ modes, int* __restrict__ mode_counts) {
   __shared__ uint8_t st[kRankMax];
   __shared__ int s_open;
   __shared__ int sh[17];
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  const RoundTab& tab = bt.rt[blockIdx.x];
+  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
+  const uint32_t* bits_c = bits + tab.bits_c0;
+  const uint32_t* bits_m = bits + tab.bits_m0;
+  const int words_c = tab.words_c, words_m = tab.words_m, k0 = tab.k_modes;
+  y += g.row0 * dp;
+  sorted += g.row0;
+  scount += g.row0;
+  modes += g.row0 * dp;
+  mode_counts += g.row0;
   const int nc = meta[ncand_slot];
   for (int r = threadIdx.x; r < nc; r += 1024) {
     uint8_t v = 0;
@@ -1015,17 +1118,31 @@ __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __res
   if (d == 0) mode_counts[k0 + q] = counts[cand];
 }
 
-// Coverage (mode 0): pixels within h of a mode in [k0, k1) stop being
-// eligible seeds (elig[rank[i]] = 0); count the pixels still eligible.  Labels (mode 1):
-// most similar mode in [k0, k1), lowest index on ties.
+// Coverage (mode 0): pixels within h of a new mode, [rt.k_modes,
+// rt.k_modes + meta[k1_slot]), stop being eligible seeds (elig[rank[i]] =
+// 0); count the pixels still eligible.  Labels (mode 1): most similar mode
+// in [0, rt.k_modes), lowest index on ties; count the pixels farther than h
+// from every mode.
 template <int DP>
-__global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int n, const float* __restrict__ modes,
-                                                int k0, int k1, int k1_slot, float thr, int mode,
+__global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restrict__ x,
+                                                const float* __restrict__ modes, int k1_slot, int mode,
                                                 uint8_t* __restrict__ elig, const int* __restrict__ rank,
-                                                int* __restrict__ meta, const int* __restrict__ fg_idx,
-                                                int* __restrict__ labels) {
+                                                const int* __restrict__ fg_idx) {
   constexpr int KT = 64;
-  if (k1_slot >= 0) k1 = k0 + meta[k1_slot];
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  const int n = g.n;
+  if ((int)blockIdx.x * 256 >= n) return;
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
+  const int k0 = mode == 0 ? bt.rt[f].k_modes : 0;
+  const int k1 = mode == 0 ? k0 + meta[k1_slot] : bt.rt[f].k_modes;
+  const float thr = g.thr;
+  int* labels = g.labels;
+  x += g.row0 * DP;
+  modes += g.row0 * DP;
+  if (elig) elig += g.elig0;
+  if (rank) rank += g.row0;
+  if (fg_idx) fg_idx += g.row0;
   __shared__ float sm[KT * DP];
   const int i = blockIdx.x * 256 + threadIdx.x;
   float xi[DP];
@@ -1067,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int
   } else {
     int far = 0;
     if (i < n) {
-      labels[fg_idx[i]] = arg;
+      if (labels) labels[fg_idx[i]] = arg;
       far = best < thr ? 1 : 0;
     }
     far = wave_sum_i(far);
@@ -1075,22 +1192,45 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_iota(int* __restrict__ p, int count) {
+__global__ __launch_bounds__(256) void k_iota(Batch bt, int* __restrict__ p) {
+  const int f = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < count) p[i] = i;
+  if (i < bt.rt[f].nact) p[bt.geo[f].row0 + i] = i;
 }
 
-__global__ __launch_bounds__(256) void k_fill_i32(int* __restrict__ p, int64_t count, int value) {
+// meta[slot] of every frame from rt.nact (from_rt) or to `value`.
+__global__ __launch_bounds__(256) void k_set_slot(Batch bt, int slot, int from_rt, int value) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f < bt.F) bt.meta[(int64_t)f * META_COUNT + slot] = from_rt ? bt.rt[f].nact : value;
+}
+
+__global__ __launch_bounds__(256) void k_fill_labels(Batch bt) {
+  const FrameGeo& g = bt.geo[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) p[i] = value;
+  if (g.labels && i < g.desc.n_pixels) g.labels[i] = -1;
 }
 
-__global__ __launch_bounds__(256) void k_copy_rows(const float* __restrict__ src, int src_stride,
-                                                   float* __restrict__ dst, int dst_stride, int rows, int cols) {
+__global__ __launch_bounds__(256) void k_copy_rows(Batch bt, const float* __restrict__ src, float* __restrict__ dst,
+                                                   int dp) {
+  const int f = blockIdx.y;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)rows * cols) return;
-  const int64_t rr = t / cols, c = t - rr * cols;
-  dst[rr * dst_stride + c] = src[rr * src_stride + c];
+  if (t >= (int64_t)bt.rt[f].nact * dp) return;
+  const int64_t o = bt.geo[f].row0 * dp + t;
+  dst[o] = src[o];
+}
+
+__global__ __launch_bounds__(256) void k_modes_out(Batch bt, const float* __restrict__ modes,
+                                                   const int* __restrict__ mode_counts, int dp, int dim,
+                                                   const int* __restrict__ out_off, float* __restrict__ out,
+                                                   int* __restrict__ out_counts) {
+  const int f = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = bt.rt[f].k_modes;
+  if (t >= (int64_t)k * dim) return;
+  const int64_t r = t / dim, d = t - r * dim;
+  const int64_t src = bt.geo[f].row0 + r, dst = (int64_t)out_off[f] + r;
+  out[dst * dim + d] = modes[src * dp + d];
+  if (d == 0 && out_counts) out_counts[dst] = mode_counts[src];
 }
 
 __global__ __launch_bounds__(256) void k_lockstep_out(int m, int dp, int dim, const float* __restrict__ y,
@@ -1114,31 +1254,33 @@ __global__ __launch_bounds__(256) void k_lockstep_out(int m, int dp, int dim, co
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t launch_mask_count(hipStream_t s, const uint8_t* mask, int64_t n_pixels, int* block_counts,
-                             int n_mask_blocks) {
-  hipLaunchKernelGGL(k_mask_count, dim3(n_mask_blocks), dim3(256), 0, s, mask, n_pixels, block_counts);
+hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts) {
+  if (b.max_mblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask_count, dim3((unsigned)b.max_mblk, b.F), dim3(256), 0, s, b.geo, block_counts);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_blocks(hipStream_t s, int* block_counts, int n_mask_blocks, int* meta) {
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_counts, n_mask_blocks, meta);
+hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(b.F), dim3(1024), 0, s, b.geo, block_counts, b.meta);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_offsets, int n_mask_blocks,
-                          int* fg_idx, float* x32, float* x32t, uint16_t* x16, uint16_t* x16t, int* meta) {
-  switch (f.dp) {
+hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
+                          float* x32t, uint16_t* x16, uint16_t* x16t) {
+  if (b.max_mblk <= 0) return hipSuccess;
+  const dim3 grid((unsigned)b.max_mblk, b.F);
+  switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_compact<32>, dim3(n_mask_blocks), dim3(256), 0, s, f, block_offsets, fg_idx, x32, x32t,
-                         x16, x16t, meta);
+      hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
+                         b.meta);
       break;
     case 64:
-      hipLaunchKernelGGL(k_compact<64>, dim3(n_mask_blocks), dim3(256), 0, s, f, block_offsets, fg_idx, x32, x32t,
-                         x16, x16t, meta);
+      hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
+                         b.meta);
       break;
     case 128:
-      hipLaunchKernelGGL(k_compact<128>, dim3(n_mask_blocks), dim3(256), 0, s, f, block_offsets, fg_idx, x32,
-                         x32t, x16, x16t, meta);
+      hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
+                         b.meta);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1146,18 +1288,24 @@ hipError_t launch_compact(hipStream_t s, const FrameDesc& f, const int* block_of
   return hipGetLastError();
 }
 
-hipError_t launch_seed_order(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order, int* rank,
-                             uint8_t* elig, int elig_len, int* meta) {
-  if (n <= 0) return hipSuccess;
-  const int span = std::max(n, elig ? elig_len : 0);
-  hipLaunchKernelGGL(k_seed_order, dim3(cdiv(span, 256)), dim3(256), 0, s, n, half_bits, keys[0], keys[1], keys[2],
-                     keys[3], order, rank, elig, elig_len, meta);
+hipError_t launch_seed_order(hipStream_t s, const Batch& b, const uint64_t keys[4], int* order, int* rank,
+                             uint8_t* elig) {
+  if (b.max_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_order, dim3(cdiv(elig_len(b.max_n), 256), b.F), dim3(256), 0, s, b.geo, 0, 0, keys[0],
+                     keys[1], keys[2], keys[3], order, rank, elig, b.meta);
   return hipGetLastError();
 }
 
-hipError_t launch_select(hipStream_t s, const int* order, uint8_t* elig, int n, int want, int* meta, int* seed_pos,
+hipError_t launch_seed_order_plain(hipStream_t s, int n, int half_bits, const uint64_t keys[4], int* order) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_order, dim3(cdiv(n, 256)), dim3(256), 0, s, nullptr, n, half_bits, keys[0], keys[1],
+                     keys[2], keys[3], order, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(hipStream_t s, const Batch& b, const int* order, uint8_t* elig, int* seed_pos,
                          int* seed_fg) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, order, elig, n, want, meta, seed_pos, seed_fg);
+  hipLaunchKernelGGL(k_select, dim3(b.F), dim3(1024), 0, s, b.geo, b.rt, order, elig, b.meta, seed_pos, seed_fg);
   return hipGetLastError();
 }
 
@@ -1168,7 +1316,6 @@ hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, co
                      meta);
   return hipGetLastError();
 }
-
 
 StepGeom make_geom(int n) {
   StepGeom g;
@@ -1220,23 +1367,23 @@ static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
 
 #define FMS_SHIFT_CASE(BFV, CNT, DPV, STV)                                                                       \
   if (ev0 || ev1)                                                                                            \
-    hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, ev0, ev1, 0, xrm, xt, y,    \
-                          active, ctl, n_host, t, n_blocks, n_pix, thr, partial, pcount);                       \
+    hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), grid, dim3(256), 0, s, ev0, ev1, 0, b, xrm, xt, y, active, \
+                          ctl, t, partial, pcount);                                                           \
   else                                                                                                       \
-    hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), dim3(grid), dim3(256), 0, s, xrm, xt, y, active, ctl, n_host, \
-                       t, n_blocks, n_pix, thr, partial, pcount)
+    hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), grid, dim3(256), 0, s, b, xrm, xt, y, active, ctl, t, partial, \
+                       pcount)
 
-static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, const Tiling& t, int n_blocks,
-                                 int n_pix, const void* xrm, const void* xt, const float* y, const int* active,
-                                 const IterCtl& ctl, int n_host, int cap, float thr, float* partial, int* pcount,
-                                 hipEvent_t ev0, hipEvent_t ev1) {
-  if (cap <= 0 || n_blocks <= 0) {
+static hipError_t shift_dispatch(hipStream_t s, const Batch& b, bool bf16, bool count, int dp, const Tiling& t,
+                                 const void* xrm, const void* xt, const float* y, const int* active,
+                                 const IterCtl& ctl, int cap, float* partial, int* pcount, hipEvent_t ev0,
+                                 hipEvent_t ev1) {
+  if (cap <= 0 || b.max_blocks <= 0) {
     // Nothing to launch; the events still mark this point of the stream.
     hipError_t e = ev0 ? hipEventRecord(ev0, s) : hipSuccess;
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
   }
-  const unsigned grid = shift_grid(cap, t, n_blocks);
+  const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
   const int key = (bf16 ? 1000000 : 0) + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
   switch (key) {
     case 3201: FMS_SHIFT_CASE(false, false, 32, 1); break;
@@ -1271,27 +1418,26 @@ static hipError_t shift_dispatch(hipStream_t s, bool bf16, bool count, int dp, c
 }
 #undef FMS_SHIFT_CASE
 
-hipError_t launch_shift(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, const void* xrm,
-                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap, float thr,
+hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
+                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap,
                         float* partial, hipEvent_t ev0, hipEvent_t ev1) {
-  return shift_dispatch(s, bf16, false, dp, t, n_blocks, 0, xrm, xt, y, active, ctl, cap, cap, thr, partial, nullptr,
-                        ev0, ev1);
+  return shift_dispatch(s, b, bf16, false, dp, t, xrm, xt, y, active, ctl, cap, partial, nullptr, ev0, ev1);
 }
 
-hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, const float* partial,
+hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, float tol, int mode) {
+                         float* yc_next, const IterCtl& ctl, int cap, int mode) {
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
-  const ChunkPlan cp = plan_chunks(cap, t, n_blocks);
+  const ChunkPlan cp = plan_chunks(cap, t, b.max_blocks);
   int P = 1;
   while (P * 8 < cp.n_chunks && (dp / 4) * P * 2 <= 256) P <<= 1;
   const int spw = std::max(1, 256 / ((dp / 4) * P));
-  const dim3 grid(cdiv(cap, spw)), block(256);
-#define FMS_REDUCE_CASE(DPV)                                                                                     \
-  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, partial, active, y, state, iters, next_active, yc_next,   \
-                     ctl, cap, n_blocks, t, tol, mode)
+  const dim3 grid(cdiv(cap, spw), b.F), block(256);
+#define FMS_REDUCE_CASE(DPV)                                                                                      \
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, y, state, iters, next_active, yc_next, ctl, \
+                     t, mode)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
@@ -1302,48 +1448,45 @@ hipError_t launch_reduce(hipStream_t s, int dp, int n_blocks, const Tiling& t, c
   return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t s, bool bf16, int dp, const Tiling& t, int n_blocks, int n_pix, const void* xrm,
-                        const float* y, const int* list, int m, float thr, int* pcount, int* counts, const int* meta,
-                        int m_slot) {
-  if (m <= 0 || n_blocks <= 0) return hipSuccess;
-  const IterCtl ctl{const_cast<int*>(meta), nullptr, m_slot, -1, 0, 0.0};
-  hipError_t e = shift_dispatch(s, bf16, true, dp, t, n_blocks, n_pix, xrm, nullptr, y, list, ctl, m, m, thr, nullptr,
-                                pcount, nullptr, nullptr);
+hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
+                        const float* y, const int* list, int m, int* pcount, int* counts, int m_slot) {
+  if (m <= 0 || b.max_blocks <= 0) return hipSuccess;
+  const IterCtl ctl{m_slot, -1, 0.0};
+  hipError_t e = shift_dispatch(s, b, bf16, true, dp, t, xrm, nullptr, y, list, ctl, m, nullptr, pcount, nullptr,
+                                nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4)), dim3(256), 0, s, pcount, m, n_blocks, t, meta, m_slot,
-                     counts);
+  hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4), b.F), dim3(256), 0, s, b, pcount, t, m_slot, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_collect(hipStream_t s, const uint8_t* state, int* cand, int* meta) {
-  hipLaunchKernelGGL(k_collect, dim3(1), dim3(1024), 0, s, state, cand, meta);
+hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand) {
+  hipLaunchKernelGGL(k_collect, dim3(b.F), dim3(1024), 0, s, b, state, cand);
   return hipGetLastError();
 }
 
-hipError_t launch_rank(hipStream_t s, const int* cand, const int* counts, const int* meta, int* sorted, int* scount) {
-  hipLaunchKernelGGL(k_rank, dim3(1), dim3(1024), 0, s, cand, counts, meta, sorted, scount);
+hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount) {
+  hipLaunchKernelGGL(k_rank, dim3(b.F), dim3(1024), 0, s, b, cand, counts, sorted, scount);
   return hipGetLastError();
 }
 
-hipError_t launch_greedy(hipStream_t s, const uint32_t* bits_c, int words_c, const uint32_t* bits_m, int words_m,
-                         int k0, const float* y, const int* sorted, const int* scount, int* meta, int ncand_slot,
-                         int acc_slot, int dp, float* modes, int* mode_counts) {
-  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(1024), 0, s, bits_c, words_c, bits_m, words_m, k0, y, sorted, scount,
-                     meta, ncand_slot, acc_slot, dp, modes, mode_counts);
+hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, const float* y, const int* sorted,
+                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts) {
+  hipLaunchKernelGGL(k_greedy, dim3(b.F), dim3(1024), 0, s, b, bits, y, sorted, scount, ncand_slot, acc_slot, dp,
+                     modes, mode_counts);
   return hipGetLastError();
 }
 
 int simbits_words(int ncols) { return std::max(2, ((ncols + 63) / 64) * 2); }
 
-hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows, int m, const int* cols,
-                          const float* colmat, int ncols, float thr, uint32_t* bits, const int* meta, int rows_slot,
-                          int cols_slot) {
+hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
+                          const int* cols, const float* modes, int ncols, uint32_t* bits, bool mode_cols,
+                          int rows_slot, int cols_slot) {
   if (m <= 0 || ncols <= 0) return hipSuccess;
-  const int words = simbits_words(ncols);
-  const unsigned grid = (unsigned)((words / 2) * cdiv(m, 64));
+  const unsigned grid = (unsigned)((simbits_words(ncols) / 2) * cdiv(m, 64));
+  const int* c = mode_cols ? nullptr : cols;
+  const float* cm = mode_cols ? modes : nullptr;
 #define FMS_SIM_CASE(DPV)                                                                                        \
-  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid), dim3(256), 0, s, y, rows, m, cols, colmat, ncols, thr, bits, words, \
-                     meta, rows_slot, cols_slot)
+  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid, b.F), dim3(256), 0, s, b, y, rows, c, cm, bits, rows_slot, cols_slot)
   switch (dp) {
     case 32: FMS_SIM_CASE(32); break;
     case 64: FMS_SIM_CASE(64); break;
@@ -1354,19 +1497,19 @@ hipError_t launch_simbits(hipStream_t s, int dp, const float* y, const int* rows
   return hipGetLastError();
 }
 
-hipError_t launch_round_begin(hipStream_t s, int cap, int* active, uint8_t* state, int* iters, int* meta,
-                              unsigned long long* meta64, const int* seed_fg, const float* x32, int dp, float* y) {
-  const dim3 grid(cdiv(std::max(cap, 1), 256)), block(256);
+hipError_t launch_round_begin(hipStream_t s, const Batch& b, int cap, bool nsel_from_rt, int* active,
+                              uint8_t* state, int* iters, const int* seed_fg, const float* x32, int dp, float* y) {
+  const dim3 grid(cdiv(std::max(cap, 1), 256), b.F), block(256);
+  const int fr = nsel_from_rt ? 1 : 0;
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_round_begin<32>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32, y);
+      hipLaunchKernelGGL(k_round_begin<32>, grid, block, 0, s, b, cap, fr, active, state, iters, seed_fg, x32, y);
       break;
     case 64:
-      hipLaunchKernelGGL(k_round_begin<64>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32, y);
+      hipLaunchKernelGGL(k_round_begin<64>, grid, block, 0, s, b, cap, fr, active, state, iters, seed_fg, x32, y);
       break;
     case 128:
-      hipLaunchKernelGGL(k_round_begin<128>, grid, block, 0, s, cap, active, state, iters, meta, meta64, seed_fg, x32,
-                         y);
+      hipLaunchKernelGGL(k_round_begin<128>, grid, block, 0, s, b, cap, fr, active, state, iters, seed_fg, x32, y);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1382,23 +1525,19 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
   return hipGetLastError();
 }
 
-hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const float* modes, int k0, int k1, int k1_slot, float thr,
-                         int mode, uint8_t* elig, const int* rank, int* meta, const int* fg_idx,
-                         int* labels) {
-  if (n <= 0) return hipSuccess;
-  const dim3 grid(cdiv(n, 256)), block(256);
+hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
+                         int mode, uint8_t* elig, const int* rank, const int* fg_idx) {
+  if (b.max_n <= 0) return hipSuccess;
+  const dim3 grid(cdiv(b.max_n, 256), b.F), block(256);
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
-                         fg_idx, labels);
+      hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
       break;
     case 64:
-      hipLaunchKernelGGL(k_assign<64>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
-                         fg_idx, labels);
+      hipLaunchKernelGGL(k_assign<64>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
       break;
     case 128:
-      hipLaunchKernelGGL(k_assign<128>, grid, block, 0, s, x32, n, modes, k0, k1, k1_slot, thr, mode, elig, rank, meta,
-                         fg_idx, labels);
+      hipLaunchKernelGGL(k_assign<128>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1406,23 +1545,34 @@ hipError_t launch_assign(hipStream_t s, int dp, const float* x32, int n, const f
   return hipGetLastError();
 }
 
-hipError_t launch_iota(hipStream_t s, int* p, int count) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_iota, dim3(cdiv(count, 256)), dim3(256), 0, s, p, count);
+hipError_t launch_set_slot(hipStream_t s, const Batch& b, int slot, bool from_rt, int value) {
+  hipLaunchKernelGGL(k_set_slot, dim3(cdiv(b.F, 256)), dim3(256), 0, s, b, slot, from_rt ? 1 : 0, value);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_i32(hipStream_t s, int* p, int64_t count, int value) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(count, 256)), dim3(256), 0, s, p, count, value);
+hipError_t launch_fill_labels(hipStream_t s, const Batch& b, int64_t max_pixels) {
+  if (max_pixels <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_labels, dim3(cdiv(max_pixels, 256), b.F), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_rows(hipStream_t s, const float* src, int src_stride, float* dst, int dst_stride, int rows,
-                            int cols) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_rows, dim3(cdiv((int64_t)rows * cols, 256)), dim3(256), 0, s, src, src_stride, dst,
-                     dst_stride, rows, cols);
+hipError_t launch_iota(hipStream_t s, const Batch& b, int* p, int max_count) {
+  if (max_count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(cdiv(max_count, 256), b.F), dim3(256), 0, s, b, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(hipStream_t s, const Batch& b, const float* src, float* dst, int dp, int max_rows) {
+  if (max_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_rows, dim3(cdiv((int64_t)max_rows * dp, 256), b.F), dim3(256), 0, s, b, src, dst, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_modes_out(hipStream_t s, const Batch& b, const float* modes, const int* mode_counts, int dp,
+                            int dim, const int* out_off, float* out, int* out_counts, int max_rows) {
+  if (max_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_modes_out, dim3(cdiv((int64_t)max_rows * dim, 256), b.F), dim3(256), 0, s, b, modes,
+                     mode_counts, dp, dim, out_off, out, out_counts);
   return hipGetLastError();
 }
 

@@ -47,20 +47,21 @@ def test_default_params_and_status_strings():
 def test_struct_layouts_match_header(tmp_path):
     from paper_2007_14283_amd import _binding as B
     src = tmp_path / "layout.c"
-    fields_p = [f for f, _ in B.FmsParams._fields_]
-    fields_s = [f for f, _ in B.FmsStats._fields_]
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fms.h"', "int main(void) {",
-             'printf("%zu %zu\\n", sizeof(fms_params), sizeof(fms_stats));']
-    lines += [f'printf("%zu\\n", offsetof(fms_params, {f}));' for f in fields_p]
-    lines += [f'printf("%zu\\n", offsetof(fms_stats, {f}));' for f in fields_s]
+    structs = [("fms_params", B.FmsParams), ("fms_stats", B.FmsStats), ("fms_frame", B.FmsFrame)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fms.h"', "int main(void) {"]
+    want = []
+    for cname, py in structs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(py))
+        for f, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(py, f).offset)
     lines += ["return 0; }"]
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    assert vals[0] == ctypes.sizeof(B.FmsParams) and vals[1] == ctypes.sizeof(B.FmsStats)
-    want = [getattr(B.FmsParams, f).offset for f in fields_p] + [getattr(B.FmsStats, f).offset for f in fields_s]
-    assert vals[2:] == want
+    assert vals == want
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -1,0 +1,144 @@
+"""GPU parity of the batched entry point (fms_cluster_batch): each frame of a
+batch of uneven frames against the FP64 oracle run on that frame alone, and
+against the single-frame call.  Same tolerances as the single-frame tests:
+FP32 modes within 1e-5 (1 - cos), labels exact outside the counted exempt
+sets; BF16 + refine modes are FP64 fixed points and cover >= 90 % of the
+oracle's modes within 1e-3."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cluster as C
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+BF16_TOL = 1e-3
+
+# D = 32 frames of different sizes, cell counts and noise (so different
+# bandwidths by the same 99.9 % rule), one of them tiny.
+SPECS = [
+    synth.MID,
+    dataclasses.replace(synth.MID, height=96, width=128, n_cells=10, sigma=0.03, seed=7),
+    dataclasses.replace(synth.MID, height=64, width=160, n_cells=8, sigma=0.07, seed=11),
+    dataclasses.replace(synth.MID, height=24, width=20, n_cells=2, seed=5),
+]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2007_14283_amd as fms
+    fms.library()
+    return fms
+
+
+@pytest.fixture(scope="module")
+def frames():
+    return [synth.make_frame(s) for s in SPECS]
+
+
+@pytest.fixture(scope="module")
+def oracles(frames):
+    return [C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth)) for f in frames]
+
+
+def _inputs(frames, empty=()):
+    import torch
+    out = []
+    for i, f in enumerate(frames):
+        mask = torch.from_numpy(f.mask).cuda()
+        if i in empty:
+            mask = torch.zeros_like(mask)
+        out.append({"emb": torch.from_numpy(f.emb).cuda(), "mask": mask, "bandwidth": f.bandwidth})
+    return out
+
+
+def test_batch_bandwidths_differ(frames):
+    # The batch mixes bandwidths, so per-frame thresholds are exercised.
+    assert len({f.bandwidth for f in frames}) >= 2
+
+
+def test_batch_fp32_matches_oracle(F, frames, oracles):
+    _say("batch fp32", [f.spec for f in frames])
+    res = F.cluster_batch(_inputs(frames), precision=F.FP32)
+    assert len(res) == len(frames)
+    for f, o, (modes, labels, st) in zip(frames, oracles, res):
+        mm = parity.match_modes(modes.cpu().numpy(), o.modes)
+        lc = parity.compare_labels(labels.cpu().numpy(), o, mm, 1.0 - f.bandwidth)
+        print(f"{f.spec.height}x{f.spec.width} h={f.bandwidth}: modes {len(modes)}/{len(o.modes)} "
+              f"max err {mm.max_error:.2e} labels {lc}")
+        assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+        assert mm.max_error <= FP32_TOL
+        assert lc.mismatched == 0
+        np.testing.assert_array_equal(mm.pairs[:, 0], mm.pairs[:, 1])
+        for k in ("rounds", "seeds_used", "iterations_total", "n_discarded", "n_state_out", "seed_pixel_updates"):
+            assert st[k] == o.stats[k], k
+        np.testing.assert_array_equal(st["mode_counts"].cpu().numpy(), o.mode_counts)
+
+
+def test_batch_equals_single_frame_calls(F, frames):
+    _say("batch vs single", len(frames))
+    inp = _inputs(frames)
+    batch = F.cluster_batch(inp, precision=F.FP32)
+    for x, (bm, bl, bst) in zip(inp, batch):
+        sm, sl, sst = F.cluster(x["emb"], x["mask"], x["bandwidth"], precision=F.FP32)
+        assert bm.shape == sm.shape
+        err = 1.0 - np.sum(bm.cpu().double().numpy() * sm.cpu().double().numpy(), axis=1)
+        assert err.size == 0 or err.max() <= FP32_TOL
+        assert bst["rounds"] == sst["rounds"] and bst["seeds_used"] == sst["seeds_used"]
+        diff = int((bl != sl).sum().item())
+        assert diff == 0, diff
+
+
+def test_batch_bf16_refine(F, frames, oracles):
+    from oracle import meanshift as ms
+    _say("batch bf16")
+    res = F.cluster_batch(_inputs(frames), precision=F.BF16_REFINE)
+    for f, o, (modes, labels, st) in zip(frames, oracles, res):
+        m = modes.cpu().double().numpy()
+        if len(o.modes) == 0:
+            assert len(m) == 0
+            continue
+        m = m / np.linalg.norm(m, axis=1, keepdims=True)
+        _, resid, _ = ms.shift(m, o.x, 1.0 - f.bandwidth)
+        mm = parity.match_modes(modes.cpu().numpy(), o.modes)
+        within = int(np.sum(mm.errors <= BF16_TOL))
+        print(f"{f.spec.height}x{f.spec.width}: {len(m)} modes, max residual {resid.max():.2e}, "
+              f"{within}/{len(o.modes)} oracle modes within 1e-3")
+        assert np.all(resid < f.bandwidth / 1000)
+        assert within >= 0.9 * len(o.modes)
+        assert st["refine_steps"] >= 3
+
+
+def test_batch_with_empty_frame(F, frames, oracles):
+    _say("batch with an empty mask")
+    res = F.cluster_batch(_inputs(frames, empty=(1,)), precision=F.FP32)
+    modes, labels, st = res[1]
+    assert len(modes) == 0
+    assert int((labels != -1).sum().item()) == 0
+    assert st["n_fg"] == 0
+    for i in (0, 2, 3):
+        mm = parity.match_modes(res[i][0].cpu().numpy(), oracles[i].modes)
+        assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
+
+
+def test_batch_capacity_retry(F, frames, oracles):
+    # k_max = 1 forces FMS_ERR_CAPACITY with the required total; the binding
+    # grows the buffer and calls again.
+    _say("batch capacity")
+    res = F.cluster_batch(_inputs(frames), precision=F.FP32, k_max=1)
+    assert [len(r[0]) for r in res] == [len(o.modes) for o in oracles]
+
+
+def test_batch_of_one_is_the_single_frame_path(F, frames, oracles):
+    _say("batch of one")
+    (modes, labels, st), = F.cluster_batch(_inputs(frames[:1]), precision=F.FP32)
+    mm = parity.match_modes(modes.cpu().numpy(), oracles[0].modes)
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
