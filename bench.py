@@ -32,6 +32,9 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-frames", type=int, default=64,
+                    help="frames of the uneven batched workload reported under 'batched' (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--profile-run", action="store_true",
                     help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
                          "reference), then --steps frames of each form; prints a short summary only")
@@ -86,17 +89,26 @@ def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_shift_512x512_d32_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_14283_amd", "csrc", "kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2007_14283_amd", "csrc", n) for n in ("kernels.hip", "fms_internal.h")]
+
+
+def kernel_source_hash():
+    """SHA-256 over the kernel sources (kernels.hip, then fms_internal.h)."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _measured_traffic(dtype):
     """HBM bytes per launch of the fused step from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
-    source has changed since the counters were taken."""
-    import hashlib
+    sources have changed since the counters were taken."""
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        src = kernel_source_hash()
     except OSError:
         return None
     if f"kernels_sha256: {src}" not in text:
@@ -127,6 +139,50 @@ def _roofline(agg, dim, n_fg):
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": ms * 1e3 / launches, "launches": agg["step_launches"][k],
             "flops_per_launch": flops / launches}
+
+
+def _batched(fms, torch, a):
+    """The batched form on the uneven multi-frame workload: every frame of the
+    batch clustered by one fms_cluster_batch call, against the same frames
+    clustered one call at a time in FP32 (the plain form)."""
+    import synth
+    specs = synth.batch_specs(a.batch_frames)
+    frames = [synth.make_frame(sp) for sp in specs]
+    inp = [{"emb": torch.from_numpy(f.emb).cuda(), "mask": torch.from_numpy(f.mask).cuda(),
+            "bandwidth": f.bandwidth} for f in frames]
+    torch.cuda.synchronize()
+    nf = len(frames)
+    sides = sorted({sp.height for sp in specs})
+    out = {"workload": f"{nf} frames, side in {sides}, 10-300 cells, foreground 20-50%, sigma U(0.03, 0.1), "
+                       f"D={specs[0].dim}, per-frame h; frame seeds 0..{nf - 1}",
+           "frames": nf, "n_fg_total": int(sum(f.n_fg for f in frames)), "steps": a.batch_steps}
+    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32)):
+        fms.cluster_batch(inp, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        upd = 0
+        for _ in range(a.batch_steps):
+            res = fms.cluster_batch(inp, precision=prec)
+            upd += sum(r[2]["seed_pixel_updates"] + r[2]["refine_updates"] for r in res)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = fms.cluster_batch(inp, precision=prec, timing=1)[0][2]
+        agg = {k: list(st[k]) for k in ("step_ms", "step_updates", "step_launches")}
+        out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": 1e3 * dt / a.batch_steps,
+                     "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
+                     "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"])}
+    # The plain form: the same frames, one FP32 call each.
+    for x in inp[:2]:
+        fms.cluster(x["emb"], x["mask"], x["bandwidth"], precision=fms.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x in inp:
+        fms.cluster(x["emb"], x["mask"], x["bandwidth"], precision=fms.FP32)
+    torch.cuda.synchronize()
+    out["fp32_one_call_per_frame"] = {"frames_per_s": nf / (time.perf_counter() - t0)}
+    out["bf16_refine_batched_vs_fp32_one_call_per_frame"] = (out["bf16_refine"]["frames_per_s"] /
+                                                             out["fp32_one_call_per_frame"]["frames_per_s"])
+    return out
 
 
 def _cpu_threads():
@@ -194,6 +250,11 @@ def main():
         "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
         "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
     }
+
+    if a.batch_frames > 0:
+        out["batched"] = _batched(fms, torch, a)
+        print(f"batched: {out['batched']['bf16_refine']['frames_per_s']:.1f} frames/s (BF16+refine)",
+              file=sys.stderr, flush=True)
 
     if not a.no_cpu:
         from oracle import cluster as C

@@ -186,7 +186,7 @@ typedef struct {
  *                 mode_offsets[n_frames] is the required total.
  *  stats          host, n_frames entries, or NULL.  The kernel-timing fields
  *                 describe the whole call and are filled in stats[0] only.
- * A round that needs more than 8192 seeds in one frame is UNSUPPORTED in a
+ * A round that needs more than 16384 seeds in one frame is UNSUPPORTED in a
  * batch of two or more frames.
  * Errors: INVALID_ARG, UNSUPPORTED, BAD_INPUT, CAPACITY, HIP. */
 fms_status fms_cluster_batch(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames,

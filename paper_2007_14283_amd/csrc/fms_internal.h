@@ -27,7 +27,7 @@ enum MetaSlot {
 };
 
 // Largest candidate set the single-block rank/greedy kernels take.
-constexpr int kRankMax = 8192;
+constexpr int kRankMax = 16384;
 
 // Work decomposition of the fused step (see plan_chunks in kernels.hip):
 // seeds in groups of `group_seeds`, pixels in chunks of whole 32-pixel
