@@ -17,10 +17,12 @@ meanshift   Normalisation (Eq. 1), the flat-kernel cosine step (Eq. 8, 9, 11),
             mode pruning, coverage and pixel assignment (Alg. 2), and Alg. 1 as
             a brute-force reference for tiny inputs.
 cluster     The whole of Alg. 2 under the online seed optimisation policy.
+unroll      T unrolled steps from given seeds and the exact (almost everywhere)
+            gradient of the result with respect to the raw embeddings.
 
 Parity status: every function is pinned by a CPU test (see the ``tests``
 folder) except the tie-break order of the mode merge, the gamma/max_iter stop
 and the coverage rule, which the paper does not define; both sides implement
 the same reading of them ("parity unpinned" for those three choices).
 """
-from . import seed_order, osop, meanshift, cluster  # noqa: F401
+from . import seed_order, osop, meanshift, cluster, unroll  # noqa: F401

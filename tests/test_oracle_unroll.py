@@ -1,0 +1,122 @@
+"""Pins of the oracle's unrolled mean shift and its gradient (oracle/unroll.py),
+checked against FP64 central finite differences and closed-form properties.
+CPU only."""
+import numpy as np
+import pytest
+
+from oracle import meanshift as ms
+from oracle import unroll as U
+
+
+def _clusters(seed, n_per=20, k=3, dim=5, spread=0.15):
+    rng = np.random.default_rng(seed)
+    centres = rng.normal(size=(k, dim))
+    pts = np.concatenate([c + spread * rng.normal(size=(n_per, dim)) for c in centres])
+    scale = rng.uniform(0.5, 2.0, size=(len(pts), 1))  # raw rows: not unit length
+    return pts * scale
+
+
+def _case(min_margin=1e-4, h=0.3, steps=3, seeds=(0, 7, 21, 33, 50)):
+    # A seeded small problem whose similarities stay clear of the threshold at
+    # every step, so finite differences cannot flip a window membership.
+    for seed in range(200):
+        e = _clusters(seed)
+        seeds = np.array(seeds)
+        _, _, _, margin = U.forward(e, seeds, h, steps)
+        if margin > min_margin:
+            return e, seeds, h, steps
+    raise AssertionError("no case with a clear margin")
+
+
+def _fd(e, seeds, h, steps, targets, eps=1e-7):
+    g = np.zeros_like(e)
+    for i in range(e.shape[0]):
+        for d in range(e.shape[1]):
+            ep = e.copy()
+            em = e.copy()
+            ep[i, d] += eps
+            em[i, d] -= eps
+            g[i, d] = (U.loss(ep, seeds, h, steps, targets) - U.loss(em, seeds, h, steps, targets)) / (2 * eps)
+    return g
+
+
+def test_forward_is_the_plain_step_repeated():
+    e, seeds, h, steps = _case()
+    x = e / np.linalg.norm(e, axis=1, keepdims=True)
+    y = x[seeds]
+    for _ in range(steps):
+        y, _, _ = ms.shift(y, x, 1.0 - h)
+    got, _, _, _ = U.forward(e, seeds, h, steps)
+    np.testing.assert_allclose(got, y, atol=1e-15)
+
+
+def test_gradient_matches_finite_differences():
+    e, seeds, h, steps = _case()
+    rng = np.random.default_rng(1)
+    targets = rng.normal(size=(len(seeds), e.shape[1]))
+    targets /= np.linalg.norm(targets, axis=1, keepdims=True)
+    ga = U.grad(e, seeds, h, steps, targets)
+    gf = _fd(e, seeds, h, steps, targets)
+    assert np.max(np.abs(gf)) > 1e-3  # a non-trivial gradient
+    np.testing.assert_allclose(ga, gf, atol=1e-7, rtol=1e-6)
+
+
+def test_gradient_is_orthogonal_to_each_row_and_scales_inversely():
+    e, seeds, h, steps = _case()
+    g = np.ones((len(seeds), e.shape[1]))
+    ga = U.grad(e, seeds, h, steps, g)
+    np.testing.assert_allclose(np.sum(ga * e, axis=1), 0.0, atol=1e-12)
+    ga2 = U.grad(2.0 * e, seeds, h, steps, g)
+    np.testing.assert_allclose(ga2, ga / 2.0, atol=1e-14)
+
+
+def test_rows_outside_every_last_window_get_no_gradient():
+    # Seeds in two of the three clusters: the third cluster's rows are in no
+    # window.
+    e, seeds, h, steps = _case(seeds=(0, 7, 21, 33))
+    x = e / np.linalg.norm(e, axis=1, keepdims=True)
+    _, y_prev, _, _ = U.forward(e, seeds, h, steps)
+    member = np.any(y_prev @ x.T >= 1.0 - h, axis=0)
+    assert (~member).any() and member.any()
+    ga = U.grad(e, seeds, h, steps, np.ones((len(seeds), e.shape[1])))
+    assert np.all(ga[~member] == 0.0)
+    assert np.all(np.linalg.norm(ga[member], axis=1) > 0.0)
+
+
+def test_single_step_closed_form():
+    # One seed, one step: y = normalize(sum of the members of its window), and
+    # dL/de_i for a member i is (I - x x^T)(I - y y^T) g / (|V| |e_i|).
+    e, seeds, h, _ = _case(steps=1)
+    s0 = seeds[:1]
+    x = e / np.linalg.norm(e, axis=1, keepdims=True)
+    w = (x[s0] @ x.T >= 1.0 - h)[0]
+    v = x[w].sum(axis=0)
+    y = v / np.linalg.norm(v)
+    g = np.arange(1.0, e.shape[1] + 1.0)[None, :]
+    gv = (g[0] - (g[0] @ y) * y) / np.linalg.norm(v)
+    want = np.zeros_like(e)
+    for i in np.nonzero(w)[0]:
+        want[i] = (gv - (gv @ x[i]) * x[i]) / np.linalg.norm(e[i])
+    np.testing.assert_allclose(U.grad(e, s0, h, 1, g), want, atol=1e-14)
+
+
+def test_planted_mistake_is_caught():
+    # Dropping the projection of the renormalisation must break the
+    # finite-difference agreement.
+    e, seeds, h, steps = _case()
+    rng = np.random.default_rng(2)
+    targets = rng.normal(size=(len(seeds), e.shape[1]))
+    x = e / np.linalg.norm(e, axis=1, keepdims=True)
+    y, y_prev, vnorm, _ = U.forward(e, seeds, h, steps)
+    gv_wrong = targets / vnorm[:, None]
+    w = (y_prev @ x.T >= 1.0 - h).astype(float)
+    gx = w.T @ gv_wrong
+    wrong = (gx - np.sum(gx * x, axis=1, keepdims=True) * x) / np.linalg.norm(e, axis=1, keepdims=True)
+    gf = _fd(e, seeds, h, steps, targets)
+    assert np.max(np.abs(wrong - gf)) > 1e-3
+
+
+def test_steps_must_be_positive():
+    e, seeds, h, _ = _case()
+    with pytest.raises(ValueError):
+        U.forward(e, seeds, h, 0)
