@@ -219,6 +219,42 @@ fms_status fms_shift_seeds(fms_handle h, void* stream,
                            float* endpoints, int32_t* iters, uint8_t* converged,
                            int32_t* counts, fms_stats* stats);
 
+/* Differentiable form: `steps` (T >= 1) unrolled FP32 steps of Eq. 8-11 from
+ * the given seeds, every seed taking all T steps (no freezing, no early
+ * stop), for training an embedding network through the clustering.
+ *
+ *  emb, strides, mask, height, width, dim: as fms_cluster.
+ *  seed_fg        device, n_seeds int32 foreground ordinals, each in [0, n).
+ *  bandwidth      h, 0 < h < 2.
+ *  y_out          device, n_seeds*dim FP32: y_T (unit rows).
+ *  y_prev         device, n_seeds*dim FP32: y_{T-1}, kept for the backward.
+ *  v_norm         device, n_seeds FP32: |V_T|, the norm of the last window
+ *                 sum, kept for the backward.
+ * Errors: INVALID_ARG (including a seed index outside [0, n) or an empty
+ * foreground), UNSUPPORTED, BAD_INPUT, HIP. */
+fms_status fms_unroll(fms_handle h, void* stream,
+                      const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                      const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                      const int32_t* seed_fg, int32_t n_seeds, int32_t steps, double bandwidth,
+                      float* y_out, float* y_prev, float* v_norm);
+
+/* Gradient of a loss L(y_T) with respect to the embeddings, given
+ * grad_y = dL/dy_T (device, n_seeds*dim FP32) and the forward's y_out,
+ * y_prev and v_norm.  The window weights are a step function of the
+ * similarity, so only the last step contributes almost everywhere:
+ *   dL/de_p = (I - x_p x_p^T) sum_j [y_{T-1,j} . x_p >= 1 - h] dL/dV_j / |e_p|,
+ *   dL/dV_j = (I - y_j y_j^T) dL/dy_j / |V_j|,  x_p = e_p / |e_p|.
+ * The windows are recomputed from the embeddings (no kernel matrix is
+ * stored).  grad_emb: device FP32 with the same strides as emb, written
+ * completely (zero on the background).
+ * Errors: INVALID_ARG, UNSUPPORTED, BAD_INPUT, HIP. */
+fms_status fms_unroll_backward(fms_handle h, void* stream,
+                               const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                               const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                               int32_t n_seeds, double bandwidth, const float* y_out,
+                               const float* y_prev, const float* v_norm, const float* grad_y,
+                               float* grad_emb);
+
 /* The seed order: order[j] = foreground ordinal at position j, j in [0, n),
  * a permutation of [0, n) keyed by `seed` (four-round Feistel network whose
  * round keys and round function come from SplitMix64, with cycle walking).

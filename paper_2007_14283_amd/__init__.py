@@ -20,8 +20,8 @@ from typing import Dict, Optional
 
 from . import _binding as B
 
-__all__ = ["Params", "FmsError", "cluster", "cluster_batch", "shift_seeds", "seed_order", "default_params",
-           "library"]
+__all__ = ["Params", "FmsError", "cluster", "cluster_batch", "shift_seeds", "unroll", "seed_order",
+           "default_params", "library"]
 
 FP32 = B.FMS_PREC_FP32
 BF16_REFINE = B.FMS_PREC_BF16_REFINE
@@ -230,6 +230,67 @@ def cluster_batch(frames, *, layout: str = "nhwc", params: Optional[Params] = No
         sd["mode_counts"] = counts[a:b]
         res.append((modes[a:b], outs[i], sd))
     return res
+
+
+_UNROLL_FN = None
+
+
+def _unroll_function():
+    """torch.autograd.Function around fms_unroll / fms_unroll_backward (built
+    on first use so that importing this package does not import torch)."""
+    global _UNROLL_FN
+    if _UNROLL_FN is not None:
+        return _UNROLL_FN
+    import torch
+
+    class Unroll(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, emb, mask, seeds, steps, bandwidth, layout):
+            e, h, w, d, ps, cs = _frame_args(emb.detach(), layout)
+            dev = e.device
+            m, mptr = _mask_arg(mask, h, w, dev)
+            sd = torch.as_tensor(seeds).to(device=dev, dtype=torch.int32).contiguous()
+            ns = int(sd.numel())
+            y = torch.empty((ns, d), dtype=torch.float32, device=dev)
+            yp = torch.empty_like(y)
+            vn = torch.empty((ns,), dtype=torch.float32, device=dev)
+            hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+            st = library().fms_unroll(hdl, _stream_ptr(dev), ctypes.c_void_p(e.data_ptr()), ps, cs,
+                                      ctypes.c_void_p(mptr) if mptr else None, h, w, d,
+                                      ctypes.c_void_p(sd.data_ptr()), ns, steps, bandwidth,
+                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(yp.data_ptr()),
+                                      ctypes.c_void_p(vn.data_ptr()))
+            if st != B.FMS_OK:
+                raise FmsError(st, "fms_unroll")
+            ctx.save_for_backward(e, y, yp, vn)
+            ctx.geom = (m, mptr, h, w, d, ps, cs, ns, bandwidth, hdl, tuple(emb.shape))
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            e, y, yp, vn = ctx.saved_tensors
+            m, mptr, h, w, d, ps, cs, ns, bandwidth, hdl, shape = ctx.geom
+            gy = gy.to(dtype=torch.float32).contiguous()
+            grad = torch.empty_like(e)
+            st = library().fms_unroll_backward(hdl, _stream_ptr(e.device), ctypes.c_void_p(e.data_ptr()), ps, cs,
+                                               ctypes.c_void_p(mptr) if mptr else None, h, w, d, ns, bandwidth,
+                                               ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(yp.data_ptr()),
+                                               ctypes.c_void_p(vn.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                               ctypes.c_void_p(grad.data_ptr()))
+            if st != B.FMS_OK:
+                raise FmsError(st, "fms_unroll_backward")
+            return grad.reshape(shape), None, None, None, None, None
+
+    _UNROLL_FN = Unroll
+    return Unroll
+
+
+def unroll(emb, mask, seeds, steps: int = 10, bandwidth: float = 0.1, *, layout: str = "nhwc"):
+    """y_T of ``steps`` unrolled FP32 mean-shift steps from ``seeds``
+    (foreground ordinals), every seed taking all steps; differentiable with
+    respect to ``emb`` through torch.autograd (fms_unroll_backward).  Returns
+    [m, D] float32."""
+    return _unroll_function().apply(emb, mask, seeds, int(steps), float(bandwidth), layout)
 
 
 def shift_seeds(emb, mask, seeds, *, layout: str = "nhwc", params: Optional[Params] = None, **kw):

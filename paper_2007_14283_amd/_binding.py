@@ -19,7 +19,7 @@ FMS_PREC_BF16_REFINE = 1
 
 # Every entry point declared in include/fms.h.
 EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",
-           "fms_shift_seeds", "fms_seed_order", "fms_status_string")
+           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_seed_order", "fms_status_string")
 
 
 class FmsParams(ctypes.Structure):
@@ -117,6 +117,11 @@ def load(path: str = LIB_PATH):
     lib.fms_shift_seeds.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, vp, i32,
                                     ctypes.POINTER(FmsParams), vp, vp, vp, vp, ctypes.POINTER(FmsStats)]
     lib.fms_shift_seeds.restype = ctypes.c_int
+    f64 = ctypes.c_double
+    lib.fms_unroll.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, vp, i32, i32, f64, vp, vp, vp]
+    lib.fms_unroll.restype = ctypes.c_int
+    lib.fms_unroll_backward.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, i32, f64, vp, vp, vp, vp, vp]
+    lib.fms_unroll_backward.restype = ctypes.c_int
     lib.fms_seed_order.argtypes = [vp, vp, i32, u64, vp]
     lib.fms_seed_order.restype = ctypes.c_int
     lib.fms_status_string.argtypes = [ctypes.c_int]

@@ -156,7 +156,7 @@ struct fms_handle_s {
   int device = 0;
   // Pixel data of the call's frames; every row-indexed buffer holds frame f
   // from row geo[f].row0 on.
-  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig;
+  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig, enorm;
   // Centres of a round, their lists and flags, window counts and ranking.
   DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, sorted, scount;
   DevBuf pcount, partial;
@@ -401,6 +401,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   }
   const size_t R = size_t(std::max<int64_t>(rows, fms::kBlockPix)), dp = size_t(c.dp);
   HIP_TRY(h->fg_idx.ensure(R * sizeof(int)));
+  HIP_TRY(h->enorm.ensure(R * sizeof(float)));
   HIP_TRY(h->x32.ensure(R * dp * sizeof(float)));
   HIP_TRY(h->x32t.ensure(R * dp * sizeof(float)));
   if (c.bf16) {
@@ -421,7 +422,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   if (c.b.max_n > 0)
     HIP_TRY(fms::launch_compact(c.st, c.b, c.dp, h->blk.as<int>(), h->fg_idx.as<int>(), h->x32.as<float>(),
                                 h->x32t.as<float>(), c.bf16 ? h->x16.as<uint16_t>() : nullptr,
-                                c.bf16 ? h->x16t.as<uint16_t>() : nullptr));
+                                c.bf16 ? h->x16t.as<uint16_t>() : nullptr, h->enorm.as<float>()));
   return FMS_OK;
 }
 
@@ -878,6 +879,27 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   return setup_call(h, c, frames, p);
 }
 
+// A single-frame FP32 call with the library's defaults and bandwidth h.
+fms_status begin_single(fms_handle h, void* stream, const fms_frame& fr, int32_t dim, Call& c) {
+  fms_params p;
+  fms_default_params(&p);
+  p.bandwidth = fr.bandwidth;
+  return begin_call(h, stream, 1, &fr, dim, &p, c);
+}
+
+// Widen the (single) frame's centre region and partials for m centres.
+fms_status ensure_centres(fms_handle h, Call& c, int m) {
+  const size_t R = size_t(std::max(m, c.fr[0].n_pad)) + fms::kBlockPix, dp = size_t(c.dp);
+  for (DevBuf* b : {&h->y, &h->yc0, &h->yc1}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
+  for (DevBuf* b : {&h->active, &h->next_active, &h->iters, &h->ident, &h->cand, &h->counts})
+    HIP_TRY(b->ensure(R * sizeof(int)));
+  HIP_TRY(h->state.ensure(R));
+  const size_t PR = size_t(partial_rows(c, std::max(m, c.fr[0].g.n)));
+  HIP_TRY(h->pcount.ensure(PR * sizeof(int)));
+  HIP_TRY(h->partial.ensure(PR * dp * sizeof(float)));
+  return FMS_OK;
+}
+
 fms_frame frame_of(const float* emb, int64_t ps, int64_t cs, const uint8_t* mask, int32_t height, int32_t width,
                    double bandwidth, int32_t n_state_in, int32_t* labels) {
   fms_frame f;
@@ -954,7 +976,7 @@ fms_status fms_destroy(fms_handle h) {
                     &h->active, &h->next_active, &h->state,  &h->iters,   &h->seed_pos,    &h->seed_fg,
                     &h->ident,  &h->cand,    &h->counts,     &h->sorted,  &h->scount,      &h->pcount,
                     &h->partial, &h->bits,   &h->acc,        &h->modes,   &h->mode_counts, &h->meta,
-                    &h->meta64, &h->geo,     &h->rt,         &h->out_off};
+                    &h->meta64, &h->geo,     &h->rt,         &h->out_off, &h->enorm};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
@@ -1081,6 +1103,70 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.sx.seeds_used = m;
   fh.sx.n_discarded = m - nc;
   fill_stats(c, stats);
+  return FMS_OK;
+}
+
+fms_status fms_unroll(fms_handle h, void* stream, const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                      const uint8_t* mask, int32_t height, int32_t width, int32_t dim, const int32_t* seed_fg,
+                      int32_t n_seeds, int32_t steps, double bandwidth, float* y_out, float* y_prev,
+                      float* v_norm) {
+  if (!h || n_seeds < 1 || steps < 1 || !seed_fg || !y_out || !y_prev || !v_norm) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  const fms_frame fr = frame_of(emb, pixel_stride, channel_stride, mask, height, width, bandwidth, 0, nullptr);
+  Call c;
+  FMS_TRY(begin_single(h, stream, fr, dim, c));
+  FrameHost& fh = c.fr[0];
+  if (fh.g.n == 0) return FMS_ERR_INVALID_ARG;
+  const int m = n_seeds;
+  FMS_TRY(ensure_centres(h, c, m));
+  HIP_TRY(fms::launch_init_seeds(c.st, seed_fg, m, fh.g.n, h->x32.as<float>(), c.dp, h->y.as<float>(),
+                                 h->meta.as<int>()));
+  fh.rt = fms::RoundTab{};
+  fh.rt.nact = m;
+  FMS_TRY(upload_rt(h, c));
+  HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), m));
+  FMS_TRY(read_meta(h, c));
+  if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  if (h->hm(0)[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
+  // `steps` plain FP32 steps (no freezing, no early stop); y_{T-1} is kept
+  // and the last step also reports |V_T|.
+  const fms::Tiling& tl = pick_tiling(c, false, m);
+  const fms::IterCtl ctl{-1, -1, 1.0};
+  float* y = h->y.as<float>();
+  for (int t = 0; t < steps; ++t) {
+    if (t + 1 == steps) HIP_TRY(fms::launch_rows_out(c.st, m, c.dp, dim, y, y_prev));
+    HIP_TRY(fms::launch_shift(c.st, c.b, false, c.dp, tl, h->x32.p, h->x32t.p, y, h->ident.as<int>(), ctl, m,
+                              h->partial.as<float>()));
+    HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, tl, h->partial.as<float>(), h->ident.as<int>(), y,
+                               h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, nullptr, ctl, m, 1,
+                               t + 1 == steps ? v_norm : nullptr));
+  }
+  HIP_TRY(fms::launch_rows_out(c.st, m, c.dp, dim, y, y_out));
+  HIP_TRY(h->wait(c.st));
+  return FMS_OK;
+}
+
+fms_status fms_unroll_backward(fms_handle h, void* stream, const float* emb, int64_t pixel_stride,
+                               int64_t channel_stride, const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                               int32_t n_seeds, double bandwidth, const float* y_out, const float* y_prev,
+                               const float* v_norm, const float* grad_y, float* grad_emb) {
+  if (!h || n_seeds < 1 || !y_out || !y_prev || !v_norm || !grad_y || !grad_emb) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  const fms_frame fr = frame_of(emb, pixel_stride, channel_stride, mask, height, width, bandwidth, 0, nullptr);
+  Call c;
+  FMS_TRY(begin_single(h, stream, fr, dim, c));
+  const int m = n_seeds;
+  const int m_pad = (m + 15) / 16 * 16;
+  FMS_TRY(ensure_centres(h, c, m_pad));
+  float* yp = h->yc0.as<float>();
+  float* gv = h->yc1.as<float>();
+  HIP_TRY(fms::launch_rows_in(c.st, m, m_pad, dim, c.dp, y_prev, yp));
+  HIP_TRY(fms::launch_unroll_gv(c.st, m, m_pad, dim, c.dp, y_out, v_norm, grad_y, gv));
+  HIP_TRY(fms::launch_zero_strided(c.st, c.fr[0].g.desc.n_pixels, dim, pixel_stride, channel_stride, grad_emb));
+  HIP_TRY(fms::launch_unroll_grad(c.st, c.b, c.dp, h->x32.as<float>(), h->fg_idx.as<int>(), h->enorm.as<float>(), yp,
+                                  gv, m_pad, dim, pixel_stride, channel_stride, grad_emb));
+  FMS_TRY(read_meta(h, c));
+  if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   return FMS_OK;
 }
 

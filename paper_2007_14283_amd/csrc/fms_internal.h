@@ -112,8 +112,9 @@ __host__ __device__ inline int64_t elig_len(int n) { return ((int64_t)n + 15) / 
 // rows [n, n_pad) of every layout (n = meta[META_N] of the frame).
 hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts);
 hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts);
+// enorm (may be null) receives each row's raw norm |e_i|.
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t);
+                          float* x32t, uint16_t* x16, uint16_t* x16t, float* enorm);
 
 // order[j] = foreground ordinal at seed-order position j; rank = its
 // inverse.  Also sets every eligibility flag of the frame (1 for j < n, 0
@@ -172,10 +173,10 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 // plain (refinement) steps; mode 2 also counts the centres that moved at
 // least tol (or lost their window) in META_REFINE_BAD, and mode 3 besides
 // sets each centre's state (1: its move was below tol, 0: it moved, 2: its
-// window was empty).
+// window was empty).  vnorm (may be null) receives |V| of each centre.
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, int mode);
+                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm = nullptr);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
 // frame, on FP32 MFMA (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the
 // BF16 rows; the centres are rounded to BF16).  The frame's count is
@@ -218,6 +219,19 @@ hipError_t launch_copy_rows(hipStream_t s, const Batch& b, const float* src, flo
 // outputs at row out_off[f] (device array).
 hipError_t launch_modes_out(hipStream_t s, const Batch& b, const float* modes, const int* mode_counts, int dp,
                             int dim, const int* out_off, float* out, int* out_counts, int max_rows);
+// Adjoint of the unrolled steps (single frame, FP32).
+// Rows between the caller's [m][dim] layout and the padded [m_pad][dp] one.
+hipError_t launch_rows_in(hipStream_t s, int m, int m_pad, int dim, int dp, const float* src, float* dst);
+hipError_t launch_rows_out(hipStream_t s, int m, int dp, int dim, const float* src, float* dst);
+// gv = (g - (g . y) y) / |V| per centre, padded to m_pad rows of dp.
+hipError_t launch_unroll_gv(hipStream_t s, int m, int m_pad, int dim, int dp, const float* y, const float* vnorm,
+                            const float* gy, float* gv);
+hipError_t launch_zero_strided(hipStream_t s, int64_t n_pixels, int dim, int64_t ps, int64_t cs, float* out);
+// dL/de of the frame's foreground rows from the last step's windows of the
+// centres yp (m_pad rows) and their dL/dV (gv), written through the strides.
+hipError_t launch_unroll_grad(hipStream_t s, const Batch& b, int dp, const float* x32, const int* fg_idx,
+                              const float* enorm, const float* yp, const float* gv, int m_pad, int dim, int64_t ps,
+                              int64_t cs, float* grad);
 hipError_t launch_lockstep_out(hipStream_t s, int m, int dp, int dim, const float* y, const uint8_t* state,
                                const int* iters, const int* counts_in, float* endpoints, int* iters_out,
                                uint8_t* conv_out, int* counts_out);

@@ -129,13 +129,14 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
                                                  const int* __restrict__ block_offsets, int* __restrict__ fg_idx,
                                                  float* __restrict__ x32, float* __restrict__ x32t,
                                                  uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
-                                                 int* __restrict__ meta) {
+                                                 float* __restrict__ enorm, int* __restrict__ meta) {
   __shared__ int sh[5];
   const FrameGeo& gf = geo[blockIdx.y];
   const FrameDesc f = gf.desc;
   if ((int64_t)blockIdx.x * kMaskBlockPix >= f.n_pixels) return;
   block_offsets += gf.mblk0;
   fg_idx += gf.row0;
+  if (enorm) enorm += gf.row0;
   x32 += gf.row0 * DP;
   x32t += gf.row0 * DP;
   if (x16) {
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
       mx = fmaxf(mx, fabsf(v));
     }
     float vals[DP];
-    float inv = 0.f;
+    float inv = 0.f, norm = 0.f;
     if (finite && mx > 0.f) {
       int ex;
       frexpf(mx, &ex);
@@ -189,11 +190,13 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
         ss = fmaf(v, v, ss);
       }
       inv = 1.0f / sqrtf(ss);
+      norm = ldexpf(sqrtf(ss), ex);  // |e| of the raw row
     } else {
       bad += 1;
       for (int d = 0; d < DP; ++d) vals[d] = 0.f;
     }
     fg_idx[ord] = (int)p;
+    if (enorm) enorm[ord] = norm;
     float* rowp = x32 + (int64_t)ord * DP;
     uint16_t* row16 = x16 ? x16 + (int64_t)ord * DP : nullptr;
     const int64_t blk = ord / kBlockPix, q = ord % kBlockPix;
@@ -691,9 +694,9 @@ template <int DP>
 __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, const int* __restrict__ active,
                                            float* __restrict__ y, uint8_t* __restrict__ state,
                                            int* __restrict__ iters, int* __restrict__ next_active,
-                                           float* __restrict__ yc_next, int* __restrict__ next_ctr,
-                                           int* __restrict__ refine_bad, int n_act, const Tiling& tl, int n_blocks,
-                                           float tol, int mode, int wg, int nwg) {
+                                           float* __restrict__ yc_next, float* __restrict__ vnorm,
+                                           int* __restrict__ next_ctr, int* __restrict__ refine_bad, int n_act,
+                                           const Tiling& tl, int n_blocks, float tol, int mode, int wg, int nwg) {
   constexpr int Q = DP / 4;  // float4 slices per row
   __shared__ float4 part[256];
   __shared__ int s_conv;
@@ -763,6 +766,7 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     const float delta = 0.5f * dd;
     if (owner && !dead) *reinterpret_cast<float4*>(y + (int64_t)slot * DP + 4 * q) = yn;
     const bool head = owner && q == 0;
+    if (vnorm && head) vnorm[slot] = nv;
     if (mode == 0) {
       const bool conv = head && !dead && delta < tol;
       const bool next = head && !dead && !(delta < tol);
@@ -804,7 +808,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
                                                 const int* __restrict__ active, float* __restrict__ y,
                                                 uint8_t* __restrict__ state, int* __restrict__ iters,
                                                 int* __restrict__ next_active, float* __restrict__ yc_next,
-                                                IterCtl ctl, Tiling tl, int mode) {
+                                                float* __restrict__ vnorm, IterCtl ctl, Tiling tl, int mode) {
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
   int* meta = bt.meta + (int64_t)f * META_COUNT;
@@ -815,6 +819,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
   iters += g.row0;
   if (next_active) next_active += g.row0;
   if (yc_next) yc_next += g.row0 * DP;
+  if (vnorm) vnorm += g.row0;
   int n_act;
   int* next_ctr = nullptr;
   if (ctl.iter >= 0) {
@@ -824,7 +829,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
   } else {
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
-  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, yc_next, next_ctr,
+  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, yc_next, vnorm, next_ctr,
                                    meta + META_REFINE_BAD, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
                                    (int)gridDim.x);
   if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
@@ -1252,6 +1257,155 @@ __global__ __launch_bounds__(256) void k_lockstep_out(int m, int dp, int dim, co
 
 // ------------------------------------------------------------------ launchers
 
+// ------------------------------------------------------------------ adjoint of the unrolled steps
+
+// Rows of m centres between the caller's [m][dim] layout and the padded
+// [m_pad][DP] one (zero padding; rows m..m_pad-1 zero).
+__global__ __launch_bounds__(256) void k_rows_in(int m, int m_pad, int dim, int dp, const float* __restrict__ src,
+                                                 float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)m_pad * dp) return;
+  const int64_t r = t / dp, d = t - r * dp;
+  dst[t] = (r < m && d < dim) ? src[r * dim + d] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_rows_out(int m, int dp, int dim, const float* __restrict__ src,
+                                                  float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)m * dim) return;
+  const int64_t r = t / dim, d = t - r * dim;
+  dst[t] = src[r * dp + d];
+}
+
+// dL/dV of the last step per centre (one wave per centre):
+// gv = (g - (g . y) y) / |V|, the adjoint of the renormalisation y = V / |V|.
+// Rows m..m_pad-1 are zero.
+template <int DP>
+__global__ __launch_bounds__(256) void k_unroll_gv(int m, int m_pad, int dim, const float* __restrict__ y,
+                                                   const float* __restrict__ vnorm, const float* __restrict__ gy,
+                                                   float* __restrict__ gv) {
+  constexpr int PER = DP / 64 > 0 ? DP / 64 : 1;  // dimensions per lane
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= m_pad) return;
+  float yv[PER], gvv[PER];
+  float dot = 0.f;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int d = lane + 64 * k;
+    const bool on = j < m && d < dim;
+    yv[k] = on ? y[(int64_t)j * dim + d] : 0.f;
+    gvv[k] = on ? gy[(int64_t)j * dim + d] : 0.f;
+    dot = fmaf(yv[k], gvv[k], dot);
+  }
+  for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
+  const float inv = j < m ? 1.0f / vnorm[j] : 0.f;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int d = lane + 64 * k;
+    if (d < DP) gv[(int64_t)j * DP + d] = (gvv[k] - dot * yv[k]) * inv;
+  }
+}
+
+// Zero a strided [n_pixels][dim] tensor (element (p, c) at p*ps + c*cs).
+__global__ __launch_bounds__(256) void k_zero_strided(int64_t n_pixels, int dim, int64_t ps, int64_t cs,
+                                                      float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_pixels * dim) return;
+  const int64_t p = t / dim, c = t - p * dim;
+  out[p * ps + c * cs] = 0.f;
+}
+
+// Gradient of the loss with respect to the raw embeddings, for the last of
+// the unrolled steps (the only one whose derivative is not zero almost
+// everywhere):
+//   dL/dx_i = sum_j [yp_j . x_i >= thr] gv_j,   dL/de_i = (I - x_i x_i^T) dL/dx_i / |e_i|.
+// S = Yp X^T and G^T = GV^T W are chained on v_mfma_f32_16x16x4_f32 without
+// storing W: the S accumulator of lane (g, r) holds seeds 4g..4g+3 of pixel
+// r, which is exactly the B operand of the k-steps i = 0..3 of the second
+// product when k-step i pairs lane group g with seed 4g + i.  A wave owns PT
+// tiles of 16 pixels and loops over all seed tiles; no cross-wave
+// reduction.  yp and gv are padded to a multiple of 16 rows with zeros.
+template <int DP, int PT>
+__global__ __launch_bounds__(256) void k_unroll_grad(Batch bt, const float* __restrict__ x32,
+                                                     const int* __restrict__ fg_idx, const float* __restrict__ enorm,
+                                                     const float* __restrict__ yp, const float* __restrict__ gv,
+                                                     int m_pad, int dim, int64_t ps, int64_t cs,
+                                                     float* __restrict__ grad) {
+  constexpr int KS = DP / 4;    // k-steps of S (4 dimensions each)
+  constexpr int NDB = DP / 16;  // 16-dimension blocks of G^T
+  const FrameGeo& g0 = bt.geo[0];
+  const int n = g0.n;
+  const float thr = g0.thr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int tile0 = ((int)blockIdx.x * 4 + wave) * PT;  // first 16-pixel tile of this wave
+  if (tile0 * 16 >= n) return;
+  // B operands of S: x[pixel r][4k + g].
+  float xb[PT][KS];
+  f32x4 acc[PT][NDB];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int row = (tile0 + p) * 16 + r;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) xb[p][k] = row < n ? x32[(int64_t)row * DP + 4 * k + g] : 0.f;
+#pragma unroll
+    for (int db = 0; db < NDB; ++db) acc[p][db] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const f32x4 cinit = {-thr, -thr, -thr, -thr};
+  for (int s0 = 0; s0 < m_pad; s0 += 16) {
+    // A operands: yp[seed s0 + r][4k + g]; gv[seed s0 + 4g + i][16 db + r].
+    float ya[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) ya[k] = yp[(int64_t)(s0 + r) * DP + 4 * k + g];
+    float ga[4][NDB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int db = 0; db < NDB; ++db) ga[i][db] = gv[(int64_t)(s0 + 4 * g + i) * DP + 16 * db + r];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      f32x4 sc = cinit;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) sc = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[k], xb[p][k], sc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float w = (fbits(sc[i]) >> 31) ? 0.f : 1.f;
+#pragma unroll
+        for (int db = 0; db < NDB; ++db)
+          acc[p][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[i][db], w, acc[p][db], 0, 0, 0);
+      }
+    }
+  }
+  // Epilogue: lane (g, r) holds dL/dx[pixel r][16 db + 4 g + i].
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int row = (tile0 + p) * 16 + r;
+    const bool live = row < n;
+    float xv[NDB][4];
+    float dot = 0.f;
+#pragma unroll
+    for (int db = 0; db < NDB; ++db) {
+      const float4 u = live ? *reinterpret_cast<const float4*>(x32 + (int64_t)row * DP + 16 * db + 4 * g)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      xv[db][0] = u.x; xv[db][1] = u.y; xv[db][2] = u.z; xv[db][3] = u.w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dot = fmaf(acc[p][db][i], xv[db][i], dot);
+    }
+    dot += __shfl_xor(dot, 16, 64);
+    dot += __shfl_xor(dot, 32, 64);
+    if (!live) continue;
+    const float inv = 1.0f / enorm[row];
+    const int64_t pix = fg_idx[row];
+#pragma unroll
+    for (int db = 0; db < NDB; ++db)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * db + 4 * g + i;
+        if (c < dim) grad[pix * ps + (int64_t)c * cs] = (acc[p][db][i] - dot * xv[db][i]) * inv;
+      }
+  }
+}
+
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts) {
@@ -1266,21 +1420,21 @@ hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts) 
 }
 
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t) {
+                          float* x32t, uint16_t* x16, uint16_t* x16t, float* enorm) {
   if (b.max_mblk <= 0) return hipSuccess;
   const dim3 grid((unsigned)b.max_mblk, b.F);
   switch (dp) {
     case 32:
       hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         b.meta);
+                         enorm, b.meta);
       break;
     case 64:
       hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         b.meta);
+                         enorm, b.meta);
       break;
     case 128:
       hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         b.meta);
+                         enorm, b.meta);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1426,7 +1580,7 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, int mode) {
+                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm) {
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
@@ -1436,8 +1590,8 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
   const int spw = std::max(1, 256 / ((dp / 4) * P));
   const dim3 grid(cdiv(cap, spw), b.F), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                      \
-  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, y, state, iters, next_active, yc_next, ctl, \
-                     t, mode)
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, y, state, iters, next_active, yc_next,   \
+                     vnorm, ctl, t, mode)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
@@ -1582,6 +1736,61 @@ hipError_t launch_lockstep_out(hipStream_t s, int m, int dp, int dim, const floa
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lockstep_out, dim3(cdiv((int64_t)m * dim, 256)), dim3(256), 0, s, m, dp, dim, y, state, iters,
                      counts_in, endpoints, iters_out, conv_out, counts_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_in(hipStream_t s, int m, int m_pad, int dim, int dp, const float* src, float* dst) {
+  if (m_pad <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_in, dim3(cdiv((int64_t)m_pad * dp, 256)), dim3(256), 0, s, m, m_pad, dim, dp, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_out(hipStream_t s, int m, int dp, int dim, const float* src, float* dst) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_out, dim3(cdiv((int64_t)m * dim, 256)), dim3(256), 0, s, m, dp, dim, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_unroll_gv(hipStream_t s, int m, int m_pad, int dim, int dp, const float* y, const float* vnorm,
+                            const float* gy, float* gv) {
+  if (m_pad <= 0) return hipSuccess;
+  const dim3 grid(cdiv(m_pad, 4)), block(256);
+  switch (dp) {
+    case 32: hipLaunchKernelGGL(k_unroll_gv<32>, grid, block, 0, s, m, m_pad, dim, y, vnorm, gy, gv); break;
+    case 64: hipLaunchKernelGGL(k_unroll_gv<64>, grid, block, 0, s, m, m_pad, dim, y, vnorm, gy, gv); break;
+    case 128: hipLaunchKernelGGL(k_unroll_gv<128>, grid, block, 0, s, m, m_pad, dim, y, vnorm, gy, gv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_strided(hipStream_t s, int64_t n_pixels, int dim, int64_t ps, int64_t cs, float* out) {
+  if (n_pixels <= 0 || dim <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_strided, dim3(cdiv(n_pixels * dim, 256)), dim3(256), 0, s, n_pixels, dim, ps, cs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unroll_grad(hipStream_t s, const Batch& b, int dp, const float* x32, const int* fg_idx,
+                              const float* enorm, const float* yp, const float* gv, int m_pad, int dim, int64_t ps,
+                              int64_t cs, float* grad) {
+  if (b.max_n <= 0 || m_pad <= 0) return hipSuccess;
+  const int tiles = (b.max_n + 15) / 16;
+  switch (dp) {
+    case 32:
+      hipLaunchKernelGGL((k_unroll_grad<32, 4>), dim3(cdiv(tiles, 16)), dim3(256), 0, s, b, x32, fg_idx, enorm, yp, gv,
+                         m_pad, dim, ps, cs, grad);
+      break;
+    case 64:
+      hipLaunchKernelGGL((k_unroll_grad<64, 2>), dim3(cdiv(tiles, 8)), dim3(256), 0, s, b, x32, fg_idx, enorm, yp, gv,
+                         m_pad, dim, ps, cs, grad);
+      break;
+    case 128:
+      hipLaunchKernelGGL((k_unroll_grad<128, 1>), dim3(cdiv(tiles, 4)), dim3(256), 0, s, b, x32, fg_idx, enorm, yp,
+                         gv, m_pad, dim, ps, cs, grad);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
