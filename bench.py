@@ -185,6 +185,87 @@ def _batched(fms, torch, a):
     return out
 
 
+def _differentiation(fms, torch, frame, seeds_used, reps=5):
+    """The differentiable form on the 512x512 frame: T = 10 unrolled FP32
+    steps from as many seeds as the policy used (the first positions of the
+    seed order), then the gradient of sum_j y_T,j . t_j (random unit targets)
+    with respect to the embeddings."""
+    T = 10
+    emb = torch.from_numpy(frame.emb).cuda().requires_grad_(True)
+    mask = torch.from_numpy(frame.mask).cuda()
+    seeds = fms.seed_order(frame.n_fg, 0)[:seeds_used].to(torch.int32)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    targets = torch.randn((seeds_used, frame.spec.dim), generator=g)
+    targets = (targets / targets.norm(dim=1, keepdim=True)).cuda()
+
+    def step():
+        emb.grad = None
+        y = fms.unroll(emb, mask, seeds, T, frame.bandwidth)
+        (y * targets).sum().backward()
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    # T forward steps and one backward contraction of the same shape.
+    flops = (T + 1) * seeds_used * frame.n_fg * 4.0 * frame.spec.dim
+    return {"workload": f"512x512 frame, D={frame.spec.dim}, T={T} unrolled FP32 steps from {seeds_used} seeds "
+                        f"(the policy's seed count, first positions of the seed order), backward of "
+                        f"sum(y_T . unit targets) to the embeddings",
+            "seeds": seeds_used, "steps": T, "fwd_bwd_per_s": 1.0 / dt, "ms_fwd_bwd": 1e3 * dt,
+            "tflops": flops / dt / 1e12}
+
+
+def _appendix_a(fms, torch, reps=5):
+    """Appendix A overlap workload: 1000x1000, D=18, eight noise-free discs of
+    diameter 250 pulled together (overlap 0.3), P = 0.95, h = 0.1."""
+    import synth
+    emb, mask, owner, _ = synth.overlap_circles(0.3)
+    e = torch.from_numpy(emb).cuda()
+    m = torch.from_numpy(mask).cuda()
+    out = {"workload": "1000x1000, D=18 (padded to 32), 8 noise-free discs of diameter 250, overlap 0.3, "
+                       "P=0.95, h=0.1", "n_fg": int(mask.sum()), "visible_discs": int(len(set(owner[owner >= 0])))}
+    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32)):
+        fms.cluster(e, m, 0.1, precision=prec, p_target=0.95)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            modes, _, _ = fms.cluster(e, m, 0.1, precision=prec, p_target=0.95)
+        torch.cuda.synchronize()
+        out[name] = {"frames_per_s": reps / (time.perf_counter() - t0), "modes": int(len(modes))}
+    return out
+
+
+def _online_n(fms, torch, n_frames=10):
+    """N carried across a drifting synthetic 512x512 sequence (Sec. 3.2.4),
+    for N_initial in {64, 128, 256} and H in {4, 8, 16}: mean time per frame,
+    mean seeds per frame and the final N (Table 3 / Table 4 style)."""
+    import synth
+    seq = synth.drifting_sequence(synth.PLAIN512, n_frames)
+    inp = [(torch.from_numpy(f.emb).cuda(), torch.from_numpy(f.mask).cuda(), f.bandwidth) for f in seq]
+    torch.cuda.synchronize()
+    rows = []
+    for n0 in (64, 128, 256):
+        for big_h in (4.0, 8.0, 16.0):
+            n_state, seeds, t_tot = 0, 0, 0.0
+            for e, m, h in inp:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, st = fms.cluster(e, m, h, precision=fms.BF16_REFINE, n_initial=n0, big_h=big_h,
+                                       n_state_in=n_state)
+                torch.cuda.synchronize()
+                t_tot += time.perf_counter() - t0
+                n_state = st["n_state_out"]
+                seeds += st["seeds_used"]
+            rows.append({"n_initial": n0, "big_h": big_h, "ms_per_frame": 1e3 * t_tot / n_frames,
+                         "seeds_per_frame": seeds / n_frames, "final_n": n_state})
+    return {"workload": f"{n_frames} frames of the 512x512 generator, cells drifting (1, 2) px per frame, "
+                        f"BF16+refine, N carried", "runs": rows}
+
+
 def _cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -250,6 +331,13 @@ def main():
         "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
         "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
     }
+
+    out["differentiation"] = _differentiation(fms, torch, frame, int(last_f[2]["seeds_used"]))
+    print(f"differentiation: {out['differentiation']['ms_fwd_bwd']:.2f} ms forward+backward",
+          file=sys.stderr, flush=True)
+
+    out["appendix_a"] = _appendix_a(fms, torch)
+    out["online_n"] = _online_n(fms, torch)
 
     if a.batch_frames > 0:
         out["batched"] = _batched(fms, torch, a)

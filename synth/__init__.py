@@ -5,7 +5,7 @@ holds none of the clustering method's arithmetic, so both the oracle and the
 GPU path can consume its frames without sharing any of the method's code.
 """
 from .frames import (FrameSpec, Frame, make_frame, TINY, PLAIN512, PRECISION1024,
-                     MID, batch_specs, circle_points, blob_points, overlap_circles)
+                     MID, batch_specs, drifting_sequence, circle_points, blob_points, overlap_circles)
 
 __all__ = ["FrameSpec", "Frame", "make_frame", "TINY", "PLAIN512", "PRECISION1024", "MID",
-           "batch_specs", "circle_points", "blob_points", "overlap_circles"]
+           "batch_specs", "drifting_sequence", "circle_points", "blob_points", "overlap_circles"]

@@ -196,6 +196,34 @@ def batch_specs(n_frames: int = 64, dim: int = 32) -> List[FrameSpec]:
     return out
 
 
+def drifting_sequence(spec: FrameSpec, n_frames: int, drift=(1, 2)) -> List[Frame]:
+    """A synthetic video: the cells of ``make_frame(spec)`` translated by
+    ``drift`` pixels (dy, dx) per frame with wrap-around, each frame with fresh
+    per-component noise (seed spec.seed * 1000 + t) and fresh background
+    vectors.  The cell vectors, shapes and the bandwidth stay those of frame 0,
+    as for one cell line over a time-lapse."""
+    f0 = make_frame(spec)
+    H, W, D = spec.height, spec.width, spec.dim
+    out = [f0]
+    for t in range(1, n_frames):
+        rng = np.random.Generator(np.random.PCG64(spec.seed * 1000 + t))
+        owner = np.roll(f0.owner, (t * drift[0], t * drift[1]), axis=(0, 1))
+        second = np.roll(f0.second, (t * drift[0], t * drift[1]), axis=(0, 1))
+        fg = owner >= 0
+        base = np.zeros((H, W, D))
+        v = f0.centres[owner[fg]]
+        sec = second[fg]
+        mix = sec >= 0
+        v[mix] = _unit_rows(v[mix] + f0.centres[sec[mix]])
+        base[fg] = _unit_rows(v + rng.standard_normal((int(fg.sum()), D)) * spec.sigma)
+        base[~fg] = _unit_rows(rng.standard_normal((H * W - int(fg.sum()), D)))
+        nf = int(fg.sum())
+        ov = int(np.count_nonzero(fg & (second >= 0)))
+        out.append(Frame(spec, base.astype(np.float32), fg.astype(np.uint8), owner, second, f0.centres,
+                         f0.bandwidth, nf, ov / max(1, nf)))
+    return out
+
+
 def circle_points(seed: int = 0, n: int = 1500, noise: float = 0.02):
     """Two concentric circles with 10 clusters (Sec. 4.1 Data): returns an
     (n, 2) float32 point set and the cluster id of each point.  Clusters sit at
