@@ -84,11 +84,14 @@ typedef struct {
   /* Work decomposition of the fused step (0 = the library's choice): seeds per
    * group (16, 32, 64 or 128; rounded down to a size compiled for the
    * precision and D), target number of (seed group, pixel chunk) items per
-   * step, and cap on pixel chunks.  They change speed only: every result is
-   * the same up to the order of FP32 additions. */
+   * step, cap on pixel chunks, and waves per work group (4, 8 or 16, other
+   * values give FMS_ERR_UNSUPPORTED; a group's waves split its pixel chunk;
+   * halved where the group's LDS would exceed 64 KiB).  They change speed
+   * only: every result is the same up to the order of FP32 additions. */
   int32_t tile_seeds;
   int32_t tile_items;
   int32_t tile_chunks;
+  int32_t tile_waves;
 } fms_params;
 
 /* Per-call statistics (host struct). */

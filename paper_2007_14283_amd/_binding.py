@@ -41,6 +41,7 @@ class FmsParams(ctypes.Structure):
         ("tile_seeds", ctypes.c_int32),
         ("tile_items", ctypes.c_int32),
         ("tile_chunks", ctypes.c_int32),
+        ("tile_waves", ctypes.c_int32),
     ]
 
 

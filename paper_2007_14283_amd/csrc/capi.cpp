@@ -164,8 +164,9 @@ struct fms_handle_s {
   DevBuf bits, acc;
   // Modes found so far (rows of frame f from geo[f].row0 on).
   DevBuf modes, mode_counts;
-  // Per-frame counters and tables.
-  DevBuf meta, meta64, geo, rt, out_off;
+  // Per-frame counters (F * META_COUNT ints, then F * kMeta64 64-bit words,
+  // so that one copy brings both to the host) and tables.
+  DevBuf meta, geo, rt, out_off;
   // Event pairs for timing fused-step launches (created on first use).
   std::vector<hipEvent_t> events;
   hipError_t ensure_events(size_t count) {
@@ -255,6 +256,8 @@ fms_status check_params(const fms_params* p) {
   if (p->n_initial < 1 || p->max_iter < 1 || p->max_rounds < 1 || p->refine_iters < 0) return FMS_ERR_INVALID_ARG;
   if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE) return FMS_ERR_INVALID_ARG;
   if (p->tile_seeds < 0 || p->tile_items < 0 || p->tile_chunks < 0) return FMS_ERR_INVALID_ARG;
+  if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8 && p->tile_waves != 16)
+    return FMS_ERR_UNSUPPORTED;
   return FMS_OK;
 }
 
@@ -277,12 +280,12 @@ const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
 }
 
 void set_tiling(Call& c, const fms_params* p) {
-  c.tile = fms::make_tiling(c.bf16, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
-  c.tile_fp32 = fms::make_tiling(false, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks);
+  c.tile = fms::make_tiling(c.bf16, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, p->tile_waves);
+  c.tile_fp32 = fms::make_tiling(false, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, p->tile_waves);
   // A caller-fixed group size holds for every launch.
   const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
-  c.tile_big = fms::make_tiling(c.bf16, c.dp, big, p->tile_items, p->tile_chunks);
-  c.tile_fp32_big = fms::make_tiling(false, c.dp, big, p->tile_items, p->tile_chunks);
+  c.tile_big = fms::make_tiling(c.bf16, c.dp, big, p->tile_items, p->tile_chunks, p->tile_waves);
+  c.tile_fp32_big = fms::make_tiling(false, c.dp, big, p->tile_items, p->tile_chunks, p->tile_waves);
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.
@@ -321,12 +324,16 @@ fms_status upload_ints(fms_handle h, Call& c, void* dst, const int* src, size_t 
   return FMS_OK;
 }
 
-// All frames' counters (and 64-bit counters) to the host; waits.
+// Bytes of the counters of F frames: META_COUNT ints per frame, then kMeta64
+// 64-bit words per frame (META_COUNT * 4 is a multiple of 8).
+size_t meta_bytes(int F) {
+  static_assert((META_COUNT * sizeof(int)) % sizeof(unsigned long long) == 0, "64-bit counters misaligned");
+  return size_t(F) * (META_COUNT * sizeof(int) + kMeta64 * sizeof(unsigned long long));
+}
+
+// All frames' counters (and 64-bit counters) to the host in one copy; waits.
 fms_status read_meta(fms_handle h, Call& c) {
-  HIP_TRY(hipMemcpyAsync(h->hmeta.p, h->meta.p, size_t(c.F) * META_COUNT * sizeof(int), hipMemcpyDeviceToHost,
-                         c.st));
-  HIP_TRY(hipMemcpyAsync(h->hmeta.as<int>() + size_t(c.F) * META_COUNT, h->meta64.p,
-                         size_t(c.F) * kMeta64 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(hipMemcpyAsync(h->hmeta.p, h->meta.p, meta_bytes(c.F), hipMemcpyDeviceToHost, c.st));
   HIP_TRY(h->wait(c.st));
   return FMS_OK;
 }
@@ -341,10 +348,9 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   HIP_TRY(h->geo.ensure(size_t(F) * sizeof(fms::FrameGeo)));
   HIP_TRY(h->rt.ensure(size_t(F) * sizeof(fms::RoundTab)));
   HIP_TRY(h->out_off.ensure(size_t(F + 1) * sizeof(int)));
-  HIP_TRY(h->meta.ensure(size_t(F) * META_COUNT * sizeof(int)));
-  HIP_TRY(h->meta64.ensure(size_t(F) * kMeta64 * sizeof(unsigned long long)));
+  HIP_TRY(h->meta.ensure(meta_bytes(F)));
   if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
-  HIP_TRY(h->hmeta.ensure(size_t(F) * (META_COUNT * sizeof(int) + kMeta64 * sizeof(unsigned long long))));
+  HIP_TRY(h->hmeta.ensure(meta_bytes(F)));
   HIP_TRY(h->hgeo.ensure(size_t(F) * sizeof(fms::FrameGeo)));
   HIP_TRY(h->hrt.ensure(size_t(F) * sizeof(fms::RoundTab)));
   HIP_TRY(h->hoff.ensure(size_t(F + 1) * sizeof(int)));
@@ -354,7 +360,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   c.b.geo = h->geo.as<fms::FrameGeo>();
   c.b.rt = h->rt.as<fms::RoundTab>();
   c.b.meta = h->meta.as<int>();
-  c.b.meta64 = h->meta64.as<unsigned long long>();
+  c.b.meta64 = reinterpret_cast<unsigned long long*>(h->meta.as<int>() + size_t(F) * META_COUNT);
   int64_t mblk = 0;
   for (int f = 0; f < F; ++f) {
     const fms_frame& in = frames[f];
@@ -374,8 +380,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   }
   HIP_TRY(h->blk.ensure(size_t(std::max<int64_t>(mblk, 1)) * sizeof(int)));
   FMS_TRY(upload_geo(h, c));
-  HIP_TRY(hipMemsetAsync(h->meta.p, 0, size_t(F) * META_COUNT * sizeof(int), c.st));
-  HIP_TRY(hipMemsetAsync(h->meta64.p, 0, size_t(F) * kMeta64 * sizeof(unsigned long long), c.st));
+  HIP_TRY(hipMemsetAsync(h->meta.p, 0, meta_bytes(F), c.st));
   HIP_TRY(fms::launch_mask_count(c.st, c.b, h->blk.as<int>()));
   HIP_TRY(fms::launch_scan_blocks(c.st, c.b, h->blk.as<int>()));
   FMS_TRY(read_meta(h, c));
@@ -976,7 +981,7 @@ fms_status fms_destroy(fms_handle h) {
                     &h->active, &h->next_active, &h->state,  &h->iters,   &h->seed_pos,    &h->seed_fg,
                     &h->ident,  &h->cand,    &h->counts,     &h->sorted,  &h->scount,      &h->pcount,
                     &h->partial, &h->bits,   &h->acc,        &h->modes,   &h->mode_counts, &h->meta,
-                    &h->meta64, &h->geo,     &h->rt,         &h->out_off, &h->enorm};
+                    &h->geo,     &h->rt,         &h->out_off, &h->enorm};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);

@@ -35,14 +35,16 @@ constexpr int kRankMax = 16384;
 // chunks.  Defaults below; fms_params can override them.
 constexpr int kTargetItems = 512;
 constexpr int kMaxChunks = 256;
+constexpr int kWaves = 4;
 struct Tiling {
   int group_seeds;
   int target_items;
   int max_chunks;
+  int waves;  // waves per work group: 4, 8 or 16
 };
 // The tiling used for a (precision, padded D) pair given the caller's
 // requests (0 = default); group sizes round down to a compiled one.
-Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks);
+Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks, int want_waves);
 struct ChunkPlan {
   int groups;
   int n_chunks;

@@ -178,30 +178,31 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
       finite = finite && __builtin_isfinite(v);
       mx = fmaxf(mx, fabsf(v));
     }
-    float vals[DP];
+    // The row is read again (from cache) when written, instead of being held
+    // in registers: at DP = 128 a register copy would spill.
+    const bool ok = finite && mx > 0.f;
     float inv = 0.f, norm = 0.f;
-    if (finite && mx > 0.f) {
-      int ex;
+    int ex = 0;
+    if (ok) {
       frexpf(mx, &ex);
       float ss = 0.f;
-      for (int d = 0; d < DP; ++d) {
-        float v = d < f.dim ? ldexpf(src[(int64_t)d * f.channel_stride], -ex) : 0.f;
-        vals[d] = v;
+      for (int d = 0; d < f.dim; ++d) {
+        const float v = ldexpf(src[(int64_t)d * f.channel_stride], -ex);
         ss = fmaf(v, v, ss);
       }
       inv = 1.0f / sqrtf(ss);
       norm = ldexpf(sqrtf(ss), ex);  // |e| of the raw row
     } else {
       bad += 1;
-      for (int d = 0; d < DP; ++d) vals[d] = 0.f;
     }
+    auto val = [&](int d) { return ok && d < f.dim ? ldexpf(src[(int64_t)d * f.channel_stride], -ex) * inv : 0.f; };
     fg_idx[ord] = (int)p;
     if (enorm) enorm[ord] = norm;
     float* rowp = x32 + (int64_t)ord * DP;
     uint16_t* row16 = x16 ? x16 + (int64_t)ord * DP : nullptr;
     const int64_t blk = ord / kBlockPix, q = ord % kBlockPix;
     for (int d = 0; d < DP; d += 4) {
-      float4 v4 = make_float4(vals[d] * inv, vals[d + 1] * inv, vals[d + 2] * inv, vals[d + 3] * inv);
+      float4 v4 = make_float4(val(d), val(d + 1), val(d + 2), val(d + 3));
       *reinterpret_cast<float4*>(rowp + d) = v4;
       x32t[(blk * DP + d + 0) * kBlockPix + q] = v4.x;
       x32t[(blk * DP + d + 1) * kBlockPix + q] = v4.y;
@@ -393,10 +394,11 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 
 // The fused mean-shift step (Eq. 8, 10, 11) for the active seeds.
 //
-// Work group = 4 waves = one item: a group of 16*ST seeds and one pixel chunk.
-// The waves share the seeds and take every fourth block of the chunk; their
-// window sums are added in LDS in a fixed order and written as the item's
-// partial sum.  Items are spread over the XCDs so that the work groups of
+// Work group = WV waves = one item: a group of 16*ST seeds and one pixel
+// chunk.  The waves share the seeds and take every WV-th block of the chunk
+// (a wide group leaves each wave few blocks, so few dependent loads); their
+// window sums are added in LDS by a fixed-order tree and written as the
+// item's partial sum.  Items are spread over the XCDs so that the work groups of
 // one XCD walk through neighbouring items (same chunk, different seed groups)
 // and share that chunk in their L2.
 //
@@ -410,7 +412,7 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 // COUNT form: the same S^T tiles, no second product; each item writes the
 // per-seed number of its pixels inside the window (window counts at the
 // centres, used to rank candidate modes).
-template <bool BF16, bool COUNT, int DP, int ST>
+template <bool BF16, bool COUNT, int DP, int ST, int WV>
 __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
                                            const float* __restrict__ y, const int* __restrict__ active, int n_act,
                                            const Tiling& tl, int n_blocks, int n_pix, float thr,
@@ -426,8 +428,8 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int items = cp.groups * cp.n_chunks;
 
-  __shared__ f32x4 red[COUNT ? 1 : 3][ST][COUNT ? 1 : NDB][64];
-  __shared__ int redc[COUNT ? 3 : 1][ST][16];
+  __shared__ f32x4 red[COUNT ? 1 : WV / 2][ST][COUNT ? 1 : NDB][64];
+  __shared__ int redc[COUNT ? WV - 1 : 1][ST][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
   const int rowsel0 = 8 * (r >> 2) + (r & 3);
@@ -442,7 +444,7 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     const int b0 = chunk * cp.chunk_blocks;
     const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
     // Register operands of one block: rows for S (two 16-pixel tiles) and the
-    // dimension-major copy for V.  Double-buffered: block b+4 loads while b
+    // dimension-major copy for V.  Double-buffered: block b+WV loads while b
     // computes.
     AOp xa[2][2][KS];
     AOp xv[2][NDB][BF16 ? 1 : 8];
@@ -575,12 +577,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    for (; b < b1; b += 8) {
-      if (b + 4 < b1) load(1, b + 4);
+    for (; b < b1; b += 2 * WV) {
+      if (b + WV < b1) load(1, b + WV);
       compute(0, b);
-      if (b + 4 >= b1) break;
-      if (b + 8 < b1) load(0, b + 8);
-      compute(1, b + 4);
+      if (b + WV >= b1) break;
+      if (b + 2 * WV < b1) load(0, b + 2 * WV);
+      compute(1, b + WV);
     }
     if constexpr (COUNT) {
       // Counts of seed r are spread over the four lane groups, then the waves.
@@ -597,45 +599,55 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
           const int a = a0 + 16 * s + r;
-          if (a < n_act)
-            pcount[(int64_t)chunk * n_act + a] = cnt[s] + redc[0][s][r] + redc[1][s][r] + redc[2][s][r];
+          int c = cnt[s];
+#pragma unroll
+          for (int w = 0; w < WV - 1; ++w) c += redc[w][s][r];
+          if (a < n_act) pcount[(int64_t)chunk * n_act + a] = c;
         }
       }
       __syncthreads();
       continue;
     }
-    // Fixed-order sum of the four waves' window sums, then one partial per item.
+    // Fixed-order tree sum of the waves' window sums (each round the upper
+    // half of the remaining waves hands its sums to the lower half), then one
+    // partial per item.
     if constexpr (!COUNT) {
-    if (wave > 0) {
 #pragma unroll
-      for (int s = 0; s < ST; ++s)
+      for (int half = WV / 2; half >= 1; half >>= 1) {
+        if (wave >= half && wave < 2 * half) {
 #pragma unroll
-        for (int db = 0; db < NDB; ++db) red[wave - 1][s][db][lane] = acc[s][db];
-    }
-    __syncthreads();
-    if (wave == 0) {
+          for (int s = 0; s < ST; ++s)
 #pragma unroll
-      for (int s = 0; s < ST; ++s) {
-        const int a = a0 + 16 * s + r;
+            for (int db = 0; db < NDB; ++db) red[wave - half][s][db][lane] = acc[s][db];
+        }
+        __syncthreads();
+        if (wave < half) {
 #pragma unroll
-        for (int db = 0; db < NDB; ++db) {
-          f32x4 v = acc[s][db];
-          v += red[0][s][db][lane];
-          v += red[1][s][db][lane];
-          v += red[2][s][db][lane];
-          if (a < n_act)
-            *reinterpret_cast<float4*>(partial + ((int64_t)chunk * n_act + a) * DP + 16 * db + 4 * g) =
-                make_float4(v[0], v[1], v[2], v[3]);
+          for (int s = 0; s < ST; ++s)
+#pragma unroll
+            for (int db = 0; db < NDB; ++db) acc[s][db] += red[wave][s][db][lane];
+        }
+        __syncthreads();
+      }
+      if (wave == 0) {
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          const int a = a0 + 16 * s + r;
+#pragma unroll
+          for (int db = 0; db < NDB; ++db) {
+            const f32x4 v = acc[s][db];
+            if (a < n_act)
+              *reinterpret_cast<float4*>(partial + ((int64_t)chunk * n_act + a) * DP + 16 * db + 4 * g) =
+                  make_float4(v[0], v[1], v[2], v[3]);
+          }
         }
       }
-    }
-    __syncthreads();
     }
   }
 }
 
-template <bool BF16, bool COUNT, int DP, int ST>
-__global__ __launch_bounds__(256) void k_shift(Batch bt, const void* __restrict__ xrm_, const void* __restrict__ xt_,
+template <bool BF16, bool COUNT, int DP, int ST, int WV>
+__global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restrict__ xrm_, const void* __restrict__ xt_,
                                                const float* __restrict__ y, const int* __restrict__ active,
                                                IterCtl ctl, Tiling tl, float* __restrict__ partial,
                                                int* __restrict__ pcount) {
@@ -669,7 +681,7 @@ __global__ __launch_bounds__(256) void k_shift(Batch bt, const void* __restrict_
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   if (n_act <= 0) return;
-  shift_body<BF16, COUNT, DP, ST>(xrm, xt, y, active, n_act, tl, g.n_blocks, g.n, g.thr, partial, pcount,
+  shift_body<BF16, COUNT, DP, ST, WV>(xrm, xt, y, active, n_act, tl, g.n_blocks, g.n, g.thr, partial, pcount,
                                   (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -1486,13 +1498,25 @@ StepGeom make_geom(int n) {
 // SIMD.  Compiled group sizes per (precision, padded D):
 //   FP32: D 32 -> 16, 32, 64; D 64 -> 16, 32; D 128 -> 16.
 //   BF16: D 32 -> 32, 64, 128; D 64 -> 16, 32, 64; D 128 -> 16, 32.
+// Fused-step shapes compiled with WV waves per group.  Four waves: every
+// shape.  Eight or sixteen: DP = 32 only, where a wave's operands fit the
+// registers a wave of a 512- or 1024-lane group may hold without scratch (FP32
+// groups of more than 16 seeds do not at sixteen waves), and the wave tree's
+// LDS (WV/2 slots of ST x DP/16 accumulator tiles of 1 KiB) fits in 64 KiB.
+constexpr bool shift_shape_ok(bool bf16, bool count, int dp, int st, int wv) {
+  if (wv == 4) return true;
+  if ((wv != 8 && wv != 16) || dp != 32) return false;
+  if (wv == 16 && !bf16 && st >= 2) return false;
+  return count || (wv / 2) * st * (dp / 16) * 1024 <= 65536;
+}
+
 static int max_group(bool bf16, int dp) {
   if (bf16) return dp <= 32 ? 128 : (dp <= 64 ? 64 : 32);
   return dp <= 32 ? 64 : (dp <= 64 ? 32 : 16);
 }
 static int min_group(bool bf16, int dp) { return (bf16 && dp <= 32) ? 32 : 16; }
 
-Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks) {
+Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks, int want_waves) {
   Tiling t;
   // Defaults from a sweep on the 512x512, D = 32 workload (32 seeds, ~512
   // items, <= 256 chunks was fastest for both precisions).
@@ -1503,6 +1527,11 @@ Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_c
   t.group_seeds = gs;
   t.target_items = want_items > 0 ? std::max(8, std::min(want_items, 1 << 16)) : kTargetItems;
   t.max_chunks = want_chunks > 0 ? std::max(1, std::min(want_chunks, 4096)) : kMaxChunks;
+  // Waves per group: 4, 8 or 16, halved until the shape is compiled.
+  int wv = want_waves > 0 ? want_waves : kWaves;
+  wv = wv >= 16 ? 16 : (wv >= 8 ? 8 : 4);
+  while (wv > 4 && !shift_shape_ok(bf16, false, dp, gs / 16, wv)) wv /= 2;
+  t.waves = wv;
   return t;
 }
 
@@ -1519,13 +1548,34 @@ static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
   return grid < 8 ? 8 : grid;
 }
 
-#define FMS_SHIFT_CASE(BFV, CNT, DPV, STV)                                                                       \
-  if (ev0 || ev1)                                                                                            \
-    hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), grid, dim3(256), 0, s, ev0, ev1, 0, b, xrm, xt, y, active, \
-                          ctl, t, partial, pcount);                                                           \
-  else                                                                                                       \
-    hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV>), grid, dim3(256), 0, s, b, xrm, xt, y, active, ctl, t, partial, \
-                       pcount)
+template <bool BFV, bool CNT, int DPV, int STV, int WV>
+static hipError_t shift_launch_one(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
+                                   const float* y, const int* active, const IterCtl& ctl, const Tiling& t,
+                                   float* partial, int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
+  if constexpr (!shift_shape_ok(BFV, CNT, DPV, STV, WV)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (ev0 || ev1)
+      hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, ev0, ev1, 0, b, xrm, xt, y,
+                            active, ctl, t, partial, pcount);
+    else
+      hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, b, xrm, xt, y, active, ctl, t,
+                         partial, pcount);
+    return hipGetLastError();
+  }
+}
+
+template <bool BFV, bool CNT, int DPV, int STV>
+static hipError_t shift_launch_waves(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
+                                     const float* y, const int* active, const IterCtl& ctl, const Tiling& t,
+                                     float* partial, int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (t.waves) {
+    case 4: return shift_launch_one<BFV, CNT, DPV, STV, 4>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
+    case 8: return shift_launch_one<BFV, CNT, DPV, STV, 8>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
+    case 16: return shift_launch_one<BFV, CNT, DPV, STV, 16>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 static hipError_t shift_dispatch(hipStream_t s, const Batch& b, bool bf16, bool count, int dp, const Tiling& t,
                                  const void* xrm, const void* xt, const float* y, const int* active,
@@ -1539,38 +1589,39 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, bool bf16, bool 
   }
   const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
   const int key = (bf16 ? 1000000 : 0) + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
+#define FMS_SHIFT_CASE(BFV, CNT, DPV, STV) \
+  return shift_launch_waves<BFV, CNT, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1)
   switch (key) {
-    case 3201: FMS_SHIFT_CASE(false, false, 32, 1); break;
-    case 3202: FMS_SHIFT_CASE(false, false, 32, 2); break;
-    case 3204: FMS_SHIFT_CASE(false, false, 32, 4); break;
-    case 6401: FMS_SHIFT_CASE(false, false, 64, 1); break;
-    case 6402: FMS_SHIFT_CASE(false, false, 64, 2); break;
-    case 12801: FMS_SHIFT_CASE(false, false, 128, 1); break;
-    case 103201: FMS_SHIFT_CASE(false, true, 32, 1); break;
-    case 103202: FMS_SHIFT_CASE(false, true, 32, 2); break;
-    case 103204: FMS_SHIFT_CASE(false, true, 32, 4); break;
-    case 106401: FMS_SHIFT_CASE(false, true, 64, 1); break;
-    case 106402: FMS_SHIFT_CASE(false, true, 64, 2); break;
-    case 112801: FMS_SHIFT_CASE(false, true, 128, 1); break;
-    case 1103202: FMS_SHIFT_CASE(true, true, 32, 2); break;
-    case 1103204: FMS_SHIFT_CASE(true, true, 32, 4); break;
-    case 1106402: FMS_SHIFT_CASE(true, true, 64, 2); break;
-    case 1106404: FMS_SHIFT_CASE(true, true, 64, 4); break;
-    case 1112801: FMS_SHIFT_CASE(true, true, 128, 1); break;
-    case 1112802: FMS_SHIFT_CASE(true, true, 128, 2); break;
-    case 1003202: FMS_SHIFT_CASE(true, false, 32, 2); break;
-    case 1003204: FMS_SHIFT_CASE(true, false, 32, 4); break;
-    case 1003208: FMS_SHIFT_CASE(true, false, 32, 8); break;
-    case 1006401: FMS_SHIFT_CASE(true, false, 64, 1); break;
-    case 1006402: FMS_SHIFT_CASE(true, false, 64, 2); break;
-    case 1006404: FMS_SHIFT_CASE(true, false, 64, 4); break;
-    case 1012801: FMS_SHIFT_CASE(true, false, 128, 1); break;
-    case 1012802: FMS_SHIFT_CASE(true, false, 128, 2); break;
+    case 3201: FMS_SHIFT_CASE(false, false, 32, 1);
+    case 3202: FMS_SHIFT_CASE(false, false, 32, 2);
+    case 3204: FMS_SHIFT_CASE(false, false, 32, 4);
+    case 6401: FMS_SHIFT_CASE(false, false, 64, 1);
+    case 6402: FMS_SHIFT_CASE(false, false, 64, 2);
+    case 12801: FMS_SHIFT_CASE(false, false, 128, 1);
+    case 103201: FMS_SHIFT_CASE(false, true, 32, 1);
+    case 103202: FMS_SHIFT_CASE(false, true, 32, 2);
+    case 103204: FMS_SHIFT_CASE(false, true, 32, 4);
+    case 106401: FMS_SHIFT_CASE(false, true, 64, 1);
+    case 106402: FMS_SHIFT_CASE(false, true, 64, 2);
+    case 112801: FMS_SHIFT_CASE(false, true, 128, 1);
+    case 1103202: FMS_SHIFT_CASE(true, true, 32, 2);
+    case 1103204: FMS_SHIFT_CASE(true, true, 32, 4);
+    case 1106402: FMS_SHIFT_CASE(true, true, 64, 2);
+    case 1106404: FMS_SHIFT_CASE(true, true, 64, 4);
+    case 1112801: FMS_SHIFT_CASE(true, true, 128, 1);
+    case 1112802: FMS_SHIFT_CASE(true, true, 128, 2);
+    case 1003202: FMS_SHIFT_CASE(true, false, 32, 2);
+    case 1003204: FMS_SHIFT_CASE(true, false, 32, 4);
+    case 1003208: FMS_SHIFT_CASE(true, false, 32, 8);
+    case 1006401: FMS_SHIFT_CASE(true, false, 64, 1);
+    case 1006402: FMS_SHIFT_CASE(true, false, 64, 2);
+    case 1006404: FMS_SHIFT_CASE(true, false, 64, 4);
+    case 1012801: FMS_SHIFT_CASE(true, false, 128, 1);
+    case 1012802: FMS_SHIFT_CASE(true, false, 128, 2);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
 #undef FMS_SHIFT_CASE
+}
 
 hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
                         const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap,
