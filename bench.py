@@ -35,6 +35,8 @@ def _args():
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the uneven batched workload reported under 'batched' (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--only-frame", action="store_true",
+                    help="time the 512x512 frame in both forms only (no other sections; for kernel traces)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
                          "reference), then --steps frames of each form; prints a short summary only")
@@ -266,6 +268,35 @@ def _online_n(fms, torch, n_frames=10):
                         f"BF16+refine, N carried", "runs": rows}
 
 
+def _autotune(fms, torch, emb, mask, h, steps):
+    """The autotuner on the 512x512 frame: the decomposition it picks per
+    active-seed count (fused step + reduction, tuned against default), and the
+    BF16+refine frame rate with the tuned table against the defaults."""
+    t0 = time.perf_counter()
+    ent = fms.autotune(emb, mask, h, precision=fms.BF16_REFINE)
+    tune_s = time.perf_counter() - t0
+    rates = {}
+    for name in ("default", "tuned", "default_again"):
+        if name == "tuned":
+            fms.autotune(emb, mask, h, precision=fms.BF16_REFINE)
+        else:
+            fms.clear_tuning()
+        fms.cluster(emb, mask, h, precision=fms.BF16_REFINE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fms.cluster(emb, mask, h, precision=fms.BF16_REFINE)
+        torch.cuda.synchronize()
+        rates[name] = steps / (time.perf_counter() - t0)
+    fms.clear_tuning()
+    return {"tune_s": tune_s,
+            "entries": [{k: e[k] for k in ("precision", "seeds", "tile_seeds", "tile_items", "tile_waves")} |
+                        {"us_tuned": round(e["us_per_step"], 2), "us_default": round(e["us_default"], 2)}
+                        for e in ent],
+            "frames_per_s_default": 0.5 * (rates["default"] + rates["default_again"]),
+            "frames_per_s_tuned": rates["tuned"]}
+
+
 def _cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -332,10 +363,15 @@ def main():
         "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
     }
 
+    if a.only_frame:
+        print(json.dumps(out), flush=True)
+        return
+
     out["differentiation"] = _differentiation(fms, torch, frame, int(last_f[2]["seeds_used"]))
     print(f"differentiation: {out['differentiation']['ms_fwd_bwd']:.2f} ms forward+backward",
           file=sys.stderr, flush=True)
 
+    out["autotune"] = _autotune(fms, torch, emb, mask, h, a.steps)
     out["appendix_a"] = _appendix_a(fms, torch)
     out["online_n"] = _online_n(fms, torch)
 

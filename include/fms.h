@@ -258,6 +258,59 @@ fms_status fms_unroll_backward(fms_handle h, void* stream,
                                const float* y_prev, const float* v_norm, const float* grad_y,
                                float* grad_emb);
 
+/* One entry of the fused-step tiling table that fms_autotune fills (host
+ * struct). */
+typedef struct {
+  int32_t precision;    /* step form: FMS_PREC_FP32 (FP32 step) or
+                           FMS_PREC_BF16_REFINE (BF16 step) */
+  int32_t dim_padded;   /* D class: 32, 64 or 128 */
+  int32_t n_fg;         /* foreground pixels of the frame it was timed on */
+  int32_t seeds;        /* active seeds it was timed at */
+  int32_t tile_seeds;   /* the chosen work decomposition (see fms_params) */
+  int32_t tile_items;
+  int32_t tile_waves;
+  float us_per_step;    /* one fused step plus its renormalising reduction, us */
+  float us_default;     /* the same with the library's default decomposition */
+} fms_tune_entry;
+
+/* Autotuner of the fused step's work decomposition (Eq. 8, 10, 11 as run by
+ * the parallel seed loop of Alg. 2).  The decomposition changes speed only:
+ * results are the same up to the order of FP32 additions.
+ *
+ * Compacts `frame`, then for each active-seed count m in {128, 512, 2048,
+ * 8192} up to the frame's foreground count n (just n when n < 128), and each
+ * step form that `p->precision` runs (the BF16 step and the FP32 step of its
+ * refinement for FMS_PREC_BF16_REFINE; the FP32 step for FMS_PREC_FP32),
+ * times every compiled decomposition (seeds per group x about 256, 512 or
+ * 1024 items x 4, 8 or 16 waves) on m centres that start at the first m
+ * foreground pixels: one warm-up, then the mean of 6 back-to-back pairs of
+ * (fused step, renormalising reduction) between two HIP events on `stream`.
+ * The fastest per (form, m) goes into the handle's table, replacing earlier
+ * entries of the same form, D class and pixel-count bucket (n within a factor
+ * of 4).  Later single-frame calls on this handle (fms_cluster,
+ * fms_shift_seeds, fms_cluster_batch of one frame) whose tile_* parameters
+ * are all 0 take, for each fused-step launch, the entry of the launch's form
+ * and D class in the frame's bucket whose m is nearest (in ratio) to the
+ * launch's bound on active seeds; without one, and in batches of several
+ * frames (whose launches spread over the frames), the library's defaults.
+ *
+ *  frame      host struct (device pointers); its bandwidth sets the windows;
+ *             labels and n_state_in are ignored.
+ *  p          host: precision and the other checks of fms_cluster; tile_*
+ *             ignored.
+ *  entries    host, capacity rows: the entries this call chose; NULL: not
+ *             reported.
+ *  n_entries  host, or NULL: number of entries this call chose (<= 8).
+ * Synchronises `stream`.  Errors: INVALID_ARG (also an empty mask),
+ * UNSUPPORTED, BAD_INPUT, CAPACITY (entries given with capacity below the
+ * count, which *n_entries then holds; the table is updated regardless),
+ * HIP. */
+fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
+                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries);
+
+/* Empty the handle's tuned table (later calls use the library's defaults). */
+fms_status fms_clear_tuning(fms_handle h);
+
 /* The seed order: order[j] = foreground ordinal at position j, j in [0, n),
  * a permutation of [0, n) keyed by `seed` (four-round Feistel network whose
  * round keys and round function come from SplitMix64, with cycle walking).

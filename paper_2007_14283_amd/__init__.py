@@ -236,6 +236,47 @@ def cluster_batch(frames, *, layout: str = "nhwc", params: Optional[Params] = No
 _UNROLL_FN = None
 
 
+def autotune(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str = "nhwc",
+             params: Optional[Params] = None, **kw):
+    """Time the fused step's work decompositions on this frame (fms_autotune)
+    and keep the fastest in the device's handle for later calls that leave
+    the tiling to the library.  Returns the chosen entries as dicts."""
+    import torch
+    if bandwidth is not None:
+        kw["bandwidth"] = bandwidth
+    p = _params(params, kw)
+    emb, h, w, d, ps, cs = _frame_args(emb, layout)
+    dev = emb.device
+    m, mptr = _mask_arg(mask, h, w, dev)
+    fr = B.FmsFrame()
+    fr.emb = emb.data_ptr()
+    fr.pixel_stride, fr.channel_stride = ps, cs
+    fr.mask = mptr if mptr else None
+    fr.height, fr.width = h, w
+    fr.bandwidth = float(p.bandwidth)
+    fr.n_state_in = 0
+    fr.labels = None
+    entries = (B.FmsTuneEntry * 16)()
+    count = ctypes.c_int32(0)
+    lib = library()
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    cp = p.to_c()
+    st = lib.fms_autotune(hdl, _stream_ptr(dev), ctypes.byref(fr), d, ctypes.byref(cp), entries, 16,
+                          ctypes.byref(count))
+    if st != B.FMS_OK:
+        raise FmsError(st, "fms_autotune")
+    return [entries[i].as_dict() for i in range(count.value)]
+
+
+def clear_tuning(device=None):
+    """Forget the tuned decompositions of the device's handle."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = library().fms_clear_tuning(_handle(dev.index if dev.index is not None else torch.cuda.current_device()))
+    if st != B.FMS_OK:
+        raise FmsError(st, "fms_clear_tuning")
+
+
 def _unroll_function():
     """torch.autograd.Function around fms_unroll / fms_unroll_backward (built
     on first use so that importing this package does not import torch)."""

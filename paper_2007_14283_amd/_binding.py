@@ -19,7 +19,8 @@ FMS_PREC_BF16_REFINE = 1
 
 # Every entry point declared in include/fms.h.
 EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",
-           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_seed_order", "fms_status_string")
+           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_autotune", "fms_clear_tuning",
+           "fms_seed_order", "fms_status_string")
 
 
 class FmsParams(ctypes.Structure):
@@ -57,6 +58,23 @@ class FmsFrame(ctypes.Structure):
         ("n_state_in", ctypes.c_int32),
         ("labels", ctypes.c_void_p),
     ]
+
+
+class FmsTuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("dim_padded", ctypes.c_int32),
+        ("n_fg", ctypes.c_int32),
+        ("seeds", ctypes.c_int32),
+        ("tile_seeds", ctypes.c_int32),
+        ("tile_items", ctypes.c_int32),
+        ("tile_waves", ctypes.c_int32),
+        ("us_per_step", ctypes.c_float),
+        ("us_default", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class FmsStats(ctypes.Structure):
@@ -123,6 +141,11 @@ def load(path: str = LIB_PATH):
     lib.fms_unroll.restype = ctypes.c_int
     lib.fms_unroll_backward.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, i32, f64, vp, vp, vp, vp, vp]
     lib.fms_unroll_backward.restype = ctypes.c_int
+    lib.fms_autotune.argtypes = [vp, vp, ctypes.POINTER(FmsFrame), i32, ctypes.POINTER(FmsParams),
+                                 ctypes.POINTER(FmsTuneEntry), i32, ctypes.POINTER(i32)]
+    lib.fms_autotune.restype = ctypes.c_int
+    lib.fms_clear_tuning.argtypes = [vp]
+    lib.fms_clear_tuning.restype = ctypes.c_int
     lib.fms_seed_order.argtypes = [vp, vp, i32, u64, vp]
     lib.fms_seed_order.restype = ctypes.c_int
     lib.fms_status_string.argtypes = [ctypes.c_int]

@@ -144,16 +144,33 @@ struct DeviceGuard {
 };
 
 // Launches with at least kBigGroupMin centres per frame use seed groups of
-// kBigGroup (where compiled): on the 512x512, D = 32 workload a 64-seed group
-// is about 20% faster than a 32-seed one from 1,024 centres on, and no
-// slower at 256.
+// kBigGroup, and BF16 launches with at least kHugeGroupMin use kHugeGroup
+// (where compiled): on the 512x512, D = 32 workload a fused step plus its
+// reduction over 512 centres takes 16.6 us with 64-seed groups against 19.4
+// with 32, and over 8192 BF16 centres 82 us with 128-seed groups against
+// 121 with 64 (larger groups reuse each pixel tile for more seeds).
 constexpr int kBigGroup = 64;
 constexpr int kBigGroupMin = 512;
+constexpr int kHugeGroup = 128;
+constexpr int kHugeGroupMin = 2048;
 
 }  // namespace
 
+// A fused-step decomposition chosen by fms_autotune for one step form, D
+// class, pixel-count bucket and active-seed count.
+struct TunedTiling {
+  bool bf16;
+  int dp;
+  int nb;
+  int m;
+  fms::Tiling t;
+  fms_tune_entry e;
+};
+
 struct fms_handle_s {
   int device = 0;
+  // Decompositions chosen by fms_autotune (empty: the library's defaults).
+  std::vector<TunedTiling> tuned;
   // Pixel data of the call's frames; every row-indexed buffer holds frame f
   // from row geo[f].row0 on.
   DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig, enorm;
@@ -241,7 +258,11 @@ struct Call {
   int F = 0, dim = 0, dp = 32;
   bool bf16 = false;
   std::vector<FrameHost> fr;
-  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{};
+  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{};
+  // The handle's tuned decompositions when the call leaves the tiling to the
+  // library, and the pixel-count bucket of its largest frame.
+  const std::vector<TunedTiling>* tuned = nullptr;
+  int nb = 0;
   fms::Batch b{};
   int64_t max_pixels = 0;
   Timing tm;
@@ -273,8 +294,34 @@ fms_status check_frame(const fms_frame& f, int32_t dim) {
 
 double tol_of(const fms_params* p, double h) { return p->conv_tol > 0.0 ? p->conv_tol : h / 1000.0; }
 
-// Tiling of a fused-step launch with at most `bound` centres per frame.
+// Pixel-count bucket: n within a factor of 4.
+int n_bucket(int64_t n) {
+  int b = 0;
+  while (n >= 4) {
+    n >>= 2;
+    ++b;
+  }
+  return b;
+}
+
+// Tiling of a fused-step launch with at most `bound` centres per frame: the
+// tuned entry of the form, D class and bucket whose seed count is nearest in
+// ratio, else the defaults.
 const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
+  if (c.tuned) {
+    const TunedTiling* best = nullptr;
+    double bd = 0.0;
+    for (const TunedTiling& t : *c.tuned) {
+      if (t.bf16 != bf16 || t.dp != c.dp || t.nb != c.nb) continue;
+      const double d = std::fabs(std::log(double(std::max(bound, 1)) / double(t.m)));
+      if (!best || d < bd) {
+        best = &t;
+        bd = d;
+      }
+    }
+    if (best) return best->t;
+  }
+  if (bf16 && bound >= kHugeGroupMin) return c.tile_huge;
   if (bound >= kBigGroupMin) return bf16 ? c.tile_big : c.tile_fp32_big;
   return bf16 ? c.tile : c.tile_fp32;
 }
@@ -286,12 +333,19 @@ void set_tiling(Call& c, const fms_params* p) {
   const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
   c.tile_big = fms::make_tiling(c.bf16, c.dp, big, p->tile_items, p->tile_chunks, p->tile_waves);
   c.tile_fp32_big = fms::make_tiling(false, c.dp, big, p->tile_items, p->tile_chunks, p->tile_waves);
+  const int huge = p->tile_seeds > 0 ? p->tile_seeds : kHugeGroup;
+  c.tile_huge = fms::make_tiling(true, c.dp, huge, p->tile_items, p->tile_chunks, p->tile_waves);
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.
 int64_t partial_rows(const Call& c, int cap) {
-  return (int64_t)std::max({fms::shift_partial_rows(c.tile, cap), fms::shift_partial_rows(c.tile_fp32, cap),
-                            fms::shift_partial_rows(c.tile_big, cap), fms::shift_partial_rows(c.tile_fp32_big, cap)});
+  size_t r = std::max({fms::shift_partial_rows(c.tile, cap), fms::shift_partial_rows(c.tile_fp32, cap),
+                       fms::shift_partial_rows(c.tile_big, cap), fms::shift_partial_rows(c.tile_fp32_big, cap),
+                       fms::shift_partial_rows(c.tile_huge, cap)});
+  if (c.tuned)
+    for (const TunedTiling& t : *c.tuned)
+      if (t.dp == c.dp) r = std::max(r, fms::shift_partial_rows(t.t, cap));
+  return (int64_t)r;
 }
 
 // Upload the frame tables.  The pinned copy is rewritten only after the
@@ -402,6 +456,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
     part += n > 0 ? partial_rows(c, n) : 0;
     elig += fms::elig_len(n);
     c.b.max_n = std::max(c.b.max_n, n);
+    c.nb = n_bucket(c.b.max_n);
     c.b.max_blocks = std::max(c.b.max_blocks, fh.g.n_blocks);
   }
   const size_t R = size_t(std::max<int64_t>(rows, fms::kBlockPix)), dp = size_t(c.dp);
@@ -881,6 +936,11 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   c.dp = pad_dim(dim);
   c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
   set_tiling(c, p);
+  // The tuned table holds single-frame launches; a batch launch spreads over
+  // its frames and keeps the defaults.
+  if (n_frames == 1 && p->tile_seeds == 0 && p->tile_items == 0 && p->tile_chunks == 0 && p->tile_waves == 0 &&
+      !h->tuned.empty())
+    c.tuned = &h->tuned;
   return setup_call(h, c, frames, p);
 }
 
@@ -1108,6 +1168,131 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.sx.seeds_used = m;
   fh.sx.n_discarded = m - nc;
   fill_stats(c, stats);
+  return FMS_OK;
+}
+
+fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
+                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries) {
+  if (!h || !frame || !p || capacity < 0 || (capacity > 0 && !entries)) return FMS_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  fms_params q = *p;
+  q.tile_seeds = q.tile_items = q.tile_chunks = q.tile_waves = 0;
+  q.timing = 0;
+  fms_frame fr = *frame;
+  fr.labels = nullptr;
+  fr.n_state_in = 0;
+  Call c;
+  FMS_TRY(begin_call(h, stream, 1, &fr, dim, &q, c));
+  c.tuned = nullptr;
+  const int n = c.fr[0].g.n;
+  FMS_TRY(read_meta(h, c));
+  if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  if (n == 0) return FMS_ERR_INVALID_ARG;
+  std::vector<int> ms;
+  for (int m : {128, 512, 2048, 8192})
+    if (m <= n) ms.push_back(m);
+  if (ms.empty()) ms.push_back(n);
+  const int mmax = ms.back();
+  FMS_TRY(ensure_centres(h, c, mmax));
+  // Candidates of each form: every compiled (group, items, waves) shape.
+  std::vector<bool> forms{c.bf16};
+  if (c.bf16) forms.push_back(false);
+  std::vector<std::vector<fms::Tiling>> cand(forms.size());
+  size_t prows = 0;
+  for (size_t fi = 0; fi < forms.size(); ++fi) {
+    for (int gs : {16, 32, 64, 128})
+      for (int items : {256, 512, 1024})
+        for (int wv : {4, 8, 16}) {
+          const fms::Tiling t = fms::make_tiling(forms[fi], c.dp, gs, items, 0, wv);
+          if (t.group_seeds != gs || t.waves != wv) continue;  // rounded to another shape
+          cand[fi].push_back(t);
+          prows = std::max(prows, fms::shift_partial_rows(t, mmax));
+        }
+    prows = std::max(prows, size_t(partial_rows(c, mmax)));
+  }
+  HIP_TRY(h->pcount.ensure(prows * sizeof(int)));
+  HIP_TRY(h->partial.ensure(prows * size_t(c.dp) * sizeof(float)));
+  HIP_TRY(h->ensure_events(2));
+  HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), mmax));
+  int* ident = h->ident.as<int>();
+  float* y = h->y.as<float>();
+  // One warm-up, then the mean of kReps (fused step, reduction) pairs.
+  constexpr int kReps = 6;
+  auto time_one = [&](const fms::Tiling& t, bool bf16, int m, float* us) -> fms_status {
+    const void* xrm = bf16 ? h->x16.p : h->x32.p;
+    const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+    HIP_TRY(fms::launch_init_seeds(c.st, ident, m, n, h->x32.as<float>(), c.dp, y, h->meta.as<int>()));
+    const fms::IterCtl ctl{-1, -1, 1.0};
+    for (int r = 0; r <= kReps; ++r) {
+      if (r == 1) HIP_TRY(hipEventRecord(h->events[0], c.st));
+      HIP_TRY(fms::launch_shift(c.st, c.b, bf16, c.dp, t, xrm, xt, y, ident, ctl, m, h->partial.as<float>(), nullptr,
+                                nullptr));
+      HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, t, h->partial.as<float>(), ident, y, h->state.as<uint8_t>(),
+                                 h->iters.as<int>(), nullptr, nullptr, ctl, m, 1));
+    }
+    HIP_TRY(hipEventRecord(h->events[1], c.st));
+    HIP_TRY(hipEventSynchronize(h->events[1]));
+    float ms_ = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms_, h->events[0], h->events[1]));
+    *us = 1000.f * ms_ / kReps;
+    return FMS_OK;
+  };
+  std::vector<TunedTiling> found;
+  for (size_t fi = 0; fi < forms.size(); ++fi) {
+    const bool bf16 = forms[fi];
+    for (int m : ms) {
+      FrameHost& fh = c.fr[0];
+      fh.rt = fms::RoundTab{};
+      fh.rt.nact = m;
+      FMS_TRY(upload_rt(h, c));
+      float us_def = 0.f;
+      FMS_TRY(time_one(pick_tiling(c, bf16, m), bf16, m, &us_def));
+      TunedTiling best{};
+      bool have = false;
+      for (const fms::Tiling& t : cand[fi]) {
+        float us = 0.f;
+        FMS_TRY(time_one(t, bf16, m, &us));
+        if (!have || us < best.e.us_per_step) {
+          have = true;
+          best.t = t;
+          best.e.us_per_step = us;
+        }
+      }
+      best.bf16 = bf16;
+      best.dp = c.dp;
+      best.nb = n_bucket(n);
+      best.m = m;
+      best.e.precision = bf16 ? FMS_PREC_BF16_REFINE : FMS_PREC_FP32;
+      best.e.dim_padded = c.dp;
+      best.e.n_fg = n;
+      best.e.seeds = m;
+      best.e.tile_seeds = best.t.group_seeds;
+      best.e.tile_items = best.t.target_items;
+      best.e.tile_waves = best.t.waves;
+      best.e.us_default = us_def;
+      found.push_back(best);
+    }
+  }
+  // Replace the table's entries of the same forms, D class and bucket.
+  std::vector<TunedTiling> keep;
+  for (const TunedTiling& t : h->tuned) {
+    bool same = false;
+    for (const TunedTiling& u : found) same = same || (t.bf16 == u.bf16 && t.dp == u.dp && t.nb == u.nb);
+    if (!same) keep.push_back(t);
+  }
+  for (const TunedTiling& u : found) keep.push_back(u);
+  h->tuned.swap(keep);
+  const int cnt = int(found.size());
+  if (n_entries) *n_entries = cnt;
+  if (!entries) return FMS_OK;
+  if (capacity < cnt) return FMS_ERR_CAPACITY;
+  for (int i = 0; i < cnt; ++i) entries[i] = found[size_t(i)].e;
+  return FMS_OK;
+}
+
+fms_status fms_clear_tuning(fms_handle h) {
+  if (!h) return FMS_ERR_INVALID_ARG;
+  h->tuned.clear();
   return FMS_OK;
 }
 

@@ -32,10 +32,11 @@ constexpr int kRankMax = 16384;
 // Work decomposition of the fused step (see plan_chunks in kernels.hip):
 // seeds in groups of `group_seeds`, pixels in chunks of whole 32-pixel
 // blocks, about `target_items` (group, chunk) items, at most `max_chunks`
-// chunks.  Defaults below; fms_params can override them.
-constexpr int kTargetItems = 512;
-constexpr int kMaxChunks = 256;
+// chunks, `waves` waves per work group.  Defaults: kWaves waves and
+// kWaveBudget / waves items; fms_params (or fms_autotune) can override them.
 constexpr int kWaves = 4;
+constexpr int kWaveBudget = 2048;
+constexpr int kMaxChunks = 256;
 struct Tiling {
   int group_seeds;
   int target_items;

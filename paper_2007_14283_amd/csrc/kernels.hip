@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
 // ------------------------------------------------------------------ fused step
 
 // Work plan of one fused step: seeds in groups of 16*ST, pixels in chunks of
-// whole 32-pixel blocks, about kTargetItems (group, chunk) items in total.
+// whole 32-pixel blocks, about target_items (group, chunk) items in total.
 // The kernels derive it from the active count held on the device; the host
 // uses the same function with upper bounds to size the partial buffer.
 __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int n_blocks) {
@@ -1518,20 +1518,24 @@ static int min_group(bool bf16, int dp) { return (bf16 && dp <= 32) ? 32 : 16; }
 
 Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks, int want_waves) {
   Tiling t;
-  // Defaults from a sweep on the 512x512, D = 32 workload (32 seeds, ~512
-  // items, <= 256 chunks was fastest for both precisions).
+  // Defaults from sweeps on the 512x512, D = 32 frame and the 64-frame batch:
+  // 32-seed groups (larger ones for many centres, chosen by the caller), four
+  // waves per group and about 512 items, <= 256 chunks.  Eight waves and 256
+  // items make a single-frame step over 512 centres about 15% faster, but
+  // the batch (64 frames per launch) about 5% slower and the single frame no
+  // faster; fms_autotune picks them where they pay.
   int def = dp <= 64 ? 32 : 16;
   int g = want_seeds > 0 ? want_seeds : def;
   int gs = min_group(bf16, dp);
   while (gs * 2 <= g && gs * 2 <= max_group(bf16, dp)) gs *= 2;
   t.group_seeds = gs;
-  t.target_items = want_items > 0 ? std::max(8, std::min(want_items, 1 << 16)) : kTargetItems;
   t.max_chunks = want_chunks > 0 ? std::max(1, std::min(want_chunks, 4096)) : kMaxChunks;
   // Waves per group: 4, 8 or 16, halved until the shape is compiled.
   int wv = want_waves > 0 ? want_waves : kWaves;
   wv = wv >= 16 ? 16 : (wv >= 8 ? 8 : 4);
   while (wv > 4 && !shift_shape_ok(bf16, false, dp, gs / 16, wv)) wv /= 2;
   t.waves = wv;
+  t.target_items = want_items > 0 ? std::max(8, std::min(want_items, 1 << 16)) : kWaveBudget / wv;
   return t;
 }
 
@@ -1589,38 +1593,25 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, bool bf16, bool 
   }
   const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
   const int key = (bf16 ? 1000000 : 0) + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
-#define FMS_SHIFT_CASE(BFV, CNT, DPV, STV) \
-  return shift_launch_waves<BFV, CNT, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1)
+// Every (precision, padded D, seed tiles per group) shape is compiled in both
+// forms, the step and the window count.
+#define FMS_SHIFT_SHAPES(X)                                                                            \
+  X(false, 32, 1) X(false, 32, 2) X(false, 32, 4) X(false, 64, 1) X(false, 64, 2) X(false, 128, 1)   \
+  X(true, 32, 2) X(true, 32, 4) X(true, 32, 8) X(true, 64, 1) X(true, 64, 2) X(true, 64, 4)           \
+  X(true, 128, 1) X(true, 128, 2)
+#define FMS_SHIFT_CASE(BFV, DPV, STV)                                                                  \
+  case (BFV ? 1000000 : 0) + DPV * 100 + STV:                                                          \
+    return shift_launch_waves<BFV, false, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, \
+                                                    ev1);                                              \
+  case (BFV ? 1000000 : 0) + 100000 + DPV * 100 + STV:                                                 \
+    return shift_launch_waves<BFV, true, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, \
+                                                   ev1);
   switch (key) {
-    case 3201: FMS_SHIFT_CASE(false, false, 32, 1);
-    case 3202: FMS_SHIFT_CASE(false, false, 32, 2);
-    case 3204: FMS_SHIFT_CASE(false, false, 32, 4);
-    case 6401: FMS_SHIFT_CASE(false, false, 64, 1);
-    case 6402: FMS_SHIFT_CASE(false, false, 64, 2);
-    case 12801: FMS_SHIFT_CASE(false, false, 128, 1);
-    case 103201: FMS_SHIFT_CASE(false, true, 32, 1);
-    case 103202: FMS_SHIFT_CASE(false, true, 32, 2);
-    case 103204: FMS_SHIFT_CASE(false, true, 32, 4);
-    case 106401: FMS_SHIFT_CASE(false, true, 64, 1);
-    case 106402: FMS_SHIFT_CASE(false, true, 64, 2);
-    case 112801: FMS_SHIFT_CASE(false, true, 128, 1);
-    case 1103202: FMS_SHIFT_CASE(true, true, 32, 2);
-    case 1103204: FMS_SHIFT_CASE(true, true, 32, 4);
-    case 1106402: FMS_SHIFT_CASE(true, true, 64, 2);
-    case 1106404: FMS_SHIFT_CASE(true, true, 64, 4);
-    case 1112801: FMS_SHIFT_CASE(true, true, 128, 1);
-    case 1112802: FMS_SHIFT_CASE(true, true, 128, 2);
-    case 1003202: FMS_SHIFT_CASE(true, false, 32, 2);
-    case 1003204: FMS_SHIFT_CASE(true, false, 32, 4);
-    case 1003208: FMS_SHIFT_CASE(true, false, 32, 8);
-    case 1006401: FMS_SHIFT_CASE(true, false, 64, 1);
-    case 1006402: FMS_SHIFT_CASE(true, false, 64, 2);
-    case 1006404: FMS_SHIFT_CASE(true, false, 64, 4);
-    case 1012801: FMS_SHIFT_CASE(true, false, 128, 1);
-    case 1012802: FMS_SHIFT_CASE(true, false, 128, 2);
+    FMS_SHIFT_SHAPES(FMS_SHIFT_CASE)
     default: return hipErrorInvalidValue;
   }
 #undef FMS_SHIFT_CASE
+#undef FMS_SHIFT_SHAPES
 }
 
 hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,

@@ -1,0 +1,107 @@
+"""GPU tests of the fused-step autotuner (fms_autotune / fms_clear_tuning): the
+table it reports is well formed, a tuned handle still matches the FP64 oracle
+(FP32 modes within 1e-5, labels exact outside the exempt sets), a tuned call
+equals the call that fixes the same decomposition explicitly (bit for bit),
+and clearing the table restores the default path bit for bit."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cluster as C
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+# A frame with fewer than 128 foreground pixels: one seed count, one entry.
+TINY = dataclasses.replace(synth.MID, height=16, width=16, n_cells=2, r_min=3, r_max=6, seed=6)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2007_14283_amd as fms
+    fms.library()
+    yield fms
+    fms.clear_tuning()
+
+
+def _dev(frame):
+    import torch
+    return torch.from_numpy(frame.emb).cuda(), torch.from_numpy(frame.mask).cuda()
+
+
+def test_autotune_table_is_well_formed(F):
+    f = synth.make_frame(synth.MID)
+    emb, mask = _dev(f)
+    _say("autotune MID fp32 + bf16")
+    for prec, forms in ((F.FP32, {0}), (F.BF16_REFINE, {0, 1})):
+        ent = F.autotune(emb, mask, f.bandwidth, precision=prec)
+        print(ent)
+        assert {e["precision"] for e in ent} == forms
+        seeds = sorted({e["seeds"] for e in ent})
+        assert seeds == [m for m in (128, 512, 2048, 8192) if m <= f.n_fg]
+        for e in ent:
+            assert e["dim_padded"] == 32 and e["n_fg"] == f.n_fg
+            assert e["tile_items"] in (256, 512, 1024) and e["tile_waves"] in (4, 8, 16)
+            assert e["tile_seeds"] in ((32, 64, 128) if e["precision"] == 1 else (16, 32, 64))
+            assert 0 < e["us_per_step"] <= e["us_default"] * 1.5
+    F.clear_tuning()
+
+
+def test_tuned_handle_matches_oracle(F):
+    f = synth.make_frame(synth.MID)
+    emb, mask = _dev(f)
+    _say("tuned MID vs oracle")
+    F.autotune(emb, mask, f.bandwidth, precision=F.FP32)
+    modes, labels, st = F.cluster(emb, mask, f.bandwidth, precision=F.FP32)
+    F.clear_tuning()
+    o = C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth))
+    mm = parity.match_modes(modes.cpu().numpy(), o.modes)
+    lc = parity.compare_labels(labels.cpu().numpy(), o, mm, 1.0 - f.bandwidth)
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
+    assert lc.mismatched == 0
+    for k in ("rounds", "seeds_used", "iterations_total"):
+        assert st[k] == o.stats[k], k
+
+
+def test_tuned_call_equals_explicit_decomposition(F):
+    f = synth.make_frame(TINY)
+    assert f.n_fg < 128
+    emb, mask = _dev(f)
+    _say("tuned TINY vs explicit", f.n_fg)
+    ent = F.autotune(emb, mask, f.bandwidth, precision=F.FP32)
+    assert len(ent) == 1 and ent[0]["seeds"] == f.n_fg
+    e = ent[0]
+    m1, l1, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32)
+    F.clear_tuning()
+    m2, l2, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32, tile_seeds=e["tile_seeds"],
+                          tile_items=e["tile_items"], tile_waves=e["tile_waves"])
+    assert np.array_equal(m1.cpu().numpy(), m2.cpu().numpy())
+    assert np.array_equal(l1.cpu().numpy(), l2.cpu().numpy())
+
+
+def test_clear_restores_default_path(F):
+    f = synth.make_frame(synth.MID)
+    emb, mask = _dev(f)
+    _say("clear restores default")
+    F.clear_tuning()
+    m0, l0, _ = F.cluster(emb, mask, f.bandwidth, precision=F.BF16_REFINE)
+    F.autotune(emb, mask, f.bandwidth, precision=F.BF16_REFINE)
+    F.clear_tuning()
+    m1, l1, _ = F.cluster(emb, mask, f.bandwidth, precision=F.BF16_REFINE)
+    assert np.array_equal(m0.cpu().numpy(), m1.cpu().numpy())
+    assert np.array_equal(l0.cpu().numpy(), l1.cpu().numpy())
+
+
+def test_autotune_rejects_empty_mask(F):
+    import torch
+    f = synth.make_frame(TINY)
+    emb, mask = _dev(f)
+    with pytest.raises(F.FmsError):
+        F.autotune(emb, torch.zeros_like(mask), f.bandwidth)
