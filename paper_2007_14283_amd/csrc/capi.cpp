@@ -10,6 +10,7 @@
 // rounds of the frames run in lockstep.  A single-frame call is a batch of
 // one.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -69,13 +70,15 @@ struct DevBuf {
 struct PinBuf {
   void* p = nullptr;
   size_t cap = 0;
-  hipError_t ensure(size_t bytes) {
+  // An enqueued copy still reads or writes this buffer (cleared by a wait).
+  bool busy = false;
+  hipError_t ensure(size_t bytes, unsigned flags = hipHostMallocDefault) {
     if (bytes <= cap) return hipSuccess;
     if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
     const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
-    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&p, want, flags);
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -199,20 +202,41 @@ struct fms_handle_s {
   // whole-stream synchronisation).  A wait also frees the pinned tables for
   // the next upload.
   hipEvent_t sync_ev = nullptr;
-  bool uploads_in_flight = false;
   hipError_t wait(hipStream_t st) {
     hipError_t e = hipEventRecord(sync_ev, st);
     if (e == hipSuccess) e = hipEventSynchronize(sync_ev);
-    if (e == hipSuccess) uploads_in_flight = false;
+    if (e == hipSuccess)
+      clear_busy();
     return e;
   }
-  // Pinned host staging: counters (F * META_COUNT ints, then F * kMeta64
-  // 64-bit words), frame tables, output offsets, a general area.
-  PinBuf hmeta, hgeo, hrt, hoff, hstage;
-  const int* hm(int f) const { return hmeta.as<int>() + size_t(f) * META_COUNT; }
+  void clear_busy() {
+    for (PinBuf* b : {&hgeo, &hrt, &hoff, &hstage}) b->busy = false;
+  }
+  bool any_busy() const { return hgeo.busy || hrt.busy || hoff.busy || hstage.busy; }
+  // Pinned host staging: frame tables, output offsets, a general area.  A
+  // buffer is rewritten on the host only once no enqueued copy uses it.
+  PinBuf hgeo, hrt, hoff, hstage;
+  // Counters published by k_publish into coherent host memory mapped for the
+  // device (dpub): a sequence word at [0], then from word 4 on F * META_COUNT
+  // ints and F * kMeta64 64-bit words.
+  PinBuf hpub;
+  int* dpub = nullptr;
+  int pub_seq = 0;
+  hipError_t ensure_pub(size_t bytes) {
+    if (bytes <= hpub.cap && dpub) return hipSuccess;
+    hipError_t e = hpub.ensure(bytes, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) {
+      std::memset(hpub.p, 0, hpub.cap);
+      pub_seq = 0;
+      e = hipHostGetDevicePointer(reinterpret_cast<void**>(&dpub), hpub.p, 0);
+    }
+    if (e != hipSuccess) dpub = nullptr;
+    return e;
+  }
+  const int* hm(int f) const { return hpub.as<int>() + 4 + size_t(f) * META_COUNT; }
   unsigned long long hm64(int f, int F) const {
     const unsigned long long* q =
-        reinterpret_cast<const unsigned long long*>(hmeta.as<int>() + size_t(F) * META_COUNT);
+        reinterpret_cast<const unsigned long long*>(hpub.as<int>() + 4 + size_t(F) * META_COUNT);
     return q[size_t(f) * kMeta64];
   }
 };
@@ -351,30 +375,31 @@ int64_t partial_rows(const Call& c, int cap) {
 // Upload the frame tables.  The pinned copy is rewritten only after the
 // previous upload has completed.
 fms_status upload_geo(fms_handle h, Call& c) {
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  if (h->hgeo.busy) HIP_TRY(h->wait(c.st));
   fms::FrameGeo* hg = h->hgeo.as<fms::FrameGeo>();
   for (int f = 0; f < c.F; ++f) hg[f] = c.fr[f].g;
   HIP_TRY(hipMemcpyAsync(h->geo.p, hg, size_t(c.F) * sizeof(fms::FrameGeo), hipMemcpyHostToDevice, c.st));
-  h->uploads_in_flight = true;
+  h->hgeo.busy = true;
   return FMS_OK;
 }
 
 fms_status upload_rt(fms_handle h, Call& c) {
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  if (h->hrt.busy) HIP_TRY(h->wait(c.st));
   fms::RoundTab* hr = h->hrt.as<fms::RoundTab>();
   for (int f = 0; f < c.F; ++f) hr[f] = c.fr[f].rt;
   HIP_TRY(hipMemcpyAsync(h->rt.p, hr, size_t(c.F) * sizeof(fms::RoundTab), hipMemcpyHostToDevice, c.st));
-  h->uploads_in_flight = true;
+  h->hrt.busy = true;
   return FMS_OK;
 }
 
-// Staging upload of n ints to device memory (waits for earlier uploads first).
+// Staging upload of n ints to device memory (waits first if a copy still
+// uses the staging area).
 fms_status upload_ints(fms_handle h, Call& c, void* dst, const int* src, size_t n) {
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  if (h->hstage.busy) HIP_TRY(h->wait(c.st));
   HIP_TRY(h->hstage.ensure(n * sizeof(int) + 256));
   std::memcpy(h->hstage.p, src, n * sizeof(int));
   HIP_TRY(hipMemcpyAsync(dst, h->hstage.p, n * sizeof(int), hipMemcpyHostToDevice, c.st));
-  h->uploads_in_flight = true;
+  h->hstage.busy = true;
   return FMS_OK;
 }
 
@@ -385,11 +410,37 @@ size_t meta_bytes(int F) {
   return size_t(F) * (META_COUNT * sizeof(int) + kMeta64 * sizeof(unsigned long long));
 }
 
-// All frames' counters (and 64-bit counters) to the host in one copy; waits.
-fms_status read_meta(fms_handle h, Call& c) {
-  HIP_TRY(hipMemcpyAsync(h->hmeta.p, h->meta.p, meta_bytes(c.F), hipMemcpyDeviceToHost, c.st));
-  HIP_TRY(h->wait(c.st));
+// All frames' counters to the host: k_publish writes them into mapped host
+// memory and then a sequence number, which the host polls (a round trip
+// about 4 us shorter than a copy and an event wait on MI355X).
+fms_status read_meta_begin(fms_handle h, Call& c, int* seq) {
+  *seq = ++h->pub_seq;
+  HIP_TRY(fms::launch_publish(c.st, c.b, int(meta_bytes(c.F) / sizeof(int)), h->dpub, *seq));
   return FMS_OK;
+}
+
+// Wait until the counters carrying `seq` are on the host; by then everything
+// enqueued before that publish has completed.  After two seconds of polling
+// it synchronises the stream instead (which also reports a failed stream).
+fms_status read_meta_end(fms_handle h, Call& c, int seq) {
+  const int* flag = h->hpub.as<int>();
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t i = 0; __atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq; ++i) {
+    __builtin_ia32_pause();
+    if ((i & 4095) == 4095 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      HIP_TRY(hipStreamSynchronize(c.st));
+      if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq) return FMS_ERR_HIP;
+      break;
+    }
+  }
+  h->clear_busy();
+  return FMS_OK;
+}
+
+fms_status read_meta(fms_handle h, Call& c) {
+  int seq = 0;
+  FMS_TRY(read_meta_begin(h, c, &seq));
+  return read_meta_end(h, c, seq);
 }
 
 // Compact the foreground of every frame, normalise it and write the layouts;
@@ -403,8 +454,8 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   HIP_TRY(h->rt.ensure(size_t(F) * sizeof(fms::RoundTab)));
   HIP_TRY(h->out_off.ensure(size_t(F + 1) * sizeof(int)));
   HIP_TRY(h->meta.ensure(meta_bytes(F)));
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
-  HIP_TRY(h->hmeta.ensure(meta_bytes(F)));
+  if (h->any_busy()) HIP_TRY(h->wait(c.st));
+  HIP_TRY(h->ensure_pub(16 + meta_bytes(F)));
   HIP_TRY(h->hgeo.ensure(size_t(F) * sizeof(fms::FrameGeo)));
   HIP_TRY(h->hrt.ensure(size_t(F) * sizeof(fms::RoundTab)));
   HIP_TRY(h->hoff.ensure(size_t(F + 1) * sizeof(int)));
@@ -509,24 +560,36 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   static constexpr int kSched[] = {3, 6, 8};
   int t = 0, nbatch = 0;
   int bound = cap;  // active centres of any frame in the next iteration, at most
+  // Iteration t: the step, then the reduction that renormalises, freezes and
+  // compacts.  Iteration 0 reads the centres in place (the active list is
+  // the identity); later iterations read the rows the previous reduce
+  // compacted in active-list order.
+  auto iterate = [&](const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
+    const fms::IterCtl ctl{-1, it, gamma};
+    const float* yin = it == 0 ? ybuf : yc[it & 1];
+    hipError_t e = fms::launch_shift(c.st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap,
+                                     h->partial.as<float>(), e0, e1);
+    if (e == hipSuccess)
+      e = fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
+                             h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0);
+    return e;
+  };
   while (t < max_iter) {
     const int nb = std::min(kSched[std::min(nbatch, 2)], max_iter - t);
     ++nbatch;
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
     const fms::Tiling& tl = pick_tiling(c, bf16, bound);
-    for (int i = 0; i < nb; ++i, ++t) {
-      const fms::IterCtl ctl{-1, t, gamma};
-      // Iteration 0 reads the centres in place (the active list is the
-      // identity); later iterations read the rows the previous reduce
-      // compacted in active-list order.
-      const float* yin = t == 0 ? ybuf : yc[t & 1];
-      HIP_TRY(fms::launch_shift(c.st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap, h->partial.as<float>(),
-                                timing ? h->events[2 * i] : nullptr, timing ? h->events[2 * i + 1] : nullptr));
-      HIP_TRY(fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[t & 1], ybuf,
-                                 h->state.as<uint8_t>(), h->iters.as<int>(), lists[(t + 1) & 1], yc[(t + 1) & 1],
-                                 ctl, cap, 0));
-    }
-    FMS_TRY(read_meta(h, c));
+    for (int i = 0; i < nb; ++i, ++t)
+      HIP_TRY(iterate(tl, t, timing ? h->events[2 * i] : nullptr, timing ? h->events[2 * i + 1] : nullptr));
+    // The counters after this batch go to the host while the GPU runs one
+    // more iteration behind them (without timing): a round that goes on
+    // keeps the GPU busy during the host's decision, and one that stopped
+    // costs one launch pair that returns at its head.
+    int seq = 0;
+    FMS_TRY(read_meta_begin(h, c, &seq));
+    const bool spec = !timing && t < max_iter;
+    if (spec) HIP_TRY(iterate(tl, t, nullptr, nullptr));
+    FMS_TRY(read_meta_end(h, c, seq));
     if (timing) {
       for (int i = 0; i < nb; ++i) {
         float ms = 0.f;
@@ -536,7 +599,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
       }
     }
     // The early stop of each frame's next iteration, as its step kernel
-    // takes it.
+    // takes it (the speculative iteration, when there is one).
     bool all_done = true;
     bound = 0;
     for (int f = 0; f < c.F; ++f) {
@@ -549,6 +612,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
       }
     }
     if (all_done) break;
+    if (spec) ++t;
   }
   if (timing)
     for (int f = 0; f < c.F; ++f) c.tm.step_updates[pk] += int64_t(h->hm64(f, c.F));
@@ -665,7 +729,7 @@ fms_status host_converged(fms_handle h, Call& c, std::vector<int>& conv) {
   const int msel = h->hm(0)[META_NSEL];
   conv.clear();
   if (msel <= 0) return FMS_OK;
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  if (h->hstage.busy) HIP_TRY(h->wait(c.st));
   HIP_TRY(h->hstage.ensure(size_t(msel) + 256));
   HIP_TRY(hipMemcpyAsync(h->hstage.p, h->state.p, size_t(msel), hipMemcpyDeviceToHost, c.st));
   HIP_TRY(h->wait(c.st));
@@ -706,7 +770,7 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   if (k > 0)
     HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, nullptr,
                                 h->modes.as<float>(), k, bits, true, META_NCAND, -1));
-  if (h->uploads_in_flight) HIP_TRY(h->wait(c.st));
+  if (h->hstage.busy) HIP_TRY(h->wait(c.st));
   HIP_TRY(h->hstage.ensure(bytes + 256));
   HIP_TRY(hipMemcpyAsync(h->hstage.p, h->bits.p, bytes, hipMemcpyDeviceToHost, c.st));
   HIP_TRY(h->wait(c.st));
@@ -731,7 +795,32 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
 // The OSOP round loop (Sec. 3.2.4) over the frames of a call, then the BF16
 // refinement and the labels.  Modes stay in h->modes; on return rt.k_modes
 // of every frame (uploaded) is its final mode count.
-fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p) {
+// Every frame's modes (rt.k_modes uploaded) to the packed outputs at rows
+// off[f].
+fms_status write_modes(fms_handle h, Call& c, float* modes_out, int32_t* counts_out, const int* off) {
+  int kmax = 0;
+  for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.k_modes);
+  if (kmax == 0) return FMS_OK;
+  if (h->hoff.busy) HIP_TRY(h->wait(c.st));
+  std::memcpy(h->hoff.p, off, size_t(c.F) * sizeof(int));
+  HIP_TRY(hipMemcpyAsync(h->out_off.p, h->hoff.p, size_t(c.F) * sizeof(int), hipMemcpyHostToDevice, c.st));
+  h->hoff.busy = true;
+  HIP_TRY(fms::launch_modes_out(c.st, c.b, h->modes.as<float>(), h->mode_counts.as<int>(), c.dp, c.dim,
+                                h->out_off.as<int>(), modes_out, counts_out, kmax));
+  return FMS_OK;
+}
+
+// Where fms_cluster_batch wants the modes: packed rows, frame f from
+// offsets[f]; written only when the total fits k_max.
+struct ModeOutputs {
+  float* modes;
+  int32_t* counts;
+  int32_t k_max;
+  std::vector<int> offsets;  // F + 1 entries, filled by cluster_frames
+  int64_t total;
+};
+
+fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutputs& out) {
   const int F = c.F;
   const bool timing = p->timing != 0;
   if (c.b.max_n > 0) {
@@ -890,6 +979,16 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p) {
   HIP_TRY(fms::launch_set_slot(c.st, c.b, META_LEFT, false, 0));
   HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, h->x32.as<float>(), h->modes.as<float>(), -1, 1, nullptr, nullptr,
                              h->fg_idx.as<int>()));
+  // The packed modes go out before the last read of the counters, so the
+  // call ends with one wait.
+  out.offsets.assign(size_t(F) + 1, 0);
+  out.total = 0;
+  for (int f = 0; f < F; ++f) {
+    out.offsets[size_t(f)] = int(std::min<int64_t>(out.total, std::numeric_limits<int32_t>::max()));
+    out.total += c.fr[f].k_modes;
+  }
+  out.offsets[size_t(F)] = int(std::min<int64_t>(out.total, std::numeric_limits<int32_t>::max()));
+  if (out.total <= out.k_max) FMS_TRY(write_modes(h, c, out.modes, out.counts, out.offsets.data()));
   FMS_TRY(read_meta(h, c));
   for (int f = 0; f < F; ++f) {
     FrameHost& fh = c.fr[f];
@@ -902,17 +1001,6 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p) {
   return FMS_OK;
 }
 
-// Every frame's modes (rt.k_modes uploaded) to the packed outputs at rows
-// off[f].
-fms_status write_modes(fms_handle h, Call& c, float* modes_out, int32_t* counts_out, const int* off) {
-  int kmax = 0;
-  for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.k_modes);
-  if (kmax == 0) return FMS_OK;
-  FMS_TRY(upload_ints(h, c, h->out_off.p, off, size_t(c.F)));
-  HIP_TRY(fms::launch_modes_out(c.st, c.b, h->modes.as<float>(), h->mode_counts.as<int>(), c.dp, c.dim,
-                                h->out_off.as<int>(), modes_out, counts_out, kmax));
-  return FMS_OK;
-}
 
 void fill_stats(const Call& c, fms_stats* stats) {
   if (!stats) return;
@@ -1045,7 +1133,7 @@ fms_status fms_destroy(fms_handle h) {
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
-  for (PinBuf* b : {&h->hmeta, &h->hgeo, &h->hrt, &h->hoff, &h->hstage}) b->release();
+  for (PinBuf* b : {&h->hpub, &h->hgeo, &h->hrt, &h->hoff, &h->hstage}) b->release();
   delete h;
   return FMS_OK;
 }
@@ -1070,22 +1158,11 @@ fms_status fms_cluster_batch(fms_handle h, void* stream, int32_t n_frames, const
   DeviceGuard guard(h->device);
   Call c;
   FMS_TRY(begin_call(h, stream, n_frames, frames, dim, p, c));
-  FMS_TRY(cluster_frames(h, c, p));
-  int64_t total = 0;
-  std::vector<int> off(static_cast<size_t>(c.F));
-  for (int f = 0; f < c.F; ++f) {
-    off[f] = int(total);
-    mode_offsets[f] = int32_t(total);
-    total += c.fr[f].k_modes;
-  }
-  mode_offsets[c.F] = int32_t(std::min<int64_t>(total, std::numeric_limits<int32_t>::max()));
+  ModeOutputs out{modes, mode_counts, k_max, {}, 0};
+  FMS_TRY(cluster_frames(h, c, p, out));
+  for (int f = 0; f <= c.F; ++f) mode_offsets[f] = int32_t(out.offsets[size_t(f)]);
   fill_stats(c, stats);
-  if (total > k_max) {
-    HIP_TRY(h->wait(c.st));
-    return FMS_ERR_CAPACITY;
-  }
-  FMS_TRY(write_modes(h, c, modes, mode_counts, off.data()));
-  HIP_TRY(h->wait(c.st));
+  if (out.total > k_max) return FMS_ERR_CAPACITY;
   return FMS_OK;
 }
 

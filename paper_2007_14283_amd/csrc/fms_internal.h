@@ -211,6 +211,9 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
 hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
                          int mode, uint8_t* elig, const int* rank, const int* fg_idx);
 // meta[slot] of every frame to rt.nact (from_rt) or to value.
+// The counters of every frame (n_words 32-bit words from b.meta on) to host
+// memory mapped at dst (device address): data at dst[4..], then seq at dst[0].
+hipError_t launch_publish(hipStream_t s, const Batch& b, int n_words, int* dst, int seq);
 hipError_t launch_set_slot(hipStream_t s, const Batch& b, int slot, bool from_rt, int value);
 // Every frame's label map to -1.
 hipError_t launch_fill_labels(hipStream_t s, const Batch& b, int64_t max_pixels);

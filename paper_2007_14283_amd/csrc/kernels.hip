@@ -1221,6 +1221,21 @@ __global__ __launch_bounds__(256) void k_set_slot(Batch bt, int slot, int from_r
   if (f < bt.F) bt.meta[(int64_t)f * META_COUNT + slot] = from_rt ? bt.rt[f].nact : value;
 }
 
+// Copy every frame's counters (n_words 32-bit words from bt.meta, which the
+// 64-bit counters follow) into host memory at dst[4..], then, after a
+// system-scope fence, write `seq` to dst[0]: the host polls dst[0] instead of
+// waiting on an event.  One work group.
+__global__ __launch_bounds__(256) void k_publish(Batch bt, int n_words, int* __restrict__ dst, int seq) {
+  volatile int* out = dst;
+  for (int i = threadIdx.x; i < n_words; i += 256) out[4 + i] = bt.meta[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = seq;
+    __threadfence_system();
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_labels(Batch bt) {
   const FrameGeo& g = bt.geo[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1738,6 +1753,11 @@ hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_publish(hipStream_t s, const Batch& b, int n_words, int* dst, int seq) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, b, n_words, dst, seq);
   return hipGetLastError();
 }
 
