@@ -1140,16 +1140,27 @@ __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __res
 // 0); count the pixels still eligible.  Labels (mode 1): most similar mode
 // in [0, rt.k_modes), lowest index on ties; count the pixels farther than h
 // from every mode.
+//
+// The similarities come from v_mfma_f32_16x16x4_f32 with modes as rows and
+// pixels as columns: lane (g, r) feeds mode row r and pixel column r with
+// dimension g*KJ + j at step j, and receives the similarities of modes
+// 4g..4g+3 of the tile with its pixel r.  Each lane keeps the best of the
+// modes it sees (ascending, first of equals), then the four lane groups
+// combine (larger similarity, else lower index).  A wave owns PT 16-pixel
+// tiles; the work group stages up to KT modes at a time in LDS.
 template <int DP>
 __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restrict__ x,
                                                 const float* __restrict__ modes, int k1_slot, int mode,
                                                 uint8_t* __restrict__ elig, const int* __restrict__ rank,
                                                 const int* __restrict__ fg_idx) {
+  constexpr int KJ = DP / 4;
+  constexpr int PT = DP == 32 ? 4 : (DP == 64 ? 2 : 1);
   constexpr int KT = 64;
+  constexpr int LD = DP + 4;  // padded LDS row
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
   const int n = g.n;
-  if ((int)blockIdx.x * 256 >= n) return;
+  if ((int)blockIdx.x * 64 * PT >= n) return;
   int* meta = bt.meta + (int64_t)f * META_COUNT;
   const int k0 = mode == 0 ? bt.rt[f].k_modes : 0;
   const int k1 = mode == 0 ? k0 + meta[k1_slot] : bt.rt[f].k_modes;
@@ -1160,53 +1171,96 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
   if (elig) elig += g.elig0;
   if (rank) rank += g.row0;
   if (fg_idx) fg_idx += g.row0;
-  __shared__ float sm[KT * DP];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  float xi[DP];
+  __shared__ __align__(16) float sm[KT * LD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gq = lane >> 4, r = lane & 15;
+  const int p0 = (int)blockIdx.x * 64 * PT + wave * 16 * PT;
+  float xb[PT][KJ];
 #pragma unroll
-  for (int d = 0; d < DP; d += 4) {
-    float4 v = i < n ? *reinterpret_cast<const float4*>(x + (int64_t)i * DP + d) : make_float4(0.f, 0.f, 0.f, 0.f);
-    xi[d] = v.x; xi[d + 1] = v.y; xi[d + 2] = v.z; xi[d + 3] = v.w;
+  for (int t = 0; t < PT; ++t) {
+    const int i = p0 + 16 * t + r;
+#pragma unroll
+    for (int j = 0; j < KJ; j += 4) {
+      const float4 v = i < n ? *reinterpret_cast<const float4*>(x + (int64_t)i * DP + gq * KJ + j)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+      xb[t][j] = v.x;
+      xb[t][j + 1] = v.y;
+      xb[t][j + 2] = v.z;
+      xb[t][j + 3] = v.w;
+    }
   }
-  float best = -INFINITY;
-  int arg = -1;
+  float best[PT];
+  int arg[PT];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    best[t] = -INFINITY;
+    arg[t] = -1;
+  }
   for (int kb = k0; kb < k1; kb += KT) {
     const int cnt = min(KT, k1 - kb);
+    const int rows = (cnt + 15) & ~15;
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * DP; e += 256) sm[e] = modes[(int64_t)kb * DP + e];
+    for (int e = threadIdx.x; e < rows * DP; e += 256) {
+      const int q = e / DP, d = e - q * DP;
+      sm[q * LD + d] = q < cnt ? modes[(int64_t)(kb + q) * DP + d] : 0.f;
+    }
     __syncthreads();
-    for (int q = 0; q < cnt; ++q) {
-      float s = 0.f;
+    for (int mt = 0; mt < rows; mt += 16) {
+      float a[KJ];
 #pragma unroll
-      for (int d = 0; d < DP; ++d) s = fmaf(xi[d], sm[q * DP + d], s);
-      if (s > best) {
-        best = s;
-        arg = kb + q;
+      for (int j = 0; j < KJ; j += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(&sm[(mt + r) * LD + gq * KJ + j]);
+        a[j] = v.x;
+        a[j + 1] = v.y;
+        a[j + 2] = v.z;
+        a[j + 3] = v.w;
+      }
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < KJ; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], xb[t][j], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = kb + mt + 4 * gq + e;
+          if (mt + 4 * gq + e < cnt && acc[e] > best[t]) {
+            best[t] = acc[e];
+            arg[t] = idx;
+          }
+        }
       }
     }
   }
-  if (mode == 0) {
-    int left = 0;
-    if (i < n) {
-      const int pos = rank[i];
-      uint8_t e = elig[pos];
-      if (e && best >= thr) {
-        elig[pos] = 0;
-        e = 0;
+  int tally = 0;
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      const float ob = __shfl_xor(best[t], off, 64);
+      const int oa = __shfl_xor(arg[t], off, 64);
+      if (ob > best[t] || (ob == best[t] && oa < arg[t])) {
+        best[t] = ob;
+        arg[t] = oa;
       }
-      left = e ? 1 : 0;
     }
-    left = wave_sum_i(left);
-    if ((threadIdx.x & 63) == 0 && left) atomicAdd(meta + META_LEFT, left);
-  } else {
-    int far = 0;
-    if (i < n) {
-      if (labels) labels[fg_idx[i]] = arg;
-      far = best < thr ? 1 : 0;
+    const int i = p0 + 16 * t + r;
+    if (gq == 0 && i < n) {
+      if (mode == 0) {
+        const int pos = rank[i];
+        uint8_t e = elig[pos];
+        if (e && best[t] >= thr) {
+          elig[pos] = 0;
+          e = 0;
+        }
+        tally += e ? 1 : 0;
+      } else {
+        if (labels) labels[fg_idx[i]] = arg[t];
+        tally += best[t] < thr ? 1 : 0;
+      }
     }
-    far = wave_sum_i(far);
-    if ((threadIdx.x & 63) == 0 && far) atomicAdd(meta + META_LEFT, far);
   }
+  tally = wave_sum_i(tally);
+  if (lane == 0 && tally) atomicAdd(meta + META_LEFT, tally);
 }
 
 __global__ __launch_bounds__(256) void k_iota(Batch bt, int* __restrict__ p) {
@@ -1739,7 +1793,9 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
 hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
                          int mode, uint8_t* elig, const int* rank, const int* fg_idx) {
   if (b.max_n <= 0) return hipSuccess;
-  const dim3 grid(cdiv(b.max_n, 256), b.F), block(256);
+  // Pixels per work group: 4 waves x PT 16-pixel tiles (PT = 4, 2, 1).
+  const int pix = dp == 32 ? 256 : (dp == 64 ? 128 : 64);
+  const dim3 grid(cdiv(b.max_n, pix), b.F), block(256);
   switch (dp) {
     case 32:
       hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
