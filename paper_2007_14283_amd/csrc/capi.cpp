@@ -765,11 +765,8 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   uint32_t* bits = reinterpret_cast<uint32_t*>(h->bits.as<uint8_t>() + nb_n);
   HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, nc), h->x32.p, h->y.as<float>(),
                             h->cand.as<int>(), nc, h->pcount.as<int>(), counts, META_NCAND));
-  HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nullptr,
-                              nc, bits, false, META_NCAND, META_NCAND));
-  if (k > 0)
-    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, nullptr,
-                                h->modes.as<float>(), k, bits, true, META_NCAND, -1));
+  HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nc,
+                              h->modes.as<float>(), k, bits, META_NCAND, META_NCAND));
   if (h->hstage.busy) HIP_TRY(h->wait(c.st));
   HIP_TRY(h->hstage.ensure(bytes + 256));
   HIP_TRY(hipMemcpyAsync(h->hstage.p, h->bits.p, bytes, hipMemcpyDeviceToHost, c.st));
@@ -874,19 +871,16 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
       // in FP32 at the end), ranking by count (descending) then seed
       // position, greedy suppression against the modes kept so far and the
       // candidates accepted before.
-      HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
+      // Counts at every slot of the round (the list is the identity); the
+      // ranking keeps the converged ones.
       HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, pick_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
-                                h->y.as<float>(), h->cand.as<int>(), cap, h->pcount.as<int>(), h->counts.as<int>(),
-                                META_NCAND));
-      HIP_TRY(fms::launch_rank(c.st, c.b, h->cand.as<int>(), h->counts.as<int>(), h->sorted.as<int>(),
-                               h->scount.as<int>()));
-      HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, h->sorted.as<int>(),
-                                  nullptr, cap, h->bits.as<uint32_t>(), false, META_NCAND, META_NCAND));
+                                h->y.as<float>(), nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
+      HIP_TRY(fms::launch_rank_converged(c.st, c.b, h->state.as<uint8_t>(), h->counts.as<int>(), h->sorted.as<int>(),
+                                         h->scount.as<int>()));
       int kmax = 0;
       for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.rt.want > 0 ? fh.k_modes : 0);
-      if (kmax > 0)
-        HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, nullptr,
-                                    h->modes.as<float>(), kmax, h->bits.as<uint32_t>(), true, META_NCAND, -1));
+      HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, h->sorted.as<int>(),
+                                  cap, h->modes.as<float>(), kmax, h->bits.as<uint32_t>(), META_NCAND, META_NCAND));
       HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->sorted.as<int>(),
                                  h->scount.as<int>(), META_NCAND, META_NACC, c.dp, h->modes.as<float>(),
                                  h->mode_counts.as<int>()));
@@ -955,8 +949,8 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
     HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, kmax), h->x32.p, h->y.as<float>(),
                               h->cand.as<int>(), kmax, h->pcount.as<int>(), h->counts.as<int>(), META_NCAND));
-    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), kmax, h->cand.as<int>(),
-                                nullptr, kmax, h->bits.as<uint32_t>(), false, META_NCAND, META_NCAND));
+    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), kmax, h->cand.as<int>(), kmax,
+                                nullptr, 0, h->bits.as<uint32_t>(), META_NCAND, META_NCAND));
     HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->cand.as<int>(),
                                h->counts.as<int>(), META_NCAND, META_NACC, c.dp, mrows, h->mode_counts.as<int>()));
     FMS_TRY(read_meta(h, c));

@@ -186,19 +186,23 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
 // meta[m_slot], or rt.nact when m_slot < 0.
 hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
                         const float* y, const int* list, int m, int* pcount, int* counts, int m_slot);
-// Similarity bits between the rows y[rows[0..m)] and either the columns
-// y[cols[c]], c < meta[cols_slot] (mode_cols false; bits at rt.bits_c0, row
-// stride rt.words_c) or the frame's modes before the pass, c < rt.k_modes
-// (mode_cols true; bits at rt.bits_m0, stride rt.words_m).  The row count is
-// meta[rows_slot]; m and ncols bound the grid.
+// Similarity bits of rows y[rows[j]], j < meta[rows_slot] (m bounds it):
+// against columns y[cols[c]], c < meta[cols_slot] (ncols bounds it; bits at
+// rt.bits_c0, row stride rt.words_c) when cols is given, and against the
+// frame's modes before the pass, c < rt.k_modes (nmodes bounds it; bits at
+// rt.bits_m0, stride rt.words_m) when modes is given; one launch for both.
 int simbits_words(int ncols);
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
-                          const int* cols, const float* modes, int ncols, uint32_t* bits, bool mode_cols,
-                          int rows_slot, int cols_slot);
+                          const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
+                          int cols_slot);
 // Pruning on the device (one work group per frame): converged list, ranking,
 // greedy suppression.
 hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand);
 hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount);
+// Ranking straight from the round's states: the converged slots k <
+// meta[META_NSEL] by (count desc, k asc); their number to meta[META_NCAND].
+hipError_t launch_rank_converged(hipStream_t s, const Batch& b, const uint8_t* state, const int* counts, int* sorted,
+                                 int* scount);
 hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, const float* y, const int* sorted,
                          const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts);
 // Single frame: append accepted candidates (indices into list) at k0.

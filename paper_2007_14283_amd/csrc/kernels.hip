@@ -908,16 +908,22 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
 
 // Similarity bits: bit c of row j is set when row vector j and column
 // vector c are inside each other's window (dot >= thr).  Rows are
-// y[rows[j]]; columns are y[cols[c]] (cols != null) or the frame's modes.
-// A wave owns 64 columns and 16 rows; each lane keeps its column vector in
-// registers and reads the (wave-uniform) row vectors.  Row stride: `words`
-// 32-bit words, a multiple of 2.
+// y[rows[j]]; the columns of the first `split` work groups are y[cols[c]]
+// (bits at tab.bits_c0, tab.words_c words per row), those of the rest the
+// frame's modes (bits at tab.bits_m0, tab.words_m words per row).  A wave
+// owns 64 columns and 16 rows; each lane keeps its column vector in
+// registers and reads the (wave-uniform) row vectors.  Row strides are
+// multiples of 2 words.
 template <int DP>
 __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restrict__ y, const int* __restrict__ rows,
-                                                 const int* __restrict__ cols, const float* __restrict__ colmat,
-                                                 uint32_t* __restrict__ bits, int rows_slot, int cols_slot) {
+                                                 const int* __restrict__ cols_, const float* __restrict__ colmat_,
+                                                 uint32_t* __restrict__ bits, int rows_slot, int cols_slot, int split) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int f = blockIdx.y;
+  const bool mode_part = (int)blockIdx.x >= split;
+  const int bx = mode_part ? (int)blockIdx.x - split : (int)blockIdx.x;
+  const int* cols = mode_part ? nullptr : cols_;
+  const float* colmat = mode_part ? colmat_ : nullptr;
   const FrameGeo& g = bt.geo[f];
   const RoundTab& tab = bt.rt[f];
   const int* meta = bt.meta + (int64_t)f * META_COUNT;
@@ -931,8 +937,8 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
   if (colmat) colmat += g.row0 * DP;
   bits += cols ? tab.bits_c0 : tab.bits_m0;
   const int col_tiles = words / 2;
-  if (col_tiles == 0 || (int)blockIdx.x >= col_tiles * ((m + 63) / 64)) return;
-  const int ct = blockIdx.x % col_tiles, rt = blockIdx.x / col_tiles;
+  if (col_tiles == 0 || bx >= col_tiles * ((m + 63) / 64)) return;
+  const int ct = bx % col_tiles, rt = bx / col_tiles;
   const int c = ct * 64 + lane;
   float xc[DP];
   if (c < ncols) {
@@ -984,6 +990,61 @@ __global__ __launch_bounds__(1024) void k_collect(Batch bt, const uint8_t* __res
     base += tot;
   }
   if (threadIdx.x == 0) meta[META_NCAND] = base;
+}
+
+// Rank the converged slots k < meta[META_NSEL] (state[k] == 1) of the round
+// by window count (descending), then by slot (ascending, = seed position):
+// sorted[r] = k_r, scount[r] = counts[k_r]; their number goes to
+// meta[META_NCAND].  Bitonic sort of 64-bit keys in LDS, the other slots'
+// keys sorting last; NSEL <= kRankMax.
+__global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t* __restrict__ state,
+                                                         const int* __restrict__ counts, int* __restrict__ sorted,
+                                                         int* __restrict__ scount) {
+  __shared__ unsigned long long key[kRankMax];
+  __shared__ int s_nc;
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
+  state += g.row0;
+  counts += g.row0;
+  sorted += g.row0;
+  scount += g.row0;
+  const int m = meta[META_NSEL];
+  if (threadIdx.x == 0) s_nc = 0;
+  __syncthreads();
+  int np = 1;
+  while (np < m) np <<= 1;
+  int mine = 0;
+  for (int i = threadIdx.x; i < np; i += 1024) {
+    const bool c = i < m && state[i] == 1;
+    mine += c ? 1 : 0;
+    key[i] = c ? ((unsigned long long)(uint32_t)(0x7FFFFFFF - counts[i]) << 32) | (uint32_t)i : ~0ull;
+  }
+  mine = wave_sum_i(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&s_nc, mine);
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < np; i += 1024) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long a = key[i], b = key[j];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int nc = s_nc;
+  for (int r = threadIdx.x; r < nc; r += 1024) {
+    const int k = (int)(key[r] & 0xFFFFFFFFull);
+    sorted[r] = k;
+    scount[r] = counts[k];
+  }
+  if (threadIdx.x == 0) meta[META_NCAND] = nc;
 }
 
 // Rank the nc candidates by window count (descending), then by index
@@ -1729,6 +1790,12 @@ hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, i
   return hipGetLastError();
 }
 
+hipError_t launch_rank_converged(hipStream_t s, const Batch& b, const uint8_t* state, const int* counts, int* sorted,
+                                int* scount) {
+  hipLaunchKernelGGL(k_rank_converged, dim3(b.F), dim3(1024), 0, s, b, state, counts, sorted, scount);
+  return hipGetLastError();
+}
+
 hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount) {
   hipLaunchKernelGGL(k_rank, dim3(b.F), dim3(1024), 0, s, b, cand, counts, sorted, scount);
   return hipGetLastError();
@@ -1744,14 +1811,17 @@ hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, co
 int simbits_words(int ncols) { return std::max(2, ((ncols + 63) / 64) * 2); }
 
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
-                          const int* cols, const float* modes, int ncols, uint32_t* bits, bool mode_cols,
-                          int rows_slot, int cols_slot) {
-  if (m <= 0 || ncols <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((simbits_words(ncols) / 2) * cdiv(m, 64));
-  const int* c = mode_cols ? nullptr : cols;
-  const float* cm = mode_cols ? modes : nullptr;
-#define FMS_SIM_CASE(DPV)                                                                                        \
-  hipLaunchKernelGGL(k_simbits<DPV>, dim3(grid, b.F), dim3(256), 0, s, b, y, rows, c, cm, bits, rows_slot, cols_slot)
+                          const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
+                          int cols_slot) {
+  if (m <= 0) return hipSuccess;
+  const unsigned part_c = cols && ncols > 0 ? (unsigned)((simbits_words(ncols) / 2) * cdiv(m, 64)) : 0u;
+  const unsigned part_m = modes && nmodes > 0 ? (unsigned)((simbits_words(nmodes) / 2) * cdiv(m, 64)) : 0u;
+  if (part_c + part_m == 0) return hipSuccess;
+  const dim3 grid(part_c + part_m, b.F);
+  const int split = (int)part_c;
+#define FMS_SIM_CASE(DPV)                                                                                     \
+  hipLaunchKernelGGL(k_simbits<DPV>, grid, dim3(256), 0, s, b, y, rows, cols, modes, bits, rows_slot, cols_slot, \
+                     split)
   switch (dp) {
     case 32: FMS_SIM_CASE(32); break;
     case 64: FMS_SIM_CASE(64); break;
