@@ -123,14 +123,20 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict
 }
 
 // Gather the foreground rows in raster order, normalise them and write the
-// four layouts.  Each thread owns 4 consecutive pixels.
+// four layouts.  A work group takes kMaskBlockPix pixels: each thread owns 4
+// consecutive pixels for the mask scan, the foreground pixels of the block go
+// to an LDS list in raster order, and then 8 lanes take each listed pixel
+// (lane q holds dimensions KD*q .. KD*q+KD-1), so a row is read and written
+// with consecutive addresses whatever the strides.
 template <int DP>
 __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ geo,
                                                  const int* __restrict__ block_offsets, int* __restrict__ fg_idx,
                                                  float* __restrict__ x32, float* __restrict__ x32t,
                                                  uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
                                                  float* __restrict__ enorm, int* __restrict__ meta) {
+  constexpr int KD = DP / 8;  // dimensions per lane
   __shared__ int sh[5];
+  __shared__ int lp[kMaskBlockPix];
   const FrameGeo& gf = geo[blockIdx.y];
   const FrameDesc f = gf.desc;
   if ((int64_t)blockIdx.x * kMaskBlockPix >= f.n_pixels) return;
@@ -144,7 +150,8 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
     x16t += gf.row0 * DP;
   }
   meta += (int64_t)blockIdx.y * META_COUNT;
-  const int64_t base = (int64_t)blockIdx.x * kMaskBlockPix + threadIdx.x * 4;
+  const int64_t blk0 = (int64_t)blockIdx.x * kMaskBlockPix;
+  const int64_t base = blk0 + threadIdx.x * 4;
   int flags = 0, c = 0;
   for (int e = 0; e < 4; ++e) {
     int64_t p = base + e;
@@ -163,65 +170,80 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   __syncthreads();
   int wpre = 0;
   for (int w = 0; w < wave; ++w) wpre += sh[w];
-  int ord = block_offsets[blockIdx.x] + wpre + incl - c;
+  const int total = sh[0] + sh[1] + sh[2] + sh[3];
+  int local = wpre + incl - c;
+  for (int e = 0; e < 4; ++e)
+    if ((flags >> e) & 1) lp[local++] = (int)(threadIdx.x * 4 + e);
+  const int ord0 = block_offsets[blockIdx.x];
+  __syncthreads();
   int bad = 0;
-  for (int e = 0; e < 4; ++e) {
-    if (!((flags >> e) & 1)) continue;
-    const int64_t p = base + e;
+  const int q = lane & 7;
+  for (int k = (int)threadIdx.x / 8; k < total; k += 32) {
+    const int64_t p = blk0 + lp[k];
+    const int ord = ord0 + k;
     const float* src = f.emb + p * f.pixel_stride;
-    // Scale by a power of two first (exact), so the sum of squares neither
-    // overflows nor underflows for any finite non-zero row.
+    float v[KD];
     float mx = 0.f;
     bool finite = true;
-    for (int d = 0; d < f.dim; ++d) {
-      float v = src[(int64_t)d * f.channel_stride];
-      finite = finite && __builtin_isfinite(v);
-      mx = fmaxf(mx, fabsf(v));
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+      const int d = KD * q + j;
+      v[j] = d < f.dim ? src[(int64_t)d * f.channel_stride] : 0.f;
+      finite = finite && __builtin_isfinite(v[j]);
+      mx = fmaxf(mx, fabsf(v[j]));
     }
-    // The row is read again (from cache) when written, instead of being held
-    // in registers: at DP = 128 a register copy would spill.
+    // The 8 lanes of the pixel agree on the largest magnitude and on
+    // finiteness; the row is scaled by a power of two first (exact), so the
+    // sum of squares neither overflows nor underflows.
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+      mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+      finite = (__shfl_xor(finite ? 1 : 0, m, 64) != 0) && finite;
+    }
     const bool ok = finite && mx > 0.f;
-    float inv = 0.f, norm = 0.f;
     int ex = 0;
-    if (ok) {
-      frexpf(mx, &ex);
-      float ss = 0.f;
-      for (int d = 0; d < f.dim; ++d) {
-        const float v = ldexpf(src[(int64_t)d * f.channel_stride], -ex);
-        ss = fmaf(v, v, ss);
-      }
-      inv = 1.0f / sqrtf(ss);
-      norm = ldexpf(sqrtf(ss), ex);  // |e| of the raw row
-    } else {
-      bad += 1;
+    if (ok) frexpf(mx, &ex);
+    float ss = 0.f;
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+      v[j] = ok ? ldexpf(v[j], -ex) : 0.f;
+      ss = fmaf(v[j], v[j], ss);
     }
-    auto val = [&](int d) { return ok && d < f.dim ? ldexpf(src[(int64_t)d * f.channel_stride], -ex) * inv : 0.f; };
-    fg_idx[ord] = (int)p;
-    if (enorm) enorm[ord] = norm;
-    float* rowp = x32 + (int64_t)ord * DP;
-    uint16_t* row16 = x16 ? x16 + (int64_t)ord * DP : nullptr;
-    const int64_t blk = ord / kBlockPix, q = ord % kBlockPix;
-    for (int d = 0; d < DP; d += 4) {
-      float4 v4 = make_float4(val(d), val(d + 1), val(d + 2), val(d + 3));
-      *reinterpret_cast<float4*>(rowp + d) = v4;
-      x32t[(blk * DP + d + 0) * kBlockPix + q] = v4.x;
-      x32t[(blk * DP + d + 1) * kBlockPix + q] = v4.y;
-      x32t[(blk * DP + d + 2) * kBlockPix + q] = v4.z;
-      x32t[(blk * DP + d + 3) * kBlockPix + q] = v4.w;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    const float inv = ok ? 1.0f / sqrtf(ss) : 0.f;
+    if (q == 0) {
+      bad += ok ? 0 : 1;
+      fg_idx[ord] = (int)p;
+      if (enorm) enorm[ord] = ok ? ldexpf(sqrtf(ss), ex) : 0.f;  // |e| of the raw row
+    }
+    float* rowp = x32 + (int64_t)ord * DP + KD * q;
+    const int64_t blk = ord / kBlockPix, qq = ord % kBlockPix;
+#pragma unroll
+    for (int j = 0; j < KD; j += 4) {
+      const float4 v4 = make_float4(v[j] * inv, v[j + 1] * inv, v[j + 2] * inv, v[j + 3] * inv);
+      *reinterpret_cast<float4*>(rowp + j) = v4;
+      const int d = KD * q + j;
+      x32t[(blk * DP + d + 0) * kBlockPix + qq] = v4.x;
+      x32t[(blk * DP + d + 1) * kBlockPix + qq] = v4.y;
+      x32t[(blk * DP + d + 2) * kBlockPix + qq] = v4.z;
+      x32t[(blk * DP + d + 3) * kBlockPix + qq] = v4.w;
       if (!x16) continue;
-      uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
-               b3 = to_bf16_bits(v4.w);
-      row16[d] = b0;
-      row16[d + 1] = b1;
-      row16[d + 2] = b2;
-      row16[d + 3] = b3;
-      x16t[(blk * DP + d + 0) * kBlockPix + q] = b0;
-      x16t[(blk * DP + d + 1) * kBlockPix + q] = b1;
-      x16t[(blk * DP + d + 2) * kBlockPix + q] = b2;
-      x16t[(blk * DP + d + 3) * kBlockPix + q] = b3;
+      const uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
+                     b3 = to_bf16_bits(v4.w);
+      uint16_t* row16 = x16 + (int64_t)ord * DP + d;
+      row16[0] = b0;
+      row16[1] = b1;
+      row16[2] = b2;
+      row16[3] = b3;
+      x16t[(blk * DP + d + 0) * kBlockPix + qq] = b0;
+      x16t[(blk * DP + d + 1) * kBlockPix + qq] = b1;
+      x16t[(blk * DP + d + 2) * kBlockPix + qq] = b2;
+      x16t[(blk * DP + d + 3) * kBlockPix + qq] = b3;
     }
-    ++ord;
   }
+  bad = wave_sum_i(bad);
+  bad = lane == 0 ? bad : 0;
   if (bad) atomicAdd(meta + META_BAD, bad);
   // The rows from n up to the next multiple of 32 are padding: zero in every
   // layout, so they add nothing to any sum.
