@@ -571,7 +571,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
                                      h->partial.as<float>(), e0, e1);
     if (e == hipSuccess)
       e = fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
-                             h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0);
+                             h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0, nullptr, yin);
     return e;
   };
   while (t < max_iter) {

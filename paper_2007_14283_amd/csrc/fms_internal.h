@@ -177,9 +177,12 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 // least tol (or lost their window) in META_REFINE_BAD, and mode 3 besides
 // sets each centre's state (1: its move was below tol, 0: it moved, 2: its
 // window was empty).  vnorm (may be null) receives |V| of each centre.
+// ycur (may be null) holds the current centre rows in list order (the rows
+// the step read); without it they are read from y through the list.
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm = nullptr);
+                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm = nullptr,
+                         const float* ycur = nullptr);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
 // frame, on FP32 MFMA (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the
 // BF16 rows; the centres are rounded to BF16).  The frame's count is

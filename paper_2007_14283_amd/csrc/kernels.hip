@@ -313,10 +313,13 @@ __global__ __launch_bounds__(256) void k_seed_order(const FrameGeo* __restrict__
 // One 1024-thread block: take the first `want` positions of the seed order
 // (from the cursor on) that are still eligible (elig[pos] = 1: the pixel is
 // neither covered by a mode nor used as a seed) and clear them; their
-// vectors are loaded by the round's first kernel.  Each pass reads 16 consecutive
-// eligibility bytes per thread with one 16-byte load (16384 positions per
-// pass).  Positions before the cursor are all ineligible, so a pass may start
-// at the cursor rounded down to 16; `elig` is zero-padded to a multiple of 16.
+// vectors are loaded by the round's first kernel.  Each pass reads RUN = 16
+// consecutive eligibility bytes per thread in 16-byte loads (16384 positions
+// per pass; 64 per thread measured slower on the 512x512 frame, whose first
+// rounds need one pass).  Positions before the cursor are all ineligible, so
+// a pass may start at the cursor rounded down to RUN; `elig` is zero-padded
+// to a multiple of 16, and a 16-byte word is read only when it starts below
+// n.
 __global__ __launch_bounds__(1024) void k_select(const FrameGeo* __restrict__ geo, const RoundTab* __restrict__ rt,
                                                  const int* __restrict__ order, uint8_t* __restrict__ elig,
                                                  int* __restrict__ meta, int* __restrict__ seed_pos,
@@ -339,10 +342,19 @@ __global__ __launch_bounds__(1024) void k_select(const FrameGeo* __restrict__ ge
   int new_cursor = n;
   while (got < want && base < n) {
     const int p0 = base + (int)threadIdx.x * RUN;
-    uint4 e4 = make_uint4(0u, 0u, 0u, 0u);
-    if (p0 < n) e4 = *reinterpret_cast<const uint4*>(elig + p0);
-    const uint32_t ew[4] = {e4.x, e4.y, e4.z, e4.w};
-    const int cnt = __popc(e4.x) + __popc(e4.y) + __popc(e4.z) + __popc(e4.w);
+    uint32_t ew[RUN / 4];
+#pragma unroll
+    for (int w = 0; w < RUN / 16; ++w) {
+      uint4 e4 = make_uint4(0u, 0u, 0u, 0u);
+      if (p0 + 16 * w < n) e4 = *reinterpret_cast<const uint4*>(elig + p0 + 16 * w);
+      ew[4 * w] = e4.x;
+      ew[4 * w + 1] = e4.y;
+      ew[4 * w + 2] = e4.z;
+      ew[4 * w + 3] = e4.w;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < RUN / 4; ++w) cnt += __popc(ew[w]);
     int tot;
     int rank = block_exclusive_scan<1024>(cnt, &tot, sh);
     if (cnt && got + rank < want) {
@@ -726,7 +738,8 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
 // seeds (mode 0).  next_ctr receives the appends to next_active.
 template <int DP>
 __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, const int* __restrict__ active,
-                                           float* __restrict__ y, uint8_t* __restrict__ state,
+                                           const float* __restrict__ ycur, float* __restrict__ y,
+                                           uint8_t* __restrict__ state,
                                            int* __restrict__ iters, int* __restrict__ next_active,
                                            float* __restrict__ yc_next, float* __restrict__ vnorm,
                                            int* __restrict__ next_ctr, int* __restrict__ refine_bad, int n_act,
@@ -751,10 +764,12 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     const bool live_seed = a < n_act && sl < spw;
     const bool owner = live_seed && ph == 0;
     // The centre's slot and its current row do not depend on the partials:
-    // request them first.
+    // request them first (the row from the compacted copy in list order when
+    // there is one, so that it does not wait for the slot).
     const int slot = owner ? active[a] : 0;
     float4 yo = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (owner) yo = *reinterpret_cast<const float4*>(y + (int64_t)slot * DP + 4 * q);
+    if (owner)
+      yo = *reinterpret_cast<const float4*>(ycur ? ycur + (int64_t)a * DP + 4 * q : y + (int64_t)slot * DP + 4 * q);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live_seed) {
       const float4* src = reinterpret_cast<const float4*>(partial + (int64_t)a * DP + 4 * q);
@@ -839,15 +854,17 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
 
 template <int DP>
 __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restrict__ partial,
-                                                const int* __restrict__ active, float* __restrict__ y,
-                                                uint8_t* __restrict__ state, int* __restrict__ iters,
-                                                int* __restrict__ next_active, float* __restrict__ yc_next,
-                                                float* __restrict__ vnorm, IterCtl ctl, Tiling tl, int mode) {
+                                                const int* __restrict__ active, const float* __restrict__ ycur,
+                                                float* __restrict__ y, uint8_t* __restrict__ state,
+                                                int* __restrict__ iters, int* __restrict__ next_active,
+                                                float* __restrict__ yc_next, float* __restrict__ vnorm, IterCtl ctl,
+                                                Tiling tl, int mode) {
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
   int* meta = bt.meta + (int64_t)f * META_COUNT;
   partial += g.part0 * DP;
   active += g.row0;
+  if (ycur) ycur += g.row0 * DP;
   y += g.row0 * DP;
   state += g.row0;
   iters += g.row0;
@@ -863,7 +880,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
   } else {
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
-  const int conv = reduce_body<DP>(partial, active, y, state, iters, next_active, yc_next, vnorm, next_ctr,
+  const int conv = reduce_body<DP>(partial, active, ycur, y, state, iters, next_active, yc_next, vnorm, next_ctr,
                                    meta + META_REFINE_BAD, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
                                    (int)gridDim.x);
   if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
@@ -1774,7 +1791,7 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm) {
+                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm, const float* ycur) {
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
@@ -1784,8 +1801,8 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
   const int spw = std::max(1, 256 / ((dp / 4) * P));
   const dim3 grid(cdiv(cap, spw), b.F), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                      \
-  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, y, state, iters, next_active, yc_next,   \
-                     vnorm, ctl, t, mode)
+  hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, ycur, y, state, iters, next_active,     \
+                     yc_next, vnorm, ctl, t, mode)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
