@@ -875,15 +875,19 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
       // ranking keeps the converged ones.
       HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, pick_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
                                 h->y.as<float>(), nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
+      // The candidate list buffer is free in a round: it holds each
+      // candidate's first word with an earlier conflict for the greedy pass.
+      int* first = h->cand.as<int>();
       HIP_TRY(fms::launch_rank_converged(c.st, c.b, h->state.as<uint8_t>(), h->counts.as<int>(), h->sorted.as<int>(),
-                                         h->scount.as<int>()));
+                                         h->scount.as<int>(), first));
       int kmax = 0;
       for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.rt.want > 0 ? fh.k_modes : 0);
       HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->sorted.as<int>(), cap, h->sorted.as<int>(),
-                                  cap, h->modes.as<float>(), kmax, h->bits.as<uint32_t>(), META_NCAND, META_NCAND));
+                                  cap, h->modes.as<float>(), kmax, h->bits.as<uint32_t>(), META_NCAND, META_NCAND,
+                                  first));
       HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->sorted.as<int>(),
                                  h->scount.as<int>(), META_NCAND, META_NACC, c.dp, h->modes.as<float>(),
-                                 h->mode_counts.as<int>()));
+                                 h->mode_counts.as<int>(), first));
     } else {
       std::vector<int> conv;
       FMS_TRY(host_converged(h, c, conv));

@@ -194,20 +194,25 @@ hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 // rt.bits_c0, row stride rt.words_c) when cols is given, and against the
 // frame's modes before the pass, c < rt.k_modes (nmodes bounds it; bits at
 // rt.bits_m0, stride rt.words_m) when modes is given; one launch for both.
+// With `first` (cols = rows, INT_MAX-initialised), first[j] receives the
+// first word of row j holding an earlier candidate's bit.
 int simbits_words(int ncols);
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
                           const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
-                          int cols_slot);
+                          int cols_slot, int* first = nullptr);
 // Pruning on the device (one work group per frame): converged list, ranking,
 // greedy suppression.
 hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand);
 hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount);
 // Ranking straight from the round's states: the converged slots k <
 // meta[META_NSEL] by (count desc, k asc); their number to meta[META_NCAND].
+// first (may be null) is set to INT_MAX for every candidate, for
+// launch_simbits.
 hipError_t launch_rank_converged(hipStream_t s, const Batch& b, const uint8_t* state, const int* counts, int* sorted,
-                                 int* scount);
+                                 int* scount, int* first = nullptr);
 hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, const float* y, const int* sorted,
-                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts);
+                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts,
+                         const int* first = nullptr);
 // Single frame: append accepted candidates (indices into list) at k0.
 hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int* list, const int* counts,
                                const int* acc, int a, float* modes, int* mode_counts, int k0);

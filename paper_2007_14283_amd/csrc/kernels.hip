@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "fms_internal.h"
@@ -952,11 +953,14 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
 // frame's modes (bits at tab.bits_m0, tab.words_m words per row).  A wave
 // owns 64 columns and 16 rows; each lane keeps its column vector in
 // registers and reads the (wave-uniform) row vectors.  Row strides are
-// multiples of 2 words.
+// multiples of 2 words.  With `first` (candidate columns = the rows, in rank
+// order), first[j] is lowered to the first word of row j holding a column
+// c < j that is set (it must start at INT_MAX).
 template <int DP>
 __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restrict__ y, const int* __restrict__ rows,
                                                  const int* __restrict__ cols_, const float* __restrict__ colmat_,
-                                                 uint32_t* __restrict__ bits, int rows_slot, int cols_slot, int split) {
+                                                 uint32_t* __restrict__ bits, int rows_slot, int cols_slot, int split,
+                                                 int* __restrict__ first) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int f = blockIdx.y;
   const bool mode_part = (int)blockIdx.x >= split;
@@ -974,6 +978,7 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
   rows += g.row0;
   if (cols) cols += g.row0;
   if (colmat) colmat += g.row0 * DP;
+  if (first) first += g.row0;
   bits += cols ? tab.bits_c0 : tab.bits_m0;
   const int col_tiles = words / 2;
   if (col_tiles == 0 || bx >= col_tiles * ((m + 63) / 64)) return;
@@ -1003,6 +1008,13 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
     if (lane == 0) {
       bits[(int64_t)j * words + 2 * ct] = (uint32_t)bal;
       bits[(int64_t)j * words + 2 * ct + 1] = (uint32_t)(bal >> 32);
+      if (first && cols) {
+        // The columns of this tile before column j.
+        const int before = j - ct * 64;
+        const unsigned long long early =
+            before <= 0 ? 0ull : (before >= 64 ? bal : bal & ((1ull << before) - 1ull));
+        if (early) atomicMin(first + j, 2 * ct + ((uint32_t)early ? 0 : 1));
+      }
     }
   }
 }
@@ -1038,7 +1050,7 @@ __global__ __launch_bounds__(1024) void k_collect(Batch bt, const uint8_t* __res
 // keys sorting last; NSEL <= kRankMax.
 __global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t* __restrict__ state,
                                                          const int* __restrict__ counts, int* __restrict__ sorted,
-                                                         int* __restrict__ scount) {
+                                                         int* __restrict__ scount, int* __restrict__ first) {
   __shared__ unsigned long long key[kRankMax];
   __shared__ int s_nc;
   const FrameGeo& g = bt.geo[blockIdx.x];
@@ -1078,10 +1090,12 @@ __global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t
     }
   }
   const int nc = s_nc;
+  if (first) first += g.row0;
   for (int r = threadIdx.x; r < nc; r += 1024) {
     const int k = (int)(key[r] & 0xFFFFFFFFull);
     sorted[r] = k;
     scount[r] = counts[k];
+    if (first) first[r] = INT_MAX;
   }
   if (threadIdx.x == 0) meta[META_NCAND] = nc;
 }
@@ -1135,13 +1149,19 @@ __global__ __launch_bounds__(1024) void k_rank(Batch bt, const int* __restrict__
 // as soon as an earlier accepted candidate conflicts with it and accepted
 // once every earlier conflicting candidate is rejected; each pass decides at
 // least the first undecided candidate, and every decision equals the
-// sequential one whatever order the passes observe.  The accepted rows are
+// sequential one whatever order the passes observe.  A candidate scans its
+// row upwards from a cursor and stops at the first undecided conflict; the
+// next pass resumes there, so a row is read about once in all.  With
+// `first` (the first word of each row with an earlier conflict, INT_MAX for
+// none) the scan starts there instead of at word 0.  The accepted rows are
 // appended to the mode set at k0; their number goes to meta[acc_slot].
 __global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __restrict__ bits,
                                                  const float* __restrict__ y, const int* __restrict__ sorted,
                                                  const int* __restrict__ scount, int ncand_slot, int acc_slot, int dp,
-                                                 float* __restrict__ modes, int* __restrict__ mode_counts) {
+                                                 float* __restrict__ modes, int* __restrict__ mode_counts,
+                                                 const int* __restrict__ first) {
   __shared__ uint8_t st[kRankMax];
+  __shared__ uint16_t cur[kRankMax];
   __shared__ int s_open;
   __shared__ int sh[17];
   const FrameGeo& g = bt.geo[blockIdx.x];
@@ -1155,8 +1175,11 @@ __global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __res
   scount += g.row0;
   modes += g.row0 * dp;
   mode_counts += g.row0;
+  if (first) first += g.row0;
   const int nc = meta[ncand_slot];
   for (int r = threadIdx.x; r < nc; r += 1024) {
+    const int f0 = first ? first[r] : 0;
+    cur[r] = (uint16_t)(f0 == INT_MAX ? (r >> 5) + 1 : f0);
     uint8_t v = 0;
     if (k0 > 0) {
       const uint32_t* rm = bits_m + (int64_t)r * words_m;
@@ -1177,7 +1200,8 @@ __global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __res
       const uint32_t* row = bits_c + (int64_t)r * words_c;
       bool rejected = false, waiting = false;
       const int wend = r >> 5;
-      for (int w = 0; w <= wend && !rejected; ++w) {
+      int w = cur[r];
+      for (; w <= wend; ++w) {
         uint32_t b = row[w];
         if (w == wend) b &= (r & 31) ? ((1u << (r & 31)) - 1u) : 0u;
         while (b) {
@@ -1188,14 +1212,19 @@ __global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __res
             rejected = true;
             break;
           }
-          if (sk == 0) waiting = true;
+          if (sk == 0) {
+            waiting = true;
+            break;
+          }
         }
+        if (rejected || waiting) break;
       }
       if (rejected) {
         reinterpret_cast<volatile uint8_t*>(st)[r] = 2;
       } else if (!waiting) {
         reinterpret_cast<volatile uint8_t*>(st)[r] = 1;
       } else {
+        cur[r] = (uint16_t)w;
         atomicAdd(&s_open, 1);
       }
     }
@@ -1830,8 +1859,8 @@ hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, i
 }
 
 hipError_t launch_rank_converged(hipStream_t s, const Batch& b, const uint8_t* state, const int* counts, int* sorted,
-                                int* scount) {
-  hipLaunchKernelGGL(k_rank_converged, dim3(b.F), dim3(1024), 0, s, b, state, counts, sorted, scount);
+                                int* scount, int* first) {
+  hipLaunchKernelGGL(k_rank_converged, dim3(b.F), dim3(1024), 0, s, b, state, counts, sorted, scount, first);
   return hipGetLastError();
 }
 
@@ -1841,9 +1870,10 @@ hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int
 }
 
 hipError_t launch_greedy(hipStream_t s, const Batch& b, const uint32_t* bits, const float* y, const int* sorted,
-                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts) {
+                         const int* scount, int ncand_slot, int acc_slot, int dp, float* modes, int* mode_counts,
+                         const int* first) {
   hipLaunchKernelGGL(k_greedy, dim3(b.F), dim3(1024), 0, s, b, bits, y, sorted, scount, ncand_slot, acc_slot, dp,
-                     modes, mode_counts);
+                     modes, mode_counts, first);
   return hipGetLastError();
 }
 
@@ -1851,7 +1881,7 @@ int simbits_words(int ncols) { return std::max(2, ((ncols + 63) / 64) * 2); }
 
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
                           const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
-                          int cols_slot) {
+                          int cols_slot, int* first) {
   if (m <= 0) return hipSuccess;
   const unsigned part_c = cols && ncols > 0 ? (unsigned)((simbits_words(ncols) / 2) * cdiv(m, 64)) : 0u;
   const unsigned part_m = modes && nmodes > 0 ? (unsigned)((simbits_words(nmodes) / 2) * cdiv(m, 64)) : 0u;
@@ -1860,7 +1890,7 @@ hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y,
   const int split = (int)part_c;
 #define FMS_SIM_CASE(DPV)                                                                                     \
   hipLaunchKernelGGL(k_simbits<DPV>, grid, dim3(256), 0, s, b, y, rows, cols, modes, bits, rows_slot, cols_slot, \
-                     split)
+                     split, first)
   switch (dp) {
     case 32: FMS_SIM_CASE(32); break;
     case 64: FMS_SIM_CASE(64); break;
