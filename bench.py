@@ -225,6 +225,38 @@ def _differentiation(fms, torch, frame, seeds_used, reps=5):
             "tflops": flops / dt / 1e12}
 
 
+def _precision1024(fms, torch, reps=10):
+    """The precision workload: one 1024x1024 frame, 300 cells, D=32, in both
+    forms, with the mode error of each against the stored FP64 oracle result
+    (tests/golden/precision1024_oracle.npz, written from oracle/ alone)."""
+    import numpy as np
+
+    import synth
+    from tests import parity
+    spec = synth.PRECISION1024
+    f = synth.make_frame(spec)
+    g = parity.load_precision1024()
+    e = torch.from_numpy(f.emb).cuda()
+    m = torch.from_numpy(f.mask).cuda()
+    out = {"workload": f"one {spec.height}x{spec.width} frame, {spec.n_cells} cells (radii {spec.r_min}-{spec.r_max}), "
+                       f"D={spec.dim}, sigma={spec.sigma}, h={f.bandwidth}, seed {spec.seed}",
+           "n_fg": f.n_fg, "oracle_modes": int(len(g["modes"]))}
+    for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5)):
+        fms.cluster(e, m, f.bandwidth, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            modes, _, st = fms.cluster(e, m, f.bandwidth, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
+        out[name] = {"frames_per_s": 1.0 / dt, "ms_per_frame": 1e3 * dt, "modes": int(len(modes)),
+                     "max_mode_err": mm.max_error, "oracle_modes_within_tol": int(np.sum(mm.errors <= tol)),
+                     "tol": tol, "unmatched_gpu": mm.unmatched_gpu, "unmatched_oracle": mm.unmatched_oracle,
+                     "updates_per_s": (st["seed_pixel_updates"] + st["refine_updates"]) / dt}
+    return out
+
+
 def _appendix_a(fms, torch, reps=5):
     """Appendix A overlap workload: 1000x1000, D=18, eight noise-free discs of
     diameter 250 pulled together (overlap 0.3), P = 0.95, h = 0.1."""
@@ -375,6 +407,7 @@ def main():
     print(f"differentiation: {out['differentiation']['ms_fwd_bwd']:.2f} ms forward+backward",
           file=sys.stderr, flush=True)
 
+    out["precision_1024"] = _precision1024(fms, torch)
     out["autotune"] = _autotune(fms, torch, emb, mask, h, a.steps)
     out["appendix_a"] = _appendix_a(fms, torch)
     out["online_n"] = _online_n(fms, torch)

@@ -1,0 +1,39 @@
+"""Writes precision1024_oracle.npz: the FP64 oracle's result on the 1024x1024,
+300-cell, D = 32 precision workload (synth.PRECISION1024), so that GPU tests
+and the benchmark can compare with it without the ~40 s oracle run.  Calls
+only oracle/ (and synth/ for the input).  Run from the repository root:
+
+    python tests/golden/make_precision1024.py
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import cluster as C  # noqa: E402
+
+BAND = 1e-4  # the exempt band of the label comparison
+
+
+def main():
+    f = synth.make_frame(synth.PRECISION1024)
+    r = C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth))
+    thr = 1.0 - f.bandwidth
+    band = np.abs(r.best - thr) < BAND
+    tie = np.abs(r.best - r.second) < BAND
+    stats = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in r.stats.items()}
+    np.savez_compressed(os.path.join(HERE, "precision1024_oracle.npz"),
+                        modes=r.modes.astype(np.float64), mode_counts=np.asarray(r.mode_counts, np.int32),
+                        fg_labels=np.asarray(r.labels).reshape(-1)[r.fg].astype(np.int16),
+                        band=np.packbits(band), tie=np.packbits(tie), n_fg=np.int64(len(r.fg)),
+                        bandwidth=np.float64(f.bandwidth), stats=np.frombuffer(json.dumps(stats).encode(), np.uint8))
+    print(len(r.modes), "modes;", stats)
+
+
+if __name__ == "__main__":
+    main()

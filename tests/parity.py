@@ -54,9 +54,16 @@ class LabelCompare:
 
 def compare_labels(gpu_labels, res, match: ModeMatch, thr: float) -> LabelCompare:
     """Compare GPU labels (H*W, -1 background) with the oracle result."""
-    gl = np.asarray(gpu_labels).reshape(-1).astype(np.int64)
     ol = np.asarray(res.labels).reshape(-1)
-    fg = res.fg
+    band = np.abs(res.best - thr) < BAND
+    tie = np.abs(res.best - res.second) < BAND
+    return compare_labels_fg(gpu_labels, res.fg, ol[res.fg], band, tie, match)
+
+
+def compare_labels_fg(gpu_labels, fg, o_fg, band, tie, match: ModeMatch) -> LabelCompare:
+    """The same from the oracle's foreground labels and exempt masks (per
+    foreground pixel, raster order)."""
+    gl = np.asarray(gpu_labels).reshape(-1).astype(np.int64)
     bg_ok = np.all(gl[np.setdiff1d(np.arange(len(gl)), fg)] == -1)
     assert bg_ok, "background pixels must be labelled -1"
     remap = np.full(max(1, gl.max() + 1), -2, np.int64)
@@ -64,11 +71,24 @@ def compare_labels(gpu_labels, res, match: ModeMatch, thr: float) -> LabelCompar
         remap[gi] = oi
     g_fg = gl[fg]
     mapped = np.where(g_fg >= 0, remap[np.clip(g_fg, 0, None)], -1)
-    o_fg = ol[fg]
-    band = np.abs(res.best - thr) < BAND
-    tie = np.abs(res.best - res.second) < BAND
+    o_fg = np.asarray(o_fg).astype(np.int64)
     exempt = band | tie
     unmatched = mapped == -2
     bad = (mapped != o_fg) & ~unmatched
     return LabelCompare(len(fg), int(np.count_nonzero(bad & ~exempt)), int(band.sum()), int(tie.sum()),
                         int(np.count_nonzero(bad & exempt)), int(unmatched.sum()))
+
+
+def load_precision1024():
+    """The stored oracle result of the 1024x1024 precision workload
+    (tests/golden/precision1024_oracle.npz, written by make_precision1024.py
+    from oracle/ alone): a dict of modes, mode_counts, fg_labels, band, tie,
+    bandwidth and stats."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "precision1024_oracle.npz")
+    z = np.load(path)
+    n = int(z["n_fg"])
+    return {"modes": z["modes"], "mode_counts": z["mode_counts"], "fg_labels": z["fg_labels"].astype(np.int64),
+            "band": np.unpackbits(z["band"])[:n].astype(bool), "tie": np.unpackbits(z["tie"])[:n].astype(bool),
+            "bandwidth": float(z["bandwidth"]), "stats": json.loads(bytes(z["stats"]).decode())}
