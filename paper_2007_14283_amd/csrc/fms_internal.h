@@ -200,10 +200,9 @@ int simbits_words(int ncols);
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
                           const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
                           int cols_slot, int* first = nullptr);
-// Pruning on the device (one work group per frame): converged list, ranking,
-// greedy suppression.
+// Pruning on the device (one work group per frame): converged list, greedy
+// suppression.
 hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand);
-hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount);
 // Ranking straight from the round's states: the converged slots k <
 // meta[META_NSEL] by (count desc, k asc); their number to meta[META_NCAND].
 // first (may be null) is set to INT_MAX for every candidate, for

@@ -1100,48 +1100,6 @@ __global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t
   if (threadIdx.x == 0) meta[META_NCAND] = nc;
 }
 
-// Rank the nc candidates by window count (descending), then by index
-// (ascending, = seed position): sorted[r] = cand[a_r], scount[r] = count.
-// Bitonic sort of 64-bit keys in LDS; nc <= kRankMax.
-__global__ __launch_bounds__(1024) void k_rank(Batch bt, const int* __restrict__ cand, const int* __restrict__ counts,
-                                               int* __restrict__ sorted, int* __restrict__ scount) {
-  __shared__ unsigned long long key[kRankMax];
-  const FrameGeo& g = bt.geo[blockIdx.x];
-  cand += g.row0;
-  counts += g.row0;
-  sorted += g.row0;
-  scount += g.row0;
-  const int nc = bt.meta[(int64_t)blockIdx.x * META_COUNT + META_NCAND];
-  int np = 1;
-  while (np < nc) np <<= 1;
-  for (int i = threadIdx.x; i < np; i += 1024) {
-    key[i] = i < nc ? ((unsigned long long)(uint32_t)(0x7FFFFFFF - counts[i]) << 32) | (uint32_t)i
-                    : ~0ull;
-  }
-  __syncthreads();
-  for (int size = 2; size <= np; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < np; i += 1024) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;
-          const unsigned long long a = key[i], b = key[j];
-          if ((a > b) == up) {
-            key[i] = b;
-            key[j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int r = threadIdx.x; r < nc; r += 1024) {
-    const int a = (int)(key[r] & 0xFFFFFFFFull);
-    sorted[r] = cand[a];
-    scount[r] = counts[a];
-  }
-}
-
 // Greedy suppression (Alg. 2 "Prune modes") over candidates already in rank
 // order: candidate r is accepted when no existing mode is within its window
 // (row r of bits_m is empty) and no accepted candidate r' < r is (bit r' of
@@ -1861,11 +1819,6 @@ hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, i
 hipError_t launch_rank_converged(hipStream_t s, const Batch& b, const uint8_t* state, const int* counts, int* sorted,
                                 int* scount, int* first) {
   hipLaunchKernelGGL(k_rank_converged, dim3(b.F), dim3(1024), 0, s, b, state, counts, sorted, scount, first);
-  return hipGetLastError();
-}
-
-hipError_t launch_rank(hipStream_t s, const Batch& b, const int* cand, const int* counts, int* sorted, int* scount) {
-  hipLaunchKernelGGL(k_rank, dim3(b.F), dim3(1024), 0, s, b, cand, counts, sorted, scount);
   return hipGetLastError();
 }
 
