@@ -309,8 +309,9 @@ def _autotune(fms, torch, emb, mask, h, steps):
     active-seed count (fused step + reduction, tuned against default), and the
     BF16+refine frame rate with the tuned table against the defaults."""
     t0 = time.perf_counter()
-    ent = fms.autotune(emb, mask, h, precision=fms.BF16_REFINE)
+    res = fms.autotune(emb, mask, h, precision=fms.BF16_REFINE)
     tune_s = time.perf_counter() - t0
+    ent = res["entries"]
     rates = {}
     for name in ("default", "tuned", "default_again"):
         if name == "tuned":
@@ -325,7 +326,8 @@ def _autotune(fms, torch, emb, mask, h, steps):
         torch.cuda.synchronize()
         rates[name] = steps / (time.perf_counter() - t0)
     fms.clear_tuning()
-    return {"tune_s": tune_s,
+    return {"tune_s": tune_s, "kept": res["kept"], "call_ms_default": res["ms_default"],
+            "call_ms_tuned": res["ms_tuned"],
             "entries": [{k: e[k] for k in ("precision", "seeds", "tile_seeds", "tile_items", "tile_waves")} |
                         {"us_tuned": round(e["us_per_step"], 2), "us_default": round(e["us_default"], 2)}
                         for e in ent],

@@ -273,6 +273,13 @@ typedef struct {
   float us_default;     /* the same with the library's default decomposition */
 } fms_tune_entry;
 
+/* What fms_autotune decided (host struct). */
+typedef struct {
+  float ms_default;   /* median whole call on the frame without the new entries, ms */
+  float ms_tuned;     /* the same with them */
+  int32_t kept;       /* 1: the new entries are in the table (ms_tuned < ms_default) */
+} fms_tune_report;
+
 /* Autotuner of the fused step's work decomposition (Eq. 8, 10, 11 as run by
  * the parallel seed loop of Alg. 2).  The decomposition changes speed only:
  * results are the same up to the order of FP32 additions.
@@ -285,9 +292,12 @@ typedef struct {
  * 1024 items x 4, 8 or 16 waves) on m centres that start at the first m
  * foreground pixels: one warm-up, then the mean of 6 back-to-back pairs of
  * (fused step, renormalising reduction) between two HIP events on `stream`.
- * The fastest per (form, m) goes into the handle's table, replacing earlier
- * entries of the same form, D class and pixel-count bucket (n within a factor
- * of 4).  Later single-frame calls on this handle (fms_cluster,
+ * The fastest per (form, m) are then checked on whole calls of fms_cluster
+ * on the frame (one warm-up each, then 6 alternating rounds of two calls):
+ * they go into the handle's table, replacing earlier entries of the same
+ * form, D class and pixel-count bucket (n within a factor of 4), only when
+ * the median call is faster with them than without; otherwise those entries
+ * are removed and the defaults stay.  Later single-frame calls on this handle (fms_cluster,
  * fms_shift_seeds, fms_cluster_batch of one frame) whose tile_* parameters
  * are all 0 take, for each fused-step launch, the entry of the launch's form
  * and D class in the frame's bucket whose m is nearest (in ratio) to the
@@ -301,12 +311,14 @@ typedef struct {
  *  entries    host, capacity rows: the entries this call chose; NULL: not
  *             reported.
  *  n_entries  host, or NULL: number of entries this call chose (<= 8).
+ *  report     host, or NULL: the whole-call timings and whether the entries
+ *             were kept.
  * Synchronises `stream`.  Errors: INVALID_ARG (also an empty mask),
  * UNSUPPORTED, BAD_INPUT, CAPACITY (entries given with capacity below the
  * count, which *n_entries then holds; the table is updated regardless),
  * HIP. */
 fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
-                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries);
+                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries, fms_tune_report* report);
 
 /* Empty the handle's tuned table (later calls use the library's defaults). */
 fms_status fms_clear_tuning(fms_handle h);

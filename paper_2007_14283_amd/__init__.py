@@ -240,7 +240,9 @@ def autotune(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str =
              params: Optional[Params] = None, **kw):
     """Time the fused step's work decompositions on this frame (fms_autotune)
     and keep the fastest in the device's handle for later calls that leave
-    the tiling to the library.  Returns the chosen entries as dicts."""
+    the tiling to the library, when whole calls on the frame get faster with
+    them.  Returns {"entries": [dicts], "kept": bool, "ms_default": x,
+    "ms_tuned": y}."""
     import torch
     if bandwidth is not None:
         kw["bandwidth"] = bandwidth
@@ -258,14 +260,16 @@ def autotune(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str =
     fr.labels = None
     entries = (B.FmsTuneEntry * 16)()
     count = ctypes.c_int32(0)
+    report = B.FmsTuneReport()
     lib = library()
     hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
     cp = p.to_c()
     st = lib.fms_autotune(hdl, _stream_ptr(dev), ctypes.byref(fr), d, ctypes.byref(cp), entries, 16,
-                          ctypes.byref(count))
+                          ctypes.byref(count), ctypes.byref(report))
     if st != B.FMS_OK:
         raise FmsError(st, "fms_autotune")
-    return [entries[i].as_dict() for i in range(count.value)]
+    return {"entries": [entries[i].as_dict() for i in range(count.value)], "kept": bool(report.kept),
+            "ms_default": float(report.ms_default), "ms_tuned": float(report.ms_tuned)}
 
 
 def clear_tuning(device=None):

@@ -77,6 +77,14 @@ class FmsTuneEntry(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class FmsTuneReport(ctypes.Structure):
+    _fields_ = [
+        ("ms_default", ctypes.c_float),
+        ("ms_tuned", ctypes.c_float),
+        ("kept", ctypes.c_int32),
+    ]
+
+
 class FmsStats(ctypes.Structure):
     _fields_ = [
         ("seed_pixel_updates", ctypes.c_int64),
@@ -142,7 +150,7 @@ def load(path: str = LIB_PATH):
     lib.fms_unroll_backward.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, i32, f64, vp, vp, vp, vp, vp]
     lib.fms_unroll_backward.restype = ctypes.c_int
     lib.fms_autotune.argtypes = [vp, vp, ctypes.POINTER(FmsFrame), i32, ctypes.POINTER(FmsParams),
-                                 ctypes.POINTER(FmsTuneEntry), i32, ctypes.POINTER(i32)]
+                                 ctypes.POINTER(FmsTuneEntry), i32, ctypes.POINTER(i32), ctypes.POINTER(FmsTuneReport)]
     lib.fms_autotune.restype = ctypes.c_int
     lib.fms_clear_tuning.argtypes = [vp]
     lib.fms_clear_tuning.restype = ctypes.c_int

@@ -1247,7 +1247,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
 }
 
 fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
-                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries) {
+                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries, fms_tune_report* report) {
   if (!h || !frame || !p || capacity < 0 || (capacity > 0 && !entries)) return FMS_ERR_INVALID_ARG;
   DeviceGuard guard(h->device);
   fms_params q = *p;
@@ -1348,15 +1348,46 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
       found.push_back(best);
     }
   }
-  // Replace the table's entries of the same forms, D class and bucket.
-  std::vector<TunedTiling> keep;
+  // The table without entries of the same forms, D class and bucket, and
+  // with the new ones.
+  std::vector<TunedTiling> without, with;
   for (const TunedTiling& t : h->tuned) {
     bool same = false;
     for (const TunedTiling& u : found) same = same || (t.bf16 == u.bf16 && t.dp == u.dp && t.nb == u.nb);
-    if (!same) keep.push_back(t);
+    if (!same) without.push_back(t);
   }
-  for (const TunedTiling& u : found) keep.push_back(u);
-  h->tuned.swap(keep);
+  with = without;
+  for (const TunedTiling& u : found) with.push_back(u);
+  // Whole calls on the frame with each table, alternating (one warm-up call
+  // each, then kCallReps rounds of two calls); the new entries stay only
+  // when the median call is faster with them.
+  constexpr int kCallReps = 6;
+  std::vector<double> call_ms[2];
+  auto call = [&](const std::vector<TunedTiling>& table) -> fms_status {
+    h->tuned = table;
+    Call cc;
+    FMS_TRY(begin_call(h, stream, 1, &fr, dim, &q, cc));
+    ModeOutputs none{nullptr, nullptr, 0, {}, 0};
+    return cluster_frames(h, cc, &q, none);
+  };
+  for (int v = 0; v < 2; ++v) FMS_TRY(call(v ? with : without));
+  for (int r = 0; r < kCallReps; ++r)
+    for (int k = 0; k < 2; ++k) {
+      const int v = (r & 1) ? 1 - k : k;
+      const auto t0 = std::chrono::steady_clock::now();
+      FMS_TRY(call(v ? with : without));
+      FMS_TRY(call(v ? with : without));
+      call_ms[v].push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2);
+    }
+  for (auto& m : call_ms) std::sort(m.begin(), m.end());
+  const double ms_default = call_ms[0][kCallReps / 2], ms_tuned = call_ms[1][kCallReps / 2];
+  const bool kept = ms_tuned < ms_default;
+  h->tuned = kept ? with : without;
+  if (report) {
+    report->ms_default = float(ms_default);
+    report->ms_tuned = float(ms_tuned);
+    report->kept = kept ? 1 : 0;
+  }
   const int cnt = int(found.size());
   if (n_entries) *n_entries = cnt;
   if (!entries) return FMS_OK;

@@ -48,7 +48,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2007_14283_amd import _binding as B
     src = tmp_path / "layout.c"
     structs = [("fms_params", B.FmsParams), ("fms_stats", B.FmsStats), ("fms_frame", B.FmsFrame),
-               ("fms_tune_entry", B.FmsTuneEntry)]
+               ("fms_tune_entry", B.FmsTuneEntry), ("fms_tune_report", B.FmsTuneReport)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fms.h"', "int main(void) {"]
     want = []
     for cname, py in structs:

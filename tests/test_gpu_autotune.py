@@ -1,8 +1,9 @@
 """GPU tests of the fused-step autotuner (fms_autotune / fms_clear_tuning): the
 table it reports is well formed, a tuned handle still matches the FP64 oracle
-(FP32 modes within 1e-5, labels exact outside the exempt sets), a tuned call
-equals the call that fixes the same decomposition explicitly (bit for bit),
-and clearing the table restores the default path bit for bit."""
+(FP32 modes within 1e-5, labels exact outside the exempt sets), a call after
+tuning equals, bit for bit, the call that fixes the chosen decomposition
+explicitly when the entries were kept and the default call when they were
+not, and clearing the table restores the default path bit for bit."""
 import dataclasses
 
 import numpy as np
@@ -41,8 +42,11 @@ def test_autotune_table_is_well_formed(F):
     emb, mask = _dev(f)
     _say("autotune MID fp32 + bf16")
     for prec, forms in ((F.FP32, {0}), (F.BF16_REFINE, {0, 1})):
-        ent = F.autotune(emb, mask, f.bandwidth, precision=prec)
-        print(ent)
+        res = F.autotune(emb, mask, f.bandwidth, precision=prec)
+        print(res)
+        ent = res["entries"]
+        assert res["ms_default"] > 0 and res["ms_tuned"] > 0
+        assert res["kept"] == (res["ms_tuned"] < res["ms_default"])
         assert {e["precision"] for e in ent} == forms
         seeds = sorted({e["seeds"] for e in ent})
         assert seeds == [m for m in (128, 512, 2048, 8192) if m <= f.n_fg]
@@ -75,13 +79,17 @@ def test_tuned_call_equals_explicit_decomposition(F):
     assert f.n_fg < 128
     emb, mask = _dev(f)
     _say("tuned TINY vs explicit", f.n_fg)
-    ent = F.autotune(emb, mask, f.bandwidth, precision=F.FP32)
+    res = F.autotune(emb, mask, f.bandwidth, precision=F.FP32)
+    ent = res["entries"]
     assert len(ent) == 1 and ent[0]["seeds"] == f.n_fg
     e = ent[0]
     m1, l1, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32)
     F.clear_tuning()
-    m2, l2, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32, tile_seeds=e["tile_seeds"],
-                          tile_items=e["tile_items"], tile_waves=e["tile_waves"])
+    if res["kept"]:
+        m2, l2, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32, tile_seeds=e["tile_seeds"],
+                              tile_items=e["tile_items"], tile_waves=e["tile_waves"])
+    else:
+        m2, l2, _ = F.cluster(emb, mask, f.bandwidth, precision=F.FP32)
     assert np.array_equal(m1.cpu().numpy(), m2.cpu().numpy())
     assert np.array_equal(l1.cpu().numpy(), l2.cpu().numpy())
 
