@@ -142,3 +142,43 @@ def test_batch_of_one_is_the_single_frame_path(F, frames, oracles):
     (modes, labels, st), = F.cluster_batch(_inputs(frames[:1]), precision=F.FP32)
     mm = parity.match_modes(modes.cpu().numpy(), oracles[0].modes)
     assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
+
+
+def test_batch_nchw_layout(F, frames, oracles):
+    import torch
+    _say("batch nchw")
+    inp = [{"emb": torch.from_numpy(f.emb).cuda().permute(2, 0, 1).contiguous(),
+            "mask": torch.from_numpy(f.mask).cuda(), "bandwidth": f.bandwidth} for f in frames]
+    res = F.cluster_batch(inp, layout="nchw", precision=F.FP32)
+    for f, o, (modes, labels, st) in zip(frames, oracles, res):
+        mm = parity.match_modes(modes.cpu().numpy(), o.modes)
+        lc = parity.compare_labels(labels.cpu().numpy(), o, mm, 1.0 - f.bandwidth)
+        assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
+        assert lc.mismatched == 0
+
+
+def test_many_small_frames_equal_single_calls(F):
+    # 96 small frames of 11 different shapes and seeds in one call (the grid's
+    # frame dimension well beyond the CU count): every frame as its own call.
+    import torch
+    specs = [dataclasses.replace(synth.MID, height=24 + 4 * (k % 11), width=20 + 6 * (k % 7),
+                                 n_cells=2 + k % 5, r_min=3, r_max=8, seed=100 + k) for k in range(96)]
+    frames = [synth.make_frame(s) for s in specs]
+    inp = [{"emb": torch.from_numpy(f.emb).cuda(), "mask": torch.from_numpy(f.mask).cuda(),
+            "bandwidth": f.bandwidth} for f in frames]
+    _say("96 small frames")
+    res = F.cluster_batch(inp, precision=F.FP32)
+    for x, (bm, bl, bst) in zip(inp, res):
+        sm, sl, sst = F.cluster(x["emb"], x["mask"], x["bandwidth"], precision=F.FP32)
+        assert bm.shape == sm.shape
+        if len(sm):
+            err = 1.0 - np.sum(bm.cpu().double().numpy() * sm.cpu().double().numpy(), axis=1)
+            assert err.max() <= FP32_TOL
+        assert int((bl != sl).sum().item()) == 0
+        assert bst["rounds"] == sst["rounds"] and bst["seeds_used"] == sst["seeds_used"]
+    # The BF16 form may take other paths near window edges under another
+    # tiling; every frame still gets modes and labels.
+    res = F.cluster_batch(inp, precision=F.BF16_REFINE)
+    for f, (bm, bl, bst) in zip(frames, res):
+        assert len(bm) >= 1 and bst["n_fg"] == f.n_fg
+        assert int((bl >= 0).sum().item()) == f.n_fg
