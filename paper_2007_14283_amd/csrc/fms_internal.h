@@ -16,7 +16,7 @@ enum MetaSlot {
   META_CURSOR = 3,     // seed-order cursor (every earlier position is used or covered)
   META_NCONV = 4,      // converged seeds this round
   META_REFINE_BAD = 6, // refine steps whose move stayed >= tol
-  META_LEFT = 7,       // foreground pixels still eligible as seeds (coverage), or farther than h from every mode (labels)
+  META_LEFT = 7,       // nonzero iff a foreground pixel is still eligible as a seed (coverage); pixels farther than h from every mode (labels)
   META_BADSEED = 8,    // seed indices outside [0, n)
   META_DONE = 10,      // the round's iteration has stopped
   META_STEPS = 12,     // iterations run this round
@@ -217,8 +217,8 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
                                const int* acc, int a, float* modes, int* mode_counts, int k0);
 // Coverage (mode 0: against the frame's new modes [rt.k_modes, rt.k_modes +
 // meta[k1_slot])) or labels (mode 1: against modes [0, rt.k_modes)); both
-// count into META_LEFT (pixels left to seed, resp. farther than h from
-// every mode).
+// write META_LEFT (nonzero iff a pixel is left to seed, resp. the number of
+// pixels farther than h from every mode).
 hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
                          int mode, uint8_t* elig, const int* rank, const int* fg_idx);
 // meta[slot] of every frame to rt.nact (from_rt) or to value.

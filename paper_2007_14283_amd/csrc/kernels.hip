@@ -748,6 +748,7 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
   constexpr int Q = DP / 4;  // float4 slices per row
   __shared__ float4 part[256];
   __shared__ int s_conv;
+  __shared__ int s_wn[4], s_wb[4];
   const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int nc = cp.n_chunks;
   int P = 1;
@@ -755,7 +756,7 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
   const int tpr = Q * P;       // threads per seed
   const int spw = 256 / tpr;   // seeds per work group tile
   const int tiles = (n_act + spw - 1) / spw;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sl = tid / tpr, rest = tid - sl * tpr, q = rest % Q, ph = rest / Q;
   if (tid == 0) s_conv = 0;
   __syncthreads();
@@ -825,13 +826,26 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
         if (dead) state[slot] = 2;
         if (conv) state[slot] = 1;
       }
-      // Wave-aggregated list append and converged count.
+      // List append: one counter update per work group (updates of one
+      // address from every wave queue behind each other), each wave's place
+      // after the waves before it; converged count per wave into LDS.
       const unsigned long long bn = __ballot(next);
       const unsigned long long bc = __ballot(conv);
-      int base = 0;
-      if (lane == 0 && bn) base = atomicAdd(next_ctr, __popcll(bn));
-      base = __shfl(base, 0, 64);
-      const int pos = base + __popcll(bn & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wn[wave] = __popcll(bn);
+      __syncthreads();
+      if (tid == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          s_wb[w] = tot;
+          tot += s_wn[w];
+        }
+        const int b0 = tot ? atomicAdd(next_ctr, tot) : 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) s_wb[w] += b0;
+      }
+      __syncthreads();
+      const int pos = s_wb[wave] + __popcll(bn & ((1ull << lane) - 1ull));
       if (next) next_active[pos] = slot;
       if (yc_next) {
         // The seed's owner lanes copy its new row to its place in the
@@ -1346,8 +1360,23 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
       }
     }
   }
+  // One counter update per work group.  Coverage only tells whether any
+  // pixel is left to seed, so it stores a flag instead of adding (updates of
+  // one address from every work group queue behind each other); labels add
+  // the exact count.
+  __shared__ int s_tally[4];
   tally = wave_sum_i(tally);
-  if (lane == 0 && tally) atomicAdd(meta + META_LEFT, tally);
+  if (lane == 0) s_tally[wave] = tally;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int t = s_tally[0] + s_tally[1] + s_tally[2] + s_tally[3];
+    if (t > 0) {
+      if (mode == 0)
+        meta[META_LEFT] = 1;
+      else
+        atomicAdd(meta + META_LEFT, t);
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_iota(Batch bt, int* __restrict__ p) {
