@@ -37,6 +37,8 @@ def _args():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--only-frame", action="store_true",
                     help="time the 512x512 frame in both forms only (no other sections; for kernel traces)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="time the uneven batched workload only (for kernel traces)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
                          "reference), then --steps frames of each form; prints a short summary only")
@@ -357,6 +359,10 @@ def main():
 
     import paper_2007_14283_amd as fms
     import synth
+
+    if a.only_batch:
+        print(json.dumps({"batched": _batched(fms, torch, a)}), flush=True)
+        return
 
     spec = synth.PLAIN512
     frame = synth.make_frame(spec)
