@@ -169,6 +169,21 @@ def test_cluster_fp32_matches_oracle(F, torch_mod, spec, layout):
     np.testing.assert_array_equal(st["mode_counts"].cpu().numpy(), res.mode_counts)
 
 
+# The controller (Sec. 3.2.4) doubles N only while a pixel is left to seed,
+# also in the last round the limit allows.  On TINY and MID the second round
+# empties the pool: a limit of two rounds ends with nothing left (N stays),
+# a limit of one with pixels left (N doubled).
+@pytest.mark.parametrize("spec", [synth.TINY, synth.MID])
+@pytest.mark.parametrize("max_rounds", [1, 2])
+def test_round_limit_matches_oracle(F, torch_mod, spec, max_rounds):
+    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32", max_rounds=max_rounds)
+    assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
+    assert mm.max_error <= FP32_TOL
+    assert lc.mismatched == 0
+    for k in ("rounds", "seeds_used", "iterations_total", "n_discarded", "n_state_out"):
+        assert st[k] == res.stats[k], k
+
+
 def _fp64_residual(modes, res, h):
     # 1 - m . shift(m) under the FP64 map: ~0 for a true mode of the method.
     from oracle import meanshift as ms
