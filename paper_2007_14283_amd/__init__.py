@@ -20,8 +20,8 @@ from typing import Dict, Optional
 
 from . import _binding as B
 
-__all__ = ["Params", "FmsError", "cluster", "cluster_batch", "shift_seeds", "unroll", "seed_order",
-           "default_params", "library"]
+__all__ = ["Params", "FmsError", "FP32", "BF16_REFINE", "cluster", "cluster_batch", "shift_seeds", "unroll",
+           "autotune", "clear_tuning", "seed_order", "default_params", "library"]
 
 FP32 = B.FMS_PREC_FP32
 BF16_REFINE = B.FMS_PREC_BF16_REFINE
