@@ -92,6 +92,12 @@ typedef struct {
   int32_t tile_items;
   int32_t tile_chunks;
   int32_t tile_waves;
+  /* Nonzero: each batch of seed iterations (the step and reduction launches
+   * enqueued between two reads of the counters) is captured once per shape
+   * into a HIP graph, kept in the handle and replayed; 0 (the default)
+   * launches every kernel separately.  Results are identical either way.
+   * Ignored when `timing` is set. */
+  int32_t graphs;
 } fms_params;
 
 /* Per-call statistics (host struct). */

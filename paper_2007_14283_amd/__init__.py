@@ -55,6 +55,7 @@ class Params:
     tile_items: int = 0
     tile_chunks: int = 0
     tile_waves: int = 0
+    graphs: int = 0
 
     def to_c(self) -> B.FmsParams:
         c = B.FmsParams()

@@ -43,6 +43,7 @@ class FmsParams(ctypes.Structure):
         ("tile_items", ctypes.c_int32),
         ("tile_chunks", ctypes.c_int32),
         ("tile_waves", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 

@@ -170,6 +170,24 @@ struct TunedTiling {
   fms_tune_entry e;
 };
 
+// Everything the launches of one batch of seed iterations depend on: a
+// captured graph replays only for an equal key.  Only the parity of the
+// iteration number reaches the kernels, and whether the batch starts the
+// round (its first step reads the centres in place).
+struct IterKey {
+  const void* ptr[16] = {};
+  int64_t val[16] = {};
+  double gamma = 0.0;
+  bool operator==(const IterKey& o) const {
+    return std::memcmp(ptr, o.ptr, sizeof(ptr)) == 0 && std::memcmp(val, o.val, sizeof(val)) == 0 &&
+           gamma == o.gamma;
+  }
+};
+struct CachedGraph {
+  IterKey key;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct fms_handle_s {
   int device = 0;
   // Decompositions chosen by fms_autotune (empty: the library's defaults).
@@ -202,6 +220,15 @@ struct fms_handle_s {
   // whole-stream synchronisation).  A wait also frees the pinned tables for
   // the next upload.
   hipEvent_t sync_ev = nullptr;
+  // Captured iteration batches (fms_params.graphs) and the stream they are
+  // captured on (created on first use; the caller's stream may be the null
+  // stream, which cannot be captured).
+  std::vector<CachedGraph> graphs;
+  hipStream_t cap_st = nullptr;
+  void drop_graphs() {
+    for (CachedGraph& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   hipError_t wait(hipStream_t st) {
     hipError_t e = hipEventRecord(sync_ev, st);
     if (e == hipSuccess) e = hipEventSynchronize(sync_ev);
@@ -290,6 +317,7 @@ struct Call {
   fms::Batch b{};
   int64_t max_pixels = 0;
   Timing tm;
+  bool graphs = false;  // capture and replay iteration batches
 };
 
 fms_status check_params(const fms_params* p) {
@@ -537,6 +565,35 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   return FMS_OK;
 }
 
+// Launch the graph captured for `key` on stream st, capturing it first (the
+// launches `record` makes on the stream it is given) when the handle has
+// none.  The cache is emptied when it reaches 64 graphs.
+template <typename Record>
+hipError_t run_graph(fms_handle h, hipStream_t st, const IterKey& key, Record&& record) {
+  for (const CachedGraph& g : h->graphs)
+    if (g.key == key) return hipGraphLaunch(g.exec, st);
+  if (!h->cap_st) {
+    const hipError_t e = hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const hipError_t er = record(h->cap_st);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(h->cap_st, &graph);
+  if (er != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return er != hipSuccess ? er : e;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  if (h->graphs.size() >= 64) h->drop_graphs();
+  h->graphs.push_back(CachedGraph{key, exec});
+  return hipGraphLaunch(exec, st);
+}
+
 // Iterate every frame's centres y[row0 .. row0 + NSEL) (Alg. 2, the parallel
 // seed loop) until more than gamma of them converged (Sec. 3.2.3), none is
 // active, or max_iter steps; each frame stops on its own counters.  With
@@ -564,23 +621,49 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   // compacts.  Iteration 0 reads the centres in place (the active list is
   // the identity); later iterations read the rows the previous reduce
   // compacted in active-list order.
-  auto iterate = [&](const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
+  auto iterate_on = [&](hipStream_t st, const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     const fms::IterCtl ctl{-1, it, gamma};
     const float* yin = it == 0 ? ybuf : yc[it & 1];
-    hipError_t e = fms::launch_shift(c.st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap,
+    hipError_t e = fms::launch_shift(st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap,
                                      h->partial.as<float>(), e0, e1);
     if (e == hipSuccess)
-      e = fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
+      e = fms::launch_reduce(st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
                              h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0, nullptr, yin);
     return e;
+  };
+  auto iterate = [&](const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
+    return iterate_on(c.st, tl, it, e0, e1);
+  };
+  // Iterations t .. t + n - 1 as one replayed graph.
+  auto iterate_graph = [&](const fms::Tiling& tl, int t0, int n) -> hipError_t {
+    IterKey k;
+    const void* ptrs[] = {xrm, xt, ybuf, yc[0], yc[1], lists[0], lists[1], h->partial.p, h->state.p, h->iters.p,
+                          b.geo, b.rt, b.meta, b.meta64};
+    std::memcpy(k.ptr, ptrs, sizeof(ptrs));
+    const int64_t vals[] = {bf16, c.dp, tl.group_seeds, tl.target_items, tl.max_chunks, tl.waves, cap, n,
+                            t0 & 1, t0 == 0, b.F, b.max_n, b.max_blocks, b.max_mblk};
+    std::memcpy(k.val, vals, sizeof(vals));
+    k.gamma = gamma;
+    return run_graph(h, c.st, k, [&](hipStream_t st) -> hipError_t {
+      for (int i = 0; i < n; ++i) {
+        const hipError_t e = iterate_on(st, tl, t0 + i, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    });
   };
   while (t < max_iter) {
     const int nb = std::min(kSched[std::min(nbatch, 2)], max_iter - t);
     ++nbatch;
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
     const fms::Tiling& tl = pick_tiling(c, bf16, bound);
-    for (int i = 0; i < nb; ++i, ++t)
-      HIP_TRY(iterate(tl, t, timing ? h->events[2 * i] : nullptr, timing ? h->events[2 * i + 1] : nullptr));
+    if (c.graphs) {
+      HIP_TRY(iterate_graph(tl, t, nb));
+      t += nb;
+    } else {
+      for (int i = 0; i < nb; ++i, ++t)
+        HIP_TRY(iterate(tl, t, timing ? h->events[2 * i] : nullptr, timing ? h->events[2 * i + 1] : nullptr));
+    }
     // The counters after this batch go to the host while the GPU runs one
     // more iteration behind them (without timing): a round that goes on
     // keeps the GPU busy during the host's decision, and one that stopped
@@ -1021,6 +1104,7 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   c.dim = dim;
   c.dp = pad_dim(dim);
   c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
+  c.graphs = p->graphs != 0 && p->timing == 0;
   set_tiling(c, p);
   // The tuned table holds single-frame launches; a batch launch spreads over
   // its frames and keeps the defaults.
@@ -1131,6 +1215,8 @@ fms_status fms_destroy(fms_handle h) {
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
+  h->drop_graphs();
+  if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
   for (PinBuf* b : {&h->hpub, &h->hgeo, &h->hrt, &h->hoff, &h->hstage}) b->release();
   delete h;
   return FMS_OK;
