@@ -184,6 +184,46 @@ def test_round_limit_matches_oracle(F, torch_mod, spec, max_rounds):
         assert st[k] == res.stats[k], k
 
 
+# More than 16,384 candidates in one round (here the first round, 20,000
+# seeds on 27,248 foreground pixels) take the host pruning path.  The oracle
+# at that size is too slow for a test; these properties hold at any size:
+# modes pairwise outside each other's window (Alg. 2 pruning), modes fixed
+# points of the FP64 map (Eq. 8-11): all within 10 tol and at most 2 % (at
+# least one) beyond tol, since a mode stops when its last move falls below
+# tol and its next move may be slightly larger (the oracle's own modes at
+# 1024^2 show 3 of 399 beyond tol); and labels the most similar mode away
+# from near ties (Alg. 2, lowest index on ties), background -1.
+def test_host_pruning_path_properties(F, torch_mod):
+    from oracle import meanshift as ms
+    spec = synth.FrameSpec(256, 256, 30, 8, 30, 32, 0.08, 0.05, 7)
+    f = _frame(spec)
+    emb, mask = _dev(torch_mod, f)
+    h = f.bandwidth
+    _say("host pruning", f.n_fg, "n_state_in 20000")
+    modes, labels, st = F.cluster(emb, mask, h, n_state_in=20000)
+    assert f.n_fg > 20000 and st["seeds_used"] >= 20000
+    m = modes.cpu().double().numpy()
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    fg = np.flatnonzero(f.mask.reshape(-1))
+    x = f.emb.reshape(-1, f.emb.shape[-1])[fg].astype(np.float64)
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    assert len(m) >= 2
+    sim = m @ m.T
+    np.fill_diagonal(sim, -2.0)
+    assert sim.max() < 1.0 - h + 1e-5
+    _, delta, _ = ms.shift(m, x, 1.0 - h)
+    tol = h / 1000
+    print("largest FP64 residuals", np.sort(delta)[-5:], "tol", tol, "modes", len(m))
+    assert np.all(delta < 10 * tol)
+    assert np.sum(delta >= tol) <= max(1, int(0.02 * len(delta)))
+    s = x @ m.T
+    top2 = np.sort(s, axis=1)[:, -2:]
+    clear = top2[:, 1] - top2[:, 0] > 1e-4
+    lab = labels.cpu().numpy().reshape(-1)
+    np.testing.assert_array_equal(lab[fg][clear], np.argmax(s, axis=1)[clear])
+    assert np.all(np.delete(lab, fg) == -1)
+
+
 def _fp64_residual(modes, res, h):
     # 1 - m . shift(m) under the FP64 map: ~0 for a true mode of the method.
     from oracle import meanshift as ms
