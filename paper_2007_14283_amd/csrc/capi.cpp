@@ -1374,6 +1374,11 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
   HIP_TRY(h->pcount.ensure(prows * sizeof(int)));
   HIP_TRY(h->partial.ensure(prows * size_t(c.dp) * sizeof(float)));
   HIP_TRY(h->ensure_events(2));
+  // The identity list of the timed centres: k_iota writes rt.nact entries,
+  // so the count goes to the device first.
+  c.fr[0].rt = fms::RoundTab{};
+  c.fr[0].rt.nact = mmax;
+  FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), mmax));
   int* ident = h->ident.as<int>();
   float* y = h->y.as<float>();
