@@ -179,6 +179,25 @@ def _batched(fms, torch, a):
         out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": 1e3 * dt / a.batch_steps,
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
                      "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"])}
+    # Autotuned tiles: fms_autotune_batch on these frames (BF16+refine form);
+    # its entries serve the batch calls when whole calls got faster with them.
+    t0 = time.perf_counter()
+    tune = fms.autotune_batch(inp, precision=fms.BF16_REFINE)
+    tune_s = time.perf_counter() - t0
+    res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
+    res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.batch_steps):
+        res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["bf16_refine_autotuned"] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": 1e3 * dt / a.batch_steps,
+                                    "kept": tune["kept"], "tune_s": tune_s, "call_ms_default": tune["ms_default"],
+                                    "call_ms_tuned": tune["ms_tuned"], "modes": int(sum(len(r[0]) for r in res)),
+                                    "entries": [{k: e[k] for k in ("precision", "seeds", "tile_seeds", "tile_items",
+                                                                   "tile_waves")} for e in tune["entries"]]}
+    fms.clear_tuning()
     # The plain form: the same frames, one FP32 call each.
     for x in inp[:2]:
         fms.cluster(x["emb"], x["mask"], x["bandwidth"], precision=fms.FP32)

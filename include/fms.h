@@ -307,8 +307,8 @@ typedef struct {
  * fms_shift_seeds, fms_cluster_batch of one frame) whose tile_* parameters
  * are all 0 take, for each fused-step launch, the entry of the launch's form
  * and D class in the frame's bucket whose m is nearest (in ratio) to the
- * launch's bound on active seeds; without one, and in batches of several
- * frames (whose launches spread over the frames), the library's defaults.
+ * launch's bound on active seeds; without one, the library's defaults.
+ * Batches of several frames use only entries of fms_autotune_batch.
  *
  *  frame      host struct (device pointers); its bandwidth sets the windows;
  *             labels and n_state_in are ignored.
@@ -325,6 +325,23 @@ typedef struct {
  * HIP. */
 fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
                         fms_tune_entry* entries, int32_t capacity, int32_t* n_entries, fms_tune_report* report);
+
+/* fms_autotune for batches: the same candidates, seed counts m up to 2,048
+ * (each frame taking min(m, its foreground count) centres, from its first
+ * foreground pixels), the mean of 2 timed pairs, every timed launch spanning
+ * all n_frames >= 2 frames as the launches of fms_cluster_batch do, and the
+ * whole-call check on
+ * fms_cluster_batch of these frames.  The entries go into the handle's
+ * table beside the single-frame ones (entries of the same form, D class and
+ * bucket of the largest frame's pixel count, tuned on batches, are
+ * replaced), and later fms_cluster_batch calls of several frames whose
+ * tile_* parameters are all 0 use them in the same way; n_fg of an entry is
+ * the largest frame's foreground count.  Arguments and errors as for
+ * fms_autotune, `frames` being an array of n_frames host structs (INVALID_ARG
+ * also for n_frames < 2). */
+fms_status fms_autotune_batch(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames, int32_t dim,
+                              const fms_params* p, fms_tune_entry* entries, int32_t capacity, int32_t* n_entries,
+                              fms_tune_report* report);
 
 /* Empty the handle's tuned table (later calls use the library's defaults). */
 fms_status fms_clear_tuning(fms_handle h);

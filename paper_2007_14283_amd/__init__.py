@@ -21,7 +21,7 @@ from typing import Dict, Optional
 from . import _binding as B
 
 __all__ = ["Params", "FmsError", "FP32", "BF16_REFINE", "cluster", "cluster_batch", "shift_seeds", "unroll",
-           "autotune", "clear_tuning", "seed_order", "default_params", "library"]
+           "autotune", "autotune_batch", "clear_tuning", "seed_order", "default_params", "library"]
 
 FP32 = B.FMS_PREC_FP32
 BF16_REFINE = B.FMS_PREC_BF16_REFINE
@@ -269,6 +269,49 @@ def autotune(emb, mask=None, bandwidth: Optional[float] = None, *, layout: str =
                           ctypes.byref(count), ctypes.byref(report))
     if st != B.FMS_OK:
         raise FmsError(st, "fms_autotune")
+    return {"entries": [entries[i].as_dict() for i in range(count.value)], "kept": bool(report.kept),
+            "ms_default": float(report.ms_default), "ms_tuned": float(report.ms_tuned)}
+
+
+def autotune_batch(frames, *, layout: str = "nhwc", params: Optional[Params] = None, **kw):
+    """fms_autotune_batch: time the fused step's work decompositions on
+    launches spanning all ``frames`` (dicts as for ``cluster_batch``, at
+    least two) and keep the fastest in the device's handle for later batch
+    calls that leave the tiling to the library, when whole batch calls get
+    faster with them.  Returns {"entries": [dicts], "kept": bool,
+    "ms_default": x, "ms_tuned": y}."""
+    import torch
+    p = _params(params, kw)
+    frames = list(frames)
+    cframes = (B.FmsFrame * len(frames))()
+    keep = []
+    dev = d0 = None
+    for i, fr in enumerate(frames):
+        emb, h, w, d, ps, cs = _frame_args(fr["emb"], layout)
+        if d0 is None:
+            d0, dev = d, emb.device
+        elif d != d0 or emb.device != dev:
+            raise ValueError("every frame of a batch needs the same D and device")
+        m, mptr = _mask_arg(fr.get("mask"), h, w, dev)
+        keep += [emb, m]
+        cf = cframes[i]
+        cf.emb = emb.data_ptr()
+        cf.pixel_stride, cf.channel_stride = ps, cs
+        cf.mask = mptr if mptr else None
+        cf.height, cf.width = h, w
+        cf.bandwidth = float(fr["bandwidth"])
+        cf.n_state_in = 0
+        cf.labels = None
+    entries = (B.FmsTuneEntry * 16)()
+    count = ctypes.c_int32(0)
+    report = B.FmsTuneReport()
+    lib = library()
+    hdl = _handle(dev.index if dev.index is not None else torch.cuda.current_device())
+    cp = p.to_c()
+    st = lib.fms_autotune_batch(hdl, _stream_ptr(dev), len(frames), cframes, d0, ctypes.byref(cp), entries, 16,
+                                ctypes.byref(count), ctypes.byref(report))
+    if st != B.FMS_OK:
+        raise FmsError(st, "fms_autotune_batch")
     return {"entries": [entries[i].as_dict() for i in range(count.value)], "kept": bool(report.kept),
             "ms_default": float(report.ms_default), "ms_tuned": float(report.ms_tuned)}
 

@@ -19,7 +19,8 @@ FMS_PREC_BF16_REFINE = 1
 
 # Every entry point declared in include/fms.h.
 EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",
-           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_autotune", "fms_clear_tuning",
+           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_autotune", "fms_autotune_batch",
+           "fms_clear_tuning",
            "fms_seed_order", "fms_status_string")
 
 
@@ -153,6 +154,10 @@ def load(path: str = LIB_PATH):
     lib.fms_autotune.argtypes = [vp, vp, ctypes.POINTER(FmsFrame), i32, ctypes.POINTER(FmsParams),
                                  ctypes.POINTER(FmsTuneEntry), i32, ctypes.POINTER(i32), ctypes.POINTER(FmsTuneReport)]
     lib.fms_autotune.restype = ctypes.c_int
+    lib.fms_autotune_batch.argtypes = [vp, vp, i32, ctypes.POINTER(FmsFrame), i32, ctypes.POINTER(FmsParams),
+                                       ctypes.POINTER(FmsTuneEntry), i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(FmsTuneReport)]
+    lib.fms_autotune_batch.restype = ctypes.c_int
     lib.fms_clear_tuning.argtypes = [vp]
     lib.fms_clear_tuning.restype = ctypes.c_int
     lib.fms_seed_order.argtypes = [vp, vp, i32, u64, vp]

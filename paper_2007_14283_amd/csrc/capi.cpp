@@ -163,6 +163,7 @@ constexpr int kHugeGroupMin = 2048;
 // class, pixel-count bucket and active-seed count.
 struct TunedTiling {
   bool bf16;
+  bool batch;  // tuned on launches over several frames (fms_autotune_batch)
   int dp;
   int nb;
   int m;
@@ -364,7 +365,7 @@ const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
     const TunedTiling* best = nullptr;
     double bd = 0.0;
     for (const TunedTiling& t : *c.tuned) {
-      if (t.bf16 != bf16 || t.dp != c.dp || t.nb != c.nb) continue;
+      if (t.bf16 != bf16 || t.batch != (c.F > 1) || t.dp != c.dp || t.nb != c.nb) continue;
       const double d = std::fabs(std::log(double(std::max(bound, 1)) / double(t.m)));
       if (!best || d < bd) {
         best = &t;
@@ -1106,10 +1107,9 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
   c.graphs = p->graphs != 0 && p->timing == 0;
   set_tiling(c, p);
-  // The tuned table holds single-frame launches; a batch launch spreads over
-  // its frames and keeps the defaults.
-  if (n_frames == 1 && p->tile_seeds == 0 && p->tile_items == 0 && p->tile_chunks == 0 && p->tile_waves == 0 &&
-      !h->tuned.empty())
+  // The tuned table (single-frame entries for one frame, batch entries for
+  // several) applies when the call leaves the tiling to the library.
+  if (p->tile_seeds == 0 && p->tile_items == 0 && p->tile_chunks == 0 && p->tile_waves == 0 && !h->tuned.empty())
     c.tuned = &h->tuned;
   return setup_call(h, c, frames, p);
 }
@@ -1332,34 +1332,45 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   return FMS_OK;
 }
 
-fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
-                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries, fms_tune_report* report) {
-  if (!h || !frame || !p || capacity < 0 || (capacity > 0 && !entries)) return FMS_ERR_INVALID_ARG;
+// The tuner of fms_autotune (one frame) and fms_autotune_batch (several
+// frames, every launch spanning all of them, as in fms_cluster_batch).
+fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames, int32_t dim,
+                           const fms_params* p, fms_tune_entry* entries, int32_t capacity, int32_t* n_entries,
+                           fms_tune_report* report) {
+  if (!h || n_frames < 1 || !frames || !p || capacity < 0 || (capacity > 0 && !entries)) return FMS_ERR_INVALID_ARG;
   DeviceGuard guard(h->device);
   fms_params q = *p;
   q.tile_seeds = q.tile_items = q.tile_chunks = q.tile_waves = 0;
   q.timing = 0;
-  fms_frame fr = *frame;
-  fr.labels = nullptr;
-  fr.n_state_in = 0;
+  q.graphs = 0;
+  const bool batch = n_frames > 1;
+  std::vector<fms_frame> frs(frames, frames + n_frames);
+  for (fms_frame& fr : frs) {
+    fr.labels = nullptr;
+    fr.n_state_in = 0;
+  }
   Call c;
-  FMS_TRY(begin_call(h, stream, 1, &fr, dim, &q, c));
+  FMS_TRY(begin_call(h, stream, n_frames, frs.data(), dim, &q, c));
   c.tuned = nullptr;
-  const int n = c.fr[0].g.n;
+  const int n = c.b.max_n;
   FMS_TRY(read_meta(h, c));
-  if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  for (int f = 0; f < n_frames; ++f)
+    if (h->hm(f)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   if (n == 0) return FMS_ERR_INVALID_ARG;
+  // Seed counts per frame (a frame takes at most its foreground count); a
+  // batch stops at 2,048 (its steps at 8,192 seeds per frame take seconds in
+  // FP32, and larger launches take the nearest entry).
   std::vector<int> ms;
   for (int m : {128, 512, 2048, 8192})
-    if (m <= n) ms.push_back(m);
+    if (m <= n && (!batch || m <= 2048)) ms.push_back(m);
   if (ms.empty()) ms.push_back(n);
   const int mmax = ms.back();
-  FMS_TRY(ensure_centres(h, c, mmax));
+  auto m_of = [&](int f, int m) { return std::min(m, c.fr[f].g.n); };
+  if (!batch) FMS_TRY(ensure_centres(h, c, mmax));
   // Candidates of each form: every compiled (group, items, waves) shape.
   std::vector<bool> forms{c.bf16};
   if (c.bf16) forms.push_back(false);
   std::vector<std::vector<fms::Tiling>> cand(forms.size());
-  size_t prows = 0;
   for (size_t fi = 0; fi < forms.size(); ++fi) {
     for (int gs : {16, 32, 64, 128})
       for (int items : {256, 512, 1024})
@@ -1367,27 +1378,46 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
           const fms::Tiling t = fms::make_tiling(forms[fi], c.dp, gs, items, 0, wv);
           if (t.group_seeds != gs || t.waves != wv) continue;  // rounded to another shape
           cand[fi].push_back(t);
-          prows = std::max(prows, fms::shift_partial_rows(t, mmax));
         }
-    prows = std::max(prows, size_t(partial_rows(c, mmax)));
   }
+  // Chunk partials: each frame's region holds the largest any candidate
+  // (or the defaults) needs at the frame's most centres.
+  size_t prows = 0;
+  for (int f = 0; f < n_frames; ++f) {
+    FrameHost& fh = c.fr[f];
+    const int cap_f = batch ? m_of(f, mmax) : mmax;
+    size_t r = size_t(partial_rows(c, cap_f));
+    for (const auto& cf : cand)
+      for (const fms::Tiling& t : cf) r = std::max(r, fms::shift_partial_rows(t, cap_f));
+    fh.g.part0 = int64_t(prows);
+    prows += r;
+  }
+  if (batch) FMS_TRY(upload_geo(h, c));
   HIP_TRY(h->pcount.ensure(prows * sizeof(int)));
   HIP_TRY(h->partial.ensure(prows * size_t(c.dp) * sizeof(float)));
   HIP_TRY(h->ensure_events(2));
   // The identity list of the timed centres: k_iota writes rt.nact entries,
-  // so the count goes to the device first.
-  c.fr[0].rt = fms::RoundTab{};
-  c.fr[0].rt.nact = mmax;
+  // so the counts go to the device first.
+  for (int f = 0; f < n_frames; ++f) {
+    c.fr[f].rt = fms::RoundTab{};
+    c.fr[f].rt.nact = batch ? m_of(f, mmax) : mmax;
+  }
   FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), mmax));
   int* ident = h->ident.as<int>();
   float* y = h->y.as<float>();
-  // One warm-up, then the mean of kReps (fused step, reduction) pairs.
-  constexpr int kReps = 6;
+  // One warm-up, then the mean of kReps (fused step, reduction) pairs (two
+  // for a batch, whose launches are long).
+  const int kReps = batch ? 2 : 6;
   auto time_one = [&](const fms::Tiling& t, bool bf16, int m, float* us) -> fms_status {
     const void* xrm = bf16 ? h->x16.p : h->x32.p;
     const void* xt = bf16 ? h->x16t.p : h->x32t.p;
-    HIP_TRY(fms::launch_init_seeds(c.st, ident, m, n, h->x32.as<float>(), c.dp, y, h->meta.as<int>()));
+    for (int f = 0; f < n_frames; ++f) {
+      const int64_t r0 = c.fr[f].g.row0;
+      HIP_TRY(fms::launch_init_seeds(c.st, ident + r0, batch ? m_of(f, m) : m, c.fr[f].g.n,
+                                     h->x32.as<float>() + r0 * c.dp, c.dp, y + r0 * c.dp,
+                                     h->meta.as<int>() + int64_t(f) * META_COUNT));
+    }
     const fms::IterCtl ctl{-1, -1, 1.0};
     for (int r = 0; r <= kReps; ++r) {
       if (r == 1) HIP_TRY(hipEventRecord(h->events[0], c.st));
@@ -1407,9 +1437,10 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
   for (size_t fi = 0; fi < forms.size(); ++fi) {
     const bool bf16 = forms[fi];
     for (int m : ms) {
-      FrameHost& fh = c.fr[0];
-      fh.rt = fms::RoundTab{};
-      fh.rt.nact = m;
+      for (int f = 0; f < n_frames; ++f) {
+        c.fr[f].rt = fms::RoundTab{};
+        c.fr[f].rt.nact = batch ? m_of(f, m) : m;
+      }
       FMS_TRY(upload_rt(h, c));
       float us_def = 0.f;
       FMS_TRY(time_one(pick_tiling(c, bf16, m), bf16, m, &us_def));
@@ -1425,8 +1456,9 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
         }
       }
       best.bf16 = bf16;
+      best.batch = batch;
       best.dp = c.dp;
-      best.nb = n_bucket(n);
+      best.nb = c.nb;
       best.m = m;
       best.e.precision = bf16 ? FMS_PREC_BF16_REFINE : FMS_PREC_FP32;
       best.e.dim_padded = c.dp;
@@ -1444,7 +1476,8 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
   std::vector<TunedTiling> without, with;
   for (const TunedTiling& t : h->tuned) {
     bool same = false;
-    for (const TunedTiling& u : found) same = same || (t.bf16 == u.bf16 && t.dp == u.dp && t.nb == u.nb);
+    for (const TunedTiling& u : found)
+      same = same || (t.bf16 == u.bf16 && t.batch == u.batch && t.dp == u.dp && t.nb == u.nb);
     if (!same) without.push_back(t);
   }
   with = without;
@@ -1457,7 +1490,7 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
   auto call = [&](const std::vector<TunedTiling>& table) -> fms_status {
     h->tuned = table;
     Call cc;
-    FMS_TRY(begin_call(h, stream, 1, &fr, dim, &q, cc));
+    FMS_TRY(begin_call(h, stream, n_frames, frs.data(), dim, &q, cc));
     ModeOutputs none{nullptr, nullptr, 0, {}, 0};
     return cluster_frames(h, cc, &q, none);
   };
@@ -1485,6 +1518,18 @@ fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int3
   if (capacity < cnt) return FMS_ERR_CAPACITY;
   for (int i = 0; i < cnt; ++i) entries[i] = found[size_t(i)].e;
   return FMS_OK;
+}
+
+fms_status fms_autotune(fms_handle h, void* stream, const fms_frame* frame, int32_t dim, const fms_params* p,
+                        fms_tune_entry* entries, int32_t capacity, int32_t* n_entries, fms_tune_report* report) {
+  return autotune_frames(h, stream, 1, frame, dim, p, entries, capacity, n_entries, report);
+}
+
+fms_status fms_autotune_batch(fms_handle h, void* stream, int32_t n_frames, const fms_frame* frames, int32_t dim,
+                              const fms_params* p, fms_tune_entry* entries, int32_t capacity, int32_t* n_entries,
+                              fms_tune_report* report) {
+  if (n_frames < 2) return FMS_ERR_INVALID_ARG;
+  return autotune_frames(h, stream, n_frames, frames, dim, p, entries, capacity, n_entries, report);
 }
 
 fms_status fms_clear_tuning(fms_handle h) {

@@ -1,9 +1,12 @@
-"""GPU tests of the fused-step autotuner (fms_autotune / fms_clear_tuning): the
-table it reports is well formed, a tuned handle still matches the FP64 oracle
+"""GPU tests of the fused-step autotuner (fms_autotune, fms_autotune_batch,
+fms_clear_tuning).  Single frames: the table it reports is well formed, a
+tuned handle still matches the FP64 oracle
 (FP32 modes within 1e-5, labels exact outside the exempt sets), a call after
 tuning equals, bit for bit, the call that fixes the chosen decomposition
 explicitly when the entries were kept and the default call when they were
-not, and clearing the table restores the default path bit for bit."""
+not, and clearing the table restores the default path bit for bit.  Batches:
+the table is well formed, a tuned batch still matches the oracle frame by
+frame, and batch entries leave single-frame calls bit-identical."""
 import dataclasses
 
 import numpy as np
@@ -113,3 +116,61 @@ def test_autotune_rejects_empty_mask(F):
     emb, mask = _dev(f)
     with pytest.raises(F.FmsError):
         F.autotune(emb, torch.zeros_like(mask), f.bandwidth)
+
+
+# fms_autotune_batch: launches over all frames of a batch (three MID frames
+# of different seeds and TINY).
+def _batch():
+    import torch
+    specs = [synth.MID.with_seed(s) for s in (0, 1, 2)] + [TINY]
+    frames = [synth.make_frame(sp) for sp in specs]
+    inp = [{"emb": torch.from_numpy(f.emb).cuda(), "mask": torch.from_numpy(f.mask).cuda(),
+            "bandwidth": f.bandwidth} for f in frames]
+    return frames, inp
+
+
+def test_autotune_batch_table_and_oracle(F):
+    frames, inp = _batch()
+    n_max = max(f.n_fg for f in frames)
+    _say("autotune batch", [f.n_fg for f in frames])
+    res = F.autotune_batch(inp, precision=F.FP32)
+    print(res)
+    ent = res["entries"]
+    assert res["ms_default"] > 0 and res["ms_tuned"] > 0
+    assert res["kept"] == (res["ms_tuned"] < res["ms_default"])
+    assert {e["precision"] for e in ent} == {0}
+    assert sorted({e["seeds"] for e in ent}) == [m for m in (128, 512, 2048) if m <= n_max]
+    for e in ent:
+        assert e["dim_padded"] == 32 and e["n_fg"] == n_max
+        assert e["tile_items"] in (256, 512, 1024) and e["tile_waves"] in (4, 8, 16)
+        assert 0 < e["us_per_step"] <= e["us_default"] * 1.5
+    out = F.cluster_batch(inp, precision=F.FP32)
+    F.clear_tuning()
+    for f, (modes, labels, st) in zip(frames, out):
+        o = C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth))
+        mm = parity.match_modes(modes.cpu().numpy(), o.modes)
+        lc = parity.compare_labels(labels.cpu().numpy(), o, mm, 1.0 - f.bandwidth)
+        assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0 and mm.max_error <= FP32_TOL
+        assert lc.mismatched == 0
+        for k in ("rounds", "seeds_used", "iterations_total"):
+            assert st[k] == o.stats[k], k
+
+
+def test_batch_entries_leave_single_frame_calls_alone(F):
+    frames, inp = _batch()
+    f = frames[0]
+    emb, mask = _dev(f)
+    _say("batch entries vs single frame")
+    F.clear_tuning()
+    m0, l0, _ = F.cluster(emb, mask, f.bandwidth, precision=F.BF16_REFINE)
+    F.autotune_batch(inp, precision=F.BF16_REFINE)
+    m1, l1, _ = F.cluster(emb, mask, f.bandwidth, precision=F.BF16_REFINE)
+    F.clear_tuning()
+    assert np.array_equal(m0.cpu().numpy(), m1.cpu().numpy())
+    assert np.array_equal(l0.cpu().numpy(), l1.cpu().numpy())
+
+
+def test_autotune_batch_needs_two_frames(F):
+    frames, inp = _batch()
+    with pytest.raises(F.FmsError):
+        F.autotune_batch(inp[:1])
