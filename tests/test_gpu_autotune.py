@@ -174,3 +174,15 @@ def test_autotune_batch_needs_two_frames(F):
     frames, inp = _batch()
     with pytest.raises(F.FmsError):
         F.autotune_batch(inp[:1])
+
+
+def test_autotune_batch_with_an_empty_frame(F):
+    import torch
+    frames, inp = _batch()
+    inp = [inp[0], dict(inp[3], mask=torch.zeros_like(inp[3]["mask"]))]
+    _say("autotune batch with an empty frame")
+    res = F.autotune_batch(inp, precision=F.FP32)
+    assert res["entries"] and res["ms_default"] > 0
+    out = F.cluster_batch(inp, precision=F.FP32)
+    F.clear_tuning()
+    assert len(out[1][0]) == 0 and bool((out[1][1] == -1).all())
