@@ -39,6 +39,9 @@ def _args():
                     help="time the 512x512 frame in both forms only (no other sections; for kernel traces)")
     ap.add_argument("--only-batch", action="store_true",
                     help="time the uneven batched workload only (for kernel traces)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="with --profile-run: cluster the uneven batch (--batch-frames, BF16+refine) --steps "
+                         "times instead of the single frame")
     ap.add_argument("--profile-run", action="store_true",
                     help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
                          "reference), then --steps frames of each form; prints a short summary only")
@@ -56,6 +59,16 @@ def _profile_run(a):
     torch.cuda.synchronize()
     dst.copy_(ref)  # reads and writes exactly 256 MiB
     torch.cuda.synchronize()
+    if a.profile_batch:
+        frames = [synth.make_frame(sp) for sp in synth.batch_specs(a.batch_frames)]
+        inp = [{"emb": torch.from_numpy(f.emb).cuda(), "mask": torch.from_numpy(f.mask).cuda(),
+                "bandwidth": f.bandwidth} for f in frames]
+        for _ in range(a.steps):
+            res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
+        torch.cuda.synchronize()
+        print(f"profile run: copy 256 MiB, {a.steps} calls of the {len(frames)}-frame batch, "
+              f"{sum(len(r[0]) for r in res)} modes", flush=True)
+        return
     frame = synth.make_frame(synth.PLAIN512)
     emb = torch.from_numpy(frame.emb).cuda()
     mask = torch.from_numpy(frame.mask).cuda()
