@@ -384,7 +384,7 @@ def main():
         _profile_run(a)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process here; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
