@@ -79,3 +79,31 @@ def _fresh_load(B, path):
         return B.load(path)
     finally:
         B._lib = saved
+
+
+def test_null_handle_and_bad_counts_are_rejected_on_the_host():
+    # Argument checks run before any HIP call, so they need no GPU.
+    import paper_2007_14283_amd as F
+    from paper_2007_14283_amd import _binding as B
+    lib = F.library()
+    p = B.FmsParams()
+    lib.fms_default_params(ctypes.byref(p))
+    nm = ctypes.c_int32(0)
+    st = B.FmsStats()
+    bad = B.FMS_ERR_INVALID_ARG
+    assert lib.fms_destroy(None) == B.FMS_OK
+    assert lib.fms_clear_tuning(None) == bad
+    assert lib.fms_cluster(None, None, None, 32, 1, None, 4, 4, 32, ctypes.byref(p), None, None, 0,
+                           ctypes.byref(nm), None, ctypes.byref(st)) == bad
+    frames = (B.FmsFrame * 2)()
+    offs = (ctypes.c_int32 * 3)()
+    stats = (B.FmsStats * 2)()
+    assert lib.fms_cluster_batch(None, None, 2, frames, 32, ctypes.byref(p), None, None, 0, offs, stats) == bad
+    assert lib.fms_seed_order(None, None, 10, 0, None) == bad
+    n_ent = ctypes.c_int32(0)
+    rep = B.FmsTuneReport()
+    assert lib.fms_autotune(None, None, frames, 32, ctypes.byref(p), None, 0, ctypes.byref(n_ent),
+                            ctypes.byref(rep)) == bad
+    # A batch tuner needs at least two frames (checked before the handle).
+    assert lib.fms_autotune_batch(None, None, 1, frames, 32, ctypes.byref(p), None, 0, ctypes.byref(n_ent),
+                                  ctypes.byref(rep)) == bad
