@@ -39,6 +39,8 @@ def _args():
                     help="time the 512x512 frame in both forms only (no other sections; for kernel traces)")
     ap.add_argument("--only-batch", action="store_true",
                     help="time the uneven batched workload only (for kernel traces)")
+    ap.add_argument("--only-1024", action="store_true",
+                    help="time the 1024x1024 precision workload only (for kernel traces)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="with --profile-run: cluster the uneven batch (--batch-frames, BF16+refine) --steps "
                          "times instead of the single frame")
@@ -394,6 +396,9 @@ def main():
 
     if a.only_batch:
         print(json.dumps({"batched": _batched(fms, torch, a)}), flush=True)
+        return
+    if a.only_1024:
+        print(json.dumps({"precision_1024": _precision1024(fms, torch, reps=a.steps)}), flush=True)
         return
 
     spec = synth.PLAIN512
