@@ -264,7 +264,8 @@ def _differentiation(fms, torch, frame, seeds_used, reps=5):
 def _precision1024(fms, torch, reps=10):
     """The precision workload: one 1024x1024 frame, 300 cells, D=32, in both
     forms, with the mode error of each against the stored FP64 oracle result
-    (tests/golden/precision1024_oracle.npz, written from oracle/ alone)."""
+    (tests/golden/precision1024_oracle.npz, written from oracle/ alone), then
+    both forms again with the autotuner's table for this frame."""
     import numpy as np
 
     import synth
@@ -290,6 +291,27 @@ def _precision1024(fms, torch, reps=10):
                      "max_mode_err": mm.max_error, "oracle_modes_within_tol": int(np.sum(mm.errors <= tol)),
                      "tol": tol, "unmatched_gpu": mm.unmatched_gpu, "unmatched_oracle": mm.unmatched_oracle,
                      "updates_per_s": (st["seed_pixel_updates"] + st["refine_updates"]) / dt}
+    # The same frame with the decomposition table fms_autotune picks for it.
+    for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5)):
+        t0 = time.perf_counter()
+        res = fms.autotune(e, m, f.bandwidth, precision=prec)
+        tune_s = time.perf_counter() - t0
+        fms.cluster(e, m, f.bandwidth, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            modes, _, _ = fms.cluster(e, m, f.bandwidth, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        fms.clear_tuning()
+        mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
+        out[name + "_autotuned"] = {
+            "frames_per_s": 1.0 / dt, "tune_s": tune_s, "kept": res["kept"],
+            "call_ms_default": res["ms_default"], "call_ms_tuned": res["ms_tuned"],
+            "oracle_modes_within_tol": int(np.sum(mm.errors <= tol)), "unmatched_oracle": mm.unmatched_oracle,
+            "entries": [{k: q[k] for k in ("precision", "seeds", "tile_seeds", "tile_items", "tile_waves")} |
+                        {"us_tuned": round(q["us_per_step"], 2), "us_default": round(q["us_default"], 2)}
+                        for q in res["entries"]]}
     return out
 
 

@@ -357,6 +357,18 @@ int n_bucket(int64_t n) {
   return b;
 }
 
+// Default tiling of a launch with at most `bound` centres per frame.
+const fms::Tiling& default_tiling(const Call& c, bool bf16, int bound) {
+  if (bf16 && bound >= kHugeGroupMin) return c.tile_huge;
+  if (bound >= kBigGroupMin) return bf16 ? c.tile_big : c.tile_fp32_big;
+  return bf16 ? c.tile : c.tile_fp32;
+}
+
+// Tiling of a window-count launch.  The autotuner times shift launches only,
+// so count launches keep the defaults (their integer counts do not depend on
+// the decomposition).
+const fms::Tiling& count_tiling(const Call& c, bool bf16, int bound) { return default_tiling(c, bf16, bound); }
+
 // Tiling of a fused-step launch with at most `bound` centres per frame: the
 // tuned entry of the form, D class and bucket whose seed count is nearest in
 // ratio, else the defaults.
@@ -374,9 +386,7 @@ const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
     }
     if (best) return best->t;
   }
-  if (bf16 && bound >= kHugeGroupMin) return c.tile_huge;
-  if (bound >= kBigGroupMin) return bf16 ? c.tile_big : c.tile_fp32_big;
-  return bf16 ? c.tile : c.tile_fp32;
+  return default_tiling(c, bf16, bound);
 }
 
 void set_tiling(Call& c, const fms_params* p) {
@@ -847,7 +857,7 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NCAND, false, nc));
   int* counts = h->bits.as<int>();
   uint32_t* bits = reinterpret_cast<uint32_t*>(h->bits.as<uint8_t>() + nb_n);
-  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, nc), h->x32.p, h->y.as<float>(),
+  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, nc), h->x32.p, h->y.as<float>(),
                             h->cand.as<int>(), nc, h->pcount.as<int>(), counts, META_NCAND));
   HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nc,
                               h->modes.as<float>(), k, bits, META_NCAND, META_NCAND));
@@ -957,7 +967,7 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
       // candidates accepted before.
       // Counts at every slot of the round (the list is the identity); the
       // ranking keeps the converged ones.
-      HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, pick_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
+      HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, count_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
                                 h->y.as<float>(), nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
       // The candidate list buffer is free in a round: it holds each
       // candidate's first word with an earlier conflict for the greedy pass.
@@ -1035,7 +1045,7 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     HIP_TRY(fms::launch_copy_rows(c.st, c.b, mrows, h->y.as<float>(), c.dp, kmax));
     HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NSEL, true, 0));
     HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
-    HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, kmax), h->x32.p, h->y.as<float>(),
+    HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, kmax), h->x32.p, h->y.as<float>(),
                               h->cand.as<int>(), kmax, h->pcount.as<int>(), h->counts.as<int>(), META_NCAND));
     HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), kmax, h->cand.as<int>(), kmax,
                                 nullptr, 0, h->bits.as<uint32_t>(), META_NCAND, META_NCAND));
@@ -1321,7 +1331,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.rt.nact = m;
   FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, pick_tiling(c, false, m), h->x32.p, h->y.as<float>(),
+  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, m), h->x32.p, h->y.as<float>(),
                             h->ident.as<int>(), m, h->pcount.as<int>(), h->counts.as<int>(), -1));
   HIP_TRY(fms::launch_lockstep_out(c.st, m, c.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));

@@ -412,10 +412,15 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
 // whole 32-pixel blocks, about target_items (group, chunk) items in total.
 // The kernels derive it from the active count held on the device; the host
 // uses the same function with upper bounds to size the partial buffer.
+// The grid holds target_items work groups, so up to a quarter of that many
+// groups the chunk count rounds down: every item then runs in the grid's one
+// pass, where rounding up would leave a few items for a second pass that
+// the rest of the grid waits for.  Beyond, rounding down would idle up to
+// half the grid, and the count rounds up.
 __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int n_blocks) {
   ChunkPlan cp;
   const int groups = n_act > 0 ? (n_act + t.group_seeds - 1) / t.group_seeds : 1;
-  int want = (t.target_items + groups - 1) / groups;
+  int want = 4 * groups <= t.target_items ? t.target_items / groups : (t.target_items + groups - 1) / groups;
   int lim = n_blocks < t.max_chunks ? n_blocks : t.max_chunks;
   if (lim < 1) lim = 1;
   int nc = want < 1 ? 1 : (want > lim ? lim : want);
@@ -1729,9 +1734,14 @@ size_t shift_partial_rows(const Tiling& t, int cap) {
   return (size_t)std::max<int64_t>(a, 1);
 }
 
+// Work groups of a fused-step launch for at most `cap` active seeds: enough
+// for the items of any active count up to cap (groups * chunks never exceeds
+// groups(cap) * min(n_blocks, max_chunks)), at most target_items; beyond
+// that the work groups loop over the items.
 static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
-  const ChunkPlan cp = plan_chunks(cap, t, n_blocks);
-  int64_t items = (int64_t)cp.groups * cp.n_chunks;
+  const int groups = cap > 0 ? (cap + t.group_seeds - 1) / t.group_seeds : 1;
+  const int lim = std::max(1, std::min(n_blocks, t.max_chunks));
+  int64_t items = (int64_t)groups * lim;
   if (items > t.target_items) items = t.target_items;
   unsigned grid = (unsigned)((items + 7) / 8 * 8);
   return grid < 8 ? 8 : grid;
