@@ -81,7 +81,8 @@ typedef struct {
   int32_t refine_iters; /* FP32 steps that start the refinement of the BF16 form; 3. */
   int32_t timing;     /* nonzero: time every fused-step launch with HIP events on
                          `stream` and report the totals in fms_stats. */
-  /* Work decomposition of the fused step (0 = the library's choice): seeds per
+  /* Work decomposition of the fused step (0 = the library's choice: 8 waves
+   * per work group for single frames, 4 for batches): seeds per
    * group (16, 32, 64 or 128; rounded down to a size compiled for the
    * precision and D), target number of (seed group, pixel chunk) items per
    * step, cap on pixel chunks, and waves per work group (4, 8 or 16, other

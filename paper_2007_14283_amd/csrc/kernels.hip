@@ -1710,10 +1710,8 @@ Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_c
   Tiling t;
   // Defaults from sweeps on the 512x512, D = 32 frame and the 64-frame batch:
   // 32-seed groups (larger ones for many centres, chosen by the caller), four
-  // waves per group and about 512 items, <= 256 chunks.  Eight waves and 256
-  // items make a single-frame step over 512 centres about 15% faster, but
-  // the batch (64 frames per launch) about 5% slower and the single frame no
-  // faster; fms_autotune picks them where they pay.
+  // waves per group (the caller asks for eight on single frames) and
+  // kWaveBudget / waves items, <= 256 chunks.
   int def = dp <= 64 ? 32 : 16;
   int g = want_seeds > 0 ? want_seeds : def;
   int gs = min_group(bf16, dp);
