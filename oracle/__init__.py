@@ -21,8 +21,8 @@ unroll      T unrolled steps from given seeds and the exact (almost everywhere)
             gradient of the result with respect to the raw embeddings.
 
 Parity status: every function is pinned by a CPU test (see the ``tests``
-folder) except the tie-break order of the mode merge, the gamma/max_iter stop
-and the coverage rule, which the paper does not define; both sides implement
-the same reading of them ("parity unpinned" for those three choices).
+folder).  Three choices are readings the paper leaves open (the tie-break order
+of the mode merge, the strict gamma stop and the coverage rule); each is pinned
+by hand-built cases whose outcome the reading fixes exactly.
 """
 from . import seed_order, osop, meanshift, cluster, unroll  # noqa: F401

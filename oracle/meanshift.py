@@ -24,6 +24,7 @@ Definitions followed, with the readings used where the paper is loose:
 """
 from __future__ import annotations
 
+import math
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -222,7 +223,7 @@ def classic(x: np.ndarray, thr: float, tol: float, max_iter: int):
                 if s >= thr:
                     for d in range(dim):
                         acc[d] += p[d]
-            norm = sum(v * v for v in acc) ** 0.5
+            norm = math.sqrt(sum(v * v for v in acc))
             yn = [v / norm for v in acc]
             step = 1.0 - sum(a * b for a, b in zip(y, yn))
             y = yn

@@ -86,6 +86,16 @@ def test_eq19_inverts_eq14(p, i, r):
     assert osop.p_all_seeded(math.floor(nm), i, r) < p <= osop.p_all_seeded(math.ceil(nm), i, r)
 
 
+@pytest.mark.parametrize("p,i,r,want", [(0.99, 10, 1.0, 65.52), (0.99, 20, 0.3, 502.60),
+                                        (0.99, 100, 0.4, 2296.74), (0.99, 300, 0.4, 7722.81),
+                                        (0.95, 8, 0.39, 101.10)])
+def test_eq19_values(p, i, r, want):
+    # Eq. 19 worked out separately (to two decimals) for the circle data of
+    # Sec. 4.1 (I = 10, r = 1), the workloads of this hot path (I = 20, 100,
+    # 300 at 30-40 % foreground) and the Appendix A setting (P = 0.95, I = 8).
+    assert osop.n_min(p, i, r) == pytest.approx(want, abs=1e-2)
+
+
 def test_eq15_chain_equals_eq19_at_half():
     # Eq. 15-18 solve (1 - (1 - 1/(2I))^N)^I = P for N; solve it by bisection
     # and compare with Eq. 19 at r = 1/2.
@@ -160,6 +170,9 @@ def _margin_ok(x, ends, thr, margin=1e-9):
 
 @pytest.mark.parametrize("dim", [2, 3, 16])
 def test_iterate_matches_alg1_brute_force(dim):
+    # Random unit rows: the two sides sum the window members in different
+    # orders, so their centres may differ in the last bits (the bit-exact
+    # comparison is test_iterate_matches_alg1_bit_exact).
     rng = np.random.Generator(np.random.PCG64(dim))
     thr, tol = 0.9, 1e-4
     for _ in range(20):
@@ -175,6 +188,62 @@ def test_iterate_matches_alg1_brute_force(dim):
     assert it["converged"].all()
     np.testing.assert_allclose(it["endpoints"], ends, rtol=0, atol=1e-12)
     np.testing.assert_array_equal(it["iters"], its)
+
+
+def _dyadic_clusters(seed=0, k=3, per=14, dim=16):
+    # Unit rows whose entries are all +-1/4 (dim = 16): a base sign pattern per
+    # cluster with 0-4 signs flipped.  Any sum of such rows, and the sum of the
+    # squares of its entries, is exact in FP64 whatever the order, so Alg. 1's
+    # Python loops and the matrix products of the parallel iteration form the
+    # same window sums bit for bit, and a correctly rounded square root and
+    # division then give the same centres.
+    rng = np.random.default_rng(seed)
+    base = rng.choice([-0.25, 0.25], size=(k, dim))
+    rows = []
+    for b in base:
+        for _ in range(per):
+            v = b.copy()
+            v[rng.choice(dim, rng.integers(0, 5), replace=False)] *= -1
+            rows.append(v)
+    return np.array(rows)
+
+
+DYADIC_THR, DYADIC_TOL = 0.6, 1e-4
+
+
+def test_iterate_matches_alg1_bit_exact():
+    # Every vector a seed (Alg. 1) against the parallel iteration of Alg. 2 on
+    # the same starts: identical endpoints and step counts, bit for bit.
+    x = _dyadic_clusters()
+    ends, its = ms.classic(x, DYADIC_THR, DYADIC_TOL, 100)
+    assert its.max() >= 5 and len(set(its.tolist())) >= 4  # non-trivial trajectories
+    it = ms.iterate(x, np.arange(len(x)), DYADIC_THR, DYADIC_TOL, 1.0, 100)
+    assert it["converged"].all()
+    np.testing.assert_array_equal(it["endpoints"], ends)
+    np.testing.assert_array_equal(it["iters"], its)
+
+
+def test_gamma_stop_is_strict():
+    # Sec. 3.2.3 stops a round once MORE than gamma of its seeds have
+    # converged.  Pick seeds so that exactly gamma * m of them converge first
+    # (Alg. 1 gives each start's step count): the round must go on until the
+    # slow one converges too, with Alg. 1's endpoints; one step earlier would
+    # discard it.
+    x = _dyadic_clusters()
+    ends, its = ms.classic(x, DYADIC_THR, DYADIC_TOL, 100)
+    fast = np.flatnonzero(its == 3)[:9]
+    slow = np.flatnonzero(its >= 6)[:1]
+    assert len(fast) == 9 and len(slow) == 1
+    for seeds, gamma in ((np.r_[fast[:1], slow], 0.5), (np.r_[fast, slow], 0.9)):
+        it = ms.iterate(x, seeds, DYADIC_THR, DYADIC_TOL, gamma, 100)
+        assert it["converged"].all(), (gamma, it["iters"])
+        assert it["steps"] == its[slow[0]]
+        np.testing.assert_array_equal(it["iters"], its[seeds])
+        np.testing.assert_array_equal(it["endpoints"], ends[seeds])
+    # Just past the boundary the stop does come: 9 of 10 converged with
+    # gamma < 0.9 ends the round after the fast seeds' last step.
+    it = ms.iterate(x, np.r_[fast, slow], DYADIC_THR, DYADIC_TOL, 0.89, 100)
+    assert it["steps"] == 3 and it["converged"].sum() == 9
 
 
 def test_window_counts_brute_force():
@@ -193,6 +262,44 @@ def test_flat_kernel_boundary_is_inclusive():
     yn, delta, members = ms.shift(x[:1], x, 0.5)
     assert members[0] == 2
     np.testing.assert_allclose(yn[0], _unit(x[0] + x[1]), atol=1e-15)
+
+
+def test_coverage_boundary_is_inclusive():
+    # A pixel is covered when it lies inside a mode's window, boundary
+    # included (Eq. 11's d <= h).  With the mode (1, 0) the similarity is the
+    # first coordinate exactly: 0.5 = 1 - h is covered, 0.5 - 2^-40 is not.
+    modes = np.array([[1.0, 0.0]])
+    a = 0.5 - 2.0 ** -40
+    x = np.array([[0.5, math.sqrt(0.75)], [a, math.sqrt(1.0 - a * a)], [1.0, 0.0], [0.0, 1.0]])
+    assert ms.covered_by(x, modes, 0.5).tolist() == [True, False, True, False]
+    assert ms.covered_by(x, np.zeros((0, 2)), 0.5).tolist() == [False] * 4
+
+
+def test_later_round_seeds_skip_covered_pixels():
+    # The policy seeds only pixels that are neither used nor within h of a
+    # mode found in an earlier round: every round after the first takes the
+    # first such positions of the seed order.  Coverage is recomputed here
+    # from the modes the earlier rounds accepted, and it must have skipped
+    # positions (it changes the seeds).
+    f = synth.make_frame(synth.TINY)
+    res = C.cluster(f.emb, f.mask, C.Params(bandwidth=f.bandwidth))
+    assert len(res.rounds) >= 2
+    thr = 1.0 - f.bandwidth
+    order = so.seed_order(f.n_fg, 0)
+    used = np.zeros(f.n_fg, bool)
+    covered = np.zeros(f.n_fg, bool)
+    skipped_by_cover = 0
+    for rnd in res.rounds:
+        want = len(rnd.positions)
+        ok = ~used[order] & ~covered[order]
+        expect = np.flatnonzero(ok)[:want]
+        np.testing.assert_array_equal(rnd.positions, expect)
+        skipped_by_cover += int(np.count_nonzero(covered[order[:expect[-1] + 1]] & ~used[order[:expect[-1] + 1]]))
+        used[rnd.seeds] = True
+        for a in rnd.accepted:
+            m = rnd.endpoints[a]
+            covered |= np.einsum("nd,d->n", res.x, m) >= thr
+    assert skipped_by_cover > 0
 
 
 def test_tight_clusters_closed_form():
@@ -360,3 +467,35 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
     for bad in (strict, unnormalised, drops_first_member):
         assert _pins_catch(monkeypatch, bad) >= 1, bad.__name__
+
+
+def _failures(fns):
+    failures = 0
+    for fn in fns:
+        try:
+            fn()
+        except AssertionError:
+            failures += 1
+    return failures
+
+
+def test_planted_coverage_and_stop_mistakes_are_caught(monkeypatch):
+    real_cov, real_it = ms.covered_by, ms.iterate
+    cover_pins = (test_coverage_boundary_is_inclusive, test_later_round_seeds_skip_covered_pixels)
+
+    def cover_strict(x, modes, thr):  # '>' instead of '>='
+        return real_cov(x, modes, np.nextafter(thr, 2.0))
+
+    def cover_nothing(x, modes, thr):  # coverage never applied
+        return np.zeros(len(x), bool)
+
+    for bad in (cover_strict, cover_nothing):
+        monkeypatch.setattr(ms, "covered_by", bad)
+        assert _failures(cover_pins) >= 1, bad.__name__
+    monkeypatch.setattr(ms, "covered_by", real_cov)
+
+    def stop_inclusive(x, seeds, thr, tol, gamma, max_iter, trace=False):  # '>=' instead of '>'
+        return real_it(x, seeds, thr, tol, gamma - 1e-9, max_iter, trace)
+
+    monkeypatch.setattr(ms, "iterate", stop_inclusive)
+    assert _failures((test_gamma_stop_is_strict,)) >= 1

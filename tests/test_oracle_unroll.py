@@ -120,3 +120,68 @@ def test_steps_must_be_positive():
     e, seeds, h, _ = _case()
     with pytest.raises(ValueError):
         U.forward(e, seeds, h, 0)
+
+
+def crop_case(size=64):
+    """The differentiation workload's finite-difference crop: the size x size
+    window (on a grid of size) with the most foreground of the 512x512, D = 32
+    frame; 128 seeds from the seed order, T = 10 steps.  Seeds whose FP64
+    trajectory comes within 1e-5 of a window edge get a zero target (a
+    perturbation could flip one of their memberships)."""
+    import synth
+    from oracle import seed_order as so
+    frame = synth.make_frame(synth.PLAIN512)
+    best = None
+    for y0 in range(0, frame.spec.height - size + 1, size):
+        for x0 in range(0, frame.spec.width - size + 1, size):
+            c = int(frame.mask[y0:y0 + size, x0:x0 + size].sum())
+            if best is None or c > best[0]:
+                best = (c, y0, x0)
+    _, y0, x0 = best
+    emb = frame.emb[y0:y0 + size, x0:x0 + size].reshape(-1, frame.emb.shape[-1])
+    mask = frame.mask[y0:y0 + size, x0:x0 + size].reshape(-1)
+    e = emb[mask != 0].astype(np.float64)
+    h, steps = frame.bandwidth, 10
+    seeds = so.seed_order(len(e), 0)[:128].astype(np.int64)
+    x = e / np.linalg.norm(e, axis=1, keepdims=True)
+    y = x[seeds]
+    marg = np.full(len(seeds), np.inf)
+    for _ in range(steps):
+        s = y @ x.T
+        marg = np.minimum(marg, np.min(np.abs(s - (1.0 - h)), axis=1))
+        v = (s >= 1.0 - h).astype(np.float64) @ x
+        y = v / np.linalg.norm(v, axis=1, keepdims=True)
+    rng = np.random.default_rng(0)
+    targets = rng.normal(size=(len(seeds), e.shape[1]))
+    targets /= np.linalg.norm(targets, axis=1, keepdims=True)
+    targets[marg < 1e-5] = 0.0
+    coords = np.stack([rng.integers(0, len(e), 200), rng.integers(0, e.shape[1], 200)], axis=1)
+    return e, seeds, h, steps, targets, coords
+
+
+def fd_at(e, seeds, h, steps, targets, coords, eps=1e-6):
+    """FP64 central differences of L = sum_j y_T,j . target_j at the given
+    (row, dimension) coordinates of the raw embeddings.  With |L| ~ 10 the
+    rounding of the quotient is about 1e-16 |L| / eps ~ 1e-9; the kept seeds
+    sit at least 1e-5 from every window edge, ten times the perturbation."""
+    out = np.empty(len(coords))
+    for k, (i, d) in enumerate(coords):
+        ep = e.copy()
+        em = e.copy()
+        ep[i, d] += eps
+        em[i, d] -= eps
+        out[k] = (U.loss(ep, seeds, h, steps, targets) - U.loss(em, seeds, h, steps, targets)) / (2 * eps)
+    return out
+
+
+def test_gradient_matches_finite_differences_on_the_crop():
+    # The differentiation workload at its own size (64 x 64 crop of the
+    # 512 x 512, D = 32 frame, 128 seeds, T = 10): the oracle gradient equals
+    # FP64 central differences at 200 sampled coordinates.
+    e, seeds, h, steps, targets, coords = crop_case()
+    assert np.count_nonzero(np.any(targets != 0, axis=1)) >= 100
+    ga = U.grad(e, seeds, h, steps, targets)
+    gf = fd_at(e, seeds, h, steps, targets, coords)
+    got = ga[coords[:, 0], coords[:, 1]]
+    assert np.count_nonzero(np.abs(gf) > 1e-3) >= 20  # many non-trivial entries
+    np.testing.assert_allclose(got, gf, atol=1e-8, rtol=1e-5)
