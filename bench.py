@@ -1,14 +1,17 @@
 """Benchmark: frames/sec and seed x pixel updates/sec of Faster Mean-shift on one
-MI355X, 512 x 512 frame, D = 32, BF16 + FP32-refine form against the FP32 form.
+MI355X, 512 x 512 frame, D = 32, BF16 + FP32-replay form against the FP32 form.
 
 One step = one fms_cluster call on one frame already resident in HBM: compaction
 and normalisation, the seed rounds of the online seed policy (seed selection,
 fused mean-shift iterations, window counts, pruning, coverage), and the labels.
+Every call is bracketed by HIP events on the stream the library works on; the
+figure is the median over the timed calls, after the warm-up calls.
 
-Prints one JSON line.  ``value`` is BF16+FP32-refine frames/sec; the FP32 form,
-update rates, the BF16 mode error against the FP64 oracle, the roofline of the
-dominant kernel (live HIP-event timings from the library) and the oracle's CPU
-rate on the same frame are carried alongside.
+Prints one JSON line.  ``value`` is BF16+FP32-replay frames/sec; the FP32 form
+(``value_fp32``), update rates, both forms' mode error against the FP64 oracle,
+the roofline of the dominant kernel (live HIP-event timings from the library),
+the 128 x 128 workload, and the oracle's CPU rate on the same frames (all
+threads and one thread) are carried alongside.
 """
 from __future__ import annotations
 
@@ -81,22 +84,41 @@ def _profile_run(a):
     print(f"profile run: copy 256 MiB, {a.steps} frames per form, {len(modes)} modes", flush=True)
 
 
-def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
-    """Whole-frame throughput without instrumentation, then the same number of
-    frames again with per-launch kernel timing for the roofline figures."""
+def _time_calls(torch, call, steps, warmup):
+    """Median milliseconds of `steps` calls, each bracketed by HIP events on
+    the current stream (the stream the library enqueues on), after `warmup`
+    untimed calls; also the wall time of the timed loop and the last result."""
     for _ in range(warmup):
-        fms.cluster(emb, mask, h, precision=precision)
+        call()
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    last = None
+    res = []
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record()
+        last = call()
+        e1.record()
+        res.append(last)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    med = 0.5 * (ms[(steps - 1) // 2] + ms[steps // 2])
+    return med, wall, last, res
+
+
+def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
+    """Whole-frame throughput without instrumentation (median of event-timed
+    calls), then the same number of frames again with per-launch kernel
+    timing for the roofline figures."""
     agg = {"step_ms": [0.0, 0.0], "step_updates": [0, 0], "step_launches": [0, 0], "updates": 0,
            "refine_updates": 0}
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(steps):
-        last = fms.cluster(emb, mask, h, precision=precision)
-        agg["updates"] += last[2]["seed_pixel_updates"]
-        agg["refine_updates"] += last[2]["refine_updates"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    med, wall, last, res = _time_calls(torch, lambda: fms.cluster(emb, mask, h, precision=precision), steps, warmup)
+    for r in res:
+        agg["updates"] += r[2]["seed_pixel_updates"]
+        agg["refine_updates"] += r[2]["refine_updates"]
+    agg["wall_s"] = wall
+    dt = med * 1e-3 * steps
     for _ in range(steps):
         st = fms.cluster(emb, mask, h, precision=precision, timing=1)[2]
         for k in range(2):
@@ -160,6 +182,46 @@ def _roofline(agg, dim, n_fg):
             "flops_per_launch": flops / launches}
 
 
+def _accuracy(gpu_modes, gpu_labels, o_modes, fg, o_fg_labels, band, tie_of, tol):
+    """A GPU result against an oracle result: modes found within `tol`
+    (mutual best), lost oracle modes, extra GPU modes, and label mismatches
+    outside the exempt sets (bandwidth band, near ties within the band the
+    largest error of the found modes allows, pixels of lost modes)."""
+    import numpy as np
+
+    from tests import parity
+    mm = parity.match_modes(gpu_modes, o_modes)
+    good = mm.errors <= tol
+    found = set(mm.pairs[good, 1].tolist())
+    lost = [k for k in range(len(o_modes)) if k not in found]
+    max_err = float(mm.errors[good].max()) if good.any() else 0.0
+    width = parity.BAND if tol < 1e-4 else parity.tie_band(max_err)
+    gm = parity.ModeMatch(mm.pairs[good], mm.errors[good], int(len(gpu_modes) - good.sum()), len(lost))
+    lc = parity.compare_labels_fg(gpu_labels, fg, o_fg_labels, band, tie_of(width), gm, lost)
+    return {"modes": int(len(gpu_modes)), "oracle_modes": int(len(o_modes)), "found": len(found),
+            "max_mode_err": max_err, "lost": len(lost), "extra": int(len(gpu_modes) - good.sum()),
+            "label_mismatch": lc.mismatched, "label_exempt_mismatch": lc.mismatched_exempt,
+            "tie_band": width}
+
+
+def _batch_accuracy(frames, res, tol):
+    """Five frames of the batch against their stored oracle results."""
+    import numpy as np
+
+    from tests import parity
+    gold = parity.load_batch_oracle()
+    out = {}
+    for i, o in gold.items():
+        if i >= len(frames):
+            continue
+        fg = np.flatnonzero(frames[i].mask.reshape(-1))
+        out[str(i)] = _accuracy(res[i][0].cpu().numpy(), res[i][1].cpu().numpy(), o["modes"], fg, o["fg_labels"],
+                                o["band"], lambda w, o=o, n=len(fg): o["tie"] | parity.near_tie_mask(
+                                    n, o["near_idx"], o["near_gap"], w), tol)
+        out[str(i)]["side"] = frames[i].spec.height
+    return out
+
+
 def _batched(fms, torch, a):
     """The batched form on the uneven multi-frame workload: every frame of the
     batch clustered by one fms_cluster_batch call, against the same frames
@@ -180,34 +242,26 @@ def _batched(fms, torch, a):
         # so that the caching allocator holds the output tensors of two calls
         # before the timed loop (which keeps one result while making the next).
         res = fms.cluster_batch(inp, precision=prec)
-        res = fms.cluster_batch(inp, precision=prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        upd = 0
-        for _ in range(a.batch_steps):
-            res = fms.cluster_batch(inp, precision=prec)
-            upd += sum(r[2]["seed_pixel_updates"] + r[2]["refine_updates"] for r in res)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        med, wall, res, allres = _time_calls(torch, lambda: fms.cluster_batch(inp, precision=prec), a.batch_steps, 1)
+        upd = sum(r[2]["seed_pixel_updates"] + r[2]["refine_updates"] for rr in allres for r in rr)
+        dt = med * 1e-3 * a.batch_steps
         st = fms.cluster_batch(inp, precision=prec, timing=1)[0][2]
         agg = {k: list(st[k]) for k in ("step_ms", "step_updates", "step_launches")}
-        out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": 1e3 * dt / a.batch_steps,
+        out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": med,
+                     "wall_ms_per_batch": 1e3 * wall / a.batch_steps,
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
-                     "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"])}
+                     "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"]),
+                     "vs_oracle": _batch_accuracy(frames, res, 1e-3 if prec == fms.BF16_REFINE else 1e-5)}
     # Autotuned tiles: fms_autotune_batch on these frames (BF16+refine form);
     # its entries serve the batch calls when whole calls got faster with them.
     t0 = time.perf_counter()
     tune = fms.autotune_batch(inp, precision=fms.BF16_REFINE)
     tune_s = time.perf_counter() - t0
     res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
-    res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.batch_steps):
-        res = fms.cluster_batch(inp, precision=fms.BF16_REFINE)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["bf16_refine_autotuned"] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": 1e3 * dt / a.batch_steps,
+    med, wall, res, _ = _time_calls(torch, lambda: fms.cluster_batch(inp, precision=fms.BF16_REFINE),
+                                    a.batch_steps, 1)
+    dt = med * 1e-3 * a.batch_steps
+    out["bf16_refine_autotuned"] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": med,
                                     "kept": tune["kept"], "tune_s": tune_s, "call_ms_default": tune["ms_default"],
                                     "call_ms_tuned": tune["ms_tuned"], "modes": int(sum(len(r[0]) for r in res)),
                                     "entries": [{k: e[k] for k in ("precision", "seeds", "tile_seeds", "tile_items",
@@ -278,35 +332,27 @@ def _precision1024(fms, torch, reps=10):
     out = {"workload": f"one {spec.height}x{spec.width} frame, {spec.n_cells} cells (radii {spec.r_min}-{spec.r_max}), "
                        f"D={spec.dim}, sigma={spec.sigma}, h={f.bandwidth}, seed {spec.seed}",
            "n_fg": f.n_fg, "oracle_modes": int(len(g["modes"]))}
+    fg = np.flatnonzero(f.mask.reshape(-1))
     for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5)):
-        fms.cluster(e, m, f.bandwidth, precision=prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            modes, _, st = fms.cluster(e, m, f.bandwidth, precision=prec)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
-        out[name] = {"frames_per_s": 1.0 / dt, "ms_per_frame": 1e3 * dt, "modes": int(len(modes)),
-                     "max_mode_err": mm.max_error, "oracle_modes_within_tol": int(np.sum(mm.errors <= tol)),
-                     "tol": tol, "unmatched_gpu": mm.unmatched_gpu, "unmatched_oracle": mm.unmatched_oracle,
+        med, _, last, _ = _time_calls(torch, lambda p=prec: fms.cluster(e, m, f.bandwidth, precision=p), reps, 1)
+        modes, labels, st = last
+        dt = med * 1e-3
+        out[name] = {"frames_per_s": 1.0 / dt, "ms_per_frame": med, "modes": int(len(modes)), "tol": tol,
+                     "vs_oracle": _accuracy(modes.cpu().numpy(), labels.cpu().numpy(), g["modes"], fg,
+                                            g["fg_labels"], g["band"], lambda w: g["tie"] | parity.near_tie_mask(
+                                                len(fg), g["near_idx"], g["near_gap"], w), tol),
                      "updates_per_s": (st["seed_pixel_updates"] + st["refine_updates"]) / dt}
     # The same frame with the decomposition table fms_autotune picks for it.
     for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5)):
         t0 = time.perf_counter()
         res = fms.autotune(e, m, f.bandwidth, precision=prec)
         tune_s = time.perf_counter() - t0
-        fms.cluster(e, m, f.bandwidth, precision=prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            modes, _, _ = fms.cluster(e, m, f.bandwidth, precision=prec)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        med, _, last, _ = _time_calls(torch, lambda p=prec: fms.cluster(e, m, f.bandwidth, precision=p), reps, 1)
+        modes = last[0]
         fms.clear_tuning()
         mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
         out[name + "_autotuned"] = {
-            "frames_per_s": 1.0 / dt, "tune_s": tune_s, "kept": res["kept"],
+            "frames_per_s": 1e3 / med, "tune_s": tune_s, "kept": res["kept"],
             "call_ms_default": res["ms_default"], "call_ms_tuned": res["ms_tuned"],
             "oracle_modes_within_tol": int(np.sum(mm.errors <= tol)), "unmatched_oracle": mm.unmatched_oracle,
             "entries": [{k: q[k] for k in ("precision", "seeds", "tile_seeds", "tile_items", "tile_waves")} |
@@ -402,6 +448,50 @@ def _cpu_threads():
         return os.cpu_count() or 1
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(frame, reps, budget_s, threads=None):
+    """Frames/s of the FP64 oracle on `frame`: up to `reps` runs, stopping
+    once `budget_s` seconds are spent (at least one run); with `threads`, the
+    BLAS pools are limited to that many threads.  Returns (rate, runs,
+    result)."""
+    from oracle import cluster as C
+    ctx = None
+    if threads is not None:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(threads)
+    try:
+        runs, t_cpu, res = 0, 0.0, None
+        while runs == 0 or (t_cpu < budget_s and runs < reps):
+            t0 = time.perf_counter()
+            res = C.cluster(frame.emb, frame.mask, C.Params(bandwidth=frame.bandwidth))
+            t_cpu += time.perf_counter() - t0
+            runs += 1
+    finally:
+        if ctx is not None:
+            ctx.unregister()
+    return runs / t_cpu, runs, res
+
+
+def _vs_oracle(modes, labels, res, thr, tol):
+    """A single-frame GPU result against a live oracle result (_accuracy)."""
+    import numpy as np
+
+    from tests import parity
+    fg = res.fg
+    return _accuracy(modes.cpu().numpy(), labels.cpu().numpy(), res.modes, fg, np.asarray(res.labels).reshape(-1)[fg],
+                     np.abs(res.best - thr) < parity.BAND, lambda w: np.abs(res.best - res.second) < w, tol)
+
+
 def main():
     a = _args()
     if a.profile_run:
@@ -431,23 +521,28 @@ def main():
     torch.cuda.synchronize()
 
     dt_b, agg_b, last_b = _time_form(fms, torch, emb, mask, h, fms.BF16_REFINE, a.steps, a.warmup)
-    print(f"bf16+refine: {a.steps} frames in {dt_b:.3f}s", file=sys.stderr, flush=True)
+    print(f"bf16+replay: median {1e3 * dt_b / a.steps:.3f} ms per frame", file=sys.stderr, flush=True)
     dt_f, agg_f, last_f = _time_form(fms, torch, emb, mask, h, fms.FP32, a.steps, a.warmup)
-    print(f"fp32: {a.steps} frames in {dt_f:.3f}s", file=sys.stderr, flush=True)
+    print(f"fp32: median {1e3 * dt_f / a.steps:.3f} ms per frame", file=sys.stderr, flush=True)
 
     fps_b = a.steps / dt_b
     fps_f = a.steps / dt_f
     upd_b = (agg_b["updates"] + agg_b["refine_updates"]) / dt_b
     upd_f = agg_f["updates"] / dt_f
 
+    st_b = last_b[2]
+    roof_b = _roofline(agg_b, spec.dim, frame.n_fg)
     out = {
-        "metric": "frames/sec (BF16+FP32-refine) and seed-pixel updates/sec, 512x512 D=32",
+        "metric": "frames/sec (BF16+FP32-replay) and seed-pixel updates/sec, 512x512 D=32",
         "value": fps_b,
+        "value_fp32": fps_f,
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": 1e3 * dt_b / a.steps,
+        "wall_ms_per_step": 1e3 * agg_b["wall_s"] / a.steps,
+        "timing": "median of the timed calls, each bracketed by HIP events on the library's stream",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -463,12 +558,29 @@ def main():
                  "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim, frame.n_fg),
                  "kernel_ms_per_frame": agg_f["step_ms"][0] / a.steps},
         "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
-        "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
+        "bf16_replay": {k: st_b[k] for k in ("refine_steps", "refine_unconverged", "refine_step_diff",
+                                             "refine_gamma_cut", "refine_updates")},
+        "roofline": roof_b,
+        "mfma_target": {"frac_target": 0.5, "frac": roof_b["frac"], "met": roof_b["frac"] >= 0.5,
+                        "note": "fraction of dense BF16 MFMA peak reached by the fused step on this frame, "
+                                "against the 0.5 utilisation target"},
     }
 
     if a.only_frame:
         print(json.dumps(out), flush=True)
         return
+
+    # The 128x128, D=16 workload (20 cells), both forms, same protocol.
+    tiny = synth.make_frame(synth.TINY)
+    te = torch.from_numpy(tiny.emb).cuda()
+    tm = torch.from_numpy(tiny.mask).cuda()
+    cfg1 = {"workload": f"one 128x128 frame, 20 elliptic cells (radii 4-12), D=16, sigma=0.05, h={tiny.bandwidth}, "
+                        f"seed 0", "n_fg": tiny.n_fg}
+    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32)):
+        med, _, last, _ = _time_calls(torch, lambda p=prec: fms.cluster(te, tm, tiny.bandwidth, precision=p),
+                                      a.steps, a.warmup)
+        cfg1[name] = {"frames_per_s": 1e3 / med, "ms_per_frame": med, "modes": int(len(last[0])), "_last": last}
+    out["plain_128"] = cfg1
 
     out["differentiation"] = _differentiation(fms, torch, frame, int(last_f[2]["seeds_used"]))
     print(f"differentiation: {out['differentiation']['ms_fwd_bwd']:.2f} ms forward+backward",
@@ -485,25 +597,28 @@ def main():
               file=sys.stderr, flush=True)
 
     if not a.no_cpu:
-        from oracle import cluster as C
-        from tests import parity
-        runs, t_cpu, res = 0, 0.0, None
-        while runs == 0 or (t_cpu < a.cpu_seconds and runs < 10):
-            t0 = time.perf_counter()
-            res = C.cluster(frame.emb, frame.mask, C.Params(bandwidth=h))
-            t_cpu += time.perf_counter() - t0
-            runs += 1
-        out["cpu_baseline"] = {"value": runs / t_cpu, "unit": "frames/s", "cores": _cpu_threads(),
-                               "kind": "oracle",
-                               "sample": f"{runs} full frames of the same 512x512 workload (FP64 NumPy)"}
-        for name, last in (("bf16", last_b), ("fp32", last_f)):
-            mm = parity.match_modes(last[0].cpu().numpy(), res.modes)
-            lc = parity.compare_labels(last[1].cpu().numpy(), res, mm, 1.0 - h)
-            out[f"{name}_vs_oracle"] = {"max_mode_err": mm.max_error,
-                                        "modes_within_tol": int(np.sum(mm.errors <= (1e-3 if name == "bf16"
-                                                                                     else 1e-5))),
-                                        "unmatched_gpu": mm.unmatched_gpu, "unmatched_oracle": mm.unmatched_oracle,
-                                        "label_mismatch": lc.mismatched}
+        # The oracle as it stands, on the same frames: the 512x512 frame with
+        # every BLAS thread (up to 3 runs within the time budget) and with one
+        # thread (one run); the 128x128 frame 10 times each way.
+        rate, runs, res = _oracle_rate(frame, 3, a.cpu_seconds)
+        rate1, runs1, _ = _oracle_rate(frame, 1, 0.0, threads=1)
+        trate, truns, tres = _oracle_rate(tiny, 10, a.cpu_seconds)
+        trate1, truns1, _ = _oracle_rate(tiny, 10, a.cpu_seconds, threads=1)
+        out["cpu_baseline"] = {"value": rate, "unit": "frames/s", "cores": _cpu_threads(), "kind": "oracle",
+                               "sample": f"{runs} full runs on the same 512x512 frame (FP64 NumPy, all BLAS "
+                                         f"threads)",
+                               "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+                               "blas_threads": _cpu_threads(),
+                               "single_thread": {"value": rate1, "runs": runs1},
+                               "plain_128": {"value": trate, "runs": truns, "single_thread": trate1,
+                                             "single_thread_runs": truns1}}
+        for name, last, tol in (("bf16", last_b, 1e-3), ("fp32", last_f, 1e-5)):
+            out[f"{name}_vs_oracle"] = _vs_oracle(last[0], last[1], res, 1.0 - h, tol)
+        for name, tol in (("bf16_refine", 1e-3), ("fp32", 1e-5)):
+            last = cfg1[name]["_last"]
+            cfg1[name]["vs_oracle"] = _vs_oracle(last[0], last[1], tres, 1.0 - tiny.bandwidth, tol)
+    for name in ("bf16_refine", "fp32"):
+        cfg1[name].pop("_last", None)
     print(json.dumps(out), flush=True)
 
 

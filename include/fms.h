@@ -51,12 +51,18 @@ typedef enum {
 typedef enum {
   FMS_PREC_FP32 = 0,        /* every step's contractions on FP32 MFMA */
   FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) for every round's
-                               iteration; then fms_cluster refines the frame's modes
-                               once, after the last round (refine_iters FP32 steps,
-                               then FP32 iteration under the same early stop), and
-                               fms_shift_seeds refines the converged seeds
-                               (refine_iters steps).  Coverage and the seed-count
-                               controller see the BF16 endpoints. */
+                               iteration (Eq. 8, 10, 11, Sec. 3.2.1); then each
+                               converged seed takes its final refine_iters
+                               iterations again on FP32 MFMA, from the centre it
+                               had that many steps before it stopped, with the
+                               same stopping test (at most refine_iters + 1 FP32
+                               steps; a seed still moving after them is dropped
+                               with the round's unconverged seeds).  The BF16
+                               iteration runs one step past its early stop, and
+                               the early stop is then taken on the FP32 step
+                               counts.  Window counts, pruning, coverage, the
+                               controller and the labels all work on those FP32
+                               endpoints. */
 } fms_precision;
 
 /* Clustering parameters.  fms_default_params fills the paper's values. */
@@ -78,7 +84,9 @@ typedef struct {
   int32_t max_iter;   /* cap on iterations per round (not in the paper); 100. */
   int32_t max_rounds; /* cap on seed rounds per frame (not in the paper); 32. */
   int32_t precision;  /* fms_precision. */
-  int32_t refine_iters; /* FP32 steps that start the refinement of the BF16 form; 3. */
+  int32_t refine_iters; /* BF16 form: final iterations of each converged seed
+                           taken again in FP32 (0 = none: BF16 endpoints);
+                           0..8, larger values give FMS_ERR_UNSUPPORTED; 2. */
   int32_t timing;     /* nonzero: time every fused-step launch with HIP events on
                          `stream` and report the totals in fms_stats. */
   /* Work decomposition of the fused step (0 = the library's choice: 8 waves
@@ -109,16 +117,17 @@ typedef struct {
   int32_t rounds;             /* seed rounds run */
   int32_t seeds_used;         /* seeds iterated */
   int32_t iterations_total;   /* iterations summed over rounds (refine steps excluded) */
-  int32_t refine_steps;       /* FP32 refine steps run (BF16 form) */
+  int32_t refine_steps;       /* BF16 form: FP32 replay steps run, summed over rounds */
   int32_t n_discarded;        /* seeds dropped unconverged by the early stop */
   int32_t n_uncovered;        /* foreground pixels farther than h from every mode */
   int32_t n_state_out;        /* N to carry into the next frame (Sec. 3.2.4) */
-  int32_t refine_unconverged; /* BF16 form: fms_cluster: modes dropped because they were still
-                                 moving when the refinement's early stop ended it;
-                                 fms_shift_seeds: seeds whose last refine step moved >= tol */
-  int32_t refine_merged;      /* BF16 form: modes dropped after refinement because they
-                                 fell inside the window of an earlier mode */
-  int64_t refine_updates;     /* (seeds) * n summed over FP32 refine steps */
+  int32_t refine_unconverged; /* BF16 form: seeds converged in BF16 that the FP32 replay
+                                 did not freeze (dropped) */
+  int32_t refine_step_diff;   /* BF16 form: replayed seeds the FP32 stopping test froze
+                                 after a different number of steps than the BF16 one */
+  int64_t refine_updates;     /* BF16 form: (active seeds) * n summed over FP32 replay steps */
+  int32_t refine_gamma_cut;   /* BF16 form: replayed seeds dropped because, counted in FP32
+                                 steps, they converged after the round's early stop */
   /* Fused-step kernel timing, filled when fms_params.timing is nonzero.
    * Index 0: FP32 form of the step, index 1: BF16 form. */
   double step_ms[2];          /* summed launch durations (HIP events), ms */
@@ -128,7 +137,7 @@ typedef struct {
 
 /* Fill *p with the paper's defaults (bandwidth 0.1, tol h/1000, gamma 0.9,
  * N_initial 128, L 2, H 8, P 0.99) and this library's caps (max_iter 100,
- * max_rounds 32, FP32, 3 refine steps, seed 0).  p: host, not NULL. */
+ * max_rounds 32, FP32, 2 refine iterations, seed 0).  p: host, not NULL. */
 void fms_default_params(fms_params* p);
 
 /* Create a handle bound to GPU `device_ordinal`.  *out receives the handle.
@@ -212,14 +221,18 @@ fms_status fms_cluster_batch(fms_handle h, void* stream, int32_t n_frames, const
  *                 raster-ordered list of foreground pixels), each in [0, n).
  *  p              host; bandwidth, conv_tol, gamma, max_iter, precision and
  *                 refine_iters are used.
- *  endpoints      device, n_seeds*dim FP32: final centre of each seed.
+ *  endpoints      device, n_seeds*dim FP32: final centre of each seed (for
+ *                 FMS_PREC_BF16_REFINE with refine_iters > 0, the FP32
+ *                 replay's centre for the seeds converged in BF16).
  *  iters          device, n_seeds int32: steps taken until it converged or
- *                 the round stopped (refine steps excluded).
- *  converged      device, n_seeds bytes: 1 = converged, 0 = discarded.
+ *                 the round stopped (the BF16 iteration's count; replay steps
+ *                 excluded).
+ *  converged      device, n_seeds bytes: 1 = converged (for the BF16 form:
+ *                 and frozen by the FP32 replay), 0 = discarded.
  *  counts         device, n_seeds int32: window count at converged endpoints,
  *                 -1 for discarded seeds; may be NULL.
- *  stats          host or NULL (seed_pixel_updates, iterations_total,
- *                 refine_unconverged, n_fg are filled).
+ *  stats          host or NULL (seed_pixel_updates, iterations_total, n_fg
+ *                 and, for the BF16 form, the refine_* fields are filled).
  * Errors: INVALID_ARG (including a seed index outside [0, n)), UNSUPPORTED,
  * BAD_INPUT, HIP. */
 fms_status fms_shift_seeds(fms_handle h, void* stream,
@@ -294,7 +307,7 @@ typedef struct {
  * Compacts `frame`, then for each active-seed count m in {128, 512, 2048,
  * 8192} up to the frame's foreground count n (just n when n < 128), and each
  * step form that `p->precision` runs (the BF16 step and the FP32 step of its
- * refinement for FMS_PREC_BF16_REFINE; the FP32 step for FMS_PREC_FP32),
+ * replay for FMS_PREC_BF16_REFINE; the FP32 step for FMS_PREC_FP32),
  * times every compiled decomposition (seeds per group x about 256, 512 or
  * 1024 items x 4, 8 or 16 waves) on m centres that start at the first m
  * foreground pixels: one warm-up, then the mean of 6 back-to-back pairs of

@@ -49,7 +49,7 @@ class Params:
     max_iter: int = 100
     max_rounds: int = 32
     precision: int = FP32
-    refine_iters: int = 3
+    refine_iters: int = 2
     timing: int = 0
     tile_seeds: int = 0
     tile_items: int = 0

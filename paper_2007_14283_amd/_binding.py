@@ -100,8 +100,9 @@ class FmsStats(ctypes.Structure):
         ("n_uncovered", ctypes.c_int32),
         ("n_state_out", ctypes.c_int32),
         ("refine_unconverged", ctypes.c_int32),
-        ("refine_merged", ctypes.c_int32),
+        ("refine_step_diff", ctypes.c_int32),
         ("refine_updates", ctypes.c_int64),
+        ("refine_gamma_cut", ctypes.c_int32),
         ("step_ms", ctypes.c_double * 2),
         ("step_updates", ctypes.c_int64 * 2),
         ("step_launches", ctypes.c_int32 * 2),

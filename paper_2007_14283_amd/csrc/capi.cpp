@@ -33,6 +33,7 @@ using fms::META_NCAND;
 using fms::META_NCONV;
 using fms::META_NSEL;
 using fms::META_REFINE_BAD;
+using fms::META_REFINE_DIFF;
 using fms::META_STEPS;
 
 struct DevBuf {
@@ -199,6 +200,9 @@ struct fms_handle_s {
   // Centres of a round, their lists and flags, window counts and ranking.
   DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, sorted, scount;
   DevBuf pcount, partial;
+  // BF16 form: the last centres of every seed's trajectory (ring slabs) and
+  // the FP32 replay's centres, states and step counts.
+  DevBuf ring, yr, rstate, riters;
   // Similarity bits of the pruning passes (all frames), accepted list.
   DevBuf bits, acc;
   // Modes found so far (rows of frame f from geo[f].row0 on).
@@ -319,7 +323,14 @@ struct Call {
   int64_t max_pixels = 0;
   Timing tm;
   bool graphs = false;  // capture and replay iteration batches
+  // BF16 form: iterations of each converged seed taken again in FP32
+  // (fms_params.refine_iters; 0 = none), and the stride of one ring slab.
+  int ring_len = 0;
+  int64_t ring_stride = 0;
 };
+
+// Most FP32 replay iterations of the BF16 form (ring slabs kept per seed).
+constexpr int kMaxRefine = 8;
 
 fms_status check_params(const fms_params* p) {
   if (!p) return FMS_ERR_INVALID_ARG;
@@ -328,6 +339,7 @@ fms_status check_params(const fms_params* p) {
   if (!(p->p_target > 0.0 && p->p_target < 1.0)) return FMS_ERR_INVALID_ARG;
   if (!std::isfinite(p->conv_tol)) return FMS_ERR_INVALID_ARG;
   if (p->n_initial < 1 || p->max_iter < 1 || p->max_rounds < 1 || p->refine_iters < 0) return FMS_ERR_INVALID_ARG;
+  if (p->refine_iters > kMaxRefine) return FMS_ERR_UNSUPPORTED;
   if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE) return FMS_ERR_INVALID_ARG;
   if (p->tile_seeds < 0 || p->tile_items < 0 || p->tile_chunks < 0) return FMS_ERR_INVALID_ARG;
   if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8 && p->tile_waves != 16)
@@ -490,6 +502,19 @@ fms_status read_meta(fms_handle h, Call& c) {
   return read_meta_end(h, c, seq);
 }
 
+// BF16 form: ring slabs and replay buffers for R rows per buffer (the rows of
+// every row-indexed centre buffer).
+fms_status ensure_replay(fms_handle h, Call& c, size_t R) {
+  if (c.ring_len <= 0) return FMS_OK;
+  const size_t dp = size_t(c.dp);
+  c.ring_stride = int64_t(R * dp);
+  HIP_TRY(h->ring.ensure(size_t(c.ring_len) * R * dp * sizeof(float)));
+  HIP_TRY(h->yr.ensure(R * dp * sizeof(float)));
+  HIP_TRY(h->riters.ensure(R * sizeof(int)));
+  HIP_TRY(h->rstate.ensure(R));
+  return FMS_OK;
+}
+
 // Compact the foreground of every frame, normalise it and write the layouts;
 // set every frame's label map to -1.  The frames' n, rows and tables are
 // set; the caller checks META_BAD at its next read of the counters (no
@@ -567,6 +592,7 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
     HIP_TRY(h->x16t.ensure(R * dp * sizeof(uint16_t)));
   }
   for (DevBuf* b : {&h->y, &h->yc0, &h->yc1, &h->modes}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
+  FMS_TRY(ensure_replay(h, c, R));
   for (DevBuf* b : {&h->order, &h->rank, &h->active, &h->next_active, &h->iters, &h->seed_pos, &h->seed_fg,
                     &h->ident, &h->cand, &h->counts, &h->sorted, &h->scount, &h->mode_counts})
     HIP_TRY(b->ensure(R * sizeof(int)));
@@ -620,13 +646,17 @@ hipError_t run_graph(fms_handle h, hipStream_t st, const IterKey& key, Record&& 
 // frame's centre count is rt.nact.  The active count, the early-stop test and
 // the done flag live on the device; the host enqueues iterations in batches
 // and reads the counters back between batches.  cap: most centres of any
-// frame.  On return h->hm(f) holds every frame's counters.
+// frame.  extra: steps a frame goes on after its first step that saw more
+// than gamma converged (IterCtl::extra).  On return h->hm(f) holds every
+// frame's counters.
 fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double gamma, int max_iter, bool bf16,
-                          bool timing, const int* seed_fg, bool nsel_from_rt) {
+                          bool timing, const int* seed_fg, bool nsel_from_rt, int extra = 0) {
   const fms::Batch& b = c.b;
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
   const int pk = bf16 ? 1 : 0;
+  // The BF16 form keeps the last centres of each trajectory for the replay.
+  float* ring = bf16 && c.ring_len > 0 ? h->ring.as<float>() : nullptr;
   HIP_TRY(fms::launch_round_begin(c.st, b, cap, nsel_from_rt, h->active.as<int>(), h->state.as<uint8_t>(),
                                   h->iters.as<int>(), seed_fg, h->x32.as<float>(), c.dp, ybuf));
   int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
@@ -641,13 +671,14 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   // the identity); later iterations read the rows the previous reduce
   // compacted in active-list order.
   auto iterate_on = [&](hipStream_t st, const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
-    const fms::IterCtl ctl{-1, it, gamma};
+    const fms::IterCtl ctl{-1, it, gamma, extra};
     const float* yin = it == 0 ? ybuf : yc[it & 1];
     hipError_t e = fms::launch_shift(st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap,
                                      h->partial.as<float>(), e0, e1);
     if (e == hipSuccess)
       e = fms::launch_reduce(st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
-                             h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0, nullptr, yin);
+                             h->iters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1], ctl, cap, 0, nullptr, yin,
+                             ring, c.ring_stride, c.ring_len);
     return e;
   };
   auto iterate = [&](const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
@@ -657,10 +688,13 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   auto iterate_graph = [&](const fms::Tiling& tl, int t0, int n) -> hipError_t {
     IterKey k;
     const void* ptrs[] = {xrm, xt, ybuf, yc[0], yc[1], lists[0], lists[1], h->partial.p, h->state.p, h->iters.p,
-                          b.geo, b.rt, b.meta, b.meta64};
+                          b.geo, b.rt, b.meta, b.meta64, ring};
     std::memcpy(k.ptr, ptrs, sizeof(ptrs));
+    // The kernels see the iteration's parity and whether it starts the round;
+    // with extra steps the early stop also counts from absolute iterations.
+    const int64_t it_key = extra > 0 ? t0 : (t0 & 1) + 2 * (t0 == 0);
     const int64_t vals[] = {bf16, c.dp, tl.group_seeds, tl.target_items, tl.max_chunks, tl.waves, cap, n,
-                            t0 & 1, t0 == 0, b.F, b.max_n, b.max_blocks, b.max_mblk};
+                            it_key, b.F, b.max_n, b.max_blocks, b.max_mblk, c.ring_stride, c.ring_len, extra};
     std::memcpy(k.val, vals, sizeof(vals));
     k.gamma = gamma;
     return run_graph(h, c.st, k, [&](hipStream_t st) -> hipError_t {
@@ -707,7 +741,10 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
     for (int f = 0; f < c.F; ++f) {
       const int* hm = h->hm(f);
       const int act = hm[fms::META_ACT + (t & 1)];
-      const bool done = hm[fms::META_DONE] || act <= 0 || (double)hm[META_NCONV] > gamma * (double)hm[META_NSEL];
+      const bool over = (double)hm[META_NCONV] > gamma * (double)hm[META_NSEL];
+      const int gstep = hm[fms::META_GSTEP];
+      const int past = (over && gstep >= 0) ? t - gstep : 0;
+      const bool done = hm[fms::META_DONE] || act <= 0 || (over && past >= extra);
       if (!done) {
         all_done = false;
         bound = std::max(bound, act);
@@ -721,66 +758,80 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   return FMS_OK;
 }
 
-// FP32 refinement of every frame's rt.nact centres y[row0 + list[..]] (rt
-// uploaded): `steps` steps without freezing; the last one counts the centres
-// still moving, and with `cont` also sets each centre's state.  With `cont`,
-// the frames with moving centres then keep iterating the same centres (list
-// = identity) in FP32 with freezing under the early stop, up to max_steps in
-// total; their state ends 1 for converged centres and 0 for the ones still
-// moving.  rt is uploaded again unchanged on return.
-fms_status run_refine(fms_handle h, Call& c, float* y, const int* list, int cap, int steps, int max_steps,
-                      double gamma, bool cont, bool timing) {
-  if (cap <= 0 || steps <= 0) return FMS_OK;
+// Steps the BF16 iteration goes on after it first sees more than gamma of a
+// round's seeds converged: BF16 and FP32 trajectories may converge a step
+// apart, and the early stop is then taken again on FP32 step counts (see
+// run_replay), which needs the seeds that converge one step later too.
+constexpr int kReplayExtra = 1;
+int replay_extra(const Call& c) { return c.ring_len > 0 ? kReplayExtra : 0; }
+
+// BF16 form, after a round's BF16 iteration: the converged seeds of every
+// frame take their last c.ring_len iterations again in FP32 (Eq. 8, 10, 11
+// and the stopping test of Sec. 3.2.1), from the centre each one had that
+// many steps before it stopped.  The replay iterates like a round (FP32
+// steps with freezing, no early stop), ring_len + 1 steps at most, with no
+// host read; a seed the replay has not frozen by then is dropped like the
+// round's unconverged seeds.  The replayed centres, states and step counts
+// go back to the round's slots, and the early stop of Sec. 3.2.3 is taken
+// again on those FP32 step counts (a seed converging after that step is
+// dropped), so the counts, pruning and coverage that follow see the FP32
+// iteration's endpoints.  The frames' META_STEPS, meta64[0],
+// META_REFINE_BAD, META_REFINE_DIFF and META_GCUT then hold the replay's
+// figures.  cap: most seeds of any frame in the round.
+fms_status run_replay(fms_handle h, Call& c, int cap, double gamma, bool timing) {
+  if (c.ring_len <= 0 || cap <= 0) return FMS_OK;
+  const fms::Batch& b = c.b;
+  HIP_TRY(fms::launch_replay_begin(c.st, b, c.dp, c.ring_len, h->state.as<uint8_t>(), h->iters.as<int>(),
+                                   h->ring.as<float>(), c.ring_stride, h->cand.as<int>(), h->yr.as<float>(),
+                                   h->active.as<int>(), h->rstate.as<uint8_t>(), h->riters.as<int>()));
   const fms::Tiling& tl = pick_tiling(c, false, cap);
-  HIP_TRY(fms::launch_set_slot(c.st, c.b, META_REFINE_BAD, false, 0));
+  int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
+  float* yc[2] = {h->yc0.as<float>(), h->yc1.as<float>()};
+  float* yr = h->yr.as<float>();
+  const int steps = c.ring_len + 1;
   if (timing) HIP_TRY(h->ensure_events(2 * size_t(steps)));
-  for (int r = 0; r < steps; ++r) {
-    const fms::IterCtl ctl{-1, -1, 1.0};
-    HIP_TRY(fms::launch_shift(c.st, c.b, false, c.dp, tl, h->x32.p, h->x32t.p, y, list, ctl, cap,
-                              h->partial.as<float>(), timing ? h->events[2 * r] : nullptr,
-                              timing ? h->events[2 * r + 1] : nullptr));
-    HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, tl, h->partial.as<float>(), list, y, h->state.as<uint8_t>(),
-                               h->iters.as<int>(), nullptr, nullptr, ctl, cap, r + 1 < steps ? 1 : (cont ? 3 : 2)));
+  for (int it = 0; it < steps; ++it) {
+    // gamma = 1: more than all of the round's seeds can never have
+    // converged, so only an empty active list stops the replay early.
+    const fms::IterCtl ctl{-1, it, 1.0};
+    const float* yin = it == 0 ? yr : yc[it & 1];
+    // Step it reads its centres in list order (in place through the identity
+    // list at it = 0, then the rows the previous reduction compacted).
+    HIP_TRY(fms::launch_shift(c.st, b, false, c.dp, tl, h->x32.p, h->x32t.p, yin, nullptr, ctl, cap,
+                              h->partial.as<float>(), timing ? h->events[2 * it] : nullptr,
+                              timing ? h->events[2 * it + 1] : nullptr));
+    HIP_TRY(fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], yr,
+                               h->rstate.as<uint8_t>(), h->riters.as<int>(), lists[(it + 1) & 1], yc[(it + 1) & 1],
+                               ctl, cap, 0, nullptr, yin));
   }
-  FMS_TRY(read_meta(h, c));
+  HIP_TRY(fms::launch_replay_end(c.st, b, c.dp, cap, c.ring_len, h->cand.as<int>(), h->iters.as<int>(), yr,
+                                 h->rstate.as<uint8_t>(), h->riters.as<int>(), h->y.as<float>(),
+                                 h->state.as<uint8_t>()));
+  HIP_TRY(fms::launch_gamma_cut(c.st, b, gamma, h->iters.as<int>(), h->state.as<uint8_t>()));
   if (timing) {
-    for (int r = 0; r < steps; ++r) {
+    // Timed calls only: wait here so the events can be read.
+    HIP_TRY(h->wait(c.st));
+    for (int it = 0; it < steps; ++it) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * r], h->events[2 * r + 1]));
+      HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * it], h->events[2 * it + 1]));
       c.tm.step_ms[0] += ms;
       c.tm.step_launches[0] += 1;
     }
   }
-  for (FrameHost& fh : c.fr) {
-    const int64_t upd = int64_t(fh.rt.nact) * steps * int64_t(fh.g.n);
-    if (fh.rt.nact > 0) fh.sx.refine_steps += steps;
-    fh.sx.refine_updates += upd;
-    if (timing) c.tm.step_updates[0] += upd;
-  }
-  if (!cont) {
-    for (int f = 0; f < c.F; ++f) c.fr[f].sx.refine_unconverged += h->hm(f)[META_REFINE_BAD];
-    return FMS_OK;
-  }
-  // Continue, with freezing, the frames whose centres still move.
-  std::vector<int> nact(static_cast<size_t>(c.F));
-  bool any = false;
-  for (int f = 0; f < c.F; ++f) {
-    nact[f] = c.fr[f].rt.nact;
-    if (h->hm(f)[META_REFINE_BAD] == 0) c.fr[f].rt.nact = 0;
-    any = any || c.fr[f].rt.nact > 0;
-  }
-  if (!any) return FMS_OK;
-  FMS_TRY(upload_rt(h, c));
-  FMS_TRY(run_iterations(h, c, y, cap, gamma, std::max(max_steps - steps, 1), false, timing, nullptr, true));
-  for (int f = 0; f < c.F; ++f) {
-    FrameHost& fh = c.fr[f];
-    if (fh.rt.nact > 0) {
-      fh.sx.refine_steps += h->hm(f)[META_STEPS];
-      fh.sx.refine_updates += int64_t(h->hm64(f, c.F));
-    }
-    fh.rt.nact = nact[f];
-  }
-  return upload_rt(h, c);
+  return FMS_OK;
+}
+
+// The replay's figures of frame f (counters on the host) into its stats.
+void add_replay_stats(fms_handle h, Call& c, int f, Timing* tm) {
+  FrameHost& fh = c.fr[f];
+  const int* hm = h->hm(f);
+  const int64_t upd = int64_t(h->hm64(f, c.F));
+  fh.sx.refine_steps += hm[META_STEPS];
+  fh.sx.refine_updates += upd;
+  fh.sx.refine_unconverged += hm[META_REFINE_BAD];
+  fh.sx.refine_step_diff += hm[META_REFINE_DIFF];
+  fh.sx.refine_gamma_cut += hm[fms::META_GCUT];
+  if (tm) tm->step_updates[0] += upd;
 }
 
 // Bit-matrix layout of a device pruning pass: frame f's candidate x
@@ -891,9 +942,6 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   return FMS_OK;
 }
 
-// The OSOP round loop (Sec. 3.2.4) over the frames of a call, then the BF16
-// refinement and the labels.  Modes stay in h->modes; on return rt.k_modes
-// of every frame (uploaded) is its final mode count.
 // Every frame's modes (rt.k_modes uploaded) to the packed outputs at rows
 // off[f].
 fms_status write_modes(fms_handle h, Call& c, float* modes_out, int32_t* counts_out, const int* off) {
@@ -919,6 +967,9 @@ struct ModeOutputs {
   int64_t total;
 };
 
+// The OSOP round loop (Sec. 3.2.4) over the frames of a call, then the
+// labels.  Modes stay in h->modes; on return rt.k_modes of every frame
+// (uploaded) is its final mode count.
 fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutputs& out) {
   const int F = c.F;
   const bool timing = p->timing != 0;
@@ -953,7 +1004,11 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     HIP_TRY(fms::launch_select(c.st, c.b, h->order.as<int>(), h->elig.as<uint8_t>(), h->seed_pos.as<int>(),
                                h->seed_fg.as<int>()));
     FMS_TRY(run_iterations(h, c, h->y.as<float>(), cap, p->gamma, p->max_iter, c.bf16, timing, h->seed_fg.as<int>(),
-                           false));
+                           false, replay_extra(c)));
+    // BF16 form: the converged seeds' last iterations again in FP32 and the
+    // early stop taken on their FP32 step counts, so that everything from
+    // here on works on FP32 endpoints.
+    FMS_TRY(run_replay(h, c, cap, p->gamma, timing));
     if (!checked_bad) {
       for (int f = 0; f < F; ++f)
         if (h->hm(f)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
@@ -968,15 +1023,14 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     }
     int host_cand = 0;
     if (on_device) {
-      // Prune (Alg. 2): window counts at the converged endpoints (in the
-      // precision of the iteration; the BF16 form recounts its refined modes
-      // in FP32 at the end), ranking by count (descending) then seed
-      // position, greedy suppression against the modes kept so far and the
-      // candidates accepted before.
+      // Prune (Alg. 2): window counts at the converged endpoints (FP32 in
+      // both forms), ranking by count (descending) then seed position, greedy
+      // suppression against the modes kept so far and the candidates
+      // accepted before.
       // Counts at every slot of the round (the list is the identity); the
       // ranking keeps the converged ones.
-      HIP_TRY(fms::launch_count(c.st, c.b, c.bf16, c.dp, count_tiling(c, c.bf16, cap), c.bf16 ? h->x16.p : h->x32.p,
-                                h->y.as<float>(), nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
+      HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, cap), h->x32.p, h->y.as<float>(),
+                                nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
       // The candidate list buffer is free in a round: it holds each
       // candidate's first word with an earlier conflict for the greedy pass.
       int* first = h->cand.as<int>();
@@ -1010,6 +1064,7 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
         fh.live = false;
         continue;
       }
+      if (c.ring_len > 0) add_replay_stats(h, c, f, timing ? &c.tm : nullptr);
       fh.n_used += m;
       fh.sx.rounds += 1;
       fh.sx.seeds_used += m;
@@ -1026,46 +1081,6 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
         go_on = true;
       }
       fh.live = go_on;
-    }
-  }
-
-  int kmax = 0;
-  for (const FrameHost& fh : c.fr) kmax = std::max(kmax, fh.k_modes);
-  if (c.bf16 && p->refine_iters > 0 && kmax > 0) {
-    // BF16 form: every frame's modes are refined in FP32 (refine_iters steps,
-    // then FP32 iteration under the early stop; modes still moving at the
-    // stop are dropped), recounted, and a mode that now falls inside the
-    // window of an earlier kept mode is dropped (acceptance order decides).
-    if (kmax > fms::kRankMax) return FMS_ERR_UNSUPPORTED;
-    for (FrameHost& fh : c.fr) {
-      fh.rt = fms::RoundTab{};
-      fh.rt.nact = fh.k_modes;
-      fh.rt.want = fh.k_modes;
-    }
-    HIP_TRY(h->bits.ensure(size_t(layout_bits(c, false)) * sizeof(uint32_t)));
-    FMS_TRY(upload_rt(h, c));
-    float* mrows = h->modes.as<float>();
-    HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), kmax));
-    FMS_TRY(run_refine(h, c, mrows, h->ident.as<int>(), kmax, p->refine_iters, p->max_iter, p->gamma, true, timing));
-    // The refined rows move to the (now free) centre buffer; the settled ones
-    // are recounted in FP32 and pruned in index order back into the mode
-    // rows.
-    HIP_TRY(fms::launch_copy_rows(c.st, c.b, mrows, h->y.as<float>(), c.dp, kmax));
-    HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NSEL, true, 0));
-    HIP_TRY(fms::launch_collect(c.st, c.b, h->state.as<uint8_t>(), h->cand.as<int>()));
-    HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, kmax), h->x32.p, h->y.as<float>(),
-                              h->cand.as<int>(), kmax, h->pcount.as<int>(), h->counts.as<int>(), META_NCAND));
-    HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), kmax, h->cand.as<int>(), kmax,
-                                nullptr, 0, h->bits.as<uint32_t>(), META_NCAND, META_NCAND));
-    HIP_TRY(fms::launch_greedy(c.st, c.b, h->bits.as<uint32_t>(), h->y.as<float>(), h->cand.as<int>(),
-                               h->counts.as<int>(), META_NCAND, META_NACC, c.dp, mrows, h->mode_counts.as<int>()));
-    FMS_TRY(read_meta(h, c));
-    for (int f = 0; f < F; ++f) {
-      FrameHost& fh = c.fr[f];
-      const int settled = h->hm(f)[META_NCAND], kept = h->hm(f)[META_NACC];
-      fh.sx.refine_unconverged += fh.k_modes - settled;
-      fh.sx.refine_merged += settled - kept;
-      fh.k_modes = kept;
     }
   }
 
@@ -1124,6 +1139,7 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   c.dp = pad_dim(dim);
   c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
   c.graphs = p->graphs != 0 && p->timing == 0;
+  c.ring_len = c.bf16 ? p->refine_iters : 0;
   set_tiling(c, p);
   // The tuned table (single-frame entries for one frame, batch entries for
   // several) applies when the call leaves the tiling to the library.
@@ -1147,6 +1163,7 @@ fms_status ensure_centres(fms_handle h, Call& c, int m) {
   for (DevBuf* b : {&h->active, &h->next_active, &h->iters, &h->ident, &h->cand, &h->counts})
     HIP_TRY(b->ensure(R * sizeof(int)));
   HIP_TRY(h->state.ensure(R));
+  FMS_TRY(ensure_replay(h, c, R));
   const size_t PR = size_t(partial_rows(c, std::max(m, c.fr[0].g.n)));
   HIP_TRY(h->pcount.ensure(PR * sizeof(int)));
   HIP_TRY(h->partial.ensure(PR * dp * sizeof(float)));
@@ -1187,7 +1204,7 @@ void fms_default_params(fms_params* p) {
   p->max_iter = 100;
   p->max_rounds = 32;
   p->precision = FMS_PREC_FP32;
-  p->refine_iters = 3;
+  p->refine_iters = 2;
 }
 
 const char* fms_status_string(fms_status s) {
@@ -1299,18 +1316,9 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   }
   if (fh.g.n == 0) return FMS_ERR_INVALID_ARG;
   const int m = n_seeds;
-  if (m > fh.g.n) {
-    // More seeds than foreground pixels: widen the (single) frame's centre
-    // region and its chunk partials.
-    const size_t R = size_t(m) + fms::kBlockPix, dp = size_t(c.dp);
-    for (DevBuf* b : {&h->y, &h->yc0, &h->yc1}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
-    for (DevBuf* b : {&h->active, &h->next_active, &h->iters, &h->ident, &h->cand, &h->counts})
-      HIP_TRY(b->ensure(R * sizeof(int)));
-    HIP_TRY(h->state.ensure(R));
-    const size_t PR = size_t(partial_rows(c, m));
-    HIP_TRY(h->pcount.ensure(PR * sizeof(int)));
-    HIP_TRY(h->partial.ensure(PR * dp * sizeof(float)));
-  }
+  // More seeds than foreground pixels: widen the (single) frame's centre
+  // region and its chunk partials.
+  if (m > fh.g.n) FMS_TRY(ensure_centres(h, c, m));
   HIP_TRY(fms::launch_init_seeds(c.st, seed_fg, m, fh.g.n, h->x32.as<float>(), c.dp, h->y.as<float>(),
                                  h->meta.as<int>()));
   fh.rt = fms::RoundTab{};
@@ -1320,21 +1328,21 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   if (h->hm(0)[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
   const bool timing = p->timing != 0;
-  FMS_TRY(run_iterations(h, c, h->y.as<float>(), m, p->gamma, p->max_iter, c.bf16, timing, nullptr, true));
+  FMS_TRY(run_iterations(h, c, h->y.as<float>(), m, p->gamma, p->max_iter, c.bf16, timing, nullptr, true,
+                         replay_extra(c)));
   fh.sx.iterations_total = h->hm(0)[META_STEPS];
   fh.sx.seed_pixel_updates = int64_t(h->hm64(0, 1));
+  if (c.ring_len > 0) {
+    // The converged seeds' last iterations again in FP32 and the early stop
+    // on their FP32 step counts; the outputs are the replay's endpoints,
+    // step counts and converged flags.
+    FMS_TRY(run_replay(h, c, m, p->gamma, timing));
+    FMS_TRY(read_meta(h, c));
+    add_replay_stats(h, c, 0, timing ? &c.tm : nullptr);
+  }
   std::vector<int> conv;
   FMS_TRY(host_converged(h, c, conv));
   const int nc = int(conv.size());
-  if (c.bf16 && nc > 0 && p->refine_iters > 0) {
-    // The converged seeds take refine_iters FP32 steps; the output keeps the
-    // iteration's converged flags.
-    FMS_TRY(upload_ints(h, c, h->cand.p, conv.data(), size_t(nc)));
-    fh.rt.nact = nc;
-    FMS_TRY(upload_rt(h, c));
-    FMS_TRY(run_refine(h, c, h->y.as<float>(), h->cand.as<int>(), nc, p->refine_iters, p->refine_iters, p->gamma,
-                       false, timing));
-  }
   // Window counts of every slot (the output keeps them for converged seeds).
   fh.rt.nact = m;
   FMS_TRY(upload_rt(h, c));

@@ -15,10 +15,13 @@ enum MetaSlot {
   META_NSEL = 2,       // seeds selected this round
   META_CURSOR = 3,     // seed-order cursor (every earlier position is used or covered)
   META_NCONV = 4,      // converged seeds this round
-  META_REFINE_BAD = 6, // refine steps whose move stayed >= tol
+  META_REFINE_DIFF = 5, // BF16 form: replayed seeds whose FP32 stop came after another step count
+  META_REFINE_BAD = 6, // BF16 form: converged seeds the FP32 replay did not freeze
   META_LEFT = 7,       // nonzero iff a foreground pixel is still eligible as a seed (coverage); pixels farther than h from every mode (labels)
   META_BADSEED = 8,    // seed indices outside [0, n)
+  META_GSTEP = 9,      // iteration whose step first saw more than gamma converged (-1: none yet)
   META_DONE = 10,      // the round's iteration has stopped
+  META_GCUT = 11,      // BF16 form: replayed seeds dropped by the FP32 early-stop count
   META_STEPS = 12,     // iterations run this round
   META_NACC = 13,      // modes being refined / modes accepted by the last pruning pass
   META_NCAND = 14,     // converged candidates of the round
@@ -154,12 +157,16 @@ StepGeom make_geom(int n);
 // active): it sets meta[META_DONE] and skips the iteration, and the reduce
 // kernel of that iteration sees the flag.  Otherwise its first work group
 // clears the other slot and counts the iteration (META_STEPS, meta64[0]).
+// With extra > 0 the iteration goes on for `extra` more steps after the
+// first step that saw more than gamma converged (META_GSTEP records that
+// step); only an empty active list stops it sooner.
 // iter < 0: a plain step whose count is meta[nact_slot], or rt.nact when
 // nact_slot < 0.
 struct IterCtl {
   int nact_slot;
   int iter;
   double gamma;
+  int extra = 0;
 };
 // One fused mean-shift step for the active seeds (at most cap per frame):
 // partial window sums per pixel chunk.  Centre a is y[active[a]], or y[a]
@@ -172,17 +179,18 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
                         float* partial, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Sum partials, renormalise, convergence test and (mode 0) the next active
 // list and converged count.  yc_next (mode 0, may be null) receives the new
-// rows of the seeds that stay active, in next-list order.  Modes 1-3 are
-// plain (refinement) steps; mode 2 also counts the centres that moved at
-// least tol (or lost their window) in META_REFINE_BAD, and mode 3 besides
-// sets each centre's state (1: its move was below tol, 0: it moved, 2: its
-// window was empty).  vnorm (may be null) receives |V| of each centre.
-// ycur (may be null) holds the current centre rows in list order (the rows
-// the step read); without it they are read from y through the list.
+// rows of the seeds that stay active, in next-list order.  Mode 1 is a plain
+// step (no freezing, no test; a centre whose window is empty gets state 2).
+// vnorm (may be null) receives |V| of each centre.  ycur (may be null) holds
+// the current centre rows in list order (the rows the step read); without it
+// they are read from y through the list.  ring (mode 0, may be null): ring_len
+// slabs of ring_stride floats, row-indexed like y; the centre a seed starts a
+// step from goes to slab (its steps so far) % ring_len.
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
                          float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm = nullptr,
-                         const float* ycur = nullptr);
+                         const float* ycur = nullptr, float* ring = nullptr, int64_t ring_stride = 0,
+                         int ring_len = 0);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
 // frame, on FP32 MFMA (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the
 // BF16 rows; the centres are rounded to BF16).  The frame's count is
@@ -200,9 +208,32 @@ int simbits_words(int ncols);
 hipError_t launch_simbits(hipStream_t s, const Batch& b, int dp, const float* y, const int* rows, int m,
                           const int* cols, int ncols, const float* modes, int nmodes, uint32_t* bits, int rows_slot,
                           int cols_slot, int* first = nullptr);
-// Pruning on the device (one work group per frame): converged list, greedy
+// FP32 replay of the BF16 form.  Begin (one work group per frame): the
+// round's converged slots k < meta[META_NSEL] (state 1), ascending, to
+// cand[i] (their number to meta[META_NCAND]); row i of yr gets the centre
+// slot cand[i] had min(iters, ring_len) steps before it stopped (from the
+// ring of launch_reduce); the identity list in active, states and step
+// counts zero in rstate / riters, and the frame's iteration counters set as
+// at a round start (the replay then iterates like a round with gamma 1).
+// End: candidate i's row and state back to slot cand[i] of y / state, and
+// for a frozen one its FP32 step count (the steps before the replay's
+// restart plus the replay's) to iters[cand[i]]; META_REFINE_BAD counts the
+// ones not frozen, META_REFINE_DIFF the frozen ones whose replay took
+// another number of steps than min(iters, ring_len).
+// Gamma cut (one work group per frame): with those step counts, the first
+// step t at which more than gamma of the round's meta[META_NSEL] seeds had
+// converged -- the early stop of Sec. 3.2.3 taken on FP32 trajectories --
+// and every converged slot whose count exceeds t loses its converged state
+// (counted in META_GCUT).
+hipError_t launch_replay_begin(hipStream_t s, const Batch& b, int dp, int ring_len, const uint8_t* state,
+                               const int* iters, const float* ring, int64_t ring_stride, int* cand, float* yr,
+                               int* active, uint8_t* rstate, int* riters);
+hipError_t launch_replay_end(hipStream_t s, const Batch& b, int dp, int cap, int ring_len, const int* cand,
+                             int* iters, const float* yr, const uint8_t* rstate, const int* riters, float* y,
+                             uint8_t* state);
+hipError_t launch_gamma_cut(hipStream_t s, const Batch& b, double gamma, const int* iters, uint8_t* state);
+// Pruning on the device (one work group per frame): ranking and greedy
 // suppression.
-hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand);
 // Ranking straight from the round's states: the converged slots k <
 // meta[META_NSEL] by (count desc, k asc); their number to meta[META_NCAND].
 // first (may be null) is set to INT_MAX for every candidate, for
@@ -230,8 +261,6 @@ hipError_t launch_set_slot(hipStream_t s, const Batch& b, int slot, bool from_rt
 hipError_t launch_fill_labels(hipStream_t s, const Batch& b, int64_t max_pixels);
 // p[row0 + k] = k for k < rt.nact of each frame (max_count bounds the grid).
 hipError_t launch_iota(hipStream_t s, const Batch& b, int* p, int max_count);
-// rt.nact rows of each frame from src to dst (both row-indexed by frame).
-hipError_t launch_copy_rows(hipStream_t s, const Batch& b, const float* src, float* dst, int dp, int max_rows);
 // Frame f's rt.k_modes modes (first dim columns) and counts to the packed
 // outputs at row out_off[f] (device array).
 hipError_t launch_modes_out(hipStream_t s, const Batch& b, const float* modes, const int* mode_counts, int dp,

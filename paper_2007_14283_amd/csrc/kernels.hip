@@ -707,11 +707,18 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
     n_act = meta[META_ACT + (ctl.iter & 1)];
     const int n_conv = meta[META_NCONV];
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
-    // Same test, in the same precision, as the host's between batches.
-    if (n_act <= 0 || (double)n_conv > ctl.gamma * (double)meta[META_NSEL]) {
+    // Same test, in the same precision, as the host's between batches.  A
+    // step that is the first to see more than gamma converged records
+    // itself; every work group of it counts 0 steps past that point whether
+    // or not it sees the record, so they all decide alike.
+    const bool over = (double)n_conv > ctl.gamma * (double)meta[META_NSEL];
+    const int gstep = meta[META_GSTEP];
+    const int past = (over && gstep >= 0) ? ctl.iter - gstep : 0;
+    if (n_act <= 0 || (over && past >= ctl.extra)) {
       if (first) meta[META_DONE] = 1;
       return;
     }
+    if (first && over && gstep < 0) meta[META_GSTEP] = ctl.iter;
     if (first) {
       meta[META_ACT + ((ctl.iter + 1) & 1)] = 0;
       meta[META_STEPS] += 1;
@@ -736,9 +743,10 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
 // lanes with a fixed butterfly.  Work groups loop over tiles of seeds.
 //   mode 0: iterate, freezing converged seeds: next active list and
 //           converged count (the early stop is taken by the next step).
-//   mode 1: refine step (no freezing).  mode 2: refine step that also counts
-//           the seeds whose move stayed >= tol.  mode 3: as mode 2, and it
-//           sets each seed's state to its last-move test.
+//           With a ring (BF16 form), the centre a step starts from is also
+//           kept in ring slab iters % ring_len, so that the last ring_len
+//           centres of every seed's trajectory are at hand when it stops.
+//   mode 1: plain step (no freezing, no test).
 // Reduce/renormalise/converge the active seeds' tiles owned by work group wg
 // of nwg.  Returns (in every thread) this group's number of newly converged
 // seeds (mode 0).  next_ctr receives the appends to next_active.
@@ -748,7 +756,8 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
                                            uint8_t* __restrict__ state,
                                            int* __restrict__ iters, int* __restrict__ next_active,
                                            float* __restrict__ yc_next, float* __restrict__ vnorm,
-                                           int* __restrict__ next_ctr, int* __restrict__ refine_bad, int n_act,
+                                           int* __restrict__ next_ctr, float* __restrict__ ring,
+                                           int64_t ring_stride, int ring_len, int n_act,
                                            const Tiling& tl, int n_blocks, float tol, int mode, int wg, int nwg) {
   constexpr int Q = DP / 4;  // float4 slices per row
   __shared__ float4 part[256];
@@ -774,6 +783,9 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     // request them first (the row from the compacted copy in list order when
     // there is one, so that it does not wait for the slot).
     const int slot = owner ? active[a] : 0;
+    // Steps this seed has taken so far (read before the head lane adds one;
+    // a seed's Q owner lanes are in one wave).
+    const int it0 = (ring && owner) ? iters[slot] : 0;
     float4 yo = make_float4(0.f, 0.f, 0.f, 0.f);
     if (owner)
       yo = *reinterpret_cast<const float4*>(ycur ? ycur + (int64_t)a * DP + 4 * q : y + (int64_t)slot * DP + 4 * q);
@@ -826,6 +838,8 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
     if (mode == 0) {
       const bool conv = head && !dead && delta < tol;
       const bool next = head && !dead && !(delta < tol);
+      if (ring && owner && !dead)
+        *reinterpret_cast<float4*>(ring + (int64_t)(it0 % ring_len) * ring_stride + (int64_t)slot * DP + 4 * q) = yo;
       if (head) {
         iters[slot] += 1;
         if (dead) state[slot] = 2;
@@ -862,10 +876,6 @@ __device__ __forceinline__ int reduce_body(const float* __restrict__ partial, co
       if (lane == 0 && bc) atomicAdd(&s_conv, __popcll(bc));
     } else if (head) {
       if (dead) state[slot] = 2;
-      if (mode >= 2) {
-        if (mode == 3 && !dead) state[slot] = delta < tol ? 1 : 0;
-        if (dead || !(delta < tol)) atomicAdd(refine_bad, 1);
-      }
     }
     __syncthreads();
   }
@@ -878,7 +888,8 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
                                                 float* __restrict__ y, uint8_t* __restrict__ state,
                                                 int* __restrict__ iters, int* __restrict__ next_active,
                                                 float* __restrict__ yc_next, float* __restrict__ vnorm, IterCtl ctl,
-                                                Tiling tl, int mode) {
+                                                Tiling tl, int mode, float* __restrict__ ring, int64_t ring_stride,
+                                                int ring_len) {
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
   int* meta = bt.meta + (int64_t)f * META_COUNT;
@@ -891,6 +902,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
   if (next_active) next_active += g.row0;
   if (yc_next) yc_next += g.row0 * DP;
   if (vnorm) vnorm += g.row0;
+  if (ring) ring += g.row0 * DP;
   int n_act;
   int* next_ctr = nullptr;
   if (ctl.iter >= 0) {
@@ -901,7 +913,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   const int conv = reduce_body<DP>(partial, active, ycur, y, state, iters, next_active, yc_next, vnorm, next_ctr,
-                                   meta + META_REFINE_BAD, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
+                                   ring, ring_stride, ring_len, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
                                    (int)gridDim.x);
   if (mode == 0 && threadIdx.x == 0 && conv) atomicAdd(meta + META_NCONV, conv);
 }
@@ -961,6 +973,7 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
     meta[META_LEFT] = 0;  // the round's coverage counts the pixels left to seed
     meta[META_DONE] = m > 0 ? 0 : 1;
     meta[META_STEPS] = 0;
+    meta[META_GSTEP] = -1;
     meta64[0] = 0;
   }
 }
@@ -1040,15 +1053,35 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
 
 // ------------------------------------------------------------------ pruning on the device
 
-// Converged slots of the round, ascending (= seed-order order), and their
-// number in meta[META_NCAND].  One 1024-thread block.
-__global__ __launch_bounds__(1024) void k_collect(Batch bt, const uint8_t* __restrict__ state,
-                                                  int* __restrict__ cand) {
+// ------------------------------------------------------------------ FP32 replay (BF16 form)
+//
+// The BF16 form takes the last ring_len iterations of every converged seed
+// again in FP32 (Eq. 8, 10, 11 with the Sec. 3.2.1 stopping test): the
+// membership decisions and the window sum that give the seed its mode are
+// then FP32 ones.  k_replay_begin lists the round's converged slots in
+// ascending order (cand[i], i < meta[META_NCAND]), puts each one's restart
+// centre -- the centre it had min(iters, ring_len) steps before it stopped,
+// kept in the ring by the BF16 reduction -- at row i of yr, and sets the
+// replay's identity list, states, step counts and iteration counters as a
+// round start does.  One 1024-thread work group per frame.
+template <int DP>
+__global__ __launch_bounds__(1024) void k_replay_begin(Batch bt, int ring_len, const uint8_t* __restrict__ state,
+                                                       const int* __restrict__ iters, const float* __restrict__ ring,
+                                                       int64_t ring_stride, int* __restrict__ cand,
+                                                       float* __restrict__ yr, int* __restrict__ active,
+                                                       uint8_t* __restrict__ rstate, int* __restrict__ riters) {
   __shared__ int sh[17];
-  const FrameGeo& g = bt.geo[blockIdx.x];
-  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
+  const int f = blockIdx.x;
+  const FrameGeo& g = bt.geo[f];
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
   state += g.row0;
+  iters += g.row0;
+  ring += g.row0 * DP;
   cand += g.row0;
+  yr += g.row0 * DP;
+  active += g.row0;
+  rstate += g.row0;
+  riters += g.row0;
   const int m = meta[META_NSEL];
   int base = 0;
   for (int k0 = 0; k0 < m; k0 += 1024) {
@@ -1056,10 +1089,124 @@ __global__ __launch_bounds__(1024) void k_collect(Batch bt, const uint8_t* __res
     const int c = (k < m && state[k] == 1) ? 1 : 0;
     int tot;
     const int r = block_exclusive_scan<1024>(c, &tot, sh);
-    if (c) cand[base + r] = k;
+    if (c) {
+      const int i = base + r;
+      const int t = max(iters[k], 1);
+      const int back = min(t, ring_len);
+      const float4* src = reinterpret_cast<const float4*>(ring + (int64_t)((t - back) % ring_len) * ring_stride +
+                                                          (int64_t)k * DP);
+      float4* dst = reinterpret_cast<float4*>(yr + (int64_t)i * DP);
+#pragma unroll
+      for (int q = 0; q < DP / 4; ++q) dst[q] = src[q];
+      cand[i] = k;
+      active[i] = i;
+      rstate[i] = 0;
+      riters[i] = 0;
+    }
     base += tot;
   }
-  if (threadIdx.x == 0) meta[META_NCAND] = base;
+  if (threadIdx.x == 0) {
+    meta[META_NCAND] = base;
+    meta[META_ACT] = base;
+    meta[META_ACT + 1] = 0;
+    meta[META_NCONV] = 0;
+    meta[META_DONE] = base > 0 ? 0 : 1;
+    meta[META_STEPS] = 0;
+    meta[META_REFINE_BAD] = 0;
+    meta[META_REFINE_DIFF] = 0;
+    meta[META_GSTEP] = -1;
+    meta[META_GCUT] = 0;
+    bt.meta64[(int64_t)f * kMeta64] = 0;
+  }
+}
+
+// End of the replay: candidate i's FP32 centre and state go back to its slot
+// (state 1 only when the replay froze it; a seed still moving is dropped
+// with the round's unconverged ones), and a frozen one's step count becomes
+// its FP32 trajectory's: the BF16 steps before the restart plus the
+// replay's.  META_REFINE_BAD counts the candidates the replay did not
+// freeze, META_REFINE_DIFF the frozen ones whose FP32 stop came after a
+// different number of steps than the BF16 one.
+template <int DP>
+__global__ __launch_bounds__(256) void k_replay_end(Batch bt, int cap, int ring_len, const int* __restrict__ cand,
+                                                    int* __restrict__ iters, const float* __restrict__ yr,
+                                                    const uint8_t* __restrict__ rstate,
+                                                    const int* __restrict__ riters, float* __restrict__ y,
+                                                    uint8_t* __restrict__ state) {
+  const int f = blockIdx.y;
+  const FrameGeo& g = bt.geo[f];
+  int* meta = bt.meta + (int64_t)f * META_COUNT;
+  const int m = meta[META_NCAND];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < m && i < cap;
+  bool bad = false, diff = false;
+  if (live) {
+    const int k = cand[g.row0 + i];
+    const uint8_t st = rstate[g.row0 + i];
+    const float4* src = reinterpret_cast<const float4*>(yr + (g.row0 + i) * DP);
+    float4* dst = reinterpret_cast<float4*>(y + (g.row0 + k) * DP);
+#pragma unroll
+    for (int q = 0; q < DP / 4; ++q) dst[q] = src[q];
+    state[g.row0 + k] = st;
+    bad = st != 1;
+    const int t = max(iters[g.row0 + k], 1);
+    const int back = min(t, ring_len);
+    const int rit = riters[g.row0 + i];
+    diff = st == 1 && rit != back;
+    if (st == 1) iters[g.row0 + k] = t - back + rit;
+  }
+  const unsigned long long bb = __ballot(bad), bd = __ballot(diff);
+  if ((threadIdx.x & 63) == 0) {
+    if (bb) atomicAdd(meta + META_REFINE_BAD, __popcll(bb));
+    if (bd) atomicAdd(meta + META_REFINE_DIFF, __popcll(bd));
+  }
+}
+
+// The early stop of Sec. 3.2.3 on the FP32 step counts of the replay: the
+// first step t after which more than gamma of the round's seeds had
+// converged; converged slots whose count exceeds t are dropped, as the
+// plain iteration would have stopped before they converged.  Counts above
+// kCutSteps share the histogram's last bin (they can only be cut or kept
+// together).  One 1024-thread work group per frame.
+constexpr int kCutSteps = 1024;
+__global__ __launch_bounds__(1024) void k_gamma_cut(Batch bt, double gamma, const int* __restrict__ iters,
+                                                    uint8_t* __restrict__ state) {
+  __shared__ int hist[kCutSteps + 1];
+  __shared__ int s_cut, s_drop;
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
+  iters += g.row0;
+  state += g.row0;
+  const int m = meta[META_NSEL];
+  for (int t = threadIdx.x; t <= kCutSteps; t += 1024) hist[t] = 0;
+  if (threadIdx.x == 0) s_drop = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += 1024)
+    if (state[k] == 1) atomicAdd(&hist[min(max(iters[k], 0), kCutSteps)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cut = INT_MAX, run = 0;
+    for (int t = 0; t <= kCutSteps; ++t) {
+      run += hist[t];
+      if ((double)run > gamma * (double)m) {
+        cut = t;
+        break;
+      }
+    }
+    s_cut = cut;
+  }
+  __syncthreads();
+  const int cut = s_cut;
+  int drop = 0;
+  if (cut < kCutSteps)
+    for (int k = threadIdx.x; k < m; k += 1024)
+      if (state[k] == 1 && iters[k] > cut) {
+        state[k] = 0;
+        ++drop;
+      }
+  if (drop) atomicAdd(&s_drop, drop);
+  __syncthreads();
+  if (threadIdx.x == 0) meta[META_GCUT] = s_drop;
 }
 
 // Rank the converged slots k < meta[META_NSEL] (state[k] == 1) of the round
@@ -1417,14 +1564,6 @@ __global__ __launch_bounds__(256) void k_fill_labels(Batch bt) {
   if (g.labels && i < g.desc.n_pixels) g.labels[i] = -1;
 }
 
-__global__ __launch_bounds__(256) void k_copy_rows(Batch bt, const float* __restrict__ src, float* __restrict__ dst,
-                                                   int dp) {
-  const int f = blockIdx.y;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)bt.rt[f].nact * dp) return;
-  const int64_t o = bt.geo[f].row0 * dp + t;
-  dst[o] = src[o];
-}
 
 __global__ __launch_bounds__(256) void k_modes_out(Batch bt, const float* __restrict__ modes,
                                                    const int* __restrict__ mode_counts, int dp, int dim,
@@ -1815,7 +1954,9 @@ hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const 
 
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
                          const int* active, float* y, uint8_t* state, int* iters, int* next_active,
-                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm, const float* ycur) {
+                         float* yc_next, const IterCtl& ctl, int cap, int mode, float* vnorm, const float* ycur,
+                         float* ring, int64_t ring_stride, int ring_len) {
+  if (ring && ring_len < 1) return hipErrorInvalidValue;
   if (cap <= 0) return hipSuccess;
   // Enough work groups for the seed tiles of the largest active count; they
   // loop when the active count shrinks and tiles get smaller.
@@ -1826,7 +1967,7 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
   const dim3 grid(cdiv(cap, spw), b.F), block(256);
 #define FMS_REDUCE_CASE(DPV)                                                                                      \
   hipLaunchKernelGGL(k_reduce<DPV>, grid, block, 0, s, b, partial, active, ycur, y, state, iters, next_active,     \
-                     yc_next, vnorm, ctl, t, mode)
+                     yc_next, vnorm, ctl, t, mode, ring, ring_stride, ring_len)
   switch (dp) {
     case 32: FMS_REDUCE_CASE(32); break;
     case 64: FMS_REDUCE_CASE(64); break;
@@ -1848,8 +1989,47 @@ hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const 
   return hipGetLastError();
 }
 
-hipError_t launch_collect(hipStream_t s, const Batch& b, const uint8_t* state, int* cand) {
-  hipLaunchKernelGGL(k_collect, dim3(b.F), dim3(1024), 0, s, b, state, cand);
+hipError_t launch_replay_begin(hipStream_t s, const Batch& b, int dp, int ring_len, const uint8_t* state,
+                               const int* iters, const float* ring, int64_t ring_stride, int* cand, float* yr,
+                               int* active, uint8_t* rstate, int* riters) {
+  if (ring_len < 1) return hipErrorInvalidValue;
+  switch (dp) {
+#define FMS_RB_CASE(DPV)                                                                                     \
+  case DPV:                                                                                                  \
+    hipLaunchKernelGGL(k_replay_begin<DPV>, dim3(b.F), dim3(1024), 0, s, b, ring_len, state, iters, ring,    \
+                       ring_stride, cand, yr, active, rstate, riters);                                       \
+    break;
+    FMS_RB_CASE(32)
+    FMS_RB_CASE(64)
+    FMS_RB_CASE(128)
+#undef FMS_RB_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_cut(hipStream_t s, const Batch& b, double gamma, const int* iters, uint8_t* state) {
+  hipLaunchKernelGGL(k_gamma_cut, dim3(b.F), dim3(1024), 0, s, b, gamma, iters, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_end(hipStream_t s, const Batch& b, int dp, int cap, int ring_len, const int* cand,
+                             int* iters, const float* yr, const uint8_t* rstate, const int* riters, float* y,
+                             uint8_t* state) {
+  if (cap <= 0) return hipSuccess;
+  const dim3 grid(cdiv(cap, 256), b.F), block(256);
+  switch (dp) {
+#define FMS_RE_CASE(DPV)                                                                                     \
+  case DPV:                                                                                                  \
+    hipLaunchKernelGGL(k_replay_end<DPV>, grid, block, 0, s, b, cap, ring_len, cand, iters, yr, rstate,       \
+                       riters, y, state);                                                                    \
+    break;
+    FMS_RE_CASE(32)
+    FMS_RE_CASE(64)
+    FMS_RE_CASE(128)
+#undef FMS_RE_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1960,12 +2140,6 @@ hipError_t launch_fill_labels(hipStream_t s, const Batch& b, int64_t max_pixels)
 hipError_t launch_iota(hipStream_t s, const Batch& b, int* p, int max_count) {
   if (max_count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_iota, dim3(cdiv(max_count, 256), b.F), dim3(256), 0, s, b, p);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_rows(hipStream_t s, const Batch& b, const float* src, float* dst, int dp, int max_rows) {
-  if (max_rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_rows, dim3(cdiv((int64_t)max_rows * dp, 256), b.F), dim3(256), 0, s, b, src, dst, dp);
   return hipGetLastError();
 }
 

@@ -16,8 +16,11 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
 from oracle import cluster as C  # noqa: E402
+from tests.golden.make_batch_oracle import provenance  # noqa: E402
 
 BAND = 1e-4  # the exempt band of the label comparison
+GAP_KEEP = 0.02
+
 
 
 def main():
@@ -27,10 +30,15 @@ def main():
     band = np.abs(r.best - thr) < BAND
     tie = np.abs(r.best - r.second) < BAND
     stats = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in r.stats.items()}
+    # Best minus second-best similarity where it is below GAP_KEEP (argmax
+    # near-ties of a wider band than BAND can be exempted).
+    gap = r.best - r.second
+    near = np.flatnonzero(gap < GAP_KEEP)
     np.savez_compressed(os.path.join(HERE, "precision1024_oracle.npz"),
                         modes=r.modes.astype(np.float64), mode_counts=np.asarray(r.mode_counts, np.int32),
                         fg_labels=np.asarray(r.labels).reshape(-1)[r.fg].astype(np.int16),
                         band=np.packbits(band), tie=np.packbits(tie), n_fg=np.int64(len(r.fg)),
+                        near_idx=near.astype(np.int32), near_gap=gap[near].astype(np.float32), **provenance(r),
                         bandwidth=np.float64(f.bandwidth), stats=np.frombuffer(json.dumps(stats).encode(), np.uint8))
     print(len(r.modes), "modes;", stats)
 

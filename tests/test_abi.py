@@ -37,7 +37,7 @@ def test_default_params_and_status_strings():
     import paper_2007_14283_amd as F
     p = F.default_params()
     assert (p.bandwidth, p.gamma, p.n_initial, p.big_l, p.big_h, p.p_target) == (0.1, 0.9, 128, 2.0, 8.0, 0.99)
-    assert (p.max_iter, p.max_rounds, p.precision, p.refine_iters, p.conv_tol) == (100, 32, 0, 3, 0.0)
+    assert (p.max_iter, p.max_rounds, p.precision, p.refine_iters, p.conv_tol) == (100, 32, 0, 2, 0.0)
     lib = F.library()
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.fms_status_string(code)

@@ -2,15 +2,14 @@
 stored FP64 oracle result (tests/golden/precision1024_oracle.npz, written from
 oracle/ alone and pinned in test_golden_precision1024.py).  FP32 form: the same
 modes in the same order within 1e-5 (1 - cos), the same window counts and
-round statistics, labels exact outside the exempt sets.  BF16 + FP32 refine:
-every mode an FP64 fixed point up to the stopping rule (as the oracle's own
-modes, 99 % within tol = h/1000, all within 10 tol) and >= 90 % of the
-oracle's modes within 1e-3."""
+round statistics, labels exact outside the exempt sets.  BF16 + FP32 replay:
+the BF16 bar of tests/parity.py (modes within 1e-3, at most 2 % of the
+oracle's modes lost and each traced to its seed through the stored round
+seed lists, labels exact outside the exempt sets)."""
 import numpy as np
 import pytest
 
 import synth
-from oracle import meanshift as ms
 from tests import parity
 
 pytestmark = pytest.mark.gpu
@@ -62,18 +61,19 @@ def test_precision1024_fp32(F, case):
 
 
 def test_precision1024_bf16_refine(F, case):
+    import torch
     f, g, fg = case
     _say("1024x1024 bf16")
     modes, labels, st = _run(F, f, F.BF16_REFINE)
     mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
-    e = f.emb.reshape(-1, f.emb.shape[-1])[fg].astype(np.float64)
-    x = e / np.linalg.norm(e, axis=1, keepdims=True)
-    m = modes.cpu().double().numpy()
-    m = m / np.linalg.norm(m, axis=1, keepdims=True)
-    tol = f.bandwidth / 1000
-    _, resid, _ = ms.shift(m, x, 1.0 - f.bandwidth)
-    within = int(np.sum(mm.errors <= BF16_TOL))
-    print(f"bf16: {len(m)} modes, {within}/{len(g['modes'])} oracle modes within 1e-3, "
-          f"max err {mm.max_error:.2e}, max residual {resid.max():.2e}")
-    assert np.mean(resid < tol) >= 0.99 and np.all(resid < 10 * tol)
-    assert within >= 0.9 * len(g["modes"])
+    emb = torch.from_numpy(f.emb).cuda()
+    mask = torch.from_numpy(f.mask).cuda()
+    lab = labels.cpu().numpy()
+
+    def labels_cmp(width, lost, match):
+        tie = g["tie"] | parity.near_tie_mask(len(fg), g["near_idx"], g["near_gap"], width)
+        return parity.compare_labels_fg(lab, fg, g["fg_labels"], g["band"], tie, match, lost)
+
+    parity.assert_bf16_bar(F, emb, mask, f.bandwidth, modes, labels_cmp, mm, g)
+    print(f"replay: steps {st['refine_steps']}, unconverged {st['refine_unconverged']}, "
+          f"step diff {st['refine_step_diff']}")

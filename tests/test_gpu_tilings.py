@@ -2,21 +2,17 @@
 (seeds per group, waves per group) the library accepts, for each D class and
 precision, clusters a small frame to the same result as the FP64 oracle
 (FP32: modes within 1e-5 and labels exact outside the exempt sets; BF16 +
-refine: every mode an FP64 fixed point and >= 90 % of the oracle's modes within
-1e-3), and rounds large enough to take the wide seed groups by default do
-too."""
-import numpy as np
+FP32 replay: the BF16 bar of tests/parity.py), and rounds large enough to take
+the wide seed groups by default do too."""
 import pytest
 
 import synth
 from oracle import cluster as C
-from oracle import meanshift as ms
 from tests import parity
 
 pytestmark = pytest.mark.gpu
 
 FP32_TOL = 1e-5
-BF16_TOL = 1e-3
 _ORACLE = {}
 
 
@@ -52,11 +48,10 @@ def _check(F, f, res, prec, **kw):
         assert lc.mismatched == 0, kw
         assert st["rounds"] == res.stats["rounds"] and st["seeds_used"] == res.stats["seeds_used"], kw
     else:
-        m = modes.cpu().double().numpy()
-        m = m / np.linalg.norm(m, axis=1, keepdims=True)
-        _, resid, _ = ms.shift(m, res.x, 1.0 - f.bandwidth)
-        assert np.all(resid < f.bandwidth / 1000), kw
-        assert int(np.sum(mm.errors <= BF16_TOL)) >= 0.9 * len(res.modes), kw
+        lab = labels.cpu().numpy()
+        parity.assert_bf16_bar(F, emb, mask, f.bandwidth, modes, lambda w, lost, match: parity.compare_labels(
+            lab, res, match, 1.0 - f.bandwidth, tie_width=w, lost_modes=lost), mm, parity.provenance_of(res),
+            {k: v for k, v in kw.items() if k.startswith("tile_")})
 
 
 @pytest.mark.parametrize("dim", [32, 64, 128])
