@@ -237,7 +237,7 @@ def _batched(fms, torch, a):
     out = {"workload": f"{nf} frames, side in {sides}, 10-300 cells, foreground 20-50%, sigma U(0.03, 0.1), "
                        f"D={specs[0].dim}, per-frame h; frame seeds 0..{nf - 1}",
            "frames": nf, "n_fg_total": int(sum(f.n_fg for f in frames)), "steps": a.batch_steps}
-    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32)):
+    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32), ("bf16_split", fms.BF16_SPLIT)):
         # Two warm-up calls, the first result still held during the second,
         # so that the caching allocator holds the output tensors of two calls
         # before the timed loop (which keeps one result while making the next).
@@ -252,6 +252,7 @@ def _batched(fms, torch, a):
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
                      "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"]),
                      "vs_oracle": _batch_accuracy(frames, res, 1e-3 if prec == fms.BF16_REFINE else 1e-5)}
+        del res, allres
     # Autotuned tiles: fms_autotune_batch on these frames (BF16+refine form);
     # its entries serve the batch calls when whole calls got faster with them.
     t0 = time.perf_counter()
@@ -333,7 +334,8 @@ def _precision1024(fms, torch, reps=10):
                        f"D={spec.dim}, sigma={spec.sigma}, h={f.bandwidth}, seed {spec.seed}",
            "n_fg": f.n_fg, "oracle_modes": int(len(g["modes"]))}
     fg = np.flatnonzero(f.mask.reshape(-1))
-    for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5)):
+    for name, prec, tol in (("bf16_refine", fms.BF16_REFINE, 1e-3), ("fp32", fms.FP32, 1e-5),
+                            ("bf16_split", fms.BF16_SPLIT, 1e-5)):
         med, _, last, _ = _time_calls(torch, lambda p=prec: fms.cluster(e, m, f.bandwidth, precision=p), reps, 1)
         modes, labels, st = last
         dt = med * 1e-3
@@ -524,6 +526,8 @@ def main():
     print(f"bf16+replay: median {1e3 * dt_b / a.steps:.3f} ms per frame", file=sys.stderr, flush=True)
     dt_f, agg_f, last_f = _time_form(fms, torch, emb, mask, h, fms.FP32, a.steps, a.warmup)
     print(f"fp32: median {1e3 * dt_f / a.steps:.3f} ms per frame", file=sys.stderr, flush=True)
+    dt_s, agg_s, last_s = _time_form(fms, torch, emb, mask, h, fms.BF16_SPLIT, a.steps, a.warmup)
+    print(f"split bf16: median {1e3 * dt_s / a.steps:.3f} ms per frame", file=sys.stderr, flush=True)
 
     fps_b = a.steps / dt_b
     fps_f = a.steps / dt_f
@@ -557,6 +561,10 @@ def main():
         "fp32": {"frames_per_s": fps_f, "ms_per_frame": 1e3 * dt_f / a.steps, "updates_per_s": upd_f,
                  "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim, frame.n_fg),
                  "kernel_ms_per_frame": agg_f["step_ms"][0] / a.steps},
+        "bf16_split": {"frames_per_s": a.steps / dt_s, "ms_per_frame": 1e3 * dt_s / a.steps,
+                       "updates_per_s": agg_s["updates"] / dt_s, "modes": int(len(last_s[0])),
+                       "roofline": _roofline(agg_s, spec.dim, frame.n_fg),
+                       "kernel_ms_per_frame": agg_s["step_ms"][1] / a.steps},
         "bf16_kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
         "bf16_replay": {k: st_b[k] for k in ("refine_steps", "refine_unconverged", "refine_step_diff",
                                              "refine_gamma_cut", "refine_updates")},
@@ -576,7 +584,7 @@ def main():
     tm = torch.from_numpy(tiny.mask).cuda()
     cfg1 = {"workload": f"one 128x128 frame, 20 elliptic cells (radii 4-12), D=16, sigma=0.05, h={tiny.bandwidth}, "
                         f"seed 0", "n_fg": tiny.n_fg}
-    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32)):
+    for name, prec in (("bf16_refine", fms.BF16_REFINE), ("fp32", fms.FP32), ("bf16_split", fms.BF16_SPLIT)):
         med, _, last, _ = _time_calls(torch, lambda p=prec: fms.cluster(te, tm, tiny.bandwidth, precision=p),
                                       a.steps, a.warmup)
         cfg1[name] = {"frames_per_s": 1e3 / med, "ms_per_frame": med, "modes": int(len(last[0])), "_last": last}
@@ -612,12 +620,12 @@ def main():
                                "single_thread": {"value": rate1, "runs": runs1},
                                "plain_128": {"value": trate, "runs": truns, "single_thread": trate1,
                                              "single_thread_runs": truns1}}
-        for name, last, tol in (("bf16", last_b, 1e-3), ("fp32", last_f, 1e-5)):
+        for name, last, tol in (("bf16", last_b, 1e-3), ("fp32", last_f, 1e-5), ("bf16_split", last_s, 1e-5)):
             out[f"{name}_vs_oracle"] = _vs_oracle(last[0], last[1], res, 1.0 - h, tol)
-        for name, tol in (("bf16_refine", 1e-3), ("fp32", 1e-5)):
+        for name, tol in (("bf16_refine", 1e-3), ("fp32", 1e-5), ("bf16_split", 1e-5)):
             last = cfg1[name]["_last"]
             cfg1[name]["vs_oracle"] = _vs_oracle(last[0], last[1], tres, 1.0 - tiny.bandwidth, tol)
-    for name in ("bf16_refine", "fp32"):
+    for name in ("bf16_refine", "fp32", "bf16_split"):
         cfg1[name].pop("_last", None)
     print(json.dumps(out), flush=True)
 

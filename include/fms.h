@@ -50,7 +50,7 @@ typedef enum {
 
 typedef enum {
   FMS_PREC_FP32 = 0,        /* every step's contractions on FP32 MFMA */
-  FMS_PREC_BF16_REFINE = 1  /* BF16 MFMA (FP32 accumulate) for every round's
+  FMS_PREC_BF16_REFINE = 1, /* BF16 MFMA (FP32 accumulate) for every round's
                                iteration (Eq. 8, 10, 11, Sec. 3.2.1); then each
                                converged seed takes its final refine_iters
                                iterations again on FP32 MFMA, from the centre it
@@ -63,6 +63,14 @@ typedef enum {
                                counts.  Window counts, pruning, coverage, the
                                controller and the labels all work on those FP32
                                endpoints. */
+  FMS_PREC_BF16_SPLIT = 2   /* BF16 MFMA (FP32 accumulate) on values split into a
+                               high and a low BF16 part (hi = bf16(v), lo =
+                               bf16(v - hi), v kept to a relative 2^-16): each
+                               similarity takes three products (hi.hi, hi.lo,
+                               lo.hi) and each window sum two, so a similarity is
+                               off by under 5e-5 (plain BF16: 4e-3).  Every
+                               iteration runs this way; no replay.  Window counts
+                               are FP32 as in the other forms. */
 } fms_precision;
 
 /* Clustering parameters.  fms_default_params fills the paper's values. */

@@ -20,11 +20,12 @@ from typing import Dict, Optional
 
 from . import _binding as B
 
-__all__ = ["Params", "FmsError", "FP32", "BF16_REFINE", "cluster", "cluster_batch", "shift_seeds", "unroll",
+__all__ = ["Params", "FmsError", "FP32", "BF16_REFINE", "BF16_SPLIT", "cluster", "cluster_batch", "shift_seeds", "unroll",
            "autotune", "autotune_batch", "clear_tuning", "seed_order", "default_params", "library"]
 
 FP32 = B.FMS_PREC_FP32
 BF16_REFINE = B.FMS_PREC_BF16_REFINE
+BF16_SPLIT = B.FMS_PREC_BF16_SPLIT
 
 
 class FmsError(RuntimeError):

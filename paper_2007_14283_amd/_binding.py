@@ -16,6 +16,7 @@ FMS_ERR_HIP = -5
 
 FMS_PREC_FP32 = 0
 FMS_PREC_BF16_REFINE = 1
+FMS_PREC_BF16_SPLIT = 2
 
 # Every entry point declared in include/fms.h.
 EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",

@@ -163,7 +163,7 @@ constexpr int kHugeGroupMin = 2048;
 // A fused-step decomposition chosen by fms_autotune for one step form, D
 // class, pixel-count bucket and active-seed count.
 struct TunedTiling {
-  bool bf16;
+  int form;    // fms::StepForm
   bool batch;  // tuned on launches over several frames (fms_autotune_batch)
   int dp;
   int nb;
@@ -196,7 +196,7 @@ struct fms_handle_s {
   std::vector<TunedTiling> tuned;
   // Pixel data of the call's frames; every row-indexed buffer holds frame f
   // from row geo[f].row0 on.
-  DevBuf blk, fg_idx, x32, x32t, x16, x16t, order, rank, elig, enorm;
+  DevBuf blk, fg_idx, x32, x32t, x16, x16t, x16l, x16lt, order, rank, elig, enorm;
   // Centres of a round, their lists and flags, window counts and ranking.
   DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, sorted, scount;
   DevBuf pcount, partial;
@@ -312,7 +312,8 @@ struct Timing {
 struct Call {
   hipStream_t st = nullptr;
   int F = 0, dim = 0, dp = 32;
-  bool bf16 = false;
+  int form = fms::FORM_FP32;  // arithmetic of the round's iteration (fms::StepForm)
+  bool bf16 = false;          // the plain BF16 form with its FP32 replay
   std::vector<FrameHost> fr;
   fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{};
   // The handle's tuned decompositions when the call leaves the tiling to the
@@ -340,7 +341,8 @@ fms_status check_params(const fms_params* p) {
   if (!std::isfinite(p->conv_tol)) return FMS_ERR_INVALID_ARG;
   if (p->n_initial < 1 || p->max_iter < 1 || p->max_rounds < 1 || p->refine_iters < 0) return FMS_ERR_INVALID_ARG;
   if (p->refine_iters > kMaxRefine) return FMS_ERR_UNSUPPORTED;
-  if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE) return FMS_ERR_INVALID_ARG;
+  if (p->precision != FMS_PREC_FP32 && p->precision != FMS_PREC_BF16_REFINE && p->precision != FMS_PREC_BF16_SPLIT)
+    return FMS_ERR_INVALID_ARG;
   if (p->tile_seeds < 0 || p->tile_items < 0 || p->tile_chunks < 0) return FMS_ERR_INVALID_ARG;
   if (p->tile_waves != 0 && p->tile_waves != 4 && p->tile_waves != 8 && p->tile_waves != 16)
     return FMS_ERR_UNSUPPORTED;
@@ -369,27 +371,28 @@ int n_bucket(int64_t n) {
   return b;
 }
 
-// Default tiling of a launch with at most `bound` centres per frame.
-const fms::Tiling& default_tiling(const Call& c, bool bf16, int bound) {
-  if (bf16 && bound >= kHugeGroupMin) return c.tile_huge;
-  if (bound >= kBigGroupMin) return bf16 ? c.tile_big : c.tile_fp32_big;
-  return bf16 ? c.tile : c.tile_fp32;
+// Default tiling of a launch of step form `form` with at most `bound`
+// centres per frame (the call's own form, or FP32).
+const fms::Tiling& default_tiling(const Call& c, int form, int bound) {
+  if (form == fms::FORM_FP32) return bound >= kBigGroupMin ? c.tile_fp32_big : c.tile_fp32;
+  if (form == fms::FORM_BF16 && bound >= kHugeGroupMin) return c.tile_huge;
+  return bound >= kBigGroupMin ? c.tile_big : c.tile;
 }
 
-// Tiling of a window-count launch.  The autotuner times shift launches only,
-// so count launches keep the defaults (their integer counts do not depend on
-// the decomposition).
-const fms::Tiling& count_tiling(const Call& c, bool bf16, int bound) { return default_tiling(c, bf16, bound); }
+// Tiling of a window-count launch (FP32).  The autotuner times shift
+// launches only, so count launches keep the defaults (their integer counts
+// do not depend on the decomposition).
+const fms::Tiling& count_tiling(const Call& c, int bound) { return default_tiling(c, fms::FORM_FP32, bound); }
 
 // Tiling of a fused-step launch with at most `bound` centres per frame: the
 // tuned entry of the form, D class and bucket whose seed count is nearest in
 // ratio, else the defaults.
-const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
+const fms::Tiling& pick_tiling(const Call& c, int form, int bound) {
   if (c.tuned) {
     const TunedTiling* best = nullptr;
     double bd = 0.0;
     for (const TunedTiling& t : *c.tuned) {
-      if (t.bf16 != bf16 || t.batch != (c.F > 1) || t.dp != c.dp || t.nb != c.nb) continue;
+      if (t.form != form || t.batch != (c.F > 1) || t.dp != c.dp || t.nb != c.nb) continue;
       const double d = std::fabs(std::log(double(std::max(bound, 1)) / double(t.m)));
       if (!best || d < bd) {
         best = &t;
@@ -398,7 +401,7 @@ const fms::Tiling& pick_tiling(const Call& c, bool bf16, int bound) {
     }
     if (best) return best->t;
   }
-  return default_tiling(c, bf16, bound);
+  return default_tiling(c, form, bound);
 }
 
 // Waves per work group of single-frame calls when the caller fixes none.
@@ -410,14 +413,14 @@ constexpr int kSingleFrameWaves = 8;
 
 void set_tiling(Call& c, const fms_params* p) {
   const int wv = p->tile_waves > 0 ? p->tile_waves : (c.F == 1 ? kSingleFrameWaves : 0);
-  c.tile = fms::make_tiling(c.bf16, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
-  c.tile_fp32 = fms::make_tiling(false, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
+  c.tile = fms::make_tiling(c.form, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
+  c.tile_fp32 = fms::make_tiling(fms::FORM_FP32, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
   // A caller-fixed group size holds for every launch.
   const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
-  c.tile_big = fms::make_tiling(c.bf16, c.dp, big, p->tile_items, p->tile_chunks, wv);
-  c.tile_fp32_big = fms::make_tiling(false, c.dp, big, p->tile_items, p->tile_chunks, wv);
+  c.tile_big = fms::make_tiling(c.form, c.dp, big, p->tile_items, p->tile_chunks, wv);
+  c.tile_fp32_big = fms::make_tiling(fms::FORM_FP32, c.dp, big, p->tile_items, p->tile_chunks, wv);
   const int huge = p->tile_seeds > 0 ? p->tile_seeds : kHugeGroup;
-  c.tile_huge = fms::make_tiling(true, c.dp, huge, p->tile_items, p->tile_chunks, wv);
+  c.tile_huge = fms::make_tiling(fms::FORM_BF16, c.dp, huge, p->tile_items, p->tile_chunks, wv);
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.
@@ -587,9 +590,13 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   HIP_TRY(h->enorm.ensure(R * sizeof(float)));
   HIP_TRY(h->x32.ensure(R * dp * sizeof(float)));
   HIP_TRY(h->x32t.ensure(R * dp * sizeof(float)));
-  if (c.bf16) {
+  if (c.form != fms::FORM_FP32) {
     HIP_TRY(h->x16.ensure(R * dp * sizeof(uint16_t)));
     HIP_TRY(h->x16t.ensure(R * dp * sizeof(uint16_t)));
+  }
+  if (c.form == fms::FORM_SPLIT) {
+    HIP_TRY(h->x16l.ensure(R * dp * sizeof(uint16_t)));
+    HIP_TRY(h->x16lt.ensure(R * dp * sizeof(uint16_t)));
   }
   for (DevBuf* b : {&h->y, &h->yc0, &h->yc1, &h->modes}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
   FMS_TRY(ensure_replay(h, c, R));
@@ -605,8 +612,10 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   HIP_TRY(fms::launch_fill_labels(c.st, c.b, c.max_pixels));
   if (c.b.max_n > 0)
     HIP_TRY(fms::launch_compact(c.st, c.b, c.dp, h->blk.as<int>(), h->fg_idx.as<int>(), h->x32.as<float>(),
-                                h->x32t.as<float>(), c.bf16 ? h->x16.as<uint16_t>() : nullptr,
-                                c.bf16 ? h->x16t.as<uint16_t>() : nullptr, h->enorm.as<float>()));
+                                h->x32t.as<float>(), c.form != fms::FORM_FP32 ? h->x16.as<uint16_t>() : nullptr,
+                                c.form != fms::FORM_FP32 ? h->x16t.as<uint16_t>() : nullptr,
+                                c.form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr,
+                                c.form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr, h->enorm.as<float>()));
   return FMS_OK;
 }
 
@@ -649,14 +658,18 @@ hipError_t run_graph(fms_handle h, hipStream_t st, const IterKey& key, Record&& 
 // frame.  extra: steps a frame goes on after its first step that saw more
 // than gamma converged (IterCtl::extra).  On return h->hm(f) holds every
 // frame's counters.
-fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double gamma, int max_iter, bool bf16,
+fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double gamma, int max_iter, int form,
                           bool timing, const int* seed_fg, bool nsel_from_rt, int extra = 0) {
   const fms::Batch& b = c.b;
+  const bool bf16 = form != fms::FORM_FP32;  // a BF16 MFMA step
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
   const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+  const uint16_t* xrl = form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr;
+  const uint16_t* xtl = form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr;
   const int pk = bf16 ? 1 : 0;
-  // The BF16 form keeps the last centres of each trajectory for the replay.
-  float* ring = bf16 && c.ring_len > 0 ? h->ring.as<float>() : nullptr;
+  // The plain BF16 form keeps the last centres of each trajectory for the
+  // replay.
+  float* ring = form == fms::FORM_BF16 && c.ring_len > 0 ? h->ring.as<float>() : nullptr;
   HIP_TRY(fms::launch_round_begin(c.st, b, cap, nsel_from_rt, h->active.as<int>(), h->state.as<uint8_t>(),
                                   h->iters.as<int>(), seed_fg, h->x32.as<float>(), c.dp, ybuf));
   int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
@@ -673,7 +686,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   auto iterate_on = [&](hipStream_t st, const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     const fms::IterCtl ctl{-1, it, gamma, extra};
     const float* yin = it == 0 ? ybuf : yc[it & 1];
-    hipError_t e = fms::launch_shift(st, b, bf16, c.dp, tl, xrm, xt, yin, nullptr, ctl, cap,
+    hipError_t e = fms::launch_shift(st, b, form, c.dp, tl, xrm, xt, xrl, xtl, yin, nullptr, ctl, cap,
                                      h->partial.as<float>(), e0, e1);
     if (e == hipSuccess)
       e = fms::launch_reduce(st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
@@ -688,12 +701,12 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   auto iterate_graph = [&](const fms::Tiling& tl, int t0, int n) -> hipError_t {
     IterKey k;
     const void* ptrs[] = {xrm, xt, ybuf, yc[0], yc[1], lists[0], lists[1], h->partial.p, h->state.p, h->iters.p,
-                          b.geo, b.rt, b.meta, b.meta64, ring};
+                          b.geo, b.rt, b.meta, b.meta64, ring, xrl};
     std::memcpy(k.ptr, ptrs, sizeof(ptrs));
     // The kernels see the iteration's parity and whether it starts the round;
     // with extra steps the early stop also counts from absolute iterations.
     const int64_t it_key = extra > 0 ? t0 : (t0 & 1) + 2 * (t0 == 0);
-    const int64_t vals[] = {bf16, c.dp, tl.group_seeds, tl.target_items, tl.max_chunks, tl.waves, cap, n,
+    const int64_t vals[] = {form, c.dp, tl.group_seeds, tl.target_items, tl.max_chunks, tl.waves, cap, n,
                             it_key, b.F, b.max_n, b.max_blocks, b.max_mblk, c.ring_stride, c.ring_len, extra};
     std::memcpy(k.val, vals, sizeof(vals));
     k.gamma = gamma;
@@ -709,7 +722,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
     const int nb = std::min(kSched[std::min(nbatch, 2)], max_iter - t);
     ++nbatch;
     if (timing) HIP_TRY(h->ensure_events(2 * size_t(nb)));
-    const fms::Tiling& tl = pick_tiling(c, bf16, bound);
+    const fms::Tiling& tl = pick_tiling(c, form, bound);
     if (c.graphs) {
       HIP_TRY(iterate_graph(tl, t, nb));
       t += nb;
@@ -784,7 +797,7 @@ fms_status run_replay(fms_handle h, Call& c, int cap, double gamma, bool timing)
   HIP_TRY(fms::launch_replay_begin(c.st, b, c.dp, c.ring_len, h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->ring.as<float>(), c.ring_stride, h->cand.as<int>(), h->yr.as<float>(),
                                    h->active.as<int>(), h->rstate.as<uint8_t>(), h->riters.as<int>()));
-  const fms::Tiling& tl = pick_tiling(c, false, cap);
+  const fms::Tiling& tl = pick_tiling(c, fms::FORM_FP32, cap);
   int* lists[2] = {h->active.as<int>(), h->next_active.as<int>()};
   float* yc[2] = {h->yc0.as<float>(), h->yc1.as<float>()};
   float* yr = h->yr.as<float>();
@@ -797,7 +810,8 @@ fms_status run_replay(fms_handle h, Call& c, int cap, double gamma, bool timing)
     const float* yin = it == 0 ? yr : yc[it & 1];
     // Step it reads its centres in list order (in place through the identity
     // list at it = 0, then the rows the previous reduction compacted).
-    HIP_TRY(fms::launch_shift(c.st, b, false, c.dp, tl, h->x32.p, h->x32t.p, yin, nullptr, ctl, cap,
+    HIP_TRY(fms::launch_shift(c.st, b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, nullptr, yin, nullptr,
+                              ctl, cap,
                               h->partial.as<float>(), timing ? h->events[2 * it] : nullptr,
                               timing ? h->events[2 * it + 1] : nullptr));
     HIP_TRY(fms::launch_reduce(c.st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], yr,
@@ -916,7 +930,7 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NCAND, false, nc));
   int* counts = h->bits.as<int>();
   uint32_t* bits = reinterpret_cast<uint32_t*>(h->bits.as<uint8_t>() + nb_n);
-  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, nc), h->x32.p, h->y.as<float>(),
+  HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, nc), h->x32.as<float>(), h->y.as<float>(),
                             h->cand.as<int>(), nc, h->pcount.as<int>(), counts, META_NCAND));
   HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nc,
                               h->modes.as<float>(), k, bits, META_NCAND, META_NCAND));
@@ -1003,7 +1017,7 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     FMS_TRY(upload_rt(h, c));
     HIP_TRY(fms::launch_select(c.st, c.b, h->order.as<int>(), h->elig.as<uint8_t>(), h->seed_pos.as<int>(),
                                h->seed_fg.as<int>()));
-    FMS_TRY(run_iterations(h, c, h->y.as<float>(), cap, p->gamma, p->max_iter, c.bf16, timing, h->seed_fg.as<int>(),
+    FMS_TRY(run_iterations(h, c, h->y.as<float>(), cap, p->gamma, p->max_iter, c.form, timing, h->seed_fg.as<int>(),
                            false, replay_extra(c)));
     // BF16 form: the converged seeds' last iterations again in FP32 and the
     // early stop taken on their FP32 step counts, so that everything from
@@ -1029,7 +1043,7 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
       // accepted before.
       // Counts at every slot of the round (the list is the identity); the
       // ranking keeps the converged ones.
-      HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, cap), h->x32.p, h->y.as<float>(),
+      HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, cap), h->x32.as<float>(), h->y.as<float>(),
                                 nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
       // The candidate list buffer is free in a round: it holds each
       // candidate's first word with an earlier conflict for the greedy pass.
@@ -1138,6 +1152,9 @@ fms_status begin_call(fms_handle h, void* stream, int32_t n_frames, const fms_fr
   c.dim = dim;
   c.dp = pad_dim(dim);
   c.bf16 = p->precision == FMS_PREC_BF16_REFINE;
+  c.form = p->precision == FMS_PREC_BF16_REFINE ? fms::FORM_BF16
+           : p->precision == FMS_PREC_BF16_SPLIT ? fms::FORM_SPLIT
+                                                  : fms::FORM_FP32;
   c.graphs = p->graphs != 0 && p->timing == 0;
   c.ring_len = c.bf16 ? p->refine_iters : 0;
   set_tiling(c, p);
@@ -1328,7 +1345,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   if (h->hm(0)[META_BAD] != 0) return FMS_ERR_BAD_INPUT;
   if (h->hm(0)[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
   const bool timing = p->timing != 0;
-  FMS_TRY(run_iterations(h, c, h->y.as<float>(), m, p->gamma, p->max_iter, c.bf16, timing, nullptr, true,
+  FMS_TRY(run_iterations(h, c, h->y.as<float>(), m, p->gamma, p->max_iter, c.form, timing, nullptr, true,
                          replay_extra(c)));
   fh.sx.iterations_total = h->hm(0)[META_STEPS];
   fh.sx.seed_pixel_updates = int64_t(h->hm64(0, 1));
@@ -1347,7 +1364,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.rt.nact = m;
   FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(c.st, c.b, false, c.dp, count_tiling(c, false, m), h->x32.p, h->y.as<float>(),
+  HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, m), h->x32.as<float>(), h->y.as<float>(),
                             h->ident.as<int>(), m, h->pcount.as<int>(), h->counts.as<int>(), -1));
   HIP_TRY(fms::launch_lockstep_out(c.st, m, c.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
@@ -1393,9 +1410,10 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
   const int mmax = ms.back();
   auto m_of = [&](int f, int m) { return std::min(m, c.fr[f].g.n); };
   if (!batch) FMS_TRY(ensure_centres(h, c, mmax));
-  // Candidates of each form: every compiled (group, items, waves) shape.
-  std::vector<bool> forms{c.bf16};
-  if (c.bf16) forms.push_back(false);
+  // Candidates of each step form the precision runs (the plain BF16 form's
+  // replay runs FP32 steps): every compiled (group, items, waves) shape.
+  std::vector<int> forms{c.form};
+  if (c.form == fms::FORM_BF16 && c.ring_len > 0) forms.push_back(fms::FORM_FP32);
   std::vector<std::vector<fms::Tiling>> cand(forms.size());
   for (size_t fi = 0; fi < forms.size(); ++fi) {
     for (int gs : {16, 32, 64, 128})
@@ -1435,9 +1453,12 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
   // One warm-up, then the mean of kReps (fused step, reduction) pairs (two
   // for a batch, whose launches are long).
   const int kReps = batch ? 2 : 6;
-  auto time_one = [&](const fms::Tiling& t, bool bf16, int m, float* us) -> fms_status {
+  auto time_one = [&](const fms::Tiling& t, int form, int m, float* us) -> fms_status {
+    const bool bf16 = form != fms::FORM_FP32;
     const void* xrm = bf16 ? h->x16.p : h->x32.p;
     const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+    const uint16_t* xrl = form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr;
+    const uint16_t* xtl = form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr;
     for (int f = 0; f < n_frames; ++f) {
       const int64_t r0 = c.fr[f].g.row0;
       HIP_TRY(fms::launch_init_seeds(c.st, ident + r0, batch ? m_of(f, m) : m, c.fr[f].g.n,
@@ -1447,8 +1468,8 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
     const fms::IterCtl ctl{-1, -1, 1.0};
     for (int r = 0; r <= kReps; ++r) {
       if (r == 1) HIP_TRY(hipEventRecord(h->events[0], c.st));
-      HIP_TRY(fms::launch_shift(c.st, c.b, bf16, c.dp, t, xrm, xt, y, ident, ctl, m, h->partial.as<float>(), nullptr,
-                                nullptr));
+      HIP_TRY(fms::launch_shift(c.st, c.b, form, c.dp, t, xrm, xt, xrl, xtl, y, ident, ctl, m,
+                                h->partial.as<float>(), nullptr, nullptr));
       HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, t, h->partial.as<float>(), ident, y, h->state.as<uint8_t>(),
                                  h->iters.as<int>(), nullptr, nullptr, ctl, m, 1));
     }
@@ -1461,7 +1482,7 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
   };
   std::vector<TunedTiling> found;
   for (size_t fi = 0; fi < forms.size(); ++fi) {
-    const bool bf16 = forms[fi];
+    const int form = forms[fi];
     for (int m : ms) {
       for (int f = 0; f < n_frames; ++f) {
         c.fr[f].rt = fms::RoundTab{};
@@ -1469,24 +1490,26 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
       }
       FMS_TRY(upload_rt(h, c));
       float us_def = 0.f;
-      FMS_TRY(time_one(pick_tiling(c, bf16, m), bf16, m, &us_def));
+      FMS_TRY(time_one(pick_tiling(c, form, m), form, m, &us_def));
       TunedTiling best{};
       bool have = false;
       for (const fms::Tiling& t : cand[fi]) {
         float us = 0.f;
-        FMS_TRY(time_one(t, bf16, m, &us));
+        FMS_TRY(time_one(t, form, m, &us));
         if (!have || us < best.e.us_per_step) {
           have = true;
           best.t = t;
           best.e.us_per_step = us;
         }
       }
-      best.bf16 = bf16;
+      best.form = form;
       best.batch = batch;
       best.dp = c.dp;
       best.nb = c.nb;
       best.m = m;
-      best.e.precision = bf16 ? FMS_PREC_BF16_REFINE : FMS_PREC_FP32;
+      best.e.precision = form == fms::FORM_BF16 ? FMS_PREC_BF16_REFINE
+                         : form == fms::FORM_SPLIT ? FMS_PREC_BF16_SPLIT
+                                                   : FMS_PREC_FP32;
       best.e.dim_padded = c.dp;
       best.e.n_fg = n;
       best.e.seeds = m;
@@ -1503,7 +1526,7 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
   for (const TunedTiling& t : h->tuned) {
     bool same = false;
     for (const TunedTiling& u : found)
-      same = same || (t.bf16 == u.bf16 && t.batch == u.batch && t.dp == u.dp && t.nb == u.nb);
+      same = same || (t.form == u.form && t.batch == u.batch && t.dp == u.dp && t.nb == u.nb);
     if (!same) without.push_back(t);
   }
   with = without;
@@ -1588,13 +1611,13 @@ fms_status fms_unroll(fms_handle h, void* stream, const float* emb, int64_t pixe
   if (h->hm(0)[META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
   // `steps` plain FP32 steps (no freezing, no early stop); y_{T-1} is kept
   // and the last step also reports |V_T|.
-  const fms::Tiling& tl = pick_tiling(c, false, m);
+  const fms::Tiling& tl = pick_tiling(c, fms::FORM_FP32, m);
   const fms::IterCtl ctl{-1, -1, 1.0};
   float* y = h->y.as<float>();
   for (int t = 0; t < steps; ++t) {
     if (t + 1 == steps) HIP_TRY(fms::launch_rows_out(c.st, m, c.dp, dim, y, y_prev));
-    HIP_TRY(fms::launch_shift(c.st, c.b, false, c.dp, tl, h->x32.p, h->x32t.p, y, h->ident.as<int>(), ctl, m,
-                              h->partial.as<float>()));
+    HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, nullptr, y,
+                              h->ident.as<int>(), ctl, m, h->partial.as<float>()));
     HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, tl, h->partial.as<float>(), h->ident.as<int>(), y,
                                h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, nullptr, ctl, m, 1,
                                t + 1 == steps ? v_norm : nullptr));

@@ -46,9 +46,12 @@ struct Tiling {
   int max_chunks;
   int waves;  // waves per work group: 4, 8 or 16
 };
-// The tiling used for a (precision, padded D) pair given the caller's
+// Arithmetic of a fused step: FP32 MFMA; BF16 MFMA on BF16 values; BF16 MFMA
+// on values split into high and low BF16 parts (see k_shift).
+enum StepForm { FORM_FP32 = 0, FORM_BF16 = 1, FORM_SPLIT = 2 };
+// The tiling used for a (step form, padded D) pair given the caller's
 // requests (0 = default); group sizes round down to a compiled one.
-Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks, int want_waves);
+Tiling make_tiling(int form, int dp, int want_seeds, int want_items, int want_chunks, int want_waves);
 struct ChunkPlan {
   int groups;
   int n_chunks;
@@ -118,9 +121,11 @@ __host__ __device__ inline int64_t elig_len(int n) { return ((int64_t)n + 15) / 
 // rows [n, n_pad) of every layout (n = meta[META_N] of the frame).
 hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts);
 hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts);
-// enorm (may be null) receives each row's raw norm |e_i|.
+// x16 / x16t (may be null) receive the BF16 rounding of each value, xlo /
+// xlot (may be null; only with x16) the BF16 rounding of what that leaves
+// (split form).  enorm (may be null) receives each row's raw norm |e_i|.
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, float* enorm);
+                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm);
 
 // order[j] = foreground ordinal at seed-order position j; rank = its
 // inverse.  Also sets every eligibility flag of the frame (1 for j < n, 0
@@ -174,9 +179,13 @@ struct IterCtl {
 // receive the start and end of the kernel itself (hipExtLaunchKernel), not
 // of the launch call.
 size_t shift_partial_rows(const Tiling& t, int cap);
-hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
-                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap,
-                        float* partial, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// form: StepForm; xrm / xt: the row and transposed layouts of that form's
+// values (FP32 or the BF16 high parts), xrl / xtl: the low parts (split form
+// only, else null).
+hipError_t launch_shift(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
+                        const void* xt, const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                        const IterCtl& ctl, int cap, float* partial, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 // Sum partials, renormalise, convergence test and (mode 0) the next active
 // list and converged count.  yc_next (mode 0, may be null) receives the new
 // rows of the seeds that stay active, in next-list order.  Mode 1 is a plain
@@ -192,11 +201,10 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
                          const float* ycur = nullptr, float* ring = nullptr, int64_t ring_stride = 0,
                          int ring_len = 0);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
-// frame, on FP32 MFMA (xrm = the FP32 rows) or BF16 MFMA (bf16: xrm = the
-// BF16 rows; the centres are rounded to BF16).  The frame's count is
+// frame, on FP32 MFMA (x32 = the FP32 rows).  The frame's count is
 // meta[m_slot], or rt.nact when m_slot < 0.
-hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
-                        const float* y, const int* list, int m, int* pcount, int* counts, int m_slot);
+hipError_t launch_count(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* x32, const float* y,
+                        const int* list, int m, int* pcount, int* counts, int m_slot);
 // Similarity bits of rows y[rows[j]], j < meta[rows_slot] (m bounds it):
 // against columns y[cols[c]], c < meta[cols_slot] (ncols bounds it; bits at
 // rt.bits_c0, row stride rt.words_c) when cols is given, and against the

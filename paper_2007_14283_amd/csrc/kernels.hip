@@ -40,6 +40,11 @@ __device__ __forceinline__ uint32_t fbits(float f) { return __builtin_bit_cast(u
 __device__ __forceinline__ uint16_t to_bf16_bits(float f) {
   return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
+// Low BF16 part of f given its high part (bits hi): round(f - hi).  With the
+// high part, it holds f to a relative 2^-16.
+__device__ __forceinline__ uint16_t low_bf16_bits(float f, uint16_t hi) {
+  return to_bf16_bits(f - __uint_as_float((uint32_t)hi << 16));
+}
 
 __device__ __forceinline__ float wave_sum_f(float v, int width) {
   for (int m = width >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -134,6 +139,7 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
                                                  const int* __restrict__ block_offsets, int* __restrict__ fg_idx,
                                                  float* __restrict__ x32, float* __restrict__ x32t,
                                                  uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
+                                                 uint16_t* __restrict__ xlo, uint16_t* __restrict__ xlot,
                                                  float* __restrict__ enorm, int* __restrict__ meta) {
   constexpr int KD = DP / 8;  // dimensions per lane
   __shared__ int sh[5];
@@ -149,6 +155,10 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   if (x16) {
     x16 += gf.row0 * DP;
     x16t += gf.row0 * DP;
+  }
+  if (xlo) {
+    xlo += gf.row0 * DP;
+    xlot += gf.row0 * DP;
   }
   meta += (int64_t)blockIdx.y * META_COUNT;
   const int64_t blk0 = (int64_t)blockIdx.x * kMaskBlockPix;
@@ -241,6 +251,19 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
       x16t[(blk * DP + d + 1) * kBlockPix + qq] = b1;
       x16t[(blk * DP + d + 2) * kBlockPix + qq] = b2;
       x16t[(blk * DP + d + 3) * kBlockPix + qq] = b3;
+      if (!xlo) continue;
+      // Low parts: the BF16 rounding of what the high part leaves.
+      const uint16_t l0 = low_bf16_bits(v4.x, b0), l1 = low_bf16_bits(v4.y, b1), l2 = low_bf16_bits(v4.z, b2),
+                     l3 = low_bf16_bits(v4.w, b3);
+      uint16_t* rowl = xlo + (int64_t)ord * DP + d;
+      rowl[0] = l0;
+      rowl[1] = l1;
+      rowl[2] = l2;
+      rowl[3] = l3;
+      xlot[(blk * DP + d + 0) * kBlockPix + qq] = l0;
+      xlot[(blk * DP + d + 1) * kBlockPix + qq] = l1;
+      xlot[(blk * DP + d + 2) * kBlockPix + qq] = l2;
+      xlot[(blk * DP + d + 3) * kBlockPix + qq] = l3;
     }
   }
   bad = wave_sum_i(bad);
@@ -259,6 +282,10 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
       if (x16) {
         x16[row * DP + d] = 0;
         x16t[(blk * DP + d) * kBlockPix + q] = 0;
+      }
+      if (xlo) {
+        xlo[row * DP + d] = 0;
+        xlot[(blk * DP + d) * kBlockPix + q] = 0;
       }
     }
   }
@@ -449,11 +476,20 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 // FP32 accumulation; the 0/1 weights of two pixels are packed into one BF16
 // pair with one v_perm_b32 (sign bytes) and one bit-select.
 //
+// SPLIT form (with BF16): every value v -- pixel vectors and centres -- is
+// held as a high and a low BF16 part, hi = bf16(v), lo = bf16(v - hi), which
+// together keep v to a relative 2^-16.  S^T takes three products per tile
+// (hi.hi + hi.lo + lo.hi; lo.lo is below 2^-16) and V^T two (the 0/1 weights
+// are exact in BF16), all on BF16 MFMA with FP32 accumulation: a similarity
+// is off by at most 3 * 2^-16 (under 5e-5) for unit vectors, against 2^-8 for
+// the plain BF16 form.
+//
 // COUNT form: the same S^T tiles, no second product; each item writes the
 // per-seed number of its pixels inside the window (window counts at the
 // centres, used to rank candidate modes).
-template <bool BF16, bool COUNT, int DP, int ST, int WV>
+template <bool BF16, bool SPLIT, bool COUNT, int DP, int ST, int WV>
 __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
+                                           const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xtl,
                                            const float* __restrict__ y, const int* __restrict__ active, int n_act,
                                            const Tiling& tl, int n_blocks, int n_pix, float thr,
                                            float* __restrict__ partial, int* __restrict__ pcount, int wg, int nwg) {
@@ -488,18 +524,27 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     // computes.
     AOp xa[2][2][KS];
     AOp xv[2][NDB][BF16 ? 1 : 8];
+    // Low parts of the split form (unused otherwise).
+    bf16x8 xal[2][2][SPLIT ? KS : 1];
+    bf16x8 xvl[2][SPLIT ? NDB : 1];
     auto load = [&](int buf, int b) {
       if constexpr (BF16) {
-        const uint16_t* xb = reinterpret_cast<const uint16_t*>(xrm) + (int64_t)b * kBlockPix * DP;
+        const int64_t o = (int64_t)b * kBlockPix * DP;
+        const uint16_t* xb = reinterpret_cast<const uint16_t*>(xrm) + o;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int j = 0; j < KS; ++j)
+          for (int j = 0; j < KS; ++j) {
             xa[buf][t][j] = *reinterpret_cast<const bf16x8*>(xb + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
+            if constexpr (SPLIT)
+              xal[buf][t][j] = *reinterpret_cast<const bf16x8*>(xrl + o + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
+          }
 #pragma unroll
-        for (int db = 0; db < (COUNT ? 0 : NDB); ++db)
-          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) +
-                                                            ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g);
+        for (int db = 0; db < (COUNT ? 0 : NDB); ++db) {
+          const int64_t ot = ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g;
+          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) + ot);
+          if constexpr (SPLIT) xvl[buf][db] = *reinterpret_cast<const bf16x8*>(xtl + ot);
+        }
       } else {
         const float* xb = reinterpret_cast<const float*>(xrm) + (int64_t)b * kBlockPix * DP;
 #pragma unroll
@@ -529,8 +574,9 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     int b = b0 + wave;
     if (b < b1) load(0, b);
     const int a0 = grp * 16 * ST;
-    // Seed operands (B of S^T = X Y^T).
+    // Seed operands (B of S^T = X Y^T); low parts for the split form.
     AOp yb[ST][KS];
+    bf16x8 ybl[ST][SPLIT ? KS : 1];
 #pragma unroll
     for (int s = 0; s < ST; ++s) {
       const int a = a0 + 16 * s + r;
@@ -541,8 +587,15 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         for (int j = 0; j < KS; ++j) {
           float4 u = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
           float4 v = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
-          yb[s][j] = bf16x8{(__bf16)u.x, (__bf16)u.y, (__bf16)u.z, (__bf16)u.w,
-                            (__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+          const float e[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+          __bf16 hi[8], lo[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            hi[i] = (__bf16)e[i];
+            lo[i] = (__bf16)(e[i] - (float)hi[i]);
+          }
+          yb[s][j] = bf16x8{hi[0], hi[1], hi[2], hi[3], hi[4], hi[5], hi[6], hi[7]};
+          if constexpr (SPLIT) ybl[s][j] = bf16x8{lo[0], lo[1], lo[2], lo[3], lo[4], lo[5], lo[6], lo[7]};
         }
       } else {
 #pragma unroll
@@ -571,6 +624,13 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
           if constexpr (BF16) {
+            if constexpr (SPLIT) {
+              // Small cross terms first, then the main product.
+              s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xal[buf][0][j], yb[s][j], s0, 0, 0, 0);
+              s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xal[buf][1][j], yb[s][j], s1, 0, 0, 0);
+              s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][0][j], ybl[s][j], s0, 0, 0, 0);
+              s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][1][j], ybl[s][j], s1, 0, 0, 0);
+            }
             s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][0][j], yb[s][j], s0, 0, 0, 0);
             s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[buf][1][j], yb[s][j], s1, 0, 0, 0);
           } else {
@@ -600,8 +660,11 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
           u32x4 wp = {~m0 & one2, ~m1 & one2, ~m2 & one2, ~m3 & one2};
           const bf16x8 w = __builtin_bit_cast(bf16x8, wp);
 #pragma unroll
-          for (int db = 0; db < NDB; ++db)
+          for (int db = 0; db < NDB; ++db) {
+            if constexpr (SPLIT)
+              acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xvl[buf][db], w, acc[s][db], 0, 0, 0);
             acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[buf][db][0], w, acc[s][db], 0, 0, 0);
+          }
         } else {
           float w[8];
 #pragma unroll
@@ -686,8 +749,9 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   }
 }
 
-template <bool BF16, bool COUNT, int DP, int ST, int WV>
+template <bool BF16, bool SPLIT, bool COUNT, int DP, int ST, int WV>
 __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restrict__ xrm_, const void* __restrict__ xt_,
+                                               const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xtl,
                                                const float* __restrict__ y, const int* __restrict__ active,
                                                IterCtl ctl, Tiling tl, float* __restrict__ partial,
                                                int* __restrict__ pcount) {
@@ -697,6 +761,10 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
   int* meta = bt.meta + (int64_t)f * META_COUNT;
   const T* xrm = static_cast<const T*>(xrm_) + g.row0 * DP;
   const T* xt = xt_ ? static_cast<const T*>(xt_) + g.row0 * DP : nullptr;
+  if (SPLIT) {
+    xrl += g.row0 * DP;
+    xtl += g.row0 * DP;
+  }
   y += g.row0 * DP;
   if (active) active += g.row0;
   if (partial) partial += g.part0 * DP;
@@ -728,8 +796,8 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   if (n_act <= 0) return;
-  shift_body<BF16, COUNT, DP, ST, WV>(xrm, xt, y, active, n_act, tl, g.n_blocks, g.n, g.thr, partial, pcount,
-                                  (int)blockIdx.x, (int)gridDim.x);
+  shift_body<BF16, SPLIT, COUNT, DP, ST, WV>(xrm, xt, xrl, xtl, y, active, n_act, tl, g.n_blocks, g.n, g.thr,
+                                             partial, pcount, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Sum the chunk partials of each active seed in a fixed order, renormalise,
@@ -1761,21 +1829,22 @@ hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts) 
 }
 
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, float* enorm) {
+                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm) {
+  if (xlo && !x16) return hipErrorInvalidValue;
   if (b.max_mblk <= 0) return hipSuccess;
   const dim3 grid((unsigned)b.max_mblk, b.F);
   switch (dp) {
     case 32:
       hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         enorm, b.meta);
+                         xlo, xlot, enorm, b.meta);
       break;
     case 64:
       hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         enorm, b.meta);
+                         xlo, xlot, enorm, b.meta);
       break;
     case 128:
       hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         enorm, b.meta);
+                         xlo, xlot, enorm, b.meta);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1824,28 +1893,30 @@ StepGeom make_geom(int n) {
 
 // Seed groups of the fused step: enough seeds per pixel read to keep the loads
 // well below the matrix-core rate, few enough registers for several waves per
-// SIMD.  Compiled group sizes per (precision, padded D):
-//   FP32: D 32 -> 16, 32, 64; D 64 -> 16, 32; D 128 -> 16.
-//   BF16: D 32 -> 32, 64, 128; D 64 -> 16, 32, 64; D 128 -> 16, 32.
+// SIMD.  Compiled group sizes per (form, padded D):
+//   FP32:       D 32 -> 16, 32, 64; D 64 -> 16, 32; D 128 -> 16.
+//   BF16:       D 32 -> 32, 64, 128; D 64 -> 16, 32, 64; D 128 -> 16, 32.
+//   split BF16: D 32 -> 32, 64; D 64 -> 16, 32; D 128 -> 16.
 // Fused-step shapes compiled with WV waves per group.  Four waves: every
 // shape.  Eight or sixteen: DP = 32 only, where a wave's operands fit the
 // registers a wave of a 512- or 1024-lane group may hold without scratch (FP32
-// groups of more than 16 seeds do not at sixteen waves), and the wave tree's
-// LDS (WV/2 slots of ST x DP/16 accumulator tiles of 1 KiB) fits in 64 KiB.
-constexpr bool shift_shape_ok(bool bf16, bool count, int dp, int st, int wv) {
+// groups of more than 16 seeds do not at sixteen waves, nor split-BF16 groups
+// of any size), and the wave tree's LDS (WV/2 slots of ST x DP/16 accumulator
+// tiles of 1 KiB) fits in 64 KiB.
+constexpr bool shift_shape_ok(int form, bool count, int dp, int st, int wv) {
   if (wv == 4) return true;
   if ((wv != 8 && wv != 16) || dp != 32) return false;
-  if (wv == 16 && !bf16 && st >= 2) return false;
+  if (wv == 16 && (form == FORM_SPLIT || (form == FORM_FP32 && st >= 2))) return false;
   return count || (wv / 2) * st * (dp / 16) * 1024 <= 65536;
 }
 
-static int max_group(bool bf16, int dp) {
-  if (bf16) return dp <= 32 ? 128 : (dp <= 64 ? 64 : 32);
+static int max_group(int form, int dp) {
+  if (form == FORM_BF16) return dp <= 32 ? 128 : (dp <= 64 ? 64 : 32);
   return dp <= 32 ? 64 : (dp <= 64 ? 32 : 16);
 }
-static int min_group(bool bf16, int dp) { return (bf16 && dp <= 32) ? 32 : 16; }
+static int min_group(int form, int dp) { return (form != FORM_FP32 && dp <= 32) ? 32 : 16; }
 
-Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_chunks, int want_waves) {
+Tiling make_tiling(int form, int dp, int want_seeds, int want_items, int want_chunks, int want_waves) {
   Tiling t;
   // Defaults from sweeps on the 512x512, D = 32 frame and the 64-frame batch:
   // 32-seed groups (larger ones for many centres, chosen by the caller), four
@@ -1853,14 +1924,14 @@ Tiling make_tiling(bool bf16, int dp, int want_seeds, int want_items, int want_c
   // kWaveBudget / waves items, <= 256 chunks.
   int def = dp <= 64 ? 32 : 16;
   int g = want_seeds > 0 ? want_seeds : def;
-  int gs = min_group(bf16, dp);
-  while (gs * 2 <= g && gs * 2 <= max_group(bf16, dp)) gs *= 2;
+  int gs = min_group(form, dp);
+  while (gs * 2 <= g && gs * 2 <= max_group(form, dp)) gs *= 2;
   t.group_seeds = gs;
   t.max_chunks = want_chunks > 0 ? std::max(1, std::min(want_chunks, 4096)) : kMaxChunks;
   // Waves per group: 4, 8 or 16, halved until the shape is compiled.
   int wv = want_waves > 0 ? want_waves : kWaves;
   wv = wv >= 16 ? 16 : (wv >= 8 ? 8 : 4);
-  while (wv > 4 && !shift_shape_ok(bf16, false, dp, gs / 16, wv)) wv /= 2;
+  while (wv > 4 && !shift_shape_ok(form, false, dp, gs / 16, wv)) wv /= 2;
   t.waves = wv;
   t.target_items = want_items > 0 ? std::max(8, std::min(want_items, 1 << 16)) : kWaveBudget / wv;
   return t;
@@ -1884,72 +1955,90 @@ static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
   return grid < 8 ? 8 : grid;
 }
 
-template <bool BFV, bool CNT, int DPV, int STV, int WV>
+template <int FORM, bool CNT, int DPV, int STV, int WV>
 static hipError_t shift_launch_one(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
-                                   const float* y, const int* active, const IterCtl& ctl, const Tiling& t,
-                                   float* partial, int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
-  if constexpr (!shift_shape_ok(BFV, CNT, DPV, STV, WV)) {
+                                   const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                                   const IterCtl& ctl, const Tiling& t, float* partial, int* pcount, hipEvent_t ev0,
+                                   hipEvent_t ev1) {
+  if constexpr (!shift_shape_ok(FORM, CNT, DPV, STV, WV)) {
     return hipErrorInvalidValue;
   } else {
+    constexpr bool BFV = FORM != FORM_FP32, SPV = FORM == FORM_SPLIT;
     if (ev0 || ev1)
-      hipExtLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, ev0, ev1, 0, b, xrm, xt, y,
-                            active, ctl, t, partial, pcount);
+      hipExtLaunchKernelGGL((k_shift<BFV, SPV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, ev0, ev1, 0, b, xrm, xt,
+                            xrl, xtl, y, active, ctl, t, partial, pcount);
     else
-      hipLaunchKernelGGL((k_shift<BFV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, b, xrm, xt, y, active, ctl, t,
-                         partial, pcount);
+      hipLaunchKernelGGL((k_shift<BFV, SPV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, b, xrm, xt, xrl, xtl, y,
+                         active, ctl, t, partial, pcount);
     return hipGetLastError();
   }
 }
 
-template <bool BFV, bool CNT, int DPV, int STV>
+template <int FORM, bool CNT, int DPV, int STV>
 static hipError_t shift_launch_waves(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
-                                     const float* y, const int* active, const IterCtl& ctl, const Tiling& t,
-                                     float* partial, int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
+                                     const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                                     const IterCtl& ctl, const Tiling& t, float* partial, int* pcount, hipEvent_t ev0,
+                                     hipEvent_t ev1) {
   switch (t.waves) {
-    case 4: return shift_launch_one<BFV, CNT, DPV, STV, 4>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
-    case 8: return shift_launch_one<BFV, CNT, DPV, STV, 8>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
-    case 16: return shift_launch_one<BFV, CNT, DPV, STV, 16>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, ev1);
+    case 4:
+      return shift_launch_one<FORM, CNT, DPV, STV, 4>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+                                                      pcount, ev0, ev1);
+    case 8:
+      return shift_launch_one<FORM, CNT, DPV, STV, 8>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+                                                      pcount, ev0, ev1);
+    case 16:
+      return shift_launch_one<FORM, CNT, DPV, STV, 16>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+                                                       pcount, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
-static hipError_t shift_dispatch(hipStream_t s, const Batch& b, bool bf16, bool count, int dp, const Tiling& t,
-                                 const void* xrm, const void* xt, const float* y, const int* active,
-                                 const IterCtl& ctl, int cap, float* partial, int* pcount, hipEvent_t ev0,
-                                 hipEvent_t ev1) {
+static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool count, int dp, const Tiling& t,
+                                 const void* xrm, const void* xt, const uint16_t* xrl, const uint16_t* xtl,
+                                 const float* y, const int* active, const IterCtl& ctl, int cap, float* partial,
+                                 int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
   if (cap <= 0 || b.max_blocks <= 0) {
     // Nothing to launch; the events still mark this point of the stream.
     hipError_t e = ev0 ? hipEventRecord(ev0, s) : hipSuccess;
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
   }
+  if (form == FORM_SPLIT && (!xrl || !xtl)) return hipErrorInvalidValue;
   const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
-  const int key = (bf16 ? 1000000 : 0) + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
-// Every (precision, padded D, seed tiles per group) shape is compiled in both
-// forms, the step and the window count.
-#define FMS_SHIFT_SHAPES(X)                                                                            \
-  X(false, 32, 1) X(false, 32, 2) X(false, 32, 4) X(false, 64, 1) X(false, 64, 2) X(false, 128, 1)   \
-  X(true, 32, 2) X(true, 32, 4) X(true, 32, 8) X(true, 64, 1) X(true, 64, 2) X(true, 64, 4)           \
-  X(true, 128, 1) X(true, 128, 2)
-#define FMS_SHIFT_CASE(BFV, DPV, STV)                                                                  \
-  case (BFV ? 1000000 : 0) + DPV * 100 + STV:                                                          \
-    return shift_launch_waves<BFV, false, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, \
-                                                    ev1);                                              \
-  case (BFV ? 1000000 : 0) + 100000 + DPV * 100 + STV:                                                 \
-    return shift_launch_waves<BFV, true, DPV, STV>(s, grid, b, xrm, xt, y, active, ctl, t, partial, pcount, ev0, \
-                                                   ev1);
+  const int key = form * 1000000 + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
+// Fused steps: every (form, padded D, seed tiles per group) shape above.
+// Window counts (FP32 only: every form counts its endpoints in FP32).
+#define FMS_SHIFT_SHAPES(X)                                                                                   \
+  X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) X(FORM_FP32, 64, 2)        \
+  X(FORM_FP32, 128, 1) X(FORM_BF16, 32, 2) X(FORM_BF16, 32, 4) X(FORM_BF16, 32, 8) X(FORM_BF16, 64, 1)      \
+  X(FORM_BF16, 64, 2) X(FORM_BF16, 64, 4) X(FORM_BF16, 128, 1) X(FORM_BF16, 128, 2) X(FORM_SPLIT, 32, 2)    \
+  X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
+#define FMS_COUNT_SHAPES(X) X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) \
+  X(FORM_FP32, 64, 2) X(FORM_FP32, 128, 1)
+#define FMS_SHIFT_CASE(FV, DPV, STV)                                                                          \
+  case FV * 1000000 + DPV * 100 + STV:                                                                        \
+    return shift_launch_waves<FV, false, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial, \
+                                                   pcount, ev0, ev1);
+#define FMS_COUNT_CASE(FV, DPV, STV)                                                                          \
+  case FV * 1000000 + 100000 + DPV * 100 + STV:                                                               \
+    return shift_launch_waves<FV, true, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,  \
+                                                  pcount, ev0, ev1);
   switch (key) {
     FMS_SHIFT_SHAPES(FMS_SHIFT_CASE)
+    FMS_COUNT_SHAPES(FMS_COUNT_CASE)
     default: return hipErrorInvalidValue;
   }
 #undef FMS_SHIFT_CASE
+#undef FMS_COUNT_CASE
 #undef FMS_SHIFT_SHAPES
+#undef FMS_COUNT_SHAPES
 }
 
-hipError_t launch_shift(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
-                        const void* xt, const float* y, const int* active, const IterCtl& ctl, int cap,
-                        float* partial, hipEvent_t ev0, hipEvent_t ev1) {
-  return shift_dispatch(s, b, bf16, false, dp, t, xrm, xt, y, active, ctl, cap, partial, nullptr, ev0, ev1);
+hipError_t launch_shift(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
+                        const void* xt, const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                        const IterCtl& ctl, int cap, float* partial, hipEvent_t ev0, hipEvent_t ev1) {
+  return shift_dispatch(s, b, form, false, dp, t, xrm, xt, xrl, xtl, y, active, ctl, cap, partial, nullptr, ev0,
+                        ev1);
 }
 
 hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* partial,
@@ -1978,12 +2067,12 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
   return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t s, const Batch& b, bool bf16, int dp, const Tiling& t, const void* xrm,
-                        const float* y, const int* list, int m, int* pcount, int* counts, int m_slot) {
+hipError_t launch_count(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* x32, const float* y,
+                        const int* list, int m, int* pcount, int* counts, int m_slot) {
   if (m <= 0 || b.max_blocks <= 0) return hipSuccess;
   const IterCtl ctl{m_slot, -1, 0.0};
-  hipError_t e = shift_dispatch(s, b, bf16, true, dp, t, xrm, nullptr, y, list, ctl, m, nullptr, pcount, nullptr,
-                                nullptr);
+  hipError_t e = shift_dispatch(s, b, FORM_FP32, true, dp, t, x32, nullptr, nullptr, nullptr, y, list, ctl, m, nullptr,
+                                pcount, nullptr, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4), b.F), dim3(256), 0, s, b, pcount, t, m_slot, counts);
   return hipGetLastError();

@@ -66,9 +66,10 @@ def test_batch_bandwidths_differ(frames):
     assert len({f.bandwidth for f in frames}) >= 2
 
 
-def test_batch_fp32_matches_oracle(F, frames, oracles):
-    _say("batch fp32", [f.spec for f in frames])
-    res = F.cluster_batch(_inputs(frames), precision=F.FP32)
+@pytest.mark.parametrize("precision", ["fp32", "split"])
+def test_batch_fp32_matches_oracle(F, frames, oracles, precision):
+    _say("batch", precision, [f.spec for f in frames])
+    res = F.cluster_batch(_inputs(frames), precision=F.FP32 if precision == "fp32" else F.BF16_SPLIT)
     assert len(res) == len(frames)
     for f, o, (modes, labels, st) in zip(frames, oracles, res):
         mm = parity.match_modes(modes.cpu().numpy(), o.modes)
@@ -125,11 +126,12 @@ def golden():
     return g, fr
 
 
-def test_batch_workload_frames_fp32(F, golden):
+@pytest.mark.parametrize("precision", ["fp32", "split"])
+def test_batch_workload_frames_fp32(F, golden, precision):
     g, fr = golden
     idx = sorted(g)
-    _say("batch workload frames fp32", idx)
-    res = F.cluster_batch(_inputs([fr[i] for i in idx]), precision=F.FP32)
+    _say("batch workload frames", precision, idx)
+    res = F.cluster_batch(_inputs([fr[i] for i in idx]), precision=F.FP32 if precision == "fp32" else F.BF16_SPLIT)
     for i, (modes, labels, st) in zip(idx, res):
         o, f = g[i], fr[i]
         fg = np.flatnonzero(f.mask.reshape(-1))

@@ -85,10 +85,14 @@ def test_seed_order_matches_oracle(F, n, seed):
 
 # ------------------------------------------------------------------ lockstep
 
+def _prec(F, precision):
+    return {"fp32": F.FP32, "bf16": F.BF16_REFINE, "split": F.BF16_SPLIT}[precision]
+
+
 def _lockstep_compare(F, torch, spec, seeds, precision, tol_mode):
     f = _frame(spec)
     emb, mask = _dev(torch, f)
-    prec = F.FP32 if precision == "fp32" else F.BF16_REFINE
+    prec = _prec(F, precision)
     _say("lockstep", spec, len(seeds), precision)
     g = F.shift_seeds(emb, mask, seeds, bandwidth=f.bandwidth, precision=prec)
     o = C.lockstep(f.emb, f.mask, seeds, C.Params(bandwidth=f.bandwidth))
@@ -102,12 +106,15 @@ def _lockstep_compare(F, torch, spec, seeds, precision, tol_mode):
     return f, g, o, ge, gi, gc, gn, risky, both, err
 
 
+# The split BF16 form keeps similarities within 5e-5 of FP64, inside the same
+# exempt band, so it is held to the FP32 bar.
+@pytest.mark.parametrize("precision", ["fp32", "split"])
 @pytest.mark.parametrize("spec,m", [(synth.MID, 128), (synth.MID, 333), (synth.TINY, 200)])
-def test_lockstep_fp32(F, torch_mod, spec, m):
+def test_lockstep_fp32(F, torch_mod, spec, m, precision):
     rng = np.random.Generator(np.random.PCG64(1000 + m))
     n = _frame(spec).n_fg
     seeds = rng.choice(n, size=m, replace=False).astype(np.int32)
-    f, g, o, ge, gi, gc, gn, risky, both, err = _lockstep_compare(F, torch_mod, spec, seeds, "fp32", FP32_TOL)
+    f, g, o, ge, gi, gc, gn, risky, both, err = _lockstep_compare(F, torch_mod, spec, seeds, precision, FP32_TOL)
     safe = ~risky
     print(f"risky seeds {risky.sum()} / {m}; max err {err.max() if len(err) else 0:.3e}")
     np.testing.assert_array_equal(gc[safe], o["converged"][safe])
@@ -160,7 +167,7 @@ def _cluster_compare(F, torch, spec, precision="fp32", layout="nhwc", **kw):
     emb, mask = _dev(torch, f)
     if layout == "nchw":
         emb = emb.permute(2, 0, 1).contiguous()
-    prec = F.FP32 if precision == "fp32" else F.BF16_REFINE
+    prec = _prec(F, precision)
     _say("cluster", spec, precision, layout, kw)
     modes, labels, st = F.cluster(emb, mask, f.bandwidth, layout=layout, precision=prec, **kw)
     res = _oracle(spec, **kw)
@@ -171,9 +178,10 @@ def _cluster_compare(F, torch, spec, precision="fp32", layout="nhwc", **kw):
     return f, modes, labels, st, res, mm, lc
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split"])
 @pytest.mark.parametrize("spec,layout", [(synth.TINY, "nhwc"), (synth.MID, "nhwc"), (synth.MID, "nchw")])
-def test_cluster_fp32_matches_oracle(F, torch_mod, spec, layout):
-    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32", layout)
+def test_cluster_fp32_matches_oracle(F, torch_mod, spec, layout, precision):
+    f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, precision, layout)
     assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
     assert mm.max_error <= FP32_TOL
     assert lc.mismatched == 0
@@ -214,10 +222,11 @@ def _host_prune_case(torch):
     return f, g, emb, mask, np.flatnonzero(f.mask.reshape(-1))
 
 
-def test_host_pruning_path_fp32(F, torch_mod):
+@pytest.mark.parametrize("precision", ["fp32", "split"])
+def test_host_pruning_path_fp32(F, torch_mod, precision):
     f, g, emb, mask, fg = _host_prune_case(torch_mod)
-    _say("host pruning fp32", f.n_fg, "n_state_in", g["n_state_in"])
-    modes, labels, st = F.cluster(emb, mask, f.bandwidth, n_state_in=g["n_state_in"])
+    _say("host pruning", precision, f.n_fg, "n_state_in", g["n_state_in"])
+    modes, labels, st = F.cluster(emb, mask, f.bandwidth, n_state_in=g["n_state_in"], precision=_prec(F, precision))
     assert f.n_fg > 16384 and st["seeds_used"] >= 20000
     mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
     lc = parity.compare_labels_fg(labels.cpu().numpy(), fg, g["fg_labels"], g["band"], g["tie"], mm)
@@ -262,11 +271,11 @@ def test_cluster_bf16_refine_matches_oracle(F, torch_mod):
     assert st["refine_steps"] >= 2
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split"])
 def test_cluster_full_512_frame(F, torch_mod, precision):
     # The 512 x 512, D = 32, 100-cell frame the benchmark times.
     f, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, synth.PLAIN512, precision)
-    if precision == "fp32":
+    if precision != "bf16":
         assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
         assert mm.max_error <= FP32_TOL
         assert lc.mismatched == 0
@@ -313,12 +322,13 @@ def test_single_pixel_and_identical_vectors(F, torch_mod):
     assert st["iterations_total"] == 1
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split"])
 @pytest.mark.parametrize("dim", [2, 3, 16, 18, 33, 64, 100, 128])
-def test_cluster_dims(F, torch_mod, dim):
+def test_cluster_dims(F, torch_mod, dim, precision):
     spec = synth.FrameSpec(64, 80, 8, 5, 12, dim, 0.02 if dim > 8 else 0.005, 0.05, dim)
     f = synth.make_frame(spec)
     _FRAMES[spec] = f
-    fr, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, "fp32")
+    fr, modes, labels, st, res, mm, lc = _cluster_compare(F, torch_mod, spec, precision)
     assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0
     assert mm.max_error <= FP32_TOL
     assert lc.mismatched == 0

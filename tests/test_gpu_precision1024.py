@@ -44,10 +44,11 @@ def _run(F, f, prec):
     return F.cluster(emb, mask, f.bandwidth, precision=prec)
 
 
-def test_precision1024_fp32(F, case):
+@pytest.mark.parametrize("precision", ["fp32", "split"])
+def test_precision1024_fp32(F, case, precision):
     f, g, fg = case
-    _say("1024x1024 fp32", f.n_fg)
-    modes, labels, st = _run(F, f, F.FP32)
+    _say("1024x1024", precision, f.n_fg)
+    modes, labels, st = _run(F, f, F.FP32 if precision == "fp32" else F.BF16_SPLIT)
     mm = parity.match_modes(modes.cpu().numpy(), g["modes"])
     lc = parity.compare_labels_fg(labels.cpu().numpy(), fg, g["fg_labels"], g["band"], g["tie"], mm)
     print(f"modes {len(modes)}/{len(g['modes'])} max err {mm.max_error:.2e} labels {lc}")

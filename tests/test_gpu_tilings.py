@@ -41,7 +41,7 @@ def _check(F, f, res, prec, **kw):
     mask = torch.from_numpy(f.mask).cuda()
     modes, labels, st = F.cluster(emb, mask, f.bandwidth, precision=prec, **kw)
     mm = parity.match_modes(modes.cpu().numpy(), res.modes)
-    if prec == F.FP32:
+    if prec in (F.FP32, F.BF16_SPLIT):
         lc = parity.compare_labels(labels.cpu().numpy(), res, mm, 1.0 - f.bandwidth)
         assert mm.unmatched_gpu == 0 and mm.unmatched_oracle == 0, kw
         assert mm.max_error <= FP32_TOL, kw
@@ -54,12 +54,16 @@ def _check(F, f, res, prec, **kw):
             {k: v for k, v in kw.items() if k.startswith("tile_")})
 
 
+def _prec(F, precision):
+    return {"fp32": F.FP32, "bf16": F.BF16_REFINE, "split": F.BF16_SPLIT}[precision]
+
+
 @pytest.mark.parametrize("dim", [32, 64, 128])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split"])
 def test_every_decomposition(F, dim, precision):
     spec = synth.FrameSpec(64, 80, 8, 5, 12, dim, 0.02, 0.05, 11 + dim)
     f, res = _case(spec)
-    prec = F.FP32 if precision == "fp32" else F.BF16_REFINE
+    prec = _prec(F, precision)
     for seeds in (16, 32, 64, 128):
         for waves in (4, 8, 16):
             for items in (256, 1024):
@@ -67,10 +71,10 @@ def test_every_decomposition(F, dim, precision):
                 _check(F, f, res, prec, tile_seeds=seeds, tile_waves=waves, tile_items=items)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split"])
 def test_large_rounds_take_wide_groups(F, precision):
     # A first round of 4096 seeds: the default decomposition switches to
-    # 64-seed (FP32) and 128-seed (BF16) groups for these launches.
+    # 64-seed (FP32, split BF16) and 128-seed (BF16) groups for these launches.
     f, res = _case(synth.MID, n_initial=4096)
     _say("wide groups", precision, f.n_fg)
-    _check(F, f, res, F.FP32 if precision == "fp32" else F.BF16_REFINE, n_initial=4096)
+    _check(F, f, res, _prec(F, precision), n_initial=4096)
