@@ -250,6 +250,40 @@ fms_status fms_shift_seeds(fms_handle h, void* stream,
                            float* endpoints, int32_t* iters, uint8_t* converged,
                            int32_t* counts, fms_stats* stats);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fms_shift_seeds, FP32
+ * form, with every buffer of its work -- the compacted frame, the centres and
+ * their lists, the chunk partials, the window counts, the counters and the
+ * frame tables -- in one fixed device array per GPU (about 38 MiB, held from
+ * the library's first use on that GPU until the process ends), never in
+ * memory it allocates.  The handle supplies only its GPU and its mapped
+ * counter area (both set up by fms_create); its tuning table is not used.
+ *
+ * Arguments, outputs and results are those of fms_shift_seeds with
+ * p->precision = FMS_PREC_FP32 (same kernels and work decomposition, so the
+ * same endpoints, step counts, flags and window counts).  stats: n_fg,
+ * seeds_used, iterations_total, seed_pixel_updates and n_discarded are
+ * filled, the rest zero (n_min NaN).
+ *
+ * Limits (beyond them FMS_ERR_UNSUPPORTED, nothing written to the outputs):
+ * height * width <= 1,048,576; foreground pixels <= 131,072 (counted on the
+ * GPU: past it the frame's rows are not kept, the outputs' contents are
+ * unspecified and the call returns FMS_ERR_UNSUPPORTED at its end); n_seeds <=
+ * 4096; dim <= 32; precision FP32 and timing 0; tiling requests whose chunk
+ * partials exceed 32,768 rows.
+ *
+ * Every call on a GPU uses that GPU's one array, whatever the handle: calls
+ * that overlap on one GPU (several host threads, or streams that run
+ * concurrently) race and their results are undefined; the array keeps the
+ * last call's contents, and each call writes everything it reads first.
+ * Errors: as fms_shift_seeds, plus FMS_ERR_UNSUPPORTED for the limits above. */
+fms_status fms_shift_seeds_noalloc(fms_handle h, void* stream,
+                                   const float* emb, int64_t pixel_stride, int64_t channel_stride,
+                                   const uint8_t* mask, int32_t height, int32_t width, int32_t dim,
+                                   const int32_t* seed_fg, int32_t n_seeds, const fms_params* p,
+                                   float* endpoints, int32_t* iters, uint8_t* converged,
+                                   int32_t* counts, fms_stats* stats);
+
 /* Differentiable form: `steps` (T >= 1) unrolled FP32 steps of Eq. 8-11 from
  * the given seeds, every seed taking all T steps (no freezing, no early
  * stop), for training an embedding network through the clustering.

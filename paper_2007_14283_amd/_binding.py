@@ -20,7 +20,7 @@ FMS_PREC_BF16_SPLIT = 2
 
 # Every entry point declared in include/fms.h.
 EXPORTS = ("fms_default_params", "fms_create", "fms_destroy", "fms_cluster", "fms_cluster_batch",
-           "fms_shift_seeds", "fms_unroll", "fms_unroll_backward", "fms_autotune", "fms_autotune_batch",
+           "fms_shift_seeds", "fms_shift_seeds_noalloc", "fms_unroll", "fms_unroll_backward", "fms_autotune", "fms_autotune_batch",
            "fms_clear_tuning",
            "fms_seed_order", "fms_status_string")
 
@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     lib.fms_shift_seeds.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, vp, i32,
                                     ctypes.POINTER(FmsParams), vp, vp, vp, vp, ctypes.POINTER(FmsStats)]
     lib.fms_shift_seeds.restype = ctypes.c_int
+    lib.fms_shift_seeds_noalloc.argtypes = lib.fms_shift_seeds.argtypes
+    lib.fms_shift_seeds_noalloc.restype = ctypes.c_int
     f64 = ctypes.c_double
     lib.fms_unroll.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, i32, vp, i32, i32, f64, vp, vp, vp]
     lib.fms_unroll.restype = ctypes.c_int

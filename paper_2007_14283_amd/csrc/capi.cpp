@@ -192,6 +192,9 @@ struct CachedGraph {
 
 struct fms_handle_s {
   int device = 0;
+  // Device address of the no-allocation entry point's fixed buffer on this
+  // handle's GPU (hipGetSymbolAddress at fms_create).
+  unsigned char* na_scratch = nullptr;
   // Decompositions chosen by fms_autotune (empty: the library's defaults).
   std::vector<TunedTiling> tuned;
   // Pixel data of the call's frames; every row-indexed buffer holds frame f
@@ -1202,6 +1205,172 @@ fms_frame frame_of(const float* emb, int64_t ps, int64_t cs, const uint8_t* mask
   return f;
 }
 
+// ------------------------------------------------------------------ no-allocation lockstep
+//
+// fms_shift_seeds_noalloc runs fms_shift_seeds' FP32 path on one fixed
+// device array per GPU instead of the handle's growable workspace: the
+// frame's layouts, the centres and their lists, the chunk partials, the
+// window counts, the counters and the frame tables all live in `scratch`.
+// Capacity: H * W <= kNaMaxPixels, foreground <= kNaMaxFg, seeds <=
+// kNaMaxSeeds, D <= 32, chunk partials <= kNaPartialRows rows.
+constexpr int64_t kNaMaxPixels = int64_t(1) << 20;
+constexpr int kNaMaxFg = 1 << 17;
+constexpr int kNaMaxSeeds = 4096;
+constexpr int kNaDp = 32;
+constexpr int64_t kNaPartialRows = 32768;
+constexpr int kNaCentreRows = kNaMaxSeeds + fms::kBlockPix;
+
+constexpr size_t na_align(size_t b) { return (b + 255) / 256 * 256; }
+// Byte offsets of the regions of `scratch`.
+struct NaLayout {
+  static constexpr size_t blk = 0;
+  static constexpr size_t fg_idx = blk + na_align(sizeof(int) * size_t(kNaMaxPixels / fms::kMaskBlockPix));
+  static constexpr size_t x32 = fg_idx + na_align(sizeof(int) * size_t(kNaMaxFg));
+  static constexpr size_t x32t = x32 + na_align(sizeof(float) * size_t(kNaMaxFg) * kNaDp);
+  static constexpr size_t y = x32t + na_align(sizeof(float) * size_t(kNaMaxFg) * kNaDp);
+  static constexpr size_t yc0 = y + na_align(sizeof(float) * size_t(kNaCentreRows) * kNaDp);
+  static constexpr size_t yc1 = yc0 + na_align(sizeof(float) * size_t(kNaCentreRows) * kNaDp);
+  static constexpr size_t active = yc1 + na_align(sizeof(float) * size_t(kNaCentreRows) * kNaDp);
+  static constexpr size_t next_active = active + na_align(sizeof(int) * size_t(kNaCentreRows));
+  static constexpr size_t iters = next_active + na_align(sizeof(int) * size_t(kNaCentreRows));
+  static constexpr size_t ident = iters + na_align(sizeof(int) * size_t(kNaCentreRows));
+  static constexpr size_t counts = ident + na_align(sizeof(int) * size_t(kNaCentreRows));
+  static constexpr size_t state = counts + na_align(sizeof(int) * size_t(kNaCentreRows));
+  static constexpr size_t pcount = state + na_align(size_t(kNaCentreRows));
+  static constexpr size_t partial = pcount + na_align(sizeof(int) * size_t(kNaPartialRows));
+  static constexpr size_t meta = partial + na_align(sizeof(float) * size_t(kNaPartialRows) * kNaDp);
+  static constexpr size_t geo = meta + na_align(sizeof(int) * META_COUNT + sizeof(unsigned long long) * fms::kMeta64);
+  static constexpr size_t rt = geo + na_align(sizeof(fms::FrameGeo));
+  static constexpr size_t bytes = rt + na_align(sizeof(fms::RoundTab));
+};
+
+}  // namespace
+
+// The fixed buffer of fms_shift_seeds_noalloc (about 38 MiB), one copy per
+// GPU for the life of the process.  Host code never uses this name as an
+// address: fms_create looks up each GPU's copy with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[NaLayout::bytes];
+
+namespace {
+
+fms_status shift_seeds_noalloc(fms_handle h, void* stream, const float* emb, int64_t pixel_stride,
+                               int64_t channel_stride, const uint8_t* mask, int32_t height, int32_t width,
+                               int32_t dim, const int32_t* seed_fg, int32_t n_seeds, const fms_params* p,
+                               float* endpoints, int32_t* iters, uint8_t* converged, int32_t* counts,
+                               fms_stats* stats) {
+  if (!h || !p) return FMS_ERR_INVALID_ARG;
+  if (n_seeds < 0 || (n_seeds > 0 && (!seed_fg || !endpoints || !iters || !converged))) return FMS_ERR_INVALID_ARG;
+  FMS_TRY(check_params(p));
+  const fms_frame fr = frame_of(emb, pixel_stride, channel_stride, mask, height, width, p->bandwidth, 0, nullptr);
+  FMS_TRY(check_frame(fr, dim));
+  if (p->precision != FMS_PREC_FP32 || p->timing != 0) return FMS_ERR_UNSUPPORTED;
+  const int64_t P = int64_t(height) * int64_t(width);
+  if (dim > kNaDp || P > kNaMaxPixels || n_seeds > kNaMaxSeeds) return FMS_ERR_UNSUPPORTED;
+  if (!h->na_scratch || !h->dpub || h->hpub.cap < 16 + meta_bytes(1)) return FMS_ERR_HIP;
+  DeviceGuard guard(h->device);
+  Call c;
+  c.st = static_cast<hipStream_t>(stream);
+  c.F = 1;
+  c.dim = dim;
+  c.dp = kNaDp;
+  c.form = fms::FORM_FP32;
+  set_tiling(c, p);  // the handle's tuning table is not used
+  const int m = n_seeds;
+  // Chunk partials of the FP32 tilings the steps and the window counts take.
+  if (m > 0 && int64_t(std::max(fms::shift_partial_rows(c.tile_fp32, m),
+                                fms::shift_partial_rows(c.tile_fp32_big, m))) > kNaPartialRows)
+    return FMS_ERR_UNSUPPORTED;
+  unsigned char* base = h->na_scratch;
+  int* blk = reinterpret_cast<int*>(base + NaLayout::blk);
+  int* fg_idx = reinterpret_cast<int*>(base + NaLayout::fg_idx);
+  float* x32 = reinterpret_cast<float*>(base + NaLayout::x32);
+  float* x32t = reinterpret_cast<float*>(base + NaLayout::x32t);
+  float* y = reinterpret_cast<float*>(base + NaLayout::y);
+  float* yc[2] = {reinterpret_cast<float*>(base + NaLayout::yc0), reinterpret_cast<float*>(base + NaLayout::yc1)};
+  int* lists[2] = {reinterpret_cast<int*>(base + NaLayout::active), reinterpret_cast<int*>(base + NaLayout::next_active)};
+  int* its = reinterpret_cast<int*>(base + NaLayout::iters);
+  int* ident = reinterpret_cast<int*>(base + NaLayout::ident);
+  int* cnt = reinterpret_cast<int*>(base + NaLayout::counts);
+  uint8_t* state = base + NaLayout::state;
+  int* pcount = reinterpret_cast<int*>(base + NaLayout::pcount);
+  float* partial = reinterpret_cast<float*>(base + NaLayout::partial);
+  int* meta = reinterpret_cast<int*>(base + NaLayout::meta);
+  auto* geo = reinterpret_cast<fms::FrameGeo*>(base + NaLayout::geo);
+  auto* rtab = reinterpret_cast<fms::RoundTab*>(base + NaLayout::rt);
+  c.b.F = 1;
+  c.b.geo = geo;
+  c.b.rt = rtab;
+  c.b.meta = meta;
+  c.b.meta64 = reinterpret_cast<unsigned long long*>(meta + META_COUNT);
+  c.b.max_n = kNaMaxFg;
+  c.b.max_blocks = kNaMaxFg / fms::kBlockPix;
+  c.b.max_mblk = (P + fms::kMaskBlockPix - 1) / fms::kMaskBlockPix;
+  c.fr.assign(1, FrameHost{});
+  fms::FrameGeo g{};
+  g.desc = fms::FrameDesc{emb, pixel_stride, channel_stride, mask, P, dim, kNaDp};
+  g.thr = float(1.0 - p->bandwidth);
+  g.tol = float(tol_of(p, p->bandwidth));
+  fms::RoundTab rt{};
+  rt.nact = m;
+  // Tables and counters, compaction (rows beyond the capacity are neither
+  // written nor used), seeds, the round's start.
+  HIP_TRY(fms::launch_set_tables(c.st, g, rt, geo, rtab, meta, c.b.meta64));
+  HIP_TRY(fms::launch_mask_count(c.st, c.b, blk));
+  HIP_TRY(fms::launch_scan_blocks(c.st, c.b, blk));
+  HIP_TRY(fms::launch_compact(c.st, c.b, kNaDp, blk, fg_idx, x32, x32t, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              kNaMaxFg));
+  HIP_TRY(fms::launch_geo_from_count(c.st, c.b, kNaMaxFg));
+  if (m > 0) {
+    HIP_TRY(fms::launch_init_seeds(c.st, seed_fg, m, -1, x32, kNaDp, y, meta));
+    HIP_TRY(fms::launch_round_begin(c.st, c.b, m, true, lists[0], state, its, nullptr, x32, kNaDp, y));
+    // The iteration (Alg. 2, the parallel seed loop; Sec. 3.2.1 and 3.2.3),
+    // enqueued in batches with a read of the counters between them.
+    static constexpr int kSched[] = {3, 6, 8};
+    int t = 0, nbatch = 0, bound = m;
+    while (t < p->max_iter) {
+      const int nb = std::min(kSched[std::min(nbatch, 2)], p->max_iter - t);
+      ++nbatch;
+      const fms::Tiling& tl = pick_tiling(c, fms::FORM_FP32, bound);
+      for (int i = 0; i < nb; ++i, ++t) {
+        const fms::IterCtl ctl{-1, t, p->gamma, 0};
+        const float* yin = t == 0 ? y : yc[t & 1];
+        HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, kNaDp, tl, x32, x32t, nullptr, nullptr, yin, nullptr,
+                                  ctl, m, partial));
+        HIP_TRY(fms::launch_reduce(c.st, c.b, kNaDp, tl, partial, lists[t & 1], y, state, its, lists[(t + 1) & 1],
+                                   yc[(t + 1) & 1], ctl, m, 0, nullptr, yin));
+      }
+      FMS_TRY(read_meta(h, c));
+      const int* hm = h->hm(0);
+      const bool over = double(hm[META_NCONV]) > p->gamma * double(hm[META_NSEL]);
+      if (hm[fms::META_DONE] || hm[fms::META_ACT + (t & 1)] <= 0 || over) break;
+      bound = hm[fms::META_ACT + (t & 1)];
+    }
+    // Window counts at every slot (kept for the converged seeds), outputs.
+    HIP_TRY(fms::launch_iota(c.st, c.b, ident, m));
+    HIP_TRY(fms::launch_count(c.st, c.b, kNaDp, count_tiling(c, m), x32, y, ident, m, pcount, cnt, -1));
+    HIP_TRY(fms::launch_lockstep_out(c.st, m, kNaDp, dim, y, state, its, cnt, endpoints, iters, converged, counts));
+  }
+  FMS_TRY(read_meta(h, c));
+  const int* hm = h->hm(0);
+  if (hm[fms::META_OVERCAP] != 0) return FMS_ERR_UNSUPPORTED;
+  if (hm[META_N] == 0 && m > 0) return FMS_ERR_INVALID_ARG;
+  if (hm[fms::META_BAD] != 0) return FMS_ERR_BAD_INPUT;
+  if (hm[fms::META_BADSEED] != 0) return FMS_ERR_INVALID_ARG;
+  if (stats) {
+    fms_stats& sx = stats[0];
+    std::memset(&sx, 0, sizeof(sx));
+    sx.n_min = std::numeric_limits<double>::quiet_NaN();
+    sx.n_fg = hm[META_N];
+    sx.seeds_used = m;
+    if (m > 0) {
+      sx.iterations_total = hm[META_STEPS];
+      sx.seed_pixel_updates = int64_t(h->hm64(0, 1));
+      sx.n_discarded = m - hm[META_NCONV];
+    }
+  }
+  return FMS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1250,6 +1419,16 @@ fms_status fms_create(fms_handle* out, int32_t device_ordinal) {
     fms_destroy(h);
     return FMS_ERR_HIP;
   }
+  // This GPU's copy of the no-allocation entry point's buffer, and the mapped
+  // counter area every call reads (sized for one frame here, so that entry
+  // point never allocates).
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp ||
+      h->ensure_pub(16 + meta_bytes(1)) != hipSuccess) {
+    fms_destroy(h);
+    return FMS_ERR_HIP;
+  }
+  h->na_scratch = static_cast<unsigned char*>(sp);
   *out = h;
   return FMS_OK;
 }
@@ -1373,6 +1552,15 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.sx.n_discarded = m - nc;
   fill_stats(c, stats);
   return FMS_OK;
+}
+
+fms_status fms_shift_seeds_noalloc(fms_handle h, void* stream, const float* emb, int64_t pixel_stride,
+                                   int64_t channel_stride, const uint8_t* mask, int32_t height, int32_t width,
+                                   int32_t dim, const int32_t* seed_fg, int32_t n_seeds, const fms_params* p,
+                                   float* endpoints, int32_t* iters, uint8_t* converged, int32_t* counts,
+                                   fms_stats* stats) {
+  return shift_seeds_noalloc(h, stream, emb, pixel_stride, channel_stride, mask, height, width, dim, seed_fg, n_seeds,
+                             p, endpoints, iters, converged, counts, stats);
 }
 
 // The tuner of fms_autotune (one frame) and fms_autotune_batch (several

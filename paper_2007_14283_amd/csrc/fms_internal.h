@@ -25,6 +25,7 @@ enum MetaSlot {
   META_STEPS = 12,     // iterations run this round
   META_NACC = 13,      // modes being refined / modes accepted by the last pruning pass
   META_NCAND = 14,     // converged candidates of the round
+  META_OVERCAP = 15,   // foreground count beyond a fixed-capacity call's rows (0: within)
   META_ACT = 16,       // two slots (16, 17): active seeds of the even / odd iterations
   META_COUNT = 24
 };
@@ -124,8 +125,17 @@ hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts);
 // x16 / x16t (may be null) receive the BF16 rounding of each value, xlo /
 // xlot (may be null; only with x16) the BF16 rounding of what that leaves
 // (split form).  enorm (may be null) receives each row's raw norm |e_i|.
+// Rows at or beyond row_cap are not written (fixed-capacity calls).
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm);
+                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm,
+                          int64_t row_cap = INT64_MAX);
+// Single-frame calls on caller-independent fixed buffers: write the frame and
+// round tables from arguments and clear the counters (one work group); after
+// the mask scan, the foreground and block counts into the table (0 when the
+// count exceeds row_cap, which META_OVERCAP then holds).
+hipError_t launch_set_tables(hipStream_t s, const FrameGeo& g, const RoundTab& rt, FrameGeo* geo, RoundTab* rtab,
+                             int* meta, unsigned long long* meta64);
+hipError_t launch_geo_from_count(hipStream_t s, const Batch& b, int64_t row_cap);
 
 // order[j] = foreground ordinal at seed-order position j; rank = its
 // inverse.  Also sets every eligibility flag of the frame (1 for j < n, 0
@@ -138,7 +148,8 @@ hipError_t launch_seed_order_plain(hipStream_t s, int n, int half_bits, const ui
 // Each frame takes its round's rt.want seeds (one work group per frame).
 hipError_t launch_select(hipStream_t s, const Batch& b, const int* order, uint8_t* elig, int* seed_pos,
                          int* seed_fg);
-// Single frame: the given seeds' rows as the starting centres.
+// Single frame: the given seeds' rows as the starting centres (n < 0: the
+// foreground count from meta[META_N]).
 hipError_t launch_init_seeds(hipStream_t s, const int* seed_fg, int m, int n, const float* x32, int dp,
                              float* y, int* meta);
 // Start of a round's iteration (identity active list, counters) for at most

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
                                                  float* __restrict__ x32, float* __restrict__ x32t,
                                                  uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
                                                  uint16_t* __restrict__ xlo, uint16_t* __restrict__ xlot,
-                                                 float* __restrict__ enorm, int* __restrict__ meta) {
+                                                 float* __restrict__ enorm, int* __restrict__ meta, int64_t row_cap) {
   constexpr int KD = DP / 8;  // dimensions per lane
   __shared__ int sh[5];
   __shared__ int lp[kMaskBlockPix];
@@ -192,6 +192,7 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   for (int k = (int)threadIdx.x / 8; k < total; k += 32) {
     const int64_t p = blk0 + lp[k];
     const int ord = ord0 + k;
+    if (ord >= row_cap) break;  // beyond the layouts' rows (the caller reports it)
     const float* src = f.emb + p * f.pixel_stride;
     float v[KD];
     float mx = 0.f;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   if (bad) atomicAdd(meta + META_BAD, bad);
   // The rows from n up to the next multiple of 32 are padding: zero in every
   // layout, so they add nothing to any sum.
-  if (blockIdx.x == 0) {
+  if (blockIdx.x == 0 && meta[META_N] < row_cap) {
     const int n = meta[META_N];
     const int pad = (kBlockPix - n % kBlockPix) % kBlockPix;
     for (int e = threadIdx.x; e < pad * DP; e += 256) {
@@ -422,6 +423,7 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
                                                     float* __restrict__ y, int* __restrict__ meta) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= (int64_t)m * dp) return;
+  if (n < 0) n = meta[META_N];
   const int s = (int)(k / dp), d = (int)(k - (int64_t)s * dp);
   const int o = seed_fg[s];
   if (o < 0 || o >= n) {
@@ -432,6 +434,38 @@ __global__ __launch_bounds__(256) void k_init_seeds(const int* __restrict__ seed
   y[k] = x32[(int64_t)o * dp + d];
 }
 
+
+// Tables and counters of a single-frame call whose buffers the caller does
+// not allocate: the frame's table and round table are written from kernel
+// arguments (no host staging), and its counters are cleared with stores.
+__global__ __launch_bounds__(64) void k_set_tables(FrameGeo g, RoundTab rt, FrameGeo* __restrict__ geo,
+                                                  RoundTab* __restrict__ rtab, int* __restrict__ meta,
+                                                  unsigned long long* __restrict__ meta64) {
+  if (threadIdx.x == 0) {
+    *geo = g;
+    *rtab = rt;
+  }
+  for (int i = threadIdx.x; i < META_COUNT; i += 64) meta[i] = 0;
+  for (int i = threadIdx.x; i < kMeta64; i += 64) meta64[i] = 0ull;
+}
+
+// After the mask scan of such a call: the frame's foreground count and block
+// count into its table.  A count above row_cap (the rows the layouts hold)
+// leaves the frame empty for every later kernel: the table and META_N take
+// 0 and META_OVERCAP the count.
+__global__ __launch_bounds__(64) void k_geo_from_count(Batch bt, int64_t row_cap) {
+  if (threadIdx.x != 0) return;
+  FrameGeo* g = const_cast<FrameGeo*>(bt.geo);
+  int* meta = bt.meta;
+  const int n = meta[META_N];
+  const int m = n <= row_cap ? n : 0;
+  if (m != n) {
+    meta[META_OVERCAP] = n;
+    meta[META_N] = 0;
+  }
+  g->n = m;
+  g->n_blocks = (m + kBlockPix - 1) / kBlockPix;
+}
 
 // ------------------------------------------------------------------ fused step
 
@@ -1829,22 +1863,23 @@ hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts) 
 }
 
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm) {
+                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm,
+                          int64_t row_cap) {
   if (xlo && !x16) return hipErrorInvalidValue;
   if (b.max_mblk <= 0) return hipSuccess;
   const dim3 grid((unsigned)b.max_mblk, b.F);
   switch (dp) {
     case 32:
       hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta);
+                         xlo, xlot, enorm, b.meta, row_cap);
       break;
     case 64:
       hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta);
+                         xlo, xlot, enorm, b.meta, row_cap);
       break;
     case 128:
       hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta);
+                         xlo, xlot, enorm, b.meta, row_cap);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1870,6 +1905,17 @@ hipError_t launch_seed_order_plain(hipStream_t s, int n, int half_bits, const ui
 hipError_t launch_select(hipStream_t s, const Batch& b, const int* order, uint8_t* elig, int* seed_pos,
                          int* seed_fg) {
   hipLaunchKernelGGL(k_select, dim3(b.F), dim3(1024), 0, s, b.geo, b.rt, order, elig, b.meta, seed_pos, seed_fg);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_tables(hipStream_t s, const FrameGeo& g, const RoundTab& rt, FrameGeo* geo, RoundTab* rtab,
+                             int* meta, unsigned long long* meta64) {
+  hipLaunchKernelGGL(k_set_tables, dim3(1), dim3(64), 0, s, g, rt, geo, rtab, meta, meta64);
+  return hipGetLastError();
+}
+
+hipError_t launch_geo_from_count(hipStream_t s, const Batch& b, int64_t row_cap) {
+  hipLaunchKernelGGL(k_geo_from_count, dim3(1), dim3(64), 0, s, b, row_cap);
   return hipGetLastError();
 }
 
