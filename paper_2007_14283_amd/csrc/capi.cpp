@@ -1442,7 +1442,8 @@ fms_status fms_destroy(fms_handle h) {
                     &h->active, &h->next_active, &h->state,  &h->iters,   &h->seed_pos,    &h->seed_fg,
                     &h->ident,  &h->cand,    &h->counts,     &h->sorted,  &h->scount,      &h->pcount,
                     &h->partial, &h->bits,   &h->acc,        &h->modes,   &h->mode_counts, &h->meta,
-                    &h->geo,     &h->rt,         &h->out_off, &h->enorm};
+                    &h->geo,     &h->rt,         &h->out_off, &h->enorm, &h->x16l, &h->x16lt,
+                    &h->ring,    &h->yr,         &h->rstate,  &h->riters};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
