@@ -9,7 +9,7 @@ and imports nothing from it.
 Modules
 -------
 seed_order  SplitMix64 and the Feistel permutation that fixes the seed order
-            (Alg. 2 "evenly random select", read as a keyed permutation).
+            (Alg. 2's uniform random seed draw, read as a keyed permutation).
 osop        Eq. 14, Eq. 15 and Eq. 19 and the seed-count controller (Sec. 3.2.2,
             Sec. 3.2.4).
 meanshift   Normalisation (Eq. 1), the flat-kernel cosine step (Eq. 8, 9, 11),

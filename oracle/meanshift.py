@@ -11,9 +11,10 @@ Definitions followed, with the readings used where the paper is loose:
   all vectors, sum_i k_h(y, x_i) x_i / sum_i k_h(y, x_i), which is Eq. 8's mean
   without a neighbour search (Sec. 3.2.1).  The centre is renormalised every
   step; the 1/m factor then cancels.
-* Sec. 3.2.1 convergence: "the change of the distance between two iterations"
-  below h/1000 is read as the cosine distance between consecutive centres,
-  delta = 1 - y_t . y_{t+1} < tol (strict); the seed stops at y_{t+1}.
+* Sec. 3.2.1 convergence: the paper stops a seed once its movement between
+  two iterations falls below h/1000; the movement is read as the cosine
+  distance between consecutive centres, delta = 1 - y_t . y_{t+1} < tol
+  (strict), and the seed stops at y_{t+1}.
 * Sec. 3.2.3 early stopping: a round of iterations ends once more than gamma of
   its seeds have converged; seeds still moving are discarded.
 * Alg. 2 "prune modes": greedy suppression.  Converged endpoints are visited by

@@ -1,6 +1,6 @@
 """Seed order (oracle side; test infrastructure only).
 
-Alg. 2 draws its seeds "evenly random" from the vector set.  Here the draw is a
+Alg. 2 draws its seeds uniformly at random from the vector set.  Here the draw is a
 keyed pseudo-random permutation ``pi`` of the foreground ordinals 0..n-1:
 position ``j`` of the seed order holds foreground ordinal ``pi(j)``.  A round
 takes the first positions whose pixels are still eligible.

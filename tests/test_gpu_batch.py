@@ -233,3 +233,22 @@ def test_many_small_frames_equal_single_calls(F):
     for f, (bm, bl, bst) in zip(frames, res):
         assert len(bm) >= 1 and bst["n_fg"] == f.n_fg
         assert int((bl >= 0).sum().item()) == f.n_fg
+
+
+def test_batch_round_above_device_ranking_is_unsupported(F, frames):
+    # A round of more than 16,384 seeds in one frame of a batch of two or
+    # more frames (the device ranking's limit; single-frame calls prune such
+    # rounds on the host) returns FMS_ERR_UNSUPPORTED.
+    from tests.golden import make_host_prune as mhp
+    from paper_2007_14283_amd import _binding as B
+    big = synth.make_frame(mhp.SPEC)
+    assert big.n_fg > 16384
+    inp = _inputs([frames[0], big])
+    inp[1]["n_state_in"] = 16385
+    _say("batch round above 16384 seeds")
+    with pytest.raises(F.FmsError) as ei:
+        F.cluster_batch(inp, precision=F.FP32)
+    assert ei.value.status == B.FMS_ERR_UNSUPPORTED
+    # The handle still works afterwards.
+    res = F.cluster_batch(_inputs(frames[:2]), precision=F.FP32)
+    assert len(res) == 2 and len(res[0][0]) >= 1

@@ -140,3 +140,29 @@ def test_unroll_rejects_bad_seed(F, frame512):
     with pytest.raises(F.FmsError):
         F.unroll(torch.from_numpy(emb).cuda(), torch.from_numpy(mask).cuda(),
                  torch.tensor([0, n], dtype=torch.int32), 2, frame512.bandwidth)
+
+
+def test_unroll_gradient_matches_finite_differences(F, frame512):
+    # The GPU gradient on the differentiation workload's crop against FP64
+    # central differences at 200 sampled coordinates (tests/golden/unroll_fd.npz,
+    # written from oracle/ alone and pinned in test_oracle_unroll.py): FP32
+    # against FP64, within 1e-4 of the largest difference plus 1e-3 relative.
+    import os
+
+    import torch
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "unroll_fd.npz"))
+    emb_np, mask_np = _crop(frame512)
+    fg = np.flatnonzero(mask_np.reshape(-1))
+    _say("unroll finite differences", len(fg), len(z["fd"]))
+    emb = torch.from_numpy(emb_np).cuda().requires_grad_(True)
+    mask = torch.from_numpy(mask_np).cuda()
+    y = F.unroll(emb, mask, torch.from_numpy(z["seeds"].astype(np.int32)), int(z["steps"]), float(z["bandwidth"]))
+    (y * torch.from_numpy(z["targets"]).float().cuda()).sum().backward()
+    g = emb.grad.detach().cpu().double().numpy().reshape(-1, emb_np.shape[-1])
+    rows, dims = z["coords"][:, 0], z["coords"][:, 1]
+    got = g[fg[rows], dims]
+    fd = z["fd"]
+    tol = 1e-4 * np.abs(fd).max() + 1e-3 * np.abs(fd)
+    print(f"max |gpu - fd| {np.abs(got - fd).max():.2e}, largest |fd| {np.abs(fd).max():.2e}")
+    assert np.count_nonzero(np.abs(fd) > 1e-3) >= 20
+    assert np.all(np.abs(got - fd) <= tol)

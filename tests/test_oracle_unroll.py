@@ -185,3 +185,18 @@ def test_gradient_matches_finite_differences_on_the_crop():
     got = ga[coords[:, 0], coords[:, 1]]
     assert np.count_nonzero(np.abs(gf) > 1e-3) >= 20  # many non-trivial entries
     np.testing.assert_allclose(got, gf, atol=1e-8, rtol=1e-5)
+
+
+def test_stored_finite_differences_match_the_oracle_gradient():
+    # tests/golden/unroll_fd.npz (the GPU test's reference) holds the crop
+    # case's seeds, targets and coordinates and FP64 differences that equal
+    # the oracle gradient there.
+    import os
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "unroll_fd.npz"))
+    e, seeds, h, steps, targets, coords = crop_case()
+    np.testing.assert_array_equal(z["seeds"], seeds)
+    np.testing.assert_array_equal(z["coords"], coords)
+    np.testing.assert_array_equal(z["targets"], targets)
+    assert float(z["bandwidth"]) == h and int(z["steps"]) == steps
+    ga = U.grad(e, seeds, h, steps, targets)
+    np.testing.assert_allclose(ga[coords[:, 0], coords[:, 1]], z["fd"], atol=1e-8, rtol=1e-5)
