@@ -382,10 +382,23 @@ const fms::Tiling& default_tiling(const Call& c, int form, int bound) {
   return bound >= kBigGroupMin ? c.tile_big : c.tile;
 }
 
-// Tiling of a window-count launch (FP32).  The autotuner times shift
-// launches only, so count launches keep the defaults (their integer counts
-// do not depend on the decomposition).
-const fms::Tiling& count_tiling(const Call& c, int bound) { return default_tiling(c, fms::FORM_FP32, bound); }
+// Arithmetic of the window counts: the split form counts in its own
+// arithmetic, the others in FP32.
+int count_form(const Call& c) { return c.form == fms::FORM_SPLIT ? fms::FORM_SPLIT : fms::FORM_FP32; }
+
+// Tiling of a window-count launch.  The autotuner times shift launches only,
+// so count launches keep the defaults (their integer counts do not depend on
+// the decomposition).
+const fms::Tiling& count_tiling(const Call& c, int bound) { return default_tiling(c, count_form(c), bound); }
+
+// Window counts of at most m centres y[list[..]] per frame (see launch_count)
+// in the call's count arithmetic.
+hipError_t count_windows(fms_handle h, const Call& c, const float* y, const int* list, int m, int* counts,
+                         int m_slot) {
+  const bool split = count_form(c) == fms::FORM_SPLIT;
+  return fms::launch_count(c.st, c.b, count_form(c), c.dp, count_tiling(c, m), split ? h->x16.p : h->x32.p,
+                           split ? h->x16l.as<uint16_t>() : nullptr, y, list, m, h->pcount.as<int>(), counts, m_slot);
+}
 
 // Tiling of a fused-step launch with at most `bound` centres per frame: the
 // tuned entry of the form, D class and bucket whose seed count is nearest in
@@ -933,8 +946,7 @@ fms_status host_prune(fms_handle h, Call& c, const std::vector<int>& conv) {
   HIP_TRY(fms::launch_set_slot(c.st, c.b, META_NCAND, false, nc));
   int* counts = h->bits.as<int>();
   uint32_t* bits = reinterpret_cast<uint32_t*>(h->bits.as<uint8_t>() + nb_n);
-  HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, nc), h->x32.as<float>(), h->y.as<float>(),
-                            h->cand.as<int>(), nc, h->pcount.as<int>(), counts, META_NCAND));
+  HIP_TRY(count_windows(h, c, h->y.as<float>(), h->cand.as<int>(), nc, counts, META_NCAND));
   HIP_TRY(fms::launch_simbits(c.st, c.b, c.dp, h->y.as<float>(), h->cand.as<int>(), nc, h->cand.as<int>(), nc,
                               h->modes.as<float>(), k, bits, META_NCAND, META_NCAND));
   if (h->hstage.busy) HIP_TRY(h->wait(c.st));
@@ -1040,14 +1052,13 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     }
     int host_cand = 0;
     if (on_device) {
-      // Prune (Alg. 2): window counts at the converged endpoints (FP32 in
-      // both forms), ranking by count (descending) then seed position, greedy
-      // suppression against the modes kept so far and the candidates
-      // accepted before.
+      // Prune (Alg. 2): window counts at the converged endpoints (FP32, or the
+      // split form's own arithmetic), ranking by count (descending) then seed
+      // position, greedy suppression against the modes kept so far and the
+      // candidates accepted before.
       // Counts at every slot of the round (the list is the identity); the
       // ranking keeps the converged ones.
-      HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, cap), h->x32.as<float>(), h->y.as<float>(),
-                                nullptr, cap, h->pcount.as<int>(), h->counts.as<int>(), META_NSEL));
+      HIP_TRY(count_windows(h, c, h->y.as<float>(), nullptr, cap, h->counts.as<int>(), META_NSEL));
       // The candidate list buffer is free in a round: it holds each
       // candidate's first word with an earlier conflict for the greedy pass.
       int* first = h->cand.as<int>();
@@ -1347,7 +1358,8 @@ fms_status shift_seeds_noalloc(fms_handle h, void* stream, const float* emb, int
     }
     // Window counts at every slot (kept for the converged seeds), outputs.
     HIP_TRY(fms::launch_iota(c.st, c.b, ident, m));
-    HIP_TRY(fms::launch_count(c.st, c.b, kNaDp, count_tiling(c, m), x32, y, ident, m, pcount, cnt, -1));
+    HIP_TRY(fms::launch_count(c.st, c.b, fms::FORM_FP32, kNaDp, count_tiling(c, m), x32, nullptr, y, ident, m, pcount,
+                              cnt, -1));
     HIP_TRY(fms::launch_lockstep_out(c.st, m, kNaDp, dim, y, state, its, cnt, endpoints, iters, converged, counts));
   }
   FMS_TRY(read_meta(h, c));
@@ -1544,8 +1556,7 @@ fms_status fms_shift_seeds(fms_handle h, void* stream, const float* emb, int64_t
   fh.rt.nact = m;
   FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_iota(c.st, c.b, h->ident.as<int>(), m));
-  HIP_TRY(fms::launch_count(c.st, c.b, c.dp, count_tiling(c, m), h->x32.as<float>(), h->y.as<float>(),
-                            h->ident.as<int>(), m, h->pcount.as<int>(), h->counts.as<int>(), -1));
+  HIP_TRY(count_windows(h, c, h->y.as<float>(), h->ident.as<int>(), m, h->counts.as<int>(), -1));
   HIP_TRY(fms::launch_lockstep_out(c.st, m, c.dp, dim, h->y.as<float>(), h->state.as<uint8_t>(), h->iters.as<int>(),
                                    h->counts.as<int>(), endpoints, iters, converged, counts));
   HIP_TRY(h->wait(c.st));

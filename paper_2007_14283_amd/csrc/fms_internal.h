@@ -212,10 +212,12 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
                          const float* ycur = nullptr, float* ring = nullptr, int64_t ring_stride = 0,
                          int ring_len = 0);
 // Window counts |{i : y[list[a]] . x_i >= thr}| of at most m centres per
-// frame, on FP32 MFMA (x32 = the FP32 rows).  The frame's count is
-// meta[m_slot], or rt.nact when m_slot < 0.
-hipError_t launch_count(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* x32, const float* y,
-                        const int* list, int m, int* pcount, int* counts, int m_slot);
+// frame: form FORM_FP32 on FP32 MFMA (xrm = the FP32 rows, xrl null) or
+// FORM_SPLIT on BF16 MFMA (xrm / xrl = the high / low BF16 rows).  The
+// frame's count is meta[m_slot], or rt.nact when m_slot < 0.
+hipError_t launch_count(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
+                        const uint16_t* xrl, const float* y, const int* list, int m, int* pcount, int* counts,
+                        int m_slot);
 // Similarity bits of rows y[rows[j]], j < meta[rows_slot] (m bounds it):
 // against columns y[cols[c]], c < meta[cols_slot] (ncols bounds it; bits at
 // rt.bits_c0, row stride rt.words_c) when cols is given, and against the

@@ -797,7 +797,7 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
   const T* xt = xt_ ? static_cast<const T*>(xt_) + g.row0 * DP : nullptr;
   if (SPLIT) {
     xrl += g.row0 * DP;
-    xtl += g.row0 * DP;
+    if (xtl) xtl += g.row0 * DP;
   }
   y += g.row0 * DP;
   if (active) active += g.row0;
@@ -2049,18 +2049,21 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool c
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
   }
-  if (form == FORM_SPLIT && (!xrl || !xtl)) return hipErrorInvalidValue;
+  if (form == FORM_SPLIT && (!xrl || (!count && !xtl))) return hipErrorInvalidValue;
   const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
   const int key = form * 1000000 + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
 // Fused steps: every (form, padded D, seed tiles per group) shape above.
-// Window counts (FP32 only: every form counts its endpoints in FP32).
+// Window counts: FP32, and split BF16 for the split form (its similarities
+// are within 5e-5 of exact, as in its iteration); the plain BF16 form counts
+// in FP32.
 #define FMS_SHIFT_SHAPES(X)                                                                                   \
   X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) X(FORM_FP32, 64, 2)        \
   X(FORM_FP32, 128, 1) X(FORM_BF16, 32, 2) X(FORM_BF16, 32, 4) X(FORM_BF16, 32, 8) X(FORM_BF16, 64, 1)      \
   X(FORM_BF16, 64, 2) X(FORM_BF16, 64, 4) X(FORM_BF16, 128, 1) X(FORM_BF16, 128, 2) X(FORM_SPLIT, 32, 2)    \
   X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
 #define FMS_COUNT_SHAPES(X) X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) \
-  X(FORM_FP32, 64, 2) X(FORM_FP32, 128, 1)
+  X(FORM_FP32, 64, 2) X(FORM_FP32, 128, 1) X(FORM_SPLIT, 32, 2) X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 64, 1)      \
+  X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
 #define FMS_SHIFT_CASE(FV, DPV, STV)                                                                          \
   case FV * 1000000 + DPV * 100 + STV:                                                                        \
     return shift_launch_waves<FV, false, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial, \
@@ -2113,12 +2116,14 @@ hipError_t launch_reduce(hipStream_t s, const Batch& b, int dp, const Tiling& t,
   return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t s, const Batch& b, int dp, const Tiling& t, const float* x32, const float* y,
-                        const int* list, int m, int* pcount, int* counts, int m_slot) {
+hipError_t launch_count(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
+                        const uint16_t* xrl, const float* y, const int* list, int m, int* pcount, int* counts,
+                        int m_slot) {
   if (m <= 0 || b.max_blocks <= 0) return hipSuccess;
+  if (form == FORM_BF16) return hipErrorInvalidValue;
   const IterCtl ctl{m_slot, -1, 0.0};
-  hipError_t e = shift_dispatch(s, b, FORM_FP32, true, dp, t, x32, nullptr, nullptr, nullptr, y, list, ctl, m, nullptr,
-                                pcount, nullptr, nullptr);
+  hipError_t e = shift_dispatch(s, b, form, true, dp, t, xrm, nullptr, xrl, nullptr, y, list, ctl, m, nullptr, pcount,
+                                nullptr, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4), b.F), dim3(256), 0, s, b, pcount, t, m_slot, counts);
   return hipGetLastError();
