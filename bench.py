@@ -442,6 +442,33 @@ def _autotune(fms, torch, emb, mask, h, steps):
             "frames_per_s_tuned": rates["tuned"]}
 
 
+def _step_scaling(fms, torch, emb, mask, frame, reps=5):
+    """One fused step (no reduction) of each form at 128 to 8,192 active
+    seeds on the 512x512 frame (the first positions of the seed order), timed
+    with the library's kernel-bound events (fms_params.timing): median of
+    `reps` launches.  TFLOP/s count the algorithmic 4 D flops per seed-pixel
+    update; the split form issues 2.5 times as many on the matrix cores."""
+    import numpy as np
+    n = frame.n_fg
+    order = fms.seed_order(n, 0).to(torch.int32)
+    rows = []
+    for name, prec, peak, issue in (("fp32", fms.FP32, 157.3, 1.0), ("bf16", fms.BF16_REFINE, 2500.0, 1.0),
+                                    ("bf16_split", fms.BF16_SPLIT, 2500.0, 2.5)):
+        k = 0 if prec == fms.FP32 else 1
+        for m in (128, 512, 2048, 8192):
+            ts = []
+            for _ in range(reps + 1):
+                st = fms.shift_seeds(emb, mask, order[:m], bandwidth=frame.bandwidth, precision=prec, max_iter=1,
+                                     gamma=1.0, refine_iters=0, timing=1)["stats"]
+                ts.append(st["step_ms"][k] / max(1, st["step_launches"][k]))
+            us = 1e3 * float(np.median(ts[1:]))
+            tf = m * n * 4.0 * frame.spec.dim / (us * 1e-6) / 1e12
+            rows.append({"form": name, "active_seeds": m, "us": us, "tflops": tf, "frac": tf / peak,
+                         "issued_frac": issue * tf / peak})
+    return {"workload": "one fused step on the 512x512 frame, first positions of the seed order as centres",
+            "peak_tflops": {"fp32": 157.3, "bf16": 2500.0}, "rows": rows}
+
+
 def _cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -601,6 +628,7 @@ def main():
         cfg1[name] = {"frames_per_s": 1e3 / med, "ms_per_frame": med, "modes": int(len(last[0])), "_last": last}
     out["plain_128"] = cfg1
 
+    out["step_scaling"] = _step_scaling(fms, torch, emb, mask, frame)
     out["differentiation"] = _differentiation(fms, torch, frame, int(last_f[2]["seeds_used"]))
     print(f"differentiation: {out['differentiation']['ms_fwd_bwd']:.2f} ms forward+backward",
           file=sys.stderr, flush=True)

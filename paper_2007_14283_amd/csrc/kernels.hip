@@ -129,7 +129,8 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict
 }
 
 // Gather the foreground rows in raster order, normalise them and write the
-// four layouts.  A work group takes kMaskBlockPix pixels: each thread owns 4
+// row layouts (FP32, and the BF16 high and low parts when asked; k_transpose
+// then writes the dimension-major copies).  A work group takes kMaskBlockPix pixels: each thread owns 4
 // consecutive pixels for the mask scan, the foreground pixels of the block go
 // to an LDS list in raster order, and then 8 lanes take each listed pixel
 // (lane q holds dimensions KD*q .. KD*q+KD-1), so a row is read and written
@@ -137,10 +138,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict
 template <int DP>
 __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ geo,
                                                  const int* __restrict__ block_offsets, int* __restrict__ fg_idx,
-                                                 float* __restrict__ x32, float* __restrict__ x32t,
-                                                 uint16_t* __restrict__ x16, uint16_t* __restrict__ x16t,
-                                                 uint16_t* __restrict__ xlo, uint16_t* __restrict__ xlot,
-                                                 float* __restrict__ enorm, int* __restrict__ meta, int64_t row_cap) {
+                                                 float* __restrict__ x32, uint16_t* __restrict__ x16,
+                                                 uint16_t* __restrict__ xlo, float* __restrict__ enorm,
+                                                 int* __restrict__ meta, int64_t row_cap) {
   constexpr int KD = DP / 8;  // dimensions per lane
   __shared__ int sh[5];
   __shared__ int lp[kMaskBlockPix];
@@ -151,15 +151,8 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   fg_idx += gf.row0;
   if (enorm) enorm += gf.row0;
   x32 += gf.row0 * DP;
-  x32t += gf.row0 * DP;
-  if (x16) {
-    x16 += gf.row0 * DP;
-    x16t += gf.row0 * DP;
-  }
-  if (xlo) {
-    xlo += gf.row0 * DP;
-    xlot += gf.row0 * DP;
-  }
+  if (x16) x16 += gf.row0 * DP;
+  if (xlo) xlo += gf.row0 * DP;
   meta += (int64_t)blockIdx.y * META_COUNT;
   const int64_t blk0 = (int64_t)blockIdx.x * kMaskBlockPix;
   const int64_t base = blk0 + threadIdx.x * 4;
@@ -230,65 +223,88 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
       if (enorm) enorm[ord] = ok ? ldexpf(sqrtf(ss), ex) : 0.f;  // |e| of the raw row
     }
     float* rowp = x32 + (int64_t)ord * DP + KD * q;
-    const int64_t blk = ord / kBlockPix, qq = ord % kBlockPix;
 #pragma unroll
     for (int j = 0; j < KD; j += 4) {
       const float4 v4 = make_float4(v[j] * inv, v[j + 1] * inv, v[j + 2] * inv, v[j + 3] * inv);
       *reinterpret_cast<float4*>(rowp + j) = v4;
-      const int d = KD * q + j;
-      x32t[(blk * DP + d + 0) * kBlockPix + qq] = v4.x;
-      x32t[(blk * DP + d + 1) * kBlockPix + qq] = v4.y;
-      x32t[(blk * DP + d + 2) * kBlockPix + qq] = v4.z;
-      x32t[(blk * DP + d + 3) * kBlockPix + qq] = v4.w;
       if (!x16) continue;
+      const int d = KD * q + j;
       const uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
                      b3 = to_bf16_bits(v4.w);
-      uint16_t* row16 = x16 + (int64_t)ord * DP + d;
-      row16[0] = b0;
-      row16[1] = b1;
-      row16[2] = b2;
-      row16[3] = b3;
-      x16t[(blk * DP + d + 0) * kBlockPix + qq] = b0;
-      x16t[(blk * DP + d + 1) * kBlockPix + qq] = b1;
-      x16t[(blk * DP + d + 2) * kBlockPix + qq] = b2;
-      x16t[(blk * DP + d + 3) * kBlockPix + qq] = b3;
+      *reinterpret_cast<uint2*>(x16 + (int64_t)ord * DP + d) =
+          make_uint2((uint32_t)b0 | ((uint32_t)b1 << 16), (uint32_t)b2 | ((uint32_t)b3 << 16));
       if (!xlo) continue;
       // Low parts: the BF16 rounding of what the high part leaves.
       const uint16_t l0 = low_bf16_bits(v4.x, b0), l1 = low_bf16_bits(v4.y, b1), l2 = low_bf16_bits(v4.z, b2),
                      l3 = low_bf16_bits(v4.w, b3);
-      uint16_t* rowl = xlo + (int64_t)ord * DP + d;
-      rowl[0] = l0;
-      rowl[1] = l1;
-      rowl[2] = l2;
-      rowl[3] = l3;
-      xlot[(blk * DP + d + 0) * kBlockPix + qq] = l0;
-      xlot[(blk * DP + d + 1) * kBlockPix + qq] = l1;
-      xlot[(blk * DP + d + 2) * kBlockPix + qq] = l2;
-      xlot[(blk * DP + d + 3) * kBlockPix + qq] = l3;
+      *reinterpret_cast<uint2*>(xlo + (int64_t)ord * DP + d) =
+          make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
     }
   }
   bad = wave_sum_i(bad);
   bad = lane == 0 ? bad : 0;
   if (bad) atomicAdd(meta + META_BAD, bad);
   // The rows from n up to the next multiple of 32 are padding: zero in every
-  // layout, so they add nothing to any sum.
+  // row layout (and so in the transposed ones), so they add nothing to any
+  // sum.
   if (blockIdx.x == 0 && meta[META_N] < row_cap) {
     const int n = meta[META_N];
     const int pad = (kBlockPix - n % kBlockPix) % kBlockPix;
     for (int e = threadIdx.x; e < pad * DP; e += 256) {
       const int64_t row = n + e / DP, d = e % DP;
-      const int64_t blk = row / kBlockPix, q = row % kBlockPix;
       x32[row * DP + d] = 0.f;
-      x32t[(blk * DP + d) * kBlockPix + q] = 0.f;
-      if (x16) {
-        x16[row * DP + d] = 0;
-        x16t[(blk * DP + d) * kBlockPix + q] = 0;
-      }
-      if (xlo) {
-        xlo[row * DP + d] = 0;
-        xlot[(blk * DP + d) * kBlockPix + q] = 0;
-      }
+      if (x16) x16[row * DP + d] = 0;
+      if (xlo) xlo[row * DP + d] = 0;
     }
+  }
+}
+
+// The dimension-major copies of every 32-pixel block (x32t, and with x16t /
+// xlot the BF16 high and low parts), from the FP32 rows k_compact wrote: one
+// wave per block stages the block's 32 x DP values in LDS with 16-byte row
+// loads and writes each transposed block, a contiguous 32 * DP values, with
+// 16-byte (FP32) and 8-byte (BF16) stores.  The block count follows
+// meta[META_N] (nothing when it exceeds row_cap).
+template <int DP>
+__global__ __launch_bounds__(64) void k_transpose(const FrameGeo* __restrict__ geo, const float* __restrict__ x32,
+                                                  float* __restrict__ x32t, uint16_t* __restrict__ x16t,
+                                                  uint16_t* __restrict__ xlot, const int* __restrict__ meta,
+                                                  int64_t row_cap) {
+  constexpr int E = kBlockPix * DP;  // values per block
+  __shared__ float tile[kBlockPix][DP + 1];
+  const FrameGeo& gf = geo[blockIdx.y];
+  const int n = meta[(int64_t)blockIdx.y * META_COUNT + META_N];
+  if (n > row_cap) return;
+  const int blk = (int)blockIdx.x;
+  if (blk * kBlockPix >= n) return;
+  const int64_t base = (gf.row0 + (int64_t)blk * kBlockPix) * DP;  // same offset in every layout
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < E / 256; ++i) {
+    const int e = 4 * lane + 256 * i;
+    const float4 u = *reinterpret_cast<const float4*>(x32 + base + e);
+    const int r = e / DP, c = e % DP;
+    tile[r][c] = u.x;
+    tile[r][c + 1] = u.y;
+    tile[r][c + 2] = u.z;
+    tile[r][c + 3] = u.w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < E / 256; ++i) {
+    const int o = 4 * lane + 256 * i;  // transposed index: dimension o / 32, pixels o % 32 .. + 3
+    const int d = o / kBlockPix, p = o % kBlockPix;
+    const float4 v = make_float4(tile[p][d], tile[p + 1][d], tile[p + 2][d], tile[p + 3][d]);
+    *reinterpret_cast<float4*>(x32t + base + o) = v;
+    if (!x16t) continue;
+    const uint16_t b0 = to_bf16_bits(v.x), b1 = to_bf16_bits(v.y), b2 = to_bf16_bits(v.z), b3 = to_bf16_bits(v.w);
+    *reinterpret_cast<uint2*>(x16t + base + o) =
+        make_uint2((uint32_t)b0 | ((uint32_t)b1 << 16), (uint32_t)b2 | ((uint32_t)b3 << 16));
+    if (!xlot) continue;
+    const uint16_t l0 = low_bf16_bits(v.x, b0), l1 = low_bf16_bits(v.y, b1), l2 = low_bf16_bits(v.z, b2),
+                   l3 = low_bf16_bits(v.w, b3);
+    *reinterpret_cast<uint2*>(xlot + base + o) =
+        make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
   }
 }
 
@@ -1870,19 +1886,34 @@ hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* bloc
   const dim3 grid((unsigned)b.max_mblk, b.F);
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta, row_cap);
+      hipLaunchKernelGGL(k_compact<32>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x16, xlo, enorm,
+                         b.meta, row_cap);
       break;
     case 64:
-      hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta, row_cap);
+      hipLaunchKernelGGL(k_compact<64>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x16, xlo, enorm,
+                         b.meta, row_cap);
       break;
     case 128:
-      hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x32t, x16, x16t,
-                         xlo, xlot, enorm, b.meta, row_cap);
+      hipLaunchKernelGGL(k_compact<128>, grid, dim3(256), 0, s, b.geo, block_offsets, fg_idx, x32, x16, xlo, enorm,
+                         b.meta, row_cap);
       break;
     default:
       return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.max_blocks <= 0) return e;
+  // The transposed copies, one wave per 32-pixel block of the largest frame.
+  const dim3 tgrid((unsigned)b.max_blocks, b.F);
+  switch (dp) {
+    case 32:
+      hipLaunchKernelGGL(k_transpose<32>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_transpose<64>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      break;
+    default:
+      hipLaunchKernelGGL(k_transpose<128>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      break;
   }
   return hipGetLastError();
 }
