@@ -1002,6 +1002,9 @@ struct ModeOutputs {
 fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutputs& out) {
   const int F = c.F;
   const bool timing = p->timing != 0;
+  // Coverage and labels take the split form's arithmetic in that form, FP32
+  // otherwise (BF16 iterations end in FP32 replays).
+  const bool split = c.form == fms::FORM_SPLIT;
   if (c.b.max_n > 0) {
     uint64_t keys[4];
     round_keys(p->seed, keys);
@@ -1080,8 +1083,9 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
     }
     // Coverage by the new modes, and the pool left to seed; then one read of
     // the counters.
-    HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, h->x32.as<float>(), h->modes.as<float>(), META_NACC, 0,
-                               h->elig.as<uint8_t>(), h->rank.as<int>(), nullptr));
+    HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, split, h->x32.as<float>(), h->x16.as<uint16_t>(),
+                               h->x16l.as<uint16_t>(), h->modes.as<float>(), META_NACC, 0, h->elig.as<uint8_t>(),
+                               h->rank.as<int>(), nullptr));
     FMS_TRY(read_meta(h, c));
     for (int f = 0; f < F; ++f) {
       FrameHost& fh = c.fr[f];
@@ -1120,7 +1124,8 @@ fms_status cluster_frames(fms_handle h, Call& c, const fms_params* p, ModeOutput
   }
   FMS_TRY(upload_rt(h, c));
   HIP_TRY(fms::launch_set_slot(c.st, c.b, META_LEFT, false, 0));
-  HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, h->x32.as<float>(), h->modes.as<float>(), -1, 1, nullptr, nullptr,
+  HIP_TRY(fms::launch_assign(c.st, c.b, c.dp, split, h->x32.as<float>(), h->x16.as<uint16_t>(),
+                             h->x16l.as<uint16_t>(), h->modes.as<float>(), -1, 1, nullptr, nullptr,
                              h->fg_idx.as<int>()));
   // The packed modes go out before the last read of the counters, so the
   // call ends with one wait.

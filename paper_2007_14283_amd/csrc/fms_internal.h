@@ -270,9 +270,12 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
 // Coverage (mode 0: against the frame's new modes [rt.k_modes, rt.k_modes +
 // meta[k1_slot])) or labels (mode 1: against modes [0, rt.k_modes)); both
 // write META_LEFT (nonzero iff a pixel is left to seed, resp. the number of
-// pixels farther than h from every mode).
-hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
-                         int mode, uint8_t* elig, const int* rank, const int* fg_idx);
+// pixels farther than h from every mode).  split: similarities in the split
+// form's arithmetic from the BF16 high/low pixel rows xh, xl (x32 unused);
+// else FP32 from x32.
+hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, bool split, const float* x32, const uint16_t* xh,
+                         const uint16_t* xl, const float* modes, int k1_slot, int mode, uint8_t* elig,
+                         const int* rank, const int* fg_idx);
 // meta[slot] of every frame to rt.nact (from_rt) or to value.
 // The counters of every frame (n_words 32-bit words from b.meta on) to host
 // memory mapped at dst (device address): data at dst[4..], then seq at dst[0].

@@ -1519,15 +1519,26 @@ __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __res
 // modes it sees (ascending, first of equals), then the four lane groups
 // combine (larger similarity, else lower index).  A wave owns PT 16-pixel
 // tiles; the work group stages up to KT modes at a time in LDS.
-template <int DP>
+//
+// SPLIT (the split form's arithmetic): the pixels come as their BF16 high and
+// low parts (x16, x16l) and the modes split into the same; each similarity takes hi.hi + hi.lo + lo.hi on
+// v_mfma_f32_16x16x32_bf16 (lane (g, r) feeds dimensions 8g..8g+7 of mode r
+// and of pixel r per 32-dimension step), with the same output layout, so a
+// similarity is within 3 * 2^-16 of exact, as in the split form's steps.  The
+// modes are split once, as they are staged, into two BF16 LDS tiles.
+template <int DP, bool SPLIT>
 __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restrict__ x,
+                                                const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl,
                                                 const float* __restrict__ modes, int k1_slot, int mode,
                                                 uint8_t* __restrict__ elig, const int* __restrict__ rank,
                                                 const int* __restrict__ fg_idx) {
   constexpr int KJ = DP / 4;
+  constexpr int KS = DP / 32;  // 32-dimension steps of the split form
   constexpr int PT = DP == 32 ? 4 : (DP == 64 ? 2 : 1);
   constexpr int KT = 64;
-  constexpr int LD = DP + 4;  // padded LDS row
+  constexpr int LD = DP + 4;   // padded FP32 LDS row
+  constexpr int LDB = DP + 8;  // padded BF16 LDS row (16-byte aligned)
+  constexpr int SM_BYTES = SPLIT ? 2 * KT * LDB * 2 : KT * LD * 4;
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
   const int n = g.n;
@@ -1537,27 +1548,45 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
   const int k1 = mode == 0 ? k0 + meta[k1_slot] : bt.rt[f].k_modes;
   const float thr = g.thr;
   int* labels = g.labels;
-  x += g.row0 * DP;
+  if (SPLIT) {
+    xh += g.row0 * DP;
+    xl += g.row0 * DP;
+  } else {
+    x += g.row0 * DP;
+  }
   modes += g.row0 * DP;
   if (elig) elig += g.elig0;
   if (rank) rank += g.row0;
   if (fg_idx) fg_idx += g.row0;
-  __shared__ __align__(16) float sm[KT * LD];
+  __shared__ __align__(16) unsigned char smraw[SM_BYTES];
+  float* sm = reinterpret_cast<float*>(smraw);
+  __bf16* smh = reinterpret_cast<__bf16*>(smraw);
+  __bf16* sml = smh + KT * LDB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gq = lane >> 4, r = lane & 15;
   const int p0 = (int)blockIdx.x * 64 * PT + wave * 16 * PT;
-  float xb[PT][KJ];
+  float xb[PT][SPLIT ? 1 : KJ];
+  bf16x8 xbh[PT][SPLIT ? KS : 1], xbl[PT][SPLIT ? KS : 1];
 #pragma unroll
   for (int t = 0; t < PT; ++t) {
     const int i = p0 + 16 * t + r;
+    if constexpr (SPLIT) {
+      const bf16x8 z = {};
 #pragma unroll
-    for (int j = 0; j < KJ; j += 4) {
-      const float4 v = i < n ? *reinterpret_cast<const float4*>(x + (int64_t)i * DP + gq * KJ + j)
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-      xb[t][j] = v.x;
-      xb[t][j + 1] = v.y;
-      xb[t][j + 2] = v.z;
-      xb[t][j + 3] = v.w;
+      for (int j = 0; j < KS; ++j) {
+        xbh[t][j] = i < n ? *reinterpret_cast<const bf16x8*>(xh + (int64_t)i * DP + 8 * gq + 32 * j) : z;
+        xbl[t][j] = i < n ? *reinterpret_cast<const bf16x8*>(xl + (int64_t)i * DP + 8 * gq + 32 * j) : z;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KJ; j += 4) {
+        const float4 v = i < n ? *reinterpret_cast<const float4*>(x + (int64_t)i * DP + gq * KJ + j)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+        xb[t][j] = v.x;
+        xb[t][j + 1] = v.y;
+        xb[t][j + 2] = v.z;
+        xb[t][j + 3] = v.w;
+      }
     }
   }
   float best[PT];
@@ -1573,24 +1602,49 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
     __syncthreads();
     for (int e = threadIdx.x; e < rows * DP; e += 256) {
       const int q = e / DP, d = e - q * DP;
-      sm[q * LD + d] = q < cnt ? modes[(int64_t)(kb + q) * DP + d] : 0.f;
+      const float v = q < cnt ? modes[(int64_t)(kb + q) * DP + d] : 0.f;
+      if constexpr (SPLIT) {
+        const __bf16 h = (__bf16)v;
+        smh[q * LDB + d] = h;
+        sml[q * LDB + d] = (__bf16)(v - (float)h);
+      } else {
+        sm[q * LD + d] = v;
+      }
     }
     __syncthreads();
     for (int mt = 0; mt < rows; mt += 16) {
-      float a[KJ];
+      float a[SPLIT ? 1 : KJ];
+      bf16x8 ah[SPLIT ? KS : 1], al[SPLIT ? KS : 1];
+      if constexpr (SPLIT) {
 #pragma unroll
-      for (int j = 0; j < KJ; j += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(&sm[(mt + r) * LD + gq * KJ + j]);
-        a[j] = v.x;
-        a[j + 1] = v.y;
-        a[j + 2] = v.z;
-        a[j + 3] = v.w;
+        for (int j = 0; j < KS; ++j) {
+          ah[j] = *reinterpret_cast<const bf16x8*>(&smh[(mt + r) * LDB + 8 * gq + 32 * j]);
+          al[j] = *reinterpret_cast<const bf16x8*>(&sml[(mt + r) * LDB + 8 * gq + 32 * j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < KJ; j += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(&sm[(mt + r) * LD + gq * KJ + j]);
+          a[j] = v.x;
+          a[j + 1] = v.y;
+          a[j + 2] = v.z;
+          a[j + 3] = v.w;
+        }
       }
 #pragma unroll
       for (int t = 0; t < PT; ++t) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int j = 0; j < KJ; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], xb[t][j], acc, 0, 0, 0);
+          for (int j = 0; j < KS; ++j) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[j], xbh[t][j], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[j], xbl[t][j], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[j], xbh[t][j], acc, 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < KJ; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], xb[t][j], acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int idx = kb + mt + 4 * gq + e;
@@ -2270,25 +2324,31 @@ hipError_t launch_append_modes(hipStream_t s, int dp, const float* y, const int*
   return hipGetLastError();
 }
 
-hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, const float* x32, const float* modes, int k1_slot,
-                         int mode, uint8_t* elig, const int* rank, const int* fg_idx) {
+hipError_t launch_assign(hipStream_t s, const Batch& b, int dp, bool split, const float* x32, const uint16_t* xh,
+                         const uint16_t* xl, const float* modes, int k1_slot, int mode, uint8_t* elig,
+                         const int* rank, const int* fg_idx) {
   if (b.max_n <= 0) return hipSuccess;
+  if (split && (!xh || !xl)) return hipErrorInvalidValue;
+  if (!split && !x32) return hipErrorInvalidValue;
   // Pixels per work group: 4 waves x PT 16-pixel tiles (PT = 4, 2, 1).
   const int pix = dp == 32 ? 256 : (dp == 64 ? 128 : 64);
   const dim3 grid(cdiv(b.max_n, pix), b.F), block(256);
+#define FMS_ASSIGN(D, S) \
+  hipLaunchKernelGGL((k_assign<D, S>), grid, block, 0, s, b, x32, xh, xl, modes, k1_slot, mode, elig, rank, fg_idx)
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_assign<32>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
+      if (split) FMS_ASSIGN(32, true); else FMS_ASSIGN(32, false);
       break;
     case 64:
-      hipLaunchKernelGGL(k_assign<64>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
+      if (split) FMS_ASSIGN(64, true); else FMS_ASSIGN(64, false);
       break;
     case 128:
-      hipLaunchKernelGGL(k_assign<128>, grid, block, 0, s, b, x32, modes, k1_slot, mode, elig, rank, fg_idx);
+      if (split) FMS_ASSIGN(128, true); else FMS_ASSIGN(128, false);
       break;
     default:
       return hipErrorInvalidValue;
   }
+#undef FMS_ASSIGN
   return hipGetLastError();
 }
 
