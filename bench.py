@@ -47,6 +47,11 @@ def _args():
     ap.add_argument("--profile-batch", action="store_true",
                     help="with --profile-run: cluster the uneven batch (--batch-frames, split BF16) --steps "
                          "times instead of the single frame")
+    ap.add_argument("--profile-form", choices=("all", "fp32", "bf16", "split"), default="all",
+                    help="with --profile-run on the single frame: the arithmetic form(s) to run")
+    ap.add_argument("--profile-steps", action="store_true",
+                    help="with --profile-run: single fused steps of each form on the 512x512 frame at "
+                         "128, 512, 2048 and 8192 active seeds (--steps launches each, in that order)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for hardware-counter passes: one plain 256 MiB device copy (the byte-count "
                          "reference), then --steps frames of each form; prints a short summary only")
@@ -64,6 +69,20 @@ def _profile_run(a):
     torch.cuda.synchronize()
     dst.copy_(ref)  # reads and writes exactly 256 MiB
     torch.cuda.synchronize()
+    if a.profile_steps:
+        frame = synth.make_frame(synth.PLAIN512)
+        emb = torch.from_numpy(frame.emb).cuda()
+        mask = torch.from_numpy(frame.mask).cuda()
+        order = fms.seed_order(frame.n_fg, 0)
+        for prec in (fms.FP32, fms.BF16_REFINE, fms.BF16_SPLIT):
+            for m in STEP_SEEDS:
+                for _ in range(a.steps):
+                    fms.shift_seeds(emb, mask, order[:m], bandwidth=frame.bandwidth, precision=prec, max_iter=1,
+                                    gamma=1.0, refine_iters=0)
+        torch.cuda.synchronize()
+        print(f"profile run: copy 256 MiB, then for fp32, bf16, split and m in {STEP_SEEDS}: "
+              f"{a.steps} single steps each", flush=True)
+        return
     if a.profile_batch:
         frames = [synth.make_frame(sp) for sp in synth.batch_specs(a.batch_frames)]
         inp = [{"emb": torch.from_numpy(f.emb).cuda(), "mask": torch.from_numpy(f.mask).cuda(),
@@ -77,7 +96,9 @@ def _profile_run(a):
     frame = synth.make_frame(synth.PLAIN512)
     emb = torch.from_numpy(frame.emb).cuda()
     mask = torch.from_numpy(frame.mask).cuda()
-    for prec in (fms.FP32, fms.BF16_REFINE, fms.BF16_SPLIT):
+    forms = {"fp32": (fms.FP32,), "bf16": (fms.BF16_REFINE,), "split": (fms.BF16_SPLIT,),
+             "all": (fms.FP32, fms.BF16_REFINE, fms.BF16_SPLIT)}[a.profile_form]
+    for prec in forms:
         for _ in range(a.steps):
             modes, _, st = fms.cluster(emb, mask, frame.bandwidth, precision=prec)
     torch.cuda.synchronize()
@@ -442,6 +463,9 @@ def _autotune(fms, torch, emb, mask, h, steps):
             "frames_per_s_tuned": rates["tuned"]}
 
 
+STEP_SEEDS = (128, 512, 2048, 8192)
+
+
 def _step_scaling(fms, torch, emb, mask, frame, reps=5):
     """One fused step (no reduction) of each form at 128 to 8,192 active
     seeds on the 512x512 frame (the first positions of the seed order), timed
@@ -455,7 +479,7 @@ def _step_scaling(fms, torch, emb, mask, frame, reps=5):
     for name, prec, peak, issue in (("fp32", fms.FP32, 157.3, 1.0), ("bf16", fms.BF16_REFINE, 2500.0, 1.0),
                                     ("bf16_split", fms.BF16_SPLIT, 2500.0, 2.5)):
         k = 0 if prec == fms.FP32 else 1
-        for m in (128, 512, 2048, 8192):
+        for m in STEP_SEEDS:
             ts = []
             for _ in range(reps + 1):
                 st = fms.shift_seeds(emb, mask, order[:m], bandwidth=frame.bandwidth, precision=prec, max_iter=1,

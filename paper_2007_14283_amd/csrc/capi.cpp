@@ -148,11 +148,14 @@ struct DeviceGuard {
 };
 
 // Launches with at least kBigGroupMin centres per frame use seed groups of
-// kBigGroup, and BF16 launches with at least kHugeGroupMin use kHugeGroup
-// (where compiled): on the 512x512, D = 32 workload a fused step plus its
-// reduction over 512 centres takes 16.6 us with 64-seed groups against 19.4
-// with 32, and over 8192 BF16 centres 82 us with 128-seed groups against
-// 121 with 64 (larger groups reuse each pixel tile for more seeds).
+// kBigGroup, and BF16 launches (plain or split) with at least kHugeGroupMin
+// use kHugeGroup (where compiled): on the 512x512, D = 32 workload a fused
+// step plus its reduction over 512 centres takes 16.6 us with 64-seed groups
+// against 19.4 with 32, and over 8192 BF16 centres 82 us with 128-seed
+// groups against 121 with 64 (larger groups reuse each pixel tile for more
+// seeds; there a step's pixel loads, not its MFMA work, bound it).  The split
+// step over 2048 and 8192 centres takes 51 and 168 us with 128-seed groups
+// against 57 and 196 with 64.
 constexpr int kBigGroup = 64;
 constexpr int kBigGroupMin = 512;
 constexpr int kHugeGroup = 128;
@@ -318,7 +321,7 @@ struct Call {
   int form = fms::FORM_FP32;  // arithmetic of the round's iteration (fms::StepForm)
   bool bf16 = false;          // the plain BF16 form with its FP32 replay
   std::vector<FrameHost> fr;
-  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{};
+  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{}, tile_huge_split{};
   // The handle's tuned decompositions when the call leaves the tiling to the
   // library, and the pixel-count bucket of its largest frame.
   const std::vector<TunedTiling>* tuned = nullptr;
@@ -378,7 +381,8 @@ int n_bucket(int64_t n) {
 // centres per frame (the call's own form, or FP32).
 const fms::Tiling& default_tiling(const Call& c, int form, int bound) {
   if (form == fms::FORM_FP32) return bound >= kBigGroupMin ? c.tile_fp32_big : c.tile_fp32;
-  if (form == fms::FORM_BF16 && bound >= kHugeGroupMin) return c.tile_huge;
+  if (form != fms::FORM_FP32 && bound >= kHugeGroupMin)
+    return form == fms::FORM_SPLIT ? c.tile_huge_split : c.tile_huge;
   return bound >= kBigGroupMin ? c.tile_big : c.tile;
 }
 
@@ -437,13 +441,15 @@ void set_tiling(Call& c, const fms_params* p) {
   c.tile_fp32_big = fms::make_tiling(fms::FORM_FP32, c.dp, big, p->tile_items, p->tile_chunks, wv);
   const int huge = p->tile_seeds > 0 ? p->tile_seeds : kHugeGroup;
   c.tile_huge = fms::make_tiling(fms::FORM_BF16, c.dp, huge, p->tile_items, p->tile_chunks, wv);
+  c.tile_huge_split = fms::make_tiling(fms::FORM_SPLIT, c.dp, huge, p->tile_items, p->tile_chunks, wv);
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.
 int64_t partial_rows(const Call& c, int cap) {
   size_t r = std::max({fms::shift_partial_rows(c.tile, cap), fms::shift_partial_rows(c.tile_fp32, cap),
                        fms::shift_partial_rows(c.tile_big, cap), fms::shift_partial_rows(c.tile_fp32_big, cap),
-                       fms::shift_partial_rows(c.tile_huge, cap)});
+                       fms::shift_partial_rows(c.tile_huge, cap),
+                       fms::shift_partial_rows(c.tile_huge_split, cap)});
   if (c.tuned)
     for (const TunedTiling& t : *c.tuned)
       if (t.dp == c.dp) r = std::max(r, fms::shift_partial_rows(t.t, cap));

@@ -546,6 +546,10 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   constexpr int KJ = DP / 4;     // dimensions held per lane group
   constexpr int KS = BF16 ? DP / 32 : DP / 4;  // MFMA steps of S per 16x16 tile
   constexpr int NDB = DP / 16;   // 16-dimension blocks of V
+  // Register buffers of pixel blocks: up to PD - 1 blocks are in flight while
+  // one computes.  Sixteen-wave groups (128 registers per lane) and the
+  // largest seed groups keep two.
+  constexpr int PD = (DP == 32 && WV < 16) ? ((BF16 && !SPLIT) ? (ST >= 8 ? 3 : 4) : (ST >= 8 ? 2 : 3)) : 2;
   typedef typename std::conditional<BF16, uint16_t, float>::type T;
   typedef typename std::conditional<BF16, bf16x8, float>::type AOp;
   const T* __restrict__ xrm = static_cast<const T*>(xrm_);
@@ -570,13 +574,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     const int b0 = chunk * cp.chunk_blocks;
     const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
     // Register operands of one block: rows for S (two 16-pixel tiles) and the
-    // dimension-major copy for V.  Double-buffered: block b+WV loads while b
-    // computes.
-    AOp xa[2][2][KS];
-    AOp xv[2][NDB][BF16 ? 1 : 8];
+    // dimension-major copy for V, in PD buffers.
+    AOp xa[PD][2][KS];
+    AOp xv[PD][NDB][BF16 ? 1 : 8];
     // Low parts of the split form (unused otherwise).
-    bf16x8 xal[2][2][SPLIT ? KS : 1];
-    bf16x8 xvl[2][SPLIT ? NDB : 1];
+    bf16x8 xal[PD][2][SPLIT ? KS : 1];
+    bf16x8 xvl[PD][SPLIT ? NDB : 1];
     auto load = [&](int buf, int b) {
       if constexpr (BF16) {
         const int64_t o = (int64_t)b * kBlockPix * DP;
@@ -619,10 +622,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    // The first pixel block is requested before the seeds: the two loads
+    // The first pixel blocks are requested before the seeds: the loads
     // overlap instead of queueing behind each other.
     int b = b0 + wave;
-    if (b < b1) load(0, b);
+#pragma unroll
+    for (int k = 0; k < PD - 1; ++k)
+      if (b + k * WV < b1) load(k, b + k * WV);
     const int a0 = grp * 16 * ST;
     // Seed operands (B of S^T = X Y^T); low parts for the split form.
     AOp yb[ST][KS];
@@ -730,12 +735,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    for (; b < b1; b += 2 * WV) {
-      if (b + WV < b1) load(1, b + WV);
-      compute(0, b);
-      if (b + WV >= b1) break;
-      if (b + 2 * WV < b1) load(0, b + 2 * WV);
-      compute(1, b + WV);
+    for (; b < b1; b += PD * WV) {
+#pragma unroll
+      for (int u = 0; u < PD; ++u) {
+        if (b + (u + PD - 1) * WV < b1) load((u + PD - 1) % PD, b + (u + PD - 1) * WV);
+        if (b + u * WV < b1) compute(u, b + u * WV);
+      }
     }
     if constexpr (COUNT) {
       // Counts of seed r are spread over the four lane groups, then the waves.
@@ -2037,12 +2042,16 @@ StepGeom make_geom(int n) {
 constexpr bool shift_shape_ok(int form, bool count, int dp, int st, int wv) {
   if (wv == 4) return true;
   if ((wv != 8 && wv != 16) || dp != 32) return false;
-  if (wv == 16 && (form == FORM_SPLIT || (form == FORM_FP32 && st >= 2))) return false;
+  // Sixteen waves leave 128 registers per lane: not enough for the split
+  // form or the larger FP32 / BF16 groups without spilling.
+  if (wv == 16 && (form == FORM_SPLIT || (form == FORM_FP32 && st >= 2) || (form == FORM_BF16 && st >= 4)))
+    return false;
   return count || (wv / 2) * st * (dp / 16) * 1024 <= 65536;
 }
 
 static int max_group(int form, int dp) {
-  if (form == FORM_BF16) return dp <= 32 ? 128 : (dp <= 64 ? 64 : 32);
+  if (form != FORM_FP32 && dp <= 32) return 128;
+  if (form == FORM_BF16) return dp <= 64 ? 64 : 32;
   return dp <= 32 ? 64 : (dp <= 64 ? 32 : 16);
 }
 static int min_group(int form, int dp) { return (form != FORM_FP32 && dp <= 32) ? 32 : 16; }
@@ -2145,10 +2154,10 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool c
   X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) X(FORM_FP32, 64, 2)        \
   X(FORM_FP32, 128, 1) X(FORM_BF16, 32, 2) X(FORM_BF16, 32, 4) X(FORM_BF16, 32, 8) X(FORM_BF16, 64, 1)      \
   X(FORM_BF16, 64, 2) X(FORM_BF16, 64, 4) X(FORM_BF16, 128, 1) X(FORM_BF16, 128, 2) X(FORM_SPLIT, 32, 2)    \
-  X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
+  X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 32, 8) X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
 #define FMS_COUNT_SHAPES(X) X(FORM_FP32, 32, 1) X(FORM_FP32, 32, 2) X(FORM_FP32, 32, 4) X(FORM_FP32, 64, 1) \
-  X(FORM_FP32, 64, 2) X(FORM_FP32, 128, 1) X(FORM_SPLIT, 32, 2) X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 64, 1)      \
-  X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
+  X(FORM_FP32, 64, 2) X(FORM_FP32, 128, 1) X(FORM_SPLIT, 32, 2) X(FORM_SPLIT, 32, 4) X(FORM_SPLIT, 32, 8)      \
+  X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
 #define FMS_SHIFT_CASE(FV, DPV, STV)                                                                          \
   case FV * 1000000 + DPV * 100 + STV:                                                                        \
     return shift_launch_waves<FV, false, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial, \
