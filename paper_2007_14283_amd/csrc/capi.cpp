@@ -202,7 +202,7 @@ struct fms_handle_s {
   std::vector<TunedTiling> tuned;
   // Pixel data of the call's frames; every row-indexed buffer holds frame f
   // from row geo[f].row0 on.
-  DevBuf blk, fg_idx, x32, x32t, x16, x16t, x16l, x16lt, order, rank, elig, enorm;
+  DevBuf blk, fg_idx, x32, x32t, x16, x16l, order, rank, elig, enorm;
   // Centres of a round, their lists and flags, window counts and ranking.
   DevBuf y, yc0, yc1, active, next_active, state, iters, seed_pos, seed_fg, ident, cand, counts, sorted, scount;
   DevBuf pcount, partial;
@@ -610,16 +610,14 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   const size_t R = size_t(std::max<int64_t>(rows, fms::kBlockPix)), dp = size_t(c.dp);
   HIP_TRY(h->fg_idx.ensure(R * sizeof(int)));
   HIP_TRY(h->enorm.ensure(R * sizeof(float)));
+  // Layouts: FP32 rows always (seeds, labels); the FP32 dimension-major copy
+  // where FP32 steps run (the FP32 form and the BF16 form's replay); BF16
+  // rows for the BF16 forms, whose steps transpose blocks in LDS.
+  const bool fp32_steps = c.form != fms::FORM_SPLIT;
   HIP_TRY(h->x32.ensure(R * dp * sizeof(float)));
-  HIP_TRY(h->x32t.ensure(R * dp * sizeof(float)));
-  if (c.form != fms::FORM_FP32) {
-    HIP_TRY(h->x16.ensure(R * dp * sizeof(uint16_t)));
-    HIP_TRY(h->x16t.ensure(R * dp * sizeof(uint16_t)));
-  }
-  if (c.form == fms::FORM_SPLIT) {
-    HIP_TRY(h->x16l.ensure(R * dp * sizeof(uint16_t)));
-    HIP_TRY(h->x16lt.ensure(R * dp * sizeof(uint16_t)));
-  }
+  if (fp32_steps) HIP_TRY(h->x32t.ensure(R * dp * sizeof(float)));
+  if (c.form != fms::FORM_FP32) HIP_TRY(h->x16.ensure(R * dp * sizeof(uint16_t)));
+  if (c.form == fms::FORM_SPLIT) HIP_TRY(h->x16l.ensure(R * dp * sizeof(uint16_t)));
   for (DevBuf* b : {&h->y, &h->yc0, &h->yc1, &h->modes}) HIP_TRY(b->ensure(R * dp * sizeof(float)));
   FMS_TRY(ensure_replay(h, c, R));
   for (DevBuf* b : {&h->order, &h->rank, &h->active, &h->next_active, &h->iters, &h->seed_pos, &h->seed_fg,
@@ -634,10 +632,9 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   HIP_TRY(fms::launch_fill_labels(c.st, c.b, c.max_pixels));
   if (c.b.max_n > 0)
     HIP_TRY(fms::launch_compact(c.st, c.b, c.dp, h->blk.as<int>(), h->fg_idx.as<int>(), h->x32.as<float>(),
-                                h->x32t.as<float>(), c.form != fms::FORM_FP32 ? h->x16.as<uint16_t>() : nullptr,
-                                c.form != fms::FORM_FP32 ? h->x16t.as<uint16_t>() : nullptr,
-                                c.form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr,
-                                c.form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr, h->enorm.as<float>()));
+                                fp32_steps ? h->x32t.as<float>() : nullptr,
+                                c.form != fms::FORM_FP32 ? h->x16.as<uint16_t>() : nullptr,
+                                c.form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr, h->enorm.as<float>()));
   return FMS_OK;
 }
 
@@ -685,9 +682,8 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   const fms::Batch& b = c.b;
   const bool bf16 = form != fms::FORM_FP32;  // a BF16 MFMA step
   const void* xrm = bf16 ? h->x16.p : h->x32.p;
-  const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+  const void* xt = bf16 ? nullptr : h->x32t.p;
   const uint16_t* xrl = form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr;
-  const uint16_t* xtl = form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr;
   const int pk = bf16 ? 1 : 0;
   // The plain BF16 form keeps the last centres of each trajectory for the
   // replay.
@@ -708,7 +704,7 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
   auto iterate_on = [&](hipStream_t st, const fms::Tiling& tl, int it, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     const fms::IterCtl ctl{-1, it, gamma, extra};
     const float* yin = it == 0 ? ybuf : yc[it & 1];
-    hipError_t e = fms::launch_shift(st, b, form, c.dp, tl, xrm, xt, xrl, xtl, yin, nullptr, ctl, cap,
+    hipError_t e = fms::launch_shift(st, b, form, c.dp, tl, xrm, xt, xrl, yin, nullptr, ctl, cap,
                                      h->partial.as<float>(), e0, e1);
     if (e == hipSuccess)
       e = fms::launch_reduce(st, b, c.dp, tl, h->partial.as<float>(), lists[it & 1], ybuf, h->state.as<uint8_t>(),
@@ -832,7 +828,7 @@ fms_status run_replay(fms_handle h, Call& c, int cap, double gamma, bool timing)
     const float* yin = it == 0 ? yr : yc[it & 1];
     // Step it reads its centres in list order (in place through the identity
     // list at it = 0, then the rows the previous reduction compacted).
-    HIP_TRY(fms::launch_shift(c.st, b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, nullptr, yin, nullptr,
+    HIP_TRY(fms::launch_shift(c.st, b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, yin, nullptr,
                               ctl, cap,
                               h->partial.as<float>(), timing ? h->events[2 * it] : nullptr,
                               timing ? h->events[2 * it + 1] : nullptr));
@@ -1339,7 +1335,7 @@ fms_status shift_seeds_noalloc(fms_handle h, void* stream, const float* emb, int
   HIP_TRY(fms::launch_set_tables(c.st, g, rt, geo, rtab, meta, c.b.meta64));
   HIP_TRY(fms::launch_mask_count(c.st, c.b, blk));
   HIP_TRY(fms::launch_scan_blocks(c.st, c.b, blk));
-  HIP_TRY(fms::launch_compact(c.st, c.b, kNaDp, blk, fg_idx, x32, x32t, nullptr, nullptr, nullptr, nullptr, nullptr,
+  HIP_TRY(fms::launch_compact(c.st, c.b, kNaDp, blk, fg_idx, x32, x32t, nullptr, nullptr, nullptr,
                               kNaMaxFg));
   HIP_TRY(fms::launch_geo_from_count(c.st, c.b, kNaMaxFg));
   if (m > 0) {
@@ -1356,7 +1352,7 @@ fms_status shift_seeds_noalloc(fms_handle h, void* stream, const float* emb, int
       for (int i = 0; i < nb; ++i, ++t) {
         const fms::IterCtl ctl{-1, t, p->gamma, 0};
         const float* yin = t == 0 ? y : yc[t & 1];
-        HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, kNaDp, tl, x32, x32t, nullptr, nullptr, yin, nullptr,
+        HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, kNaDp, tl, x32, x32t, nullptr, yin, nullptr,
                                   ctl, m, partial));
         HIP_TRY(fms::launch_reduce(c.st, c.b, kNaDp, tl, partial, lists[t & 1], y, state, its, lists[(t + 1) & 1],
                                    yc[(t + 1) & 1], ctl, m, 0, nullptr, yin));
@@ -1460,12 +1456,12 @@ fms_status fms_destroy(fms_handle h) {
   if (!h) return FMS_OK;
   DeviceGuard guard(h->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&h->blk,    &h->fg_idx,  &h->x32,        &h->x32t,    &h->x16,         &h->x16t,
+  DevBuf* bufs[] = {&h->blk,    &h->fg_idx,  &h->x32,        &h->x32t,    &h->x16,
                     &h->order,  &h->rank,    &h->elig,       &h->y,       &h->yc0,         &h->yc1,
                     &h->active, &h->next_active, &h->state,  &h->iters,   &h->seed_pos,    &h->seed_fg,
                     &h->ident,  &h->cand,    &h->counts,     &h->sorted,  &h->scount,      &h->pcount,
                     &h->partial, &h->bits,   &h->acc,        &h->modes,   &h->mode_counts, &h->meta,
-                    &h->geo,     &h->rt,         &h->out_off, &h->enorm, &h->x16l, &h->x16lt,
+                    &h->geo,     &h->rt,         &h->out_off, &h->enorm, &h->x16l,
                     &h->ring,    &h->yr,         &h->rstate,  &h->riters};
   for (DevBuf* b : bufs) b->release();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
@@ -1667,9 +1663,8 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
   auto time_one = [&](const fms::Tiling& t, int form, int m, float* us) -> fms_status {
     const bool bf16 = form != fms::FORM_FP32;
     const void* xrm = bf16 ? h->x16.p : h->x32.p;
-    const void* xt = bf16 ? h->x16t.p : h->x32t.p;
+    const void* xt = bf16 ? nullptr : h->x32t.p;
     const uint16_t* xrl = form == fms::FORM_SPLIT ? h->x16l.as<uint16_t>() : nullptr;
-    const uint16_t* xtl = form == fms::FORM_SPLIT ? h->x16lt.as<uint16_t>() : nullptr;
     for (int f = 0; f < n_frames; ++f) {
       const int64_t r0 = c.fr[f].g.row0;
       HIP_TRY(fms::launch_init_seeds(c.st, ident + r0, batch ? m_of(f, m) : m, c.fr[f].g.n,
@@ -1679,7 +1674,7 @@ fms_status autotune_frames(fms_handle h, void* stream, int32_t n_frames, const f
     const fms::IterCtl ctl{-1, -1, 1.0};
     for (int r = 0; r <= kReps; ++r) {
       if (r == 1) HIP_TRY(hipEventRecord(h->events[0], c.st));
-      HIP_TRY(fms::launch_shift(c.st, c.b, form, c.dp, t, xrm, xt, xrl, xtl, y, ident, ctl, m,
+      HIP_TRY(fms::launch_shift(c.st, c.b, form, c.dp, t, xrm, xt, xrl, y, ident, ctl, m,
                                 h->partial.as<float>(), nullptr, nullptr));
       HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, t, h->partial.as<float>(), ident, y, h->state.as<uint8_t>(),
                                  h->iters.as<int>(), nullptr, nullptr, ctl, m, 1));
@@ -1827,7 +1822,7 @@ fms_status fms_unroll(fms_handle h, void* stream, const float* emb, int64_t pixe
   float* y = h->y.as<float>();
   for (int t = 0; t < steps; ++t) {
     if (t + 1 == steps) HIP_TRY(fms::launch_rows_out(c.st, m, c.dp, dim, y, y_prev));
-    HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, nullptr, y,
+    HIP_TRY(fms::launch_shift(c.st, c.b, fms::FORM_FP32, c.dp, tl, h->x32.p, h->x32t.p, nullptr, y,
                               h->ident.as<int>(), ctl, m, h->partial.as<float>()));
     HIP_TRY(fms::launch_reduce(c.st, c.b, c.dp, tl, h->partial.as<float>(), h->ident.as<int>(), y,
                                h->state.as<uint8_t>(), h->iters.as<int>(), nullptr, nullptr, ctl, m, 1,

@@ -122,13 +122,13 @@ __host__ __device__ inline int64_t elig_len(int n) { return ((int64_t)n + 15) / 
 // rows [n, n_pad) of every layout (n = meta[META_N] of the frame).
 hipError_t launch_mask_count(hipStream_t s, const Batch& b, int* block_counts);
 hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts);
-// x16 / x16t (may be null) receive the BF16 rounding of each value, xlo /
-// xlot (may be null; only with x16) the BF16 rounding of what that leaves
-// (split form).  enorm (may be null) receives each row's raw norm |e_i|.
-// Rows at or beyond row_cap are not written (fixed-capacity calls).
+// x32t (may be null: FP32 steps need it) receives the dimension-major FP32
+// copy, x16 (may be null) the BF16 rounding of each value, xlo (may be null;
+// only with x16) the BF16 rounding of what that leaves (split form).  enorm
+// (may be null) receives each row's raw norm |e_i|.  Rows at or beyond
+// row_cap are not written (fixed-capacity calls).
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm,
-                          int64_t row_cap = INT64_MAX);
+                          float* x32t, uint16_t* x16, uint16_t* xlo, float* enorm, int64_t row_cap = INT64_MAX);
 // Single-frame calls on caller-independent fixed buffers: write the frame and
 // round tables from arguments and clear the counters (one work group); after
 // the mask scan, the foreground and block counts into the table (0 when the
@@ -190,11 +190,11 @@ struct IterCtl {
 // receive the start and end of the kernel itself (hipExtLaunchKernel), not
 // of the launch call.
 size_t shift_partial_rows(const Tiling& t, int cap);
-// form: StepForm; xrm / xt: the row and transposed layouts of that form's
-// values (FP32 or the BF16 high parts), xrl / xtl: the low parts (split form
-// only, else null).
+// form: StepForm; xrm: the row layout of that form's values (FP32 or the
+// BF16 high parts); xt: the FP32 dimension-major layout (FP32 steps only,
+// else ignored); xrl: the BF16 low parts (split form only, else null).
 hipError_t launch_shift(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
-                        const void* xt, const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                        const void* xt, const uint16_t* xrl, const float* y, const int* active,
                         const IterCtl& ctl, int cap, float* partial, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 // Sum partials, renormalise, convergence test and (mode 0) the next active

@@ -5,8 +5,11 @@
 //   x32  [n_pad][DP]  FP32 unit rows, raster order of the foreground
 //   x32t [n_pad/32][DP][32]  the same values, each 32-pixel block stored
 //                    dimension-major, so a lane reads 8 pixels of one
-//                    dimension with one 16-byte (BF16) or two (FP32) loads
-//   x16, x16t        the same two layouts in BF16
+//                    dimension with two 16-byte loads (FP32 steps only)
+//   x16, x16l [n_pad][DP]  BF16 rows: the high part bf16(x) and the low part
+//                    bf16(x - hi) (low part for the split form only); BF16
+//                    steps transpose each block in LDS instead of reading a
+//                    second layout
 //   y    [slots][DP] FP32 seed centres
 //
 // The fused step (Eq. 8, 10, 11): for a seed tile Y and a pixel block X it
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict
 
 // Gather the foreground rows in raster order, normalise them and write the
 // row layouts (FP32, and the BF16 high and low parts when asked; k_transpose
-// then writes the dimension-major copies).  A work group takes kMaskBlockPix pixels: each thread owns 4
+// then writes the FP32 dimension-major copy when FP32 steps need it).  A work group takes kMaskBlockPix pixels: each thread owns 4
 // consecutive pixels for the mask scan, the foreground pixels of the block go
 // to an LDS list in raster order, and then 8 lanes take each listed pixel
 // (lane q holds dimensions KD*q .. KD*q+KD-1), so a row is read and written
@@ -259,16 +262,14 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   }
 }
 
-// The dimension-major copies of every 32-pixel block (x32t, and with x16t /
-// xlot the BF16 high and low parts), from the FP32 rows k_compact wrote: one
-// wave per block stages the block's 32 x DP values in LDS with 16-byte row
-// loads and writes each transposed block, a contiguous 32 * DP values, with
-// 16-byte (FP32) and 8-byte (BF16) stores.  The block count follows
+// The FP32 dimension-major copy of every 32-pixel block (x32t), from the
+// rows k_compact wrote: one wave per block stages the block's 32 x DP values
+// in LDS with 16-byte row loads and writes the transposed block, a
+// contiguous 32 * DP values, with 16-byte stores.  The block count follows
 // meta[META_N] (nothing when it exceeds row_cap).
 template <int DP>
 __global__ __launch_bounds__(64) void k_transpose(const FrameGeo* __restrict__ geo, const float* __restrict__ x32,
-                                                  float* __restrict__ x32t, uint16_t* __restrict__ x16t,
-                                                  uint16_t* __restrict__ xlot, const int* __restrict__ meta,
+                                                  float* __restrict__ x32t, const int* __restrict__ meta,
                                                   int64_t row_cap) {
   constexpr int E = kBlockPix * DP;  // values per block
   __shared__ float tile[kBlockPix][DP + 1];
@@ -296,15 +297,6 @@ __global__ __launch_bounds__(64) void k_transpose(const FrameGeo* __restrict__ g
     const int d = o / kBlockPix, p = o % kBlockPix;
     const float4 v = make_float4(tile[p][d], tile[p + 1][d], tile[p + 2][d], tile[p + 3][d]);
     *reinterpret_cast<float4*>(x32t + base + o) = v;
-    if (!x16t) continue;
-    const uint16_t b0 = to_bf16_bits(v.x), b1 = to_bf16_bits(v.y), b2 = to_bf16_bits(v.z), b3 = to_bf16_bits(v.w);
-    *reinterpret_cast<uint2*>(x16t + base + o) =
-        make_uint2((uint32_t)b0 | ((uint32_t)b1 << 16), (uint32_t)b2 | ((uint32_t)b3 << 16));
-    if (!xlot) continue;
-    const uint16_t l0 = low_bf16_bits(v.x, b0), l1 = low_bf16_bits(v.y, b1), l2 = low_bf16_bits(v.z, b2),
-                   l3 = low_bf16_bits(v.w, b3);
-    *reinterpret_cast<uint2*>(xlot + base + o) =
-        make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
   }
 }
 
@@ -485,6 +477,27 @@ __global__ __launch_bounds__(64) void k_geo_from_count(Batch bt, int64_t row_cap
 
 // ------------------------------------------------------------------ fused step
 
+// Eight BF16 values of one dimension for eight consecutive pixels, read from
+// a block staged in LDS pixel-major with ds_read_b64_tr_b16 (two reads of
+// four).  Within each 16-lane group, lane i of such a read receives element
+// i % 4 of the 8 bytes that lanes 4e + i / 4 (e = 0..3) address; so when lane
+// r of group g addresses row p0 + (r >> 2), columns c0 + 4 (r & 3) .. + 3,
+// it receives rows p0 .. p0 + 3 of column c0 + r.
+__device__ __forceinline__ bf16x8 lds_tr_b16x8(const uint16_t* p0, const uint16_t* p1) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef short s16x4 __attribute__((ext_vector_type(4)));
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((s16x4*)p0);
+  const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((s16x4*)p1);
+  const s16x8 v = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+#else
+  (void)p0;
+  (void)p1;
+  return bf16x8{};
+#endif
+}
+
 // Work plan of one fused step: seeds in groups of 16*ST, pixels in chunks of
 // whole 32-pixel blocks, about target_items (group, chunk) items in total.
 // The kernels derive it from the active count held on the device; the host
@@ -539,8 +552,7 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 // centres, used to rank candidate modes).
 template <bool BF16, bool SPLIT, bool COUNT, int DP, int ST, int WV>
 __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
-                                           const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xtl,
-                                           const float* __restrict__ y, const int* __restrict__ active, int n_act,
+                                           const uint16_t* __restrict__ xrl, const float* __restrict__ y, const int* __restrict__ active, int n_act,
                                            const Tiling& tl, int n_blocks, int n_pix, float thr,
                                            float* __restrict__ partial, int* __restrict__ pcount, int wg, int nwg) {
   constexpr int KJ = DP / 4;     // dimensions held per lane group
@@ -558,9 +570,22 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   const ChunkPlan cp = plan_chunks(n_act, tl, n_blocks);
   const int items = cp.groups * cp.n_chunks;
 
-  __shared__ f32x4 red[COUNT ? 1 : WV / 2][ST][COUNT ? 1 : NDB][64];
+  // BF16 steps read only the row layout: each wave stages its block (high,
+  // and low parts for the split form) pixel-major in its own LDS area and
+  // reads the dimension-major operand of V back with transposing reads.  The
+  // staging areas share LDS with the waves' tree sum, which starts after a
+  // barrier.
+  constexpr bool STAGE = BF16 && !COUNT;
+  constexpr int LDR = DP + 8;  // staged row, padded to keep 16-byte alignment
+  constexpr int STAGE_ELEMS = kBlockPix * LDR;
+  constexpr int STAGE_BYTES = STAGE ? WV * (SPLIT ? 2 : 1) * STAGE_ELEMS * 2 : 0;
+  typedef f32x4 RedT[COUNT ? 1 : WV / 2][ST][COUNT ? 1 : NDB][64];
+  constexpr int LDS_BYTES = STAGE_BYTES > (int)sizeof(RedT) ? STAGE_BYTES : (int)sizeof(RedT);
+  __shared__ __align__(16) unsigned char lds_raw[LDS_BYTES];
+  RedT& red = *reinterpret_cast<RedT*>(lds_raw);
   __shared__ int redc[COUNT ? WV - 1 : 1][ST][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint16_t* const stage = reinterpret_cast<uint16_t*>(lds_raw) + (STAGE ? wave * (SPLIT ? 2 : 1) * STAGE_ELEMS : 0);
   const int g = lane >> 4, r = lane & 15;
   const int rowsel0 = 8 * (r >> 2) + (r & 3);
   const f32x4 cinit = {-thr, -thr, -thr, -thr};
@@ -573,13 +598,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     const int chunk = it / cp.groups, grp = it - chunk * cp.groups;
     const int b0 = chunk * cp.chunk_blocks;
     const int b1 = min(n_blocks, b0 + cp.chunk_blocks);
-    // Register operands of one block: rows for S (two 16-pixel tiles) and the
-    // dimension-major copy for V, in PD buffers.
+    // Register operands of one block, in PD buffers: rows for S (two 16-pixel
+    // tiles) and, for FP32 steps, the dimension-major copy for V.
     AOp xa[PD][2][KS];
-    AOp xv[PD][NDB][BF16 ? 1 : 8];
+    float xv[BF16 ? 1 : PD][NDB][8];
     // Low parts of the split form (unused otherwise).
     bf16x8 xal[PD][2][SPLIT ? KS : 1];
-    bf16x8 xvl[PD][SPLIT ? NDB : 1];
     auto load = [&](int buf, int b) {
       if constexpr (BF16) {
         const int64_t o = (int64_t)b * kBlockPix * DP;
@@ -592,12 +616,6 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
             if constexpr (SPLIT)
               xal[buf][t][j] = *reinterpret_cast<const bf16x8*>(xrl + o + (rowsel0 + 4 * t) * DP + g * KJ + 8 * j);
           }
-#pragma unroll
-        for (int db = 0; db < (COUNT ? 0 : NDB); ++db) {
-          const int64_t ot = ((int64_t)b * DP + 16 * db + r) * kBlockPix + 8 * g;
-          xv[buf][db][0] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(xt) + ot);
-          if constexpr (SPLIT) xvl[buf][db] = *reinterpret_cast<const bf16x8*>(xtl + ot);
-        }
       } else {
         const float* xb = reinterpret_cast<const float*>(xrm) + (int64_t)b * kBlockPix * DP;
 #pragma unroll
@@ -673,6 +691,28 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     }
 
     auto compute = [&](int buf, int b) {
+      // BF16: the block's rows go to this wave's staging area (pixel p of the
+      // block at row p); lane (g, r) reads back dimension 16 db + r of pixels
+      // 8g .. 8g+7, the A operand of V^T = X^T W^T.  The reads are issued
+      // before S's products, which hide them.
+      bf16x8 xvt[STAGE ? NDB : 1], xvtl[STAGE && SPLIT ? NDB : 1];
+      if constexpr (STAGE) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int j = 0; j < KS; ++j) {
+            const int o = (rowsel0 + 4 * t) * LDR + g * KJ + 8 * j;
+            *reinterpret_cast<bf16x8*>(stage + o) = xa[buf][t][j];
+            if constexpr (SPLIT) *reinterpret_cast<bf16x8*>(stage + STAGE_ELEMS + o) = xal[buf][t][j];
+          }
+#pragma unroll
+        for (int db = 0; db < NDB; ++db) {
+          const int o0 = (8 * g + (r >> 2)) * LDR + 16 * db + 4 * (r & 3);
+          xvt[db] = lds_tr_b16x8(stage + o0, stage + o0 + 4 * LDR);
+          if constexpr (SPLIT)
+            xvtl[db] = lds_tr_b16x8(stage + STAGE_ELEMS + o0, stage + STAGE_ELEMS + o0 + 4 * LDR);
+        }
+      }
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
         f32x4 s0 = cinit, s1 = cinit;
@@ -717,8 +757,8 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 #pragma unroll
           for (int db = 0; db < NDB; ++db) {
             if constexpr (SPLIT)
-              acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xvl[buf][db], w, acc[s][db], 0, 0, 0);
-            acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[buf][db][0], w, acc[s][db], 0, 0, 0);
+              acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xvtl[db], w, acc[s][db], 0, 0, 0);
+            acc[s][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xvt[db], w, acc[s][db], 0, 0, 0);
           }
         } else {
           float w[8];
@@ -768,8 +808,9 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
     }
     // Fixed-order tree sum of the waves' window sums (each round the upper
     // half of the remaining waves hands its sums to the lower half), then one
-    // partial per item.
+    // partial per item.  Every wave is done with its staging area first.
     if constexpr (!COUNT) {
+      if constexpr (STAGE) __syncthreads();
 #pragma unroll
       for (int half = WV / 2; half >= 1; half >>= 1) {
         if (wave >= half && wave < 2 * half) {
@@ -806,7 +847,7 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
 
 template <bool BF16, bool SPLIT, bool COUNT, int DP, int ST, int WV>
 __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restrict__ xrm_, const void* __restrict__ xt_,
-                                               const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xtl,
+                                               const uint16_t* __restrict__ xrl,
                                                const float* __restrict__ y, const int* __restrict__ active,
                                                IterCtl ctl, Tiling tl, float* __restrict__ partial,
                                                int* __restrict__ pcount) {
@@ -818,7 +859,6 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
   const T* xt = xt_ ? static_cast<const T*>(xt_) + g.row0 * DP : nullptr;
   if (SPLIT) {
     xrl += g.row0 * DP;
-    if (xtl) xtl += g.row0 * DP;
   }
   y += g.row0 * DP;
   if (active) active += g.row0;
@@ -851,7 +891,7 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
   }
   if (n_act <= 0) return;
-  shift_body<BF16, SPLIT, COUNT, DP, ST, WV>(xrm, xt, xrl, xtl, y, active, n_act, tl, g.n_blocks, g.n, g.thr,
+  shift_body<BF16, SPLIT, COUNT, DP, ST, WV>(xrm, xt, xrl, y, active, n_act, tl, g.n_blocks, g.n, g.thr,
                                              partial, pcount, (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -1938,8 +1978,7 @@ hipError_t launch_scan_blocks(hipStream_t s, const Batch& b, int* block_counts) 
 }
 
 hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* block_offsets, int* fg_idx, float* x32,
-                          float* x32t, uint16_t* x16, uint16_t* x16t, uint16_t* xlo, uint16_t* xlot, float* enorm,
-                          int64_t row_cap) {
+                          float* x32t, uint16_t* x16, uint16_t* xlo, float* enorm, int64_t row_cap) {
   if (xlo && !x16) return hipErrorInvalidValue;
   if (b.max_mblk <= 0) return hipSuccess;
   const dim3 grid((unsigned)b.max_mblk, b.F);
@@ -1960,18 +1999,18 @@ hipError_t launch_compact(hipStream_t s, const Batch& b, int dp, const int* bloc
       return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || b.max_blocks <= 0) return e;
-  // The transposed copies, one wave per 32-pixel block of the largest frame.
+  if (e != hipSuccess || b.max_blocks <= 0 || !x32t) return e;
+  // The transposed copy, one wave per 32-pixel block of the largest frame.
   const dim3 tgrid((unsigned)b.max_blocks, b.F);
   switch (dp) {
     case 32:
-      hipLaunchKernelGGL(k_transpose<32>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      hipLaunchKernelGGL(k_transpose<32>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, b.meta, row_cap);
       break;
     case 64:
-      hipLaunchKernelGGL(k_transpose<64>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      hipLaunchKernelGGL(k_transpose<64>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, b.meta, row_cap);
       break;
     default:
-      hipLaunchKernelGGL(k_transpose<128>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, x16t, xlot, b.meta, row_cap);
+      hipLaunchKernelGGL(k_transpose<128>, tgrid, dim3(64), 0, s, b.geo, x32, x32t, b.meta, row_cap);
       break;
   }
   return hipGetLastError();
@@ -2097,7 +2136,7 @@ static unsigned shift_grid(int cap, const Tiling& t, int n_blocks) {
 
 template <int FORM, bool CNT, int DPV, int STV, int WV>
 static hipError_t shift_launch_one(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
-                                   const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                                   const uint16_t* xrl, const float* y, const int* active,
                                    const IterCtl& ctl, const Tiling& t, float* partial, int* pcount, hipEvent_t ev0,
                                    hipEvent_t ev1) {
   if constexpr (!shift_shape_ok(FORM, CNT, DPV, STV, WV)) {
@@ -2106,9 +2145,9 @@ static hipError_t shift_launch_one(hipStream_t s, dim3 grid, const Batch& b, con
     constexpr bool BFV = FORM != FORM_FP32, SPV = FORM == FORM_SPLIT;
     if (ev0 || ev1)
       hipExtLaunchKernelGGL((k_shift<BFV, SPV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, ev0, ev1, 0, b, xrm, xt,
-                            xrl, xtl, y, active, ctl, t, partial, pcount);
+                            xrl, y, active, ctl, t, partial, pcount);
     else
-      hipLaunchKernelGGL((k_shift<BFV, SPV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, b, xrm, xt, xrl, xtl, y,
+      hipLaunchKernelGGL((k_shift<BFV, SPV, CNT, DPV, STV, WV>), grid, dim3(64 * WV), 0, s, b, xrm, xt, xrl, y,
                          active, ctl, t, partial, pcount);
     return hipGetLastError();
   }
@@ -2116,25 +2155,25 @@ static hipError_t shift_launch_one(hipStream_t s, dim3 grid, const Batch& b, con
 
 template <int FORM, bool CNT, int DPV, int STV>
 static hipError_t shift_launch_waves(hipStream_t s, dim3 grid, const Batch& b, const void* xrm, const void* xt,
-                                     const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                                     const uint16_t* xrl, const float* y, const int* active,
                                      const IterCtl& ctl, const Tiling& t, float* partial, int* pcount, hipEvent_t ev0,
                                      hipEvent_t ev1) {
   switch (t.waves) {
     case 4:
-      return shift_launch_one<FORM, CNT, DPV, STV, 4>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+      return shift_launch_one<FORM, CNT, DPV, STV, 4>(s, grid, b, xrm, xt, xrl, y, active, ctl, t, partial,
                                                       pcount, ev0, ev1);
     case 8:
-      return shift_launch_one<FORM, CNT, DPV, STV, 8>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+      return shift_launch_one<FORM, CNT, DPV, STV, 8>(s, grid, b, xrm, xt, xrl, y, active, ctl, t, partial,
                                                       pcount, ev0, ev1);
     case 16:
-      return shift_launch_one<FORM, CNT, DPV, STV, 16>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,
+      return shift_launch_one<FORM, CNT, DPV, STV, 16>(s, grid, b, xrm, xt, xrl, y, active, ctl, t, partial,
                                                        pcount, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
 static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool count, int dp, const Tiling& t,
-                                 const void* xrm, const void* xt, const uint16_t* xrl, const uint16_t* xtl,
+                                 const void* xrm, const void* xt, const uint16_t* xrl,
                                  const float* y, const int* active, const IterCtl& ctl, int cap, float* partial,
                                  int* pcount, hipEvent_t ev0, hipEvent_t ev1) {
   if (cap <= 0 || b.max_blocks <= 0) {
@@ -2143,7 +2182,8 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool c
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
   }
-  if (form == FORM_SPLIT && (!xrl || (!count && !xtl))) return hipErrorInvalidValue;
+  if (form == FORM_SPLIT && !xrl) return hipErrorInvalidValue;
+  if (form == FORM_FP32 && !count && !xt) return hipErrorInvalidValue;
   const dim3 grid(shift_grid(cap, t, b.max_blocks), b.F);
   const int key = form * 1000000 + (count ? 100000 : 0) + dp * 100 + t.group_seeds / 16;
 // Fused steps: every (form, padded D, seed tiles per group) shape above.
@@ -2160,11 +2200,11 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool c
   X(FORM_SPLIT, 64, 1) X(FORM_SPLIT, 64, 2) X(FORM_SPLIT, 128, 1)
 #define FMS_SHIFT_CASE(FV, DPV, STV)                                                                          \
   case FV * 1000000 + DPV * 100 + STV:                                                                        \
-    return shift_launch_waves<FV, false, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial, \
+    return shift_launch_waves<FV, false, DPV, STV>(s, grid, b, xrm, xt, xrl, y, active, ctl, t, partial, \
                                                    pcount, ev0, ev1);
 #define FMS_COUNT_CASE(FV, DPV, STV)                                                                          \
   case FV * 1000000 + 100000 + DPV * 100 + STV:                                                               \
-    return shift_launch_waves<FV, true, DPV, STV>(s, grid, b, xrm, xt, xrl, xtl, y, active, ctl, t, partial,  \
+    return shift_launch_waves<FV, true, DPV, STV>(s, grid, b, xrm, xt, xrl, y, active, ctl, t, partial,  \
                                                   pcount, ev0, ev1);
   switch (key) {
     FMS_SHIFT_SHAPES(FMS_SHIFT_CASE)
@@ -2178,9 +2218,9 @@ static hipError_t shift_dispatch(hipStream_t s, const Batch& b, int form, bool c
 }
 
 hipError_t launch_shift(hipStream_t s, const Batch& b, int form, int dp, const Tiling& t, const void* xrm,
-                        const void* xt, const uint16_t* xrl, const uint16_t* xtl, const float* y, const int* active,
+                        const void* xt, const uint16_t* xrl, const float* y, const int* active,
                         const IterCtl& ctl, int cap, float* partial, hipEvent_t ev0, hipEvent_t ev1) {
-  return shift_dispatch(s, b, form, false, dp, t, xrm, xt, xrl, xtl, y, active, ctl, cap, partial, nullptr, ev0,
+  return shift_dispatch(s, b, form, false, dp, t, xrm, xt, xrl, y, active, ctl, cap, partial, nullptr, ev0,
                         ev1);
 }
 
@@ -2216,7 +2256,7 @@ hipError_t launch_count(hipStream_t s, const Batch& b, int form, int dp, const T
   if (m <= 0 || b.max_blocks <= 0) return hipSuccess;
   if (form == FORM_BF16) return hipErrorInvalidValue;
   const IterCtl ctl{m_slot, -1, 0.0};
-  hipError_t e = shift_dispatch(s, b, form, true, dp, t, xrm, nullptr, xrl, nullptr, y, list, ctl, m, nullptr, pcount,
+  hipError_t e = shift_dispatch(s, b, form, true, dp, t, xrm, nullptr, xrl, y, list, ctl, m, nullptr, pcount,
                                 nullptr, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_counts, dim3(cdiv(m, 4), b.F), dim3(256), 0, s, b, pcount, t, m_slot, counts);
