@@ -26,6 +26,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+# Bytes per pixel value a step of each form reads (the split form keeps two
+# BF16 parts), and the MFMA peak it runs against.
+STEP_BYTES = {"fp32": 4, "bf16": 2, "split": 4}
+STEP_PEAK = {"fp32": "fp32", "bf16": "bf16", "split": "bf16"}
 
 
 def _args():
@@ -49,6 +54,9 @@ def _args():
                          "times instead of the single frame")
     ap.add_argument("--profile-form", choices=("all", "fp32", "bf16", "split"), default="all",
                     help="with --profile-run on the single frame: the arithmetic form(s) to run")
+    ap.add_argument("--profile-side", type=int, choices=(512, 1024), default=512,
+                    help="with --profile-run on the single frame: the 512x512 frame or the 1024x1024 "
+                         "precision frame")
     ap.add_argument("--profile-steps", action="store_true",
                     help="with --profile-run: single fused steps of each form on the 512x512 frame at "
                          "128, 512, 2048 and 8192 active seeds (--steps launches each, in that order)")
@@ -93,7 +101,7 @@ def _profile_run(a):
         print(f"profile run: copy 256 MiB, {a.steps} calls of the {len(frames)}-frame batch, "
               f"{sum(len(r[0]) for r in res)} modes", flush=True)
         return
-    frame = synth.make_frame(synth.PLAIN512)
+    frame = synth.make_frame(synth.PLAIN512 if a.profile_side == 512 else synth.PRECISION1024)
     emb = torch.from_numpy(frame.emb).cuda()
     mask = torch.from_numpy(frame.mask).cuda()
     forms = {"fp32": (fms.FP32,), "bf16": (fms.BF16_REFINE,), "split": (fms.BF16_SPLIT,),
@@ -164,10 +172,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def _measured_traffic(dtype):
-    """HBM bytes per launch of the fused step from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
-    sources have changed since the counters were taken."""
+def _measured_traffic(form):
+    """HBM bytes per launch of the fused step of a form (fp32, bf16, split) on
+    the 512x512 frame from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources have
+    changed since the counters were taken."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = kernel_source_hash()
@@ -177,30 +186,45 @@ def _measured_traffic(dtype):
         return None
     for line in text.splitlines():
         f = line.split()
-        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == dtype:
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == form:
             return float(f[2])
     return None
 
 
-def _roofline(agg, dim, n_fg):
-    # Dominant kernel: the fused-step form with the larger summed duration.
+def _roofline(agg, dim, n_fg, form):
+    """Roofline of the dominant kernel, the fused step of the form with the
+    larger summed duration (the BF16 form's replay runs FP32 steps).  Its
+    algorithmic work: 4 D flops per seed-pixel update, and per launch the
+    pixels once (n x D x b bytes, b from STEP_BYTES) plus the active centres in
+    and out (2 x N_act x D x 4).  A launch's floor is the larger of its MFMA
+    and HBM times (the min of the two update rates); `bound` is the term that
+    dominates the summed floors, and `frac` its achieved rate over its peak,
+    which is the summed floor over the measured time."""
     k = 1 if agg["step_ms"][1] >= agg["step_ms"][0] else 0
-    dtype = "bf16" if k == 1 else "fp32"
+    kform = form if k == 1 else "fp32"
     ms = agg["step_ms"][k]
-    flops = agg["step_updates"][k] * 4.0 * dim  # 2D for the dot product + 2D for the masked sum
+    t = ms * 1e-3
     launches = max(1, agg["step_launches"][k])
-    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    peak = PEAK_TFLOPS[dtype]
-    # Algorithmic bytes per launch: the pixels once (n x D x b) plus the
-    # active centres in and out (2 x N_act x D x 4), averaged over launches.
-    b = 2 if dtype == "bf16" else 4
+    flops = agg["step_updates"][k] * 4.0 * dim  # 2D for the dot product + 2D for the masked sum
     seeds = agg["step_updates"][k] / max(1, n_fg)
-    alg_bytes = n_fg * dim * b + 8.0 * dim * seeds / launches
-    return {"kernel": "k_shift_" + dtype, "bound": "mfma", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": _measured_traffic(dtype),
-            "algorithmic_bytes_per_launch": alg_bytes,
+    nbytes = launches * n_fg * dim * STEP_BYTES[kform] + 8.0 * dim * seeds
+    peak_f = PEAK_TFLOPS[STEP_PEAK[kform]]
+    t_mfma = flops / (peak_f * 1e12)
+    t_hbm = nbytes / (PEAK_HBM_GBPS * 1e9)
+    tflops = flops / t / 1e12 if t > 0 else 0.0
+    gbps = nbytes / t / 1e9 if t > 0 else 0.0
+    if t_hbm > t_mfma:
+        bound, achieved, peak, unit = "hbm", gbps, PEAK_HBM_GBPS, "GB/s"
+    else:
+        bound, achieved, peak, unit = "mfma", tflops, peak_f, "TFLOP/s"
+    return {"kernel": "k_shift_" + kform, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": _measured_traffic(kform),
+            "algorithmic_bytes_per_launch": nbytes / launches, "flops_per_launch": flops / launches,
             "avg_launch_us": ms * 1e3 / launches, "launches": agg["step_launches"][k],
-            "flops_per_launch": flops / launches}
+            "mean_active_seeds": seeds / launches,
+            "mfma": {"achieved_tflops": tflops, "peak": peak_f, "frac": tflops / peak_f,
+                     "issued_frac": tflops / peak_f * (2.5 if kform == "split" else 1.0)},
+            "hbm": {"achieved_gbps": gbps, "peak": PEAK_HBM_GBPS, "frac": gbps / PEAK_HBM_GBPS}}
 
 
 def _accuracy(gpu_modes, gpu_labels, o_modes, fg, o_fg_labels, band, tie_of, tol):
@@ -271,7 +295,8 @@ def _batched(fms, torch, a):
         out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": med,
                      "wall_ms_per_batch": 1e3 * wall / a.batch_steps,
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
-                     "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"]),
+                     "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"],
+                                           {fms.FP32: "fp32", fms.BF16_REFINE: "bf16", fms.BF16_SPLIT: "split"}[prec]),
                      "vs_oracle": _batch_accuracy(frames, res, 1e-3 if prec == fms.BF16_REFINE else 1e-5)}
         del res, allres
     # Autotuned tiles: fms_autotune_batch on these frames (split BF16 form);
@@ -589,7 +614,7 @@ def main():
     upd_s = agg_s["updates"] / dt_s
 
     st_b = last_b[2]
-    roof_s = _roofline(agg_s, spec.dim, frame.n_fg)
+    roof_s = _roofline(agg_s, spec.dim, frame.n_fg, "split")
     # The headline is the BF16 form that meets the 1e-3 mode-error bar with
     # the fewest frames lost to rounding: the split (hi/lo) BF16 form, which
     # runs every contraction on BF16 MFMA and returns the oracle's modes to
@@ -621,16 +646,17 @@ def main():
         "modes": int(len(last_s[0])),
         "speedup_vs_fp32": fps_s / fps_f,
         "fp32": {"frames_per_s": fps_f, "ms_per_frame": 1e3 * dt_f / a.steps, "updates_per_s": upd_f,
-                 "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim, frame.n_fg),
+                 "modes": int(len(last_f[0])), "roofline": _roofline(agg_f, spec.dim, frame.n_fg, "fp32"),
                  "kernel_ms_per_frame": agg_f["step_ms"][0] / a.steps},
         "bf16_refine": {"frames_per_s": fps_b, "ms_per_frame": 1e3 * dt_b / a.steps, "updates_per_s": upd_b,
-                        "modes": int(len(last_b[0])), "roofline": _roofline(agg_b, spec.dim, frame.n_fg),
+                        "modes": int(len(last_b[0])), "roofline": _roofline(agg_b, spec.dim, frame.n_fg, "bf16"),
                         "kernel_ms_per_frame": [agg_b["step_ms"][0] / a.steps, agg_b["step_ms"][1] / a.steps],
                         "replay": {k: st_b[k] for k in ("refine_steps", "refine_unconverged", "refine_step_diff",
                                                         "refine_gamma_cut", "refine_updates")}},
         "kernel_ms_per_frame": agg_s["step_ms"][1] / a.steps,
         "roofline": roof_s,
-        "mfma_target": {"frac_target": 0.5, "frac": roof_s["frac"], "met": roof_s["frac"] >= 0.5,
+        "mfma_target": {"frac_target": 0.5, "frac": roof_s["mfma"]["frac"], "met": roof_s["mfma"]["frac"] >= 0.5,
+                        "issued_frac": roof_s["mfma"]["issued_frac"],
                         "note": "algorithmic flops (4D per seed-pixel update) of the fused step on this frame over "
                                 "dense BF16 MFMA peak, against the 0.5 utilisation target; the split form issues "
                                 "2.5x those flops on the matrix cores"},
