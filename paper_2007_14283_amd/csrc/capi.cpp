@@ -153,9 +153,9 @@ struct DeviceGuard {
 // step plus its reduction over 512 centres takes 16.6 us with 64-seed groups
 // against 19.4 with 32, and over 8192 BF16 centres 82 us with 128-seed
 // groups against 121 with 64 (larger groups reuse each pixel tile for more
-// seeds; there a step's pixel loads, not its MFMA work, bound it).  The split
-// step over 2048 and 8192 centres takes 51 and 168 us with 128-seed groups
-// against 57 and 196 with 64.
+// seeds; there a step's pixel loads, not its MFMA work, bound it).  Split
+// steps take 128-seed groups in batched calls (four waves per group; the
+// 64-frame batch runs 8% faster with them).
 constexpr int kBigGroup = 64;
 constexpr int kBigGroupMin = 512;
 constexpr int kHugeGroup = 128;
@@ -442,6 +442,9 @@ void set_tiling(Call& c, const fms_params* p) {
   const int huge = p->tile_seeds > 0 ? p->tile_seeds : kHugeGroup;
   c.tile_huge = fms::make_tiling(fms::FORM_BF16, c.dp, huge, p->tile_items, p->tile_chunks, wv);
   c.tile_huge_split = fms::make_tiling(fms::FORM_SPLIT, c.dp, huge, p->tile_items, p->tile_chunks, wv);
+  // 128-seed split groups are compiled for four waves only: where more are
+  // asked for (single frames), the 64-seed tiling with them is faster.
+  if (wv > 0 && c.tile_huge_split.waves < wv) c.tile_huge_split = c.tile_big;
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.

@@ -574,10 +574,12 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   // and low parts for the split form) pixel-major in its own LDS area and
   // reads the dimension-major operand of V back with transposing reads.  The
   // staging areas share LDS with the waves' tree sum, which starts after a
-  // barrier.
+  // barrier.  A staged row's 16-byte chunks are permuted, chunk q of pixel p
+  // stored at q ^ swz(p), swz(p) = 2 ((p >> 3) mod DP/16): a transposing
+  // read then spreads its 16 rows (4 per 8-pixel group) over all banks, and
+  // so does a row store (at D = 32).
   constexpr bool STAGE = BF16 && !COUNT;
-  constexpr int LDR = DP + 8;  // staged row, padded to keep 16-byte alignment
-  constexpr int STAGE_ELEMS = kBlockPix * LDR;
+  constexpr int STAGE_ELEMS = kBlockPix * DP;
   constexpr int STAGE_BYTES = STAGE ? WV * (SPLIT ? 2 : 1) * STAGE_ELEMS * 2 : 0;
   typedef f32x4 RedT[COUNT ? 1 : WV / 2][ST][COUNT ? 1 : NDB][64];
   constexpr int LDS_BYTES = STAGE_BYTES > (int)sizeof(RedT) ? STAGE_BYTES : (int)sizeof(RedT);
@@ -586,6 +588,7 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   __shared__ int redc[COUNT ? WV - 1 : 1][ST][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint16_t* const stage = reinterpret_cast<uint16_t*>(lds_raw) + (STAGE ? wave * (SPLIT ? 2 : 1) * STAGE_ELEMS : 0);
+  auto swz = [](int p) { return 2 * ((p >> 3) & (DP / 16 - 1)); };
   const int g = lane >> 4, r = lane & 15;
   const int rowsel0 = 8 * (r >> 2) + (r & 3);
   const f32x4 cinit = {-thr, -thr, -thr, -thr};
@@ -701,16 +704,20 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int j = 0; j < KS; ++j) {
-            const int o = (rowsel0 + 4 * t) * LDR + g * KJ + 8 * j;
+            const int p = rowsel0 + 4 * t;
+            const int o = p * DP + 8 * (((g * KJ) / 8 + j) ^ swz(p));
             *reinterpret_cast<bf16x8*>(stage + o) = xa[buf][t][j];
             if constexpr (SPLIT) *reinterpret_cast<bf16x8*>(stage + STAGE_ELEMS + o) = xal[buf][t][j];
           }
 #pragma unroll
         for (int db = 0; db < NDB; ++db) {
-          const int o0 = (8 * g + (r >> 2)) * LDR + 16 * db + 4 * (r & 3);
-          xvt[db] = lds_tr_b16x8(stage + o0, stage + o0 + 4 * LDR);
+          // Rows 8g + (r >> 2) and 4 further (same permutation), columns
+          // 16 db + 4 (r & 3) .. + 3: half r & 1 of chunk 2 db + (r & 3) / 2.
+          const int p0 = 8 * g + (r >> 2);
+          const int o0 = p0 * DP + 8 * ((2 * db + ((r & 3) >> 1)) ^ swz(p0)) + 4 * (r & 1);
+          xvt[db] = lds_tr_b16x8(stage + o0, stage + o0 + 4 * DP);
           if constexpr (SPLIT)
-            xvtl[db] = lds_tr_b16x8(stage + STAGE_ELEMS + o0, stage + STAGE_ELEMS + o0 + 4 * LDR);
+            xvtl[db] = lds_tr_b16x8(stage + STAGE_ELEMS + o0, stage + STAGE_ELEMS + o0 + 4 * DP);
         }
       }
 #pragma unroll
@@ -2082,9 +2089,11 @@ constexpr bool shift_shape_ok(int form, bool count, int dp, int st, int wv) {
   if (wv == 4) return true;
   if ((wv != 8 && wv != 16) || dp != 32) return false;
   // Sixteen waves leave 128 registers per lane: not enough for the split
-  // form or the larger FP32 / BF16 groups without spilling.
+  // form or the larger FP32 / BF16 groups without spilling; eight leave 256,
+  // not enough for 128-seed split groups.
   if (wv == 16 && (form == FORM_SPLIT || (form == FORM_FP32 && st >= 2) || (form == FORM_BF16 && st >= 4)))
     return false;
+  if (wv == 8 && form == FORM_SPLIT && st >= 8 && !count) return false;
   return count || (wv / 2) * st * (dp / 16) * 1024 <= 65536;
 }
 
