@@ -1154,7 +1154,8 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
 // (bits at tab.bits_c0, tab.words_c words per row), those of the rest the
 // frame's modes (bits at tab.bits_m0, tab.words_m words per row).  A wave
 // owns 64 columns and 16 rows; each lane keeps its column vector in
-// registers and reads the (wave-uniform) row vectors.  Row strides are
+// registers and reads the row vectors, staged in LDS per work group, as
+// broadcasts.  Row strides are
 // multiples of 2 words.  With `first` (candidate columns = the rows, in rank
 // order), first[j] is lowered to the first word of row j holding a column
 // c < j that is set (it must start at INT_MAX).
@@ -1198,11 +1199,22 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
 #pragma unroll
     for (int d = 0; d < DP; ++d) xc[d] = 0.f;
   }
+  // The tile's 64 row vectors are staged in LDS with one round of loads
+  // (read back as broadcasts), instead of one dependent load per row.
+  __shared__ __align__(16) float rs[64 * DP];
+  for (int e = threadIdx.x; e < 16 * DP; e += 256) {
+    const int q = e / (DP / 4), d4 = e - q * (DP / 4);
+    const int j = rt * 64 + q;
+    const float4 u = j < m ? *reinterpret_cast<const float4*>(y + (int64_t)rows[j] * DP + 4 * d4)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+    *reinterpret_cast<float4*>(&rs[q * DP + 4 * d4]) = u;
+  }
+  __syncthreads();
   const int j0 = rt * 64 + wave * 16;
   for (int jj = 0; jj < 16; ++jj) {
     const int j = j0 + jj;
     if (j >= m) break;
-    const float* rv = y + (int64_t)rows[j] * DP;
+    const float* rv = &rs[(wave * 16 + jj) * DP];
     float dot = 0.f;
 #pragma unroll
     for (int d = 0; d < DP; ++d) dot = fmaf(rv[d], xc[d], dot);
