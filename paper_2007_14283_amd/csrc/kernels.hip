@@ -1394,8 +1394,11 @@ __global__ __launch_bounds__(1024) void k_gamma_cut(Batch bt, double gamma, cons
 // Rank the converged slots k < meta[META_NSEL] (state[k] == 1) of the round
 // by window count (descending), then by slot (ascending, = seed position):
 // sorted[r] = k_r, scount[r] = counts[k_r]; their number goes to
-// meta[META_NCAND].  Bitonic sort of 64-bit keys in LDS, the other slots'
-// keys sorting last; NSEL <= kRankMax.
+// meta[META_NCAND].  Bitonic sort of 64-bit keys, the other slots' keys
+// sorting last; NSEL <= kRankMax.  Up to 1,024 keys sit one per thread and
+// exchange within a wave by shuffles (strides below 64) and through LDS
+// otherwise, so a sort of 512 keys passes 6 barriers instead of 45; larger
+// sets sort in LDS.
 __global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t* __restrict__ state,
                                                          const int* __restrict__ counts, int* __restrict__ sorted,
                                                          int* __restrict__ scount, int* __restrict__ first) {
@@ -1421,20 +1424,45 @@ __global__ __launch_bounds__(1024) void k_rank_converged(Batch bt, const uint8_t
   mine = wave_sum_i(mine);
   if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&s_nc, mine);
   __syncthreads();
-  for (int size = 2; size <= np; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < np; i += 1024) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;
-          const unsigned long long a = key[i], b = key[j];
-          if ((a > b) == up) {
-            key[i] = b;
-            key[j] = a;
+  if (np <= 1024) {
+    // Threads at or past np hold the largest key and only meet each other.
+    const int i = threadIdx.x;
+    unsigned long long k = i < np ? key[i] : ~0ull;
+    for (int size = 2; size <= np; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        unsigned long long o;
+        if (stride >= 64) {
+          key[i] = k;
+          __syncthreads();
+          o = key[i ^ stride];
+          __syncthreads();
+        } else {
+          const uint32_t lo = __shfl_xor((uint32_t)k, stride, 64);
+          const uint32_t hi = __shfl_xor((uint32_t)(k >> 32), stride, 64);
+          o = ((unsigned long long)hi << 32) | lo;
+        }
+        const bool up = (i & size) == 0, lower = (i & stride) == 0;
+        k = (lower == up) ? (k < o ? k : o) : (k < o ? o : k);
+      }
+    }
+    key[i] = k;
+    __syncthreads();
+  } else {
+    for (int size = 2; size <= np; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < np; i += 1024) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const bool up = (i & size) == 0;
+            const unsigned long long a = key[i], b = key[j];
+            if ((a > b) == up) {
+              key[i] = b;
+              key[j] = a;
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   const int nc = s_nc;
