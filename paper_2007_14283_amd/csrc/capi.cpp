@@ -148,14 +148,12 @@ struct DeviceGuard {
 };
 
 // Launches with at least kBigGroupMin centres per frame use seed groups of
-// kBigGroup, and BF16 launches (plain or split) with at least kHugeGroupMin
-// use kHugeGroup (where compiled): on the 512x512, D = 32 workload a fused
-// step plus its reduction over 512 centres takes 16.6 us with 64-seed groups
+// kBigGroup, and plain BF16 launches with at least kHugeGroupMin use
+// kHugeGroup (where compiled): on the 512x512, D = 32 workload a fused step
+// plus its reduction over 512 centres takes 16.6 us with 64-seed groups
 // against 19.4 with 32, and over 8192 BF16 centres 82 us with 128-seed
 // groups against 121 with 64 (larger groups reuse each pixel tile for more
-// seeds; there a step's pixel loads, not its MFMA work, bound it).  Split
-// steps take 128-seed groups in batched calls (four waves per group; the
-// 64-frame batch runs 8% faster with them).
+// seeds; there a step's pixel loads, not its MFMA work, bound it).
 constexpr int kBigGroup = 64;
 constexpr int kBigGroupMin = 512;
 constexpr int kHugeGroup = 128;
@@ -321,7 +319,7 @@ struct Call {
   int form = fms::FORM_FP32;  // arithmetic of the round's iteration (fms::StepForm)
   bool bf16 = false;          // the plain BF16 form with its FP32 replay
   std::vector<FrameHost> fr;
-  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{}, tile_huge_split{};
+  fms::Tiling tile{}, tile_fp32{}, tile_big{}, tile_fp32_big{}, tile_huge{};
   // The handle's tuned decompositions when the call leaves the tiling to the
   // library, and the pixel-count bucket of its largest frame.
   const std::vector<TunedTiling>* tuned = nullptr;
@@ -381,8 +379,7 @@ int n_bucket(int64_t n) {
 // centres per frame (the call's own form, or FP32).
 const fms::Tiling& default_tiling(const Call& c, int form, int bound) {
   if (form == fms::FORM_FP32) return bound >= kBigGroupMin ? c.tile_fp32_big : c.tile_fp32;
-  if (form != fms::FORM_FP32 && bound >= kHugeGroupMin)
-    return form == fms::FORM_SPLIT ? c.tile_huge_split : c.tile_huge;
+  if (form == fms::FORM_BF16 && bound >= kHugeGroupMin) return c.tile_huge;
   return bound >= kBigGroupMin ? c.tile_big : c.tile;
 }
 
@@ -431,28 +428,36 @@ const fms::Tiling& pick_tiling(const Call& c, int form, int bound) {
 // frames, stay at four, where eight were 4-5% slower.
 constexpr int kSingleFrameWaves = 8;
 
+// Batched calls, whose launches spread over every frame, default to
+// kBatchItems items per step, and the split form to 64-seed groups at every
+// active count: the 64-frame batch (split form) ran 1,829 frames/s with both
+// against 1,618 with the single-frame defaults (512 items, 32-seed groups
+// below kBigGroupMin centres), 1,733 with the items alone and 1,657 with
+// the groups alone.
+constexpr int kBatchItems = 256;
+constexpr int kBatchSplitGroup = 64;
+
 void set_tiling(Call& c, const fms_params* p) {
-  const int wv = p->tile_waves > 0 ? p->tile_waves : (c.F == 1 ? kSingleFrameWaves : 0);
-  c.tile = fms::make_tiling(c.form, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
-  c.tile_fp32 = fms::make_tiling(fms::FORM_FP32, c.dp, p->tile_seeds, p->tile_items, p->tile_chunks, wv);
+  const bool batch = c.F > 1;
+  const int wv = p->tile_waves > 0 ? p->tile_waves : (batch ? 0 : kSingleFrameWaves);
+  const int items = p->tile_items > 0 ? p->tile_items : (batch ? kBatchItems : 0);
+  const int seeds =
+      p->tile_seeds > 0 ? p->tile_seeds : (batch && c.form == fms::FORM_SPLIT ? kBatchSplitGroup : 0);
+  c.tile = fms::make_tiling(c.form, c.dp, seeds, items, p->tile_chunks, wv);
+  c.tile_fp32 = fms::make_tiling(fms::FORM_FP32, c.dp, p->tile_seeds, items, p->tile_chunks, wv);
   // A caller-fixed group size holds for every launch.
   const int big = p->tile_seeds > 0 ? p->tile_seeds : kBigGroup;
-  c.tile_big = fms::make_tiling(c.form, c.dp, big, p->tile_items, p->tile_chunks, wv);
-  c.tile_fp32_big = fms::make_tiling(fms::FORM_FP32, c.dp, big, p->tile_items, p->tile_chunks, wv);
+  c.tile_big = fms::make_tiling(c.form, c.dp, big, items, p->tile_chunks, wv);
+  c.tile_fp32_big = fms::make_tiling(fms::FORM_FP32, c.dp, big, items, p->tile_chunks, wv);
   const int huge = p->tile_seeds > 0 ? p->tile_seeds : kHugeGroup;
-  c.tile_huge = fms::make_tiling(fms::FORM_BF16, c.dp, huge, p->tile_items, p->tile_chunks, wv);
-  c.tile_huge_split = fms::make_tiling(fms::FORM_SPLIT, c.dp, huge, p->tile_items, p->tile_chunks, wv);
-  // 128-seed split groups are compiled for four waves only: where more are
-  // asked for (single frames), the 64-seed tiling with them is faster.
-  if (wv > 0 && c.tile_huge_split.waves < wv) c.tile_huge_split = c.tile_big;
+  c.tile_huge = fms::make_tiling(fms::FORM_BF16, c.dp, huge, items, p->tile_chunks, wv);
 }
 
 // Chunk-partial rows a frame of `cap` centres needs under any tiling.
 int64_t partial_rows(const Call& c, int cap) {
   size_t r = std::max({fms::shift_partial_rows(c.tile, cap), fms::shift_partial_rows(c.tile_fp32, cap),
                        fms::shift_partial_rows(c.tile_big, cap), fms::shift_partial_rows(c.tile_fp32_big, cap),
-                       fms::shift_partial_rows(c.tile_huge, cap),
-                       fms::shift_partial_rows(c.tile_huge_split, cap)});
+                       fms::shift_partial_rows(c.tile_huge, cap)});
   if (c.tuned)
     for (const TunedTiling& t : *c.tuned)
       if (t.dp == c.dp) r = std::max(r, fms::shift_partial_rows(t.t, cap));
