@@ -133,7 +133,8 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const FrameGeo* __restrict
 
 // Gather the foreground rows in raster order, normalise them and write the
 // row layouts (FP32, and the BF16 high and low parts when asked; k_transpose
-// then writes the FP32 dimension-major copy when FP32 steps need it).  A work group takes kMaskBlockPix pixels: each thread owns 4
+// then writes the FP32 dimension-major copy when FP32 steps need it).  A
+// work group takes kMaskBlockPix pixels: each thread owns 4
 // consecutive pixels for the mask scan, the foreground pixels of the block go
 // to an LDS list in raster order, and then 8 lanes take each listed pixel
 // (lane q holds dimensions KD*q .. KD*q+KD-1), so a row is read and written
@@ -552,7 +553,8 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
 // centres, used to rank candidate modes).
 template <bool BF16, bool SPLIT, bool COUNT, int DP, int ST, int WV>
 __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const void* __restrict__ xt_,
-                                           const uint16_t* __restrict__ xrl, const float* __restrict__ y, const int* __restrict__ active, int n_act,
+                                           const uint16_t* __restrict__ xrl, const float* __restrict__ y,
+                                           const int* __restrict__ active, int n_act,
                                            const Tiling& tl, int n_blocks, int n_pix, float thr,
                                            float* __restrict__ partial, int* __restrict__ pcount, int wg, int nwg) {
   constexpr int KJ = DP / 4;     // dimensions held per lane group
@@ -1155,8 +1157,7 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
 // frame's modes (bits at tab.bits_m0, tab.words_m words per row).  A wave
 // owns 64 columns and 16 rows; each lane keeps its column vector in
 // registers and reads the row vectors, staged in LDS per work group, as
-// broadcasts.  Row strides are
-// multiples of 2 words.  With `first` (candidate columns = the rows, in rank
+// broadcasts.  Row strides are multiples of 2 words.  With `first` (candidate columns = the rows, in rank
 // order), first[j] is lowered to the first word of row j holding a column
 // c < j that is set (it must start at INT_MAX).
 template <int DP>
@@ -1613,11 +1614,12 @@ __global__ __launch_bounds__(256) void k_append_modes(int dp, const float* __res
 // tiles; the work group stages up to KT modes at a time in LDS.
 //
 // SPLIT (the split form's arithmetic): the pixels come as their BF16 high and
-// low parts (x16, x16l) and the modes split into the same; each similarity takes hi.hi + hi.lo + lo.hi on
-// v_mfma_f32_16x16x32_bf16 (lane (g, r) feeds dimensions 8g..8g+7 of mode r
-// and of pixel r per 32-dimension step), with the same output layout, so a
-// similarity is within 3 * 2^-16 of exact, as in the split form's steps.  The
-// modes are split once, as they are staged, into two BF16 LDS tiles.
+// low parts (x16, x16l) and the modes split into the same; each similarity
+// takes hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 (lane (g, r) feeds
+// dimensions 8g..8g+7 of mode r and of pixel r per 32-dimension step), with
+// the same output layout, so a similarity is within 3 * 2^-16 of exact, as in
+// the split form's steps.  The modes are split once, as they are staged, into
+// two BF16 LDS tiles.
 template <int DP, bool SPLIT>
 __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restrict__ x,
                                                 const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl,
