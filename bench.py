@@ -140,8 +140,8 @@ def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
     """Whole-frame throughput without instrumentation (median of event-timed
     calls), then the same number of frames again with per-launch kernel
     timing for the roofline figures."""
-    agg = {"step_ms": [0.0, 0.0], "step_updates": [0, 0], "step_launches": [0, 0], "updates": 0,
-           "refine_updates": 0}
+    agg = {"step_ms": [0.0, 0.0], "step_updates": [0, 0], "step_launches": [0, 0], "step_pixels": [0, 0],
+           "updates": 0, "refine_updates": 0}
     med, wall, last, res = _time_calls(torch, lambda: fms.cluster(emb, mask, h, precision=precision), steps, warmup)
     for r in res:
         agg["updates"] += r[2]["seed_pixel_updates"]
@@ -154,6 +154,7 @@ def _time_form(fms, torch, emb, mask, h, precision, steps, warmup):
             agg["step_ms"][k] += st["step_ms"][k]
             agg["step_updates"][k] += st["step_updates"][k]
             agg["step_launches"][k] += st["step_launches"][k]
+            agg["step_pixels"][k] += st["step_pixels"][k]
     torch.cuda.synchronize()
     return dt, agg, last
 
@@ -195,8 +196,9 @@ def _roofline(agg, dim, n_fg, form):
     """Roofline of the dominant kernel, the fused step of the form with the
     larger summed duration (the BF16 form's replay runs FP32 steps).  Its
     algorithmic work: 4 D flops per seed-pixel update, and per launch the
-    pixels once (n x D x b bytes, b from STEP_BYTES) plus the active centres in
-    and out (2 x N_act x D x 4).  A launch's floor is the larger of its MFMA
+    pixels of the frames it steps once (n x D x b bytes, b from STEP_BYTES;
+    the library counts n per stepped frame) plus the active centres in and out
+    (2 x N_act x D x 4).  A launch's floor is the larger of its MFMA
     and HBM times (the min of the two update rates); `bound` is the term that
     dominates the summed floors, and `frac` its achieved rate over its peak,
     which is the summed floor over the measured time."""
@@ -207,7 +209,8 @@ def _roofline(agg, dim, n_fg, form):
     launches = max(1, agg["step_launches"][k])
     flops = agg["step_updates"][k] * 4.0 * dim  # 2D for the dot product + 2D for the masked sum
     seeds = agg["step_updates"][k] / max(1, n_fg)
-    nbytes = launches * n_fg * dim * STEP_BYTES[kform] + 8.0 * dim * seeds
+    pixels = agg["step_pixels"][k]
+    nbytes = pixels * dim * STEP_BYTES[kform] + 8.0 * dim * seeds
     peak_f = PEAK_TFLOPS[STEP_PEAK[kform]]
     t_mfma = flops / (peak_f * 1e12)
     t_hbm = nbytes / (PEAK_HBM_GBPS * 1e9)
@@ -291,7 +294,7 @@ def _batched(fms, torch, a):
         upd = sum(r[2]["seed_pixel_updates"] + r[2]["refine_updates"] for rr in allres for r in rr)
         dt = med * 1e-3 * a.batch_steps
         st = fms.cluster_batch(inp, precision=prec, timing=1)[0][2]
-        agg = {k: list(st[k]) for k in ("step_ms", "step_updates", "step_launches")}
+        agg = {k: list(st[k]) for k in ("step_ms", "step_updates", "step_launches", "step_pixels")}
         out[name] = {"frames_per_s": nf * a.batch_steps / dt, "ms_per_batch": med,
                      "wall_ms_per_batch": 1e3 * wall / a.batch_steps,
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),

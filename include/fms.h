@@ -141,6 +141,8 @@ typedef struct {
   double step_ms[2];          /* summed launch durations (HIP events), ms */
   int64_t step_updates[2];    /* (active seeds) * n summed over those launches */
   int32_t step_launches[2];
+  int64_t step_pixels[2];     /* n summed over the frames those launches stepped
+                                 (the pixel rows they read) */
 } fms_stats;
 
 /* Fill *p with the paper's defaults (bandwidth 0.1, tol h/1000, gamma 0.9,

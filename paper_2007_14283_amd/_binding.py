@@ -107,6 +107,7 @@ class FmsStats(ctypes.Structure):
         ("step_ms", ctypes.c_double * 2),
         ("step_updates", ctypes.c_int64 * 2),
         ("step_launches", ctypes.c_int32 * 2),
+        ("step_pixels", ctypes.c_int64 * 2),
     ]
 
     def as_dict(self):

@@ -270,10 +270,10 @@ struct fms_handle_s {
     return e;
   }
   const int* hm(int f) const { return hpub.as<int>() + 4 + size_t(f) * META_COUNT; }
-  unsigned long long hm64(int f, int F) const {
+  unsigned long long hm64(int f, int F, int slot = 0) const {
     const unsigned long long* q =
         reinterpret_cast<const unsigned long long*>(hpub.as<int>() + 4 + size_t(F) * META_COUNT);
-    return q[size_t(f) * kMeta64];
+    return q[size_t(f) * kMeta64 + slot];
   }
 };
 
@@ -310,6 +310,7 @@ struct FrameHost {
 struct Timing {
   double step_ms[2] = {0.0, 0.0};
   int64_t step_updates[2] = {0, 0};
+  int64_t step_pixels[2] = {0, 0};
   int step_launches[2] = {0, 0};
 };
 
@@ -793,7 +794,10 @@ fms_status run_iterations(fms_handle h, Call& c, float* ybuf, int cap, double ga
     if (spec) ++t;
   }
   if (timing)
-    for (int f = 0; f < c.F; ++f) c.tm.step_updates[pk] += int64_t(h->hm64(f, c.F));
+    for (int f = 0; f < c.F; ++f) {
+      c.tm.step_updates[pk] += int64_t(h->hm64(f, c.F));
+      c.tm.step_pixels[pk] += int64_t(h->hm64(f, c.F, 1));
+    }
   return FMS_OK;
 }
 
@@ -871,7 +875,10 @@ void add_replay_stats(fms_handle h, Call& c, int f, Timing* tm) {
   fh.sx.refine_unconverged += hm[META_REFINE_BAD];
   fh.sx.refine_step_diff += hm[META_REFINE_DIFF];
   fh.sx.refine_gamma_cut += hm[fms::META_GCUT];
-  if (tm) tm->step_updates[0] += upd;
+  if (tm) {
+    tm->step_updates[0] += upd;
+    tm->step_pixels[0] += int64_t(h->hm64(f, c.F, 1));
+  }
 }
 
 // Bit-matrix layout of a device pruning pass: frame f's candidate x
@@ -1167,6 +1174,7 @@ void fill_stats(const Call& c, fms_stats* stats) {
   for (int k = 0; k < 2; ++k) {
     stats[0].step_ms[k] = c.tm.step_ms[k];
     stats[0].step_updates[k] = c.tm.step_updates[k];
+    stats[0].step_pixels[k] = c.tm.step_pixels[k];
     stats[0].step_launches[k] = c.tm.step_launches[k];
   }
 }

@@ -76,7 +76,8 @@ struct FrameDesc {
 // foreground count.  Frame f's counters are meta + f * META_COUNT and
 // meta64 + f * kMeta64.  Kernels with many work groups per frame take the
 // frame from blockIdx.y; kernels with one work group per frame from
-// blockIdx.x.
+// blockIdx.x.  meta64 slot 0: (active seeds) x n summed over the round's
+// steps; slot 1: n summed over them (the pixel rows they read).
 constexpr int kMeta64 = 4;
 struct FrameGeo {
   FrameDesc desc;  // source embeddings and mask

@@ -895,6 +895,7 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
       meta[META_ACT + ((ctl.iter + 1) & 1)] = 0;
       meta[META_STEPS] += 1;
       bt.meta64[(int64_t)f * kMeta64] += (unsigned long long)n_act * (unsigned long long)g.n;
+      bt.meta64[(int64_t)f * kMeta64 + 1] += (unsigned long long)g.n;
     }
   } else {
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
@@ -1147,6 +1148,7 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
     meta[META_STEPS] = 0;
     meta[META_GSTEP] = -1;
     meta64[0] = 0;
+    meta64[1] = 0;
   }
 }
 
@@ -1300,6 +1302,7 @@ __global__ __launch_bounds__(1024) void k_replay_begin(Batch bt, int ring_len, c
     meta[META_GSTEP] = -1;
     meta[META_GCUT] = 0;
     bt.meta64[(int64_t)f * kMeta64] = 0;
+    bt.meta64[(int64_t)f * kMeta64 + 1] = 0;
   }
 }
 
