@@ -523,6 +523,10 @@ __host__ __device__ inline ChunkPlan plan_chunks(int n_act, const Tiling& t, int
   return cp;
 }
 
+// Blocks per wave from which a step's waves load their pixel blocks
+// unconditionally (see shift_body).
+constexpr int kDeepBlocks = 8;
+
 // The fused mean-shift step (Eq. 8, 10, 11) for the active seeds.
 //
 // Work group = WV waves = one item: a group of 16*ST seeds and one pixel
@@ -588,7 +592,9 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
   __shared__ __align__(16) unsigned char lds_raw[LDS_BYTES];
   RedT& red = *reinterpret_cast<RedT*>(lds_raw);
   __shared__ int redc[COUNT ? WV - 1 : 1][ST][16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // The wave index is uniform within a wave: in a scalar register, the
+  // block loop's tests are scalar branches.
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint16_t* const stage = reinterpret_cast<uint16_t*>(lds_raw) + (STAGE ? wave * (SPLIT ? 2 : 1) * STAGE_ELEMS : 0);
   auto swz = [](int p) { return 2 * ((p >> 3) & (DP / 16 - 1)); };
   const int g = lane >> 4, r = lane & 15;
@@ -645,47 +651,58 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    // The first pixel blocks are requested before the seeds: the loads
-    // overlap instead of queueing behind each other.
     int b = b0 + wave;
-#pragma unroll
-    for (int k = 0; k < PD - 1; ++k)
-      if (b + k * WV < b1) load(k, b + k * WV);
     const int a0 = grp * 16 * ST;
     // Seed operands (B of S^T = X Y^T); low parts for the split form.
     AOp yb[ST][KS];
     bf16x8 ybl[ST][SPLIT ? KS : 1];
+    // Every lane loads: positions past the active count take the last
+    // active seed (n_act >= 1 here) and are zeroed after the loads, so no
+    // load sits behind a branch and all of them are in flight together (a
+    // branch per load makes the wave wait for each in turn).
+    auto load_seeds = [&]() {
+      int idx[ST];
 #pragma unroll
-    for (int s = 0; s < ST; ++s) {
-      const int a = a0 + 16 * s + r;
-      const float* yr =
-          a < n_act ? y + (int64_t)(active ? active[a] : a) * DP + g * KJ : nullptr;
-      if constexpr (BF16) {
+      for (int s = 0; s < ST; ++s) {
+        const int a = min(a0 + 16 * s + r, n_act - 1);
+        idx[s] = active ? active[a] : a;
+      }
+      float4 raw[ST][KJ / 4];
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-          float4 u = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-          float4 v = yr ? reinterpret_cast<const float4*>(yr + 8 * j)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const float e[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-          __bf16 hi[8], lo[8];
+      for (int s = 0; s < ST; ++s) {
+        const float4* yr = reinterpret_cast<const float4*>(y + (int64_t)idx[s] * DP + g * KJ);
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            hi[i] = (__bf16)e[i];
-            lo[i] = (__bf16)(e[i] - (float)hi[i]);
-          }
-          yb[s][j] = bf16x8{hi[0], hi[1], hi[2], hi[3], hi[4], hi[5], hi[6], hi[7]};
-          if constexpr (SPLIT) ybl[s][j] = bf16x8{lo[0], lo[1], lo[2], lo[3], lo[4], lo[5], lo[6], lo[7]};
-        }
-      } else {
+        for (int j = 0; j < KJ / 4; ++j) raw[s][j] = yr[j];
+      }
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        const bool ok = a0 + 16 * s + r < n_act;
+        float e[KJ];
 #pragma unroll
         for (int j = 0; j < KJ / 4; ++j) {
-          float4 u = yr ? reinterpret_cast<const float4*>(yr)[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-          yb[s][4 * j] = u.x;
-          yb[s][4 * j + 1] = u.y;
-          yb[s][4 * j + 2] = u.z;
-          yb[s][4 * j + 3] = u.w;
+          e[4 * j] = ok ? raw[s][j].x : 0.f;
+          e[4 * j + 1] = ok ? raw[s][j].y : 0.f;
+          e[4 * j + 2] = ok ? raw[s][j].z : 0.f;
+          e[4 * j + 3] = ok ? raw[s][j].w : 0.f;
+        }
+        if constexpr (BF16) {
+#pragma unroll
+          for (int j = 0; j < KS; ++j) {
+            __bf16 hi[8], lo[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              hi[i] = (__bf16)e[8 * j + i];
+              lo[i] = (__bf16)(e[8 * j + i] - (float)hi[i]);
+            }
+            yb[s][j] = bf16x8{hi[0], hi[1], hi[2], hi[3], hi[4], hi[5], hi[6], hi[7]};
+            if constexpr (SPLIT) ybl[s][j] = bf16x8{lo[0], lo[1], lo[2], lo[3], lo[4], lo[5], lo[6], lo[7]};
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < KJ; ++i) yb[s][i] = e[i];
         }
       }
-    }
+    };
     f32x4 acc[ST][NDB];
     int cnt[ST];
 #pragma unroll
@@ -784,11 +801,45 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
         }
       }
     };
-    for (; b < b1; b += PD * WV) {
+    // The first pixel blocks are requested before the seeds, so the loads
+    // overlap instead of queueing behind each other.  A wave with at least
+    // kDeepBlocks blocks loads unconditionally, past its last block from that
+    // block again (a cache hit): the compiler then knows how many loads are
+    // younger than a block's and waits for that block alone, keeping PD - 1
+    // blocks in flight.  Conditional loads make it wait for every load in
+    // flight, which short runs of blocks tolerate better than the extra loads.
+    // (Sixteen-wave groups, at 128 registers per lane, keep to the second
+    // form.)
+    const int nbw = b < b1 ? (b1 - 1 - b) / WV + 1 : 0;
+    if (WV < 16 && nbw >= kDeepBlocks) {
+      const int bl = b + (nbw - 1) * WV;
 #pragma unroll
-      for (int u = 0; u < PD; ++u) {
-        if (b + (u + PD - 1) * WV < b1) load((u + PD - 1) % PD, b + (u + PD - 1) * WV);
+      for (int k = 0; k < PD - 1; ++k) load(k, min(b + k * WV, bl));
+      load_seeds();
+      // Whole rounds of PD blocks run without a test, so the scheduler can
+      // overlap one block's products with the next one's.
+      for (; b + (PD - 1) * WV < b1; b += PD * WV) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+          load((u + PD - 1) % PD, min(b + (u + PD - 1) * WV, bl));
+          compute(u, b + u * WV);
+        }
+      }
+      // Fewer than PD blocks are left, all of them loaded.
+#pragma unroll
+      for (int u = 0; u < PD - 1; ++u)
         if (b + u * WV < b1) compute(u, b + u * WV);
+    } else {
+#pragma unroll
+      for (int k = 0; k < PD - 1; ++k)
+        if (b + k * WV < b1) load(k, b + k * WV);
+      load_seeds();
+      for (; b < b1; b += PD * WV) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+          if (b + (u + PD - 1) * WV < b1) load((u + PD - 1) % PD, b + (u + PD - 1) * WV);
+          if (b + u * WV < b1) compute(u, b + u * WV);
+        }
       }
     }
     if constexpr (COUNT) {
@@ -875,18 +926,23 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
   if (pcount) pcount += g.part0;
   int n_act;
   if (ctl.iter >= 0) {
-    if (meta[META_DONE]) return;
-    n_act = meta[META_ACT + (ctl.iter & 1)];
+    // Every counter is read before the one test (a single round trip; a
+    // test per counter would wait for each).
+    const int done = meta[META_DONE];
+    const int act0 = meta[META_ACT], act1 = meta[META_ACT + 1];
+    n_act = (ctl.iter & 1) ? act1 : act0;
     const int n_conv = meta[META_NCONV];
+    const int n_sel = meta[META_NSEL];
+    const int gstep = meta[META_GSTEP];
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
     // Same test, in the same precision, as the host's between batches.  A
     // step that is the first to see more than gamma converged records
     // itself; every work group of it counts 0 steps past that point whether
     // or not it sees the record, so they all decide alike.
-    const bool over = (double)n_conv > ctl.gamma * (double)meta[META_NSEL];
-    const int gstep = meta[META_GSTEP];
+    const bool over = (double)n_conv > ctl.gamma * (double)n_sel;
     const int past = (over && gstep >= 0) ? ctl.iter - gstep : 0;
-    if (n_act <= 0 || (over && past >= ctl.extra)) {
+    if ((done != 0) | (n_act <= 0) | (over & (past >= ctl.extra))) {
+      // Setting the flag again when it is set is harmless.
       if (first) meta[META_DONE] = 1;
       return;
     }
