@@ -1,5 +1,6 @@
 """Benchmark: frames/sec and seed x pixel updates/sec of Faster Mean-shift on one
-MI355X, 512 x 512 frame, D = 32, BF16 + FP32-replay form against the FP32 form.
+MI355X, 512 x 512 frame, D = 32, in the three arithmetic forms (split BF16, FP32,
+BF16 + FP32 replay).
 
 One step = one fms_cluster call on one frame already resident in HBM: compaction
 and normalisation, the seed rounds of the online seed policy (seed selection,
@@ -7,11 +8,12 @@ fused mean-shift iterations, window counts, pruning, coverage), and the labels.
 Every call is bracketed by HIP events on the stream the library works on; the
 figure is the median over the timed calls, after the warm-up calls.
 
-Prints one JSON line.  ``value`` is BF16+FP32-replay frames/sec; the FP32 form
-(``value_fp32``), update rates, both forms' mode error against the FP64 oracle,
-the roofline of the dominant kernel (live HIP-event timings from the library),
-the 128 x 128 workload, and the oracle's CPU rate on the same frames (all
-threads and one thread) are carried alongside.
+Prints one JSON line.  ``value`` is the split BF16 form's frames/sec (it meets
+the FP32 accuracy bar); the FP32 form (``value_fp32``), the BF16 + FP32 replay
+form, update rates, every form's mode error against the FP64 oracle, the
+roofline of the dominant kernel (live HIP-event timings from the library), the
+128 x 128, 1024 x 1024 and 64-frame batched workloads, and the oracle's CPU
+rate on the same frames (all threads and one thread) are carried alongside.
 """
 from __future__ import annotations
 
@@ -175,9 +177,10 @@ def kernel_source_hash():
 
 def _measured_traffic(form):
     """HBM bytes per launch of the fused step of a form (fp32, bf16, split) on
-    the 512x512 frame from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources have
-    changed since the counters were taken."""
+    the 512x512 frame, or of the split form on the 64-frame batch
+    ("batch_split"), from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy); None when the kernel sources have
+    changed since the counters were taken, or for a case not measured."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = kernel_source_hash()
@@ -192,7 +195,7 @@ def _measured_traffic(form):
     return None
 
 
-def _roofline(agg, dim, n_fg, form):
+def _roofline(agg, dim, n_fg, form, traffic_key=""):
     """Roofline of the dominant kernel, the fused step of the form with the
     larger summed duration (the BF16 form's replay runs FP32 steps).  Its
     algorithmic work: 4 D flops per seed-pixel update, and per launch the
@@ -221,7 +224,7 @@ def _roofline(agg, dim, n_fg, form):
     else:
         bound, achieved, peak, unit = "mfma", tflops, peak_f, "TFLOP/s"
     return {"kernel": "k_shift_" + kform, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": _measured_traffic(kform),
+            "frac": achieved / peak, "traffic": _measured_traffic(traffic_key + kform),
             "algorithmic_bytes_per_launch": nbytes / launches, "flops_per_launch": flops / launches,
             "avg_launch_us": ms * 1e3 / launches, "launches": agg["step_launches"][k],
             "mean_active_seeds": seeds / launches,
@@ -299,7 +302,8 @@ def _batched(fms, torch, a):
                      "wall_ms_per_batch": 1e3 * wall / a.batch_steps,
                      "updates_per_s": upd / dt, "modes": int(sum(len(r[0]) for r in res)),
                      "roofline": _roofline(agg, specs[0].dim, out["n_fg_total"],
-                                           {fms.FP32: "fp32", fms.BF16_REFINE: "bf16", fms.BF16_SPLIT: "split"}[prec]),
+                                           {fms.FP32: "fp32", fms.BF16_REFINE: "bf16", fms.BF16_SPLIT: "split"}[prec],
+                                           traffic_key="batch_"),
                      "vs_oracle": _batch_accuracy(frames, res, 1e-3 if prec == fms.BF16_REFINE else 1e-5)}
         del res, allres
     # Autotuned tiles: fms_autotune_batch on these frames (split BF16 form);
