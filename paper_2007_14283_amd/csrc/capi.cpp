@@ -477,6 +477,10 @@ fms_status upload_geo(fms_handle h, Call& c) {
 }
 
 fms_status upload_rt(fms_handle h, Call& c) {
+  if (c.b.rt_inline) {
+    c.b.rt0 = c.fr[0].rt;
+    return FMS_OK;
+  }
   if (h->hrt.busy) HIP_TRY(h->wait(c.st));
   fms::RoundTab* hr = h->hrt.as<fms::RoundTab>();
   for (int f = 0; f < c.F; ++f) hr[f] = c.fr[f].rt;
@@ -572,6 +576,9 @@ fms_status setup_call(fms_handle h, Call& c, const fms_frame* frames, const fms_
   c.b.rt = h->rt.as<fms::RoundTab>();
   c.b.meta = h->meta.as<int>();
   c.b.meta64 = reinterpret_cast<unsigned long long*>(h->meta.as<int>() + size_t(F) * META_COUNT);
+  // A single frame's round table goes with every launch, except under graph
+  // capture, whose replays keep the arguments they were captured with.
+  c.b.rt_inline = (F == 1 && !c.graphs) ? 1 : 0;
   int64_t mblk = 0;
   for (int f = 0; f < F; ++f) {
     const fms_frame& in = frames[f];

@@ -113,7 +113,14 @@ struct Batch {
   int max_n;           // largest foreground count
   int max_blocks;      // largest 32-pixel block count
   int64_t max_mblk;    // largest mask block count
+  // Single-frame calls carry their round table in the launch arguments
+  // (rt_inline), which saves a copy to the device per round.
+  int rt_inline;
+  RoundTab rt0;
 };
+// The round table of frame f of a launch (a copy: a reference into the
+// launch arguments would make the compiler copy them to scratch memory).
+__host__ __device__ inline RoundTab round_tab(const Batch& b, int f) { return b.rt_inline ? b.rt0 : b.rt[f]; }
 constexpr int kMaskBlockPix = 1024;
 // Eligibility bytes a frame of n foreground pixels needs (whole 16-byte
 // words plus one word of zero padding).

@@ -358,21 +358,19 @@ __global__ __launch_bounds__(256) void k_seed_order(const FrameGeo* __restrict__
 // a pass may start at the cursor rounded down to RUN; `elig` is zero-padded
 // to a multiple of 16, and a 16-byte word is read only when it starts below
 // n.
-__global__ __launch_bounds__(1024) void k_select(const FrameGeo* __restrict__ geo, const RoundTab* __restrict__ rt,
-                                                 const int* __restrict__ order, uint8_t* __restrict__ elig,
-                                                 int* __restrict__ meta, int* __restrict__ seed_pos,
-                                                 int* __restrict__ seed_fg) {
+__global__ __launch_bounds__(1024) void k_select(Batch bt, const int* __restrict__ order, uint8_t* __restrict__ elig,
+                                                 int* __restrict__ seed_pos, int* __restrict__ seed_fg) {
   constexpr int RUN = 16;
   __shared__ int sh[17];
   __shared__ int s_last;
   __shared__ int s_base;
-  const FrameGeo& g = geo[blockIdx.x];
-  const int n = g.n, want = rt[blockIdx.x].want;
+  const FrameGeo& g = bt.geo[blockIdx.x];
+  const int n = g.n, want = round_tab(bt, blockIdx.x).want;
   order += g.row0;
   elig += g.elig0;
   seed_pos += g.row0;
   seed_fg += g.row0;
-  meta += (int64_t)blockIdx.x * META_COUNT;
+  int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
   if (threadIdx.x == 0) s_base = meta[META_CURSOR] & ~(RUN - 1);
   __syncthreads();
   int base = s_base;
@@ -954,7 +952,7 @@ __global__ __launch_bounds__(64 * WV) void k_shift(Batch bt, const void* __restr
       bt.meta64[(int64_t)f * kMeta64 + 1] += (unsigned long long)g.n;
     }
   } else {
-    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : round_tab(bt, f).nact;
   }
   if (n_act <= 0) return;
   shift_body<BF16, SPLIT, COUNT, DP, ST, WV>(xrm, xt, xrl, y, active, n_act, tl, g.n_blocks, g.n, g.thr,
@@ -1139,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
     n_act = meta[META_ACT + (ctl.iter & 1)];
     next_ctr = meta + META_ACT + ((ctl.iter + 1) & 1);
   } else {
-    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : bt.rt[f].nact;
+    n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : round_tab(bt, f).nact;
   }
   const int conv = reduce_body<DP>(partial, active, ycur, y, state, iters, next_active, yc_next, vnorm, next_ctr,
                                    ring, ring_stride, ring_len, n_act, tl, g.n_blocks, g.tol, mode, (int)blockIdx.x,
@@ -1152,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_reduce_counts(Batch bt, const int* __re
                                                        int* __restrict__ counts) {
   const int f = blockIdx.y;
   const FrameGeo& g = bt.geo[f];
-  const int m = m_slot >= 0 ? bt.meta[(int64_t)f * META_COUNT + m_slot] : bt.rt[f].nact;
+  const int m = m_slot >= 0 ? bt.meta[(int64_t)f * META_COUNT + m_slot] : round_tab(bt, f).nact;
   pcount += g.part0;
   counts += g.row0;
   const int n_chunks = plan_chunks(m, tl, g.n_blocks).n_chunks;
@@ -1181,7 +1179,7 @@ __global__ __launch_bounds__(256) void k_round_begin(Batch bt, int cap, int nsel
   y += g.row0 * DP;
   x32 += g.row0 * DP;
   if (seed_fg) seed_fg += g.row0;
-  const int m = nsel_from_rt ? bt.rt[f].nact : meta[META_NSEL];
+  const int m = nsel_from_rt ? round_tab(bt, f).nact : meta[META_NSEL];
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < m && k < cap) {
     active[k] = k;
@@ -1230,7 +1228,7 @@ __global__ __launch_bounds__(256) void k_simbits(Batch bt, const float* __restri
   const int* cols = mode_part ? nullptr : cols_;
   const float* colmat = mode_part ? colmat_ : nullptr;
   const FrameGeo& g = bt.geo[f];
-  const RoundTab& tab = bt.rt[f];
+  const RoundTab tab = round_tab(bt, f);
   const int* meta = bt.meta + (int64_t)f * META_COUNT;
   const int m = meta[rows_slot];
   const int ncols = cols ? meta[cols_slot] : tab.k_modes;
@@ -1559,7 +1557,7 @@ __global__ __launch_bounds__(1024) void k_greedy(Batch bt, const uint32_t* __res
   __shared__ int s_open;
   __shared__ int sh[17];
   const FrameGeo& g = bt.geo[blockIdx.x];
-  const RoundTab& tab = bt.rt[blockIdx.x];
+  const RoundTab tab = round_tab(bt, blockIdx.x);
   int* meta = bt.meta + (int64_t)blockIdx.x * META_COUNT;
   const uint32_t* bits_c = bits + tab.bits_c0;
   const uint32_t* bits_m = bits + tab.bits_m0;
@@ -1697,8 +1695,8 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
   const int n = g.n;
   if ((int)blockIdx.x * 64 * PT >= n) return;
   int* meta = bt.meta + (int64_t)f * META_COUNT;
-  const int k0 = mode == 0 ? bt.rt[f].k_modes : 0;
-  const int k1 = mode == 0 ? k0 + meta[k1_slot] : bt.rt[f].k_modes;
+  const int k0 = mode == 0 ? round_tab(bt, f).k_modes : 0;
+  const int k1 = mode == 0 ? k0 + meta[k1_slot] : round_tab(bt, f).k_modes;
   const float thr = g.thr;
   int* labels = g.labels;
   if (SPLIT) {
@@ -1859,13 +1857,13 @@ __global__ __launch_bounds__(256) void k_assign(Batch bt, const float* __restric
 __global__ __launch_bounds__(256) void k_iota(Batch bt, int* __restrict__ p) {
   const int f = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < bt.rt[f].nact) p[bt.geo[f].row0 + i] = i;
+  if (i < round_tab(bt, f).nact) p[bt.geo[f].row0 + i] = i;
 }
 
 // meta[slot] of every frame from rt.nact (from_rt) or to `value`.
 __global__ __launch_bounds__(256) void k_set_slot(Batch bt, int slot, int from_rt, int value) {
   const int f = blockIdx.x * 256 + threadIdx.x;
-  if (f < bt.F) bt.meta[(int64_t)f * META_COUNT + slot] = from_rt ? bt.rt[f].nact : value;
+  if (f < bt.F) bt.meta[(int64_t)f * META_COUNT + slot] = from_rt ? round_tab(bt, f).nact : value;
 }
 
 // Copy every frame's counters (n_words 32-bit words from bt.meta, which the
@@ -1896,7 +1894,7 @@ __global__ __launch_bounds__(256) void k_modes_out(Batch bt, const float* __rest
                                                    int* __restrict__ out_counts) {
   const int f = blockIdx.y;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int k = bt.rt[f].k_modes;
+  const int k = round_tab(bt, f).k_modes;
   if (t >= (int64_t)k * dim) return;
   const int64_t r = t / dim, d = t - r * dim;
   const int64_t src = bt.geo[f].row0 + r, dst = (int64_t)out_off[f] + r;
@@ -2141,7 +2139,7 @@ hipError_t launch_seed_order_plain(hipStream_t s, int n, int half_bits, const ui
 
 hipError_t launch_select(hipStream_t s, const Batch& b, const int* order, uint8_t* elig, int* seed_pos,
                          int* seed_fg) {
-  hipLaunchKernelGGL(k_select, dim3(b.F), dim3(1024), 0, s, b.geo, b.rt, order, elig, b.meta, seed_pos, seed_fg);
+  hipLaunchKernelGGL(k_select, dim3(b.F), dim3(1024), 0, s, b, order, elig, seed_pos, seed_fg);
   return hipGetLastError();
 }
 
