@@ -1133,8 +1133,12 @@ __global__ __launch_bounds__(256) void k_reduce(Batch bt, const float* __restric
   int n_act;
   int* next_ctr = nullptr;
   if (ctl.iter >= 0) {
-    if (meta[META_DONE]) return;
-    n_act = meta[META_ACT + (ctl.iter & 1)];
+    // The counters are read before the one test (a single round trip); a
+    // reduction of no seeds has nothing to do either.
+    const int done = meta[META_DONE];
+    const int act0 = meta[META_ACT], act1 = meta[META_ACT + 1];
+    n_act = (ctl.iter & 1) ? act1 : act0;
+    if ((done != 0) | (n_act <= 0)) return;
     next_ctr = meta + META_ACT + ((ctl.iter + 1) & 1);
   } else {
     n_act = ctl.nact_slot >= 0 ? meta[ctl.nact_slot] : round_tab(bt, f).nact;
