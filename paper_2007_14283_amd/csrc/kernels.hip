@@ -186,63 +186,97 @@ __global__ __launch_bounds__(256) void k_compact(const FrameGeo* __restrict__ ge
   __syncthreads();
   int bad = 0;
   const int q = lane & 7;
-  for (int k = (int)threadIdx.x / 8; k < total; k += 32) {
-    const int64_t p = blk0 + lp[k];
-    const int ord = ord0 + k;
-    if (ord >= row_cap) break;  // beyond the layouts' rows (the caller reports it)
-    const float* src = f.emb + p * f.pixel_stride;
-    float v[KD];
-    float mx = 0.f;
-    bool finite = true;
+  // U pixels per 8-lane group per pass, their loads issued together (one
+  // pixel at a time leaves a work group waiting on one load chain after
+  // another).  Positions past the list or past row_cap load the group's
+  // first pixel again and are not written.
+  constexpr int U = 4;
+  // Pixel-major rows of whole 16-byte words (the usual H x W x D layout with
+  // D a multiple of 4) are read with 16-byte loads.
+  const bool vec = f.channel_stride == 1 && f.pixel_stride % 4 == 0 && f.dim % 4 == 0 &&
+                   (reinterpret_cast<uintptr_t>(f.emb) & 15) == 0;
+  for (int k0 = (int)threadIdx.x / 8; k0 < total; k0 += 32 * U) {
+    float v[U][KD];
+    int64_t pix[U];
+    bool live[U];
 #pragma unroll
-    for (int j = 0; j < KD; ++j) {
-      const int d = KD * q + j;
-      v[j] = d < f.dim ? src[(int64_t)d * f.channel_stride] : 0.f;
-      finite = finite && __builtin_isfinite(v[j]);
-      mx = fmaxf(mx, fabsf(v[j]));
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 32 * u;
+      live[u] = k < total && ord0 + k < row_cap;  // beyond the layouts' rows: the caller reports it
+      pix[u] = blk0 + lp[live[u] ? k : k0];
+      const float* src = f.emb + pix[u] * f.pixel_stride;
+      if (vec) {
+#pragma unroll
+        for (int j = 0; j < KD; j += 4) {
+          const int d = KD * q + j;
+          const float4 w = d < f.dim ? *reinterpret_cast<const float4*>(src + d) : make_float4(0.f, 0.f, 0.f, 0.f);
+          v[u][j] = w.x;
+          v[u][j + 1] = w.y;
+          v[u][j + 2] = w.z;
+          v[u][j + 3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < KD; ++j) {
+          const int d = KD * q + j;
+          v[u][j] = d < f.dim ? src[(int64_t)d * f.channel_stride] : 0.f;
+        }
+      }
     }
-    // The 8 lanes of the pixel agree on the largest magnitude and on
-    // finiteness; the row is scaled by a power of two first (exact), so the
-    // sum of squares neither overflows nor underflows.
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-      mx = fmaxf(mx, __shfl_xor(mx, m, 64));
-      finite = (__shfl_xor(finite ? 1 : 0, m, 64) != 0) && finite;
-    }
-    const bool ok = finite && mx > 0.f;
-    int ex = 0;
-    if (ok) frexpf(mx, &ex);
-    float ss = 0.f;
+    for (int u = 0; u < U; ++u) {
+      const int ord = ord0 + k0 + 32 * u;
+      float mx = 0.f;
+      bool finite = true;
 #pragma unroll
-    for (int j = 0; j < KD; ++j) {
-      v[j] = ok ? ldexpf(v[j], -ex) : 0.f;
-      ss = fmaf(v[j], v[j], ss);
-    }
+      for (int j = 0; j < KD; ++j) {
+        finite = finite && __builtin_isfinite(v[u][j]);
+        mx = fmaxf(mx, fabsf(v[u][j]));
+      }
+      // The 8 lanes of the pixel agree on the largest magnitude and on
+      // finiteness; the row is scaled by a power of two first (exact), so the
+      // sum of squares neither overflows nor underflows.
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) ss += __shfl_xor(ss, m, 64);
-    const float inv = ok ? 1.0f / sqrtf(ss) : 0.f;
-    if (q == 0) {
-      bad += ok ? 0 : 1;
-      fg_idx[ord] = (int)p;
-      if (enorm) enorm[ord] = ok ? ldexpf(sqrtf(ss), ex) : 0.f;  // |e| of the raw row
-    }
-    float* rowp = x32 + (int64_t)ord * DP + KD * q;
+      for (int m = 1; m < 8; m <<= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+        finite = (__shfl_xor(finite ? 1 : 0, m, 64) != 0) && finite;
+      }
+      const bool ok = finite && mx > 0.f;
+      int ex = 0;
+      if (ok) frexpf(mx, &ex);
+      float ss = 0.f;
 #pragma unroll
-    for (int j = 0; j < KD; j += 4) {
-      const float4 v4 = make_float4(v[j] * inv, v[j + 1] * inv, v[j + 2] * inv, v[j + 3] * inv);
-      *reinterpret_cast<float4*>(rowp + j) = v4;
-      if (!x16) continue;
-      const int d = KD * q + j;
-      const uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
-                     b3 = to_bf16_bits(v4.w);
-      *reinterpret_cast<uint2*>(x16 + (int64_t)ord * DP + d) =
-          make_uint2((uint32_t)b0 | ((uint32_t)b1 << 16), (uint32_t)b2 | ((uint32_t)b3 << 16));
-      if (!xlo) continue;
-      // Low parts: the BF16 rounding of what the high part leaves.
-      const uint16_t l0 = low_bf16_bits(v4.x, b0), l1 = low_bf16_bits(v4.y, b1), l2 = low_bf16_bits(v4.z, b2),
-                     l3 = low_bf16_bits(v4.w, b3);
-      *reinterpret_cast<uint2*>(xlo + (int64_t)ord * DP + d) =
-          make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
+      for (int j = 0; j < KD; ++j) {
+        v[u][j] = ok ? ldexpf(v[u][j], -ex) : 0.f;
+        ss = fmaf(v[u][j], v[u][j], ss);
+      }
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1) ss += __shfl_xor(ss, m, 64);
+      if (!live[u]) continue;
+      const float inv = ok ? 1.0f / sqrtf(ss) : 0.f;
+      if (q == 0) {
+        bad += ok ? 0 : 1;
+        fg_idx[ord] = (int)pix[u];
+        if (enorm) enorm[ord] = ok ? ldexpf(sqrtf(ss), ex) : 0.f;  // |e| of the raw row
+      }
+      float* rowp = x32 + (int64_t)ord * DP + KD * q;
+#pragma unroll
+      for (int j = 0; j < KD; j += 4) {
+        const float4 v4 = make_float4(v[u][j] * inv, v[u][j + 1] * inv, v[u][j + 2] * inv, v[u][j + 3] * inv);
+        *reinterpret_cast<float4*>(rowp + j) = v4;
+        if (!x16) continue;
+        const int d = KD * q + j;
+        const uint16_t b0 = to_bf16_bits(v4.x), b1 = to_bf16_bits(v4.y), b2 = to_bf16_bits(v4.z),
+                       b3 = to_bf16_bits(v4.w);
+        *reinterpret_cast<uint2*>(x16 + (int64_t)ord * DP + d) =
+            make_uint2((uint32_t)b0 | ((uint32_t)b1 << 16), (uint32_t)b2 | ((uint32_t)b3 << 16));
+        if (!xlo) continue;
+        // Low parts: the BF16 rounding of what the high part leaves.
+        const uint16_t l0 = low_bf16_bits(v4.x, b0), l1 = low_bf16_bits(v4.y, b1), l2 = low_bf16_bits(v4.z, b2),
+                       l3 = low_bf16_bits(v4.w, b3);
+        *reinterpret_cast<uint2*>(xlo + (int64_t)ord * DP + d) =
+            make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
+      }
     }
   }
   bad = wave_sum_i(bad);
