@@ -834,16 +834,17 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
       }
     };
     // The first pixel blocks are requested before the seeds, so the loads
-    // overlap instead of queueing behind each other.  A wave with at least
-    // kDeepBlocks blocks loads unconditionally, past its last block from that
-    // block again (a cache hit): the compiler then knows how many loads are
-    // younger than a block's and waits for that block alone, keeping PD - 1
-    // blocks in flight.  Conditional loads make it wait for every load in
-    // flight, which short runs of blocks tolerate better than the extra loads.
-    // (Sixteen-wave groups, at 128 registers per lane, keep to the second
-    // form.)
+    // overlap instead of queueing behind each other.  In plain BF16 steps a
+    // wave with at least kDeepBlocks blocks loads unconditionally, past its
+    // last block from that block again (a cache hit): the compiler then knows
+    // how many loads are younger than a block's and waits for that block
+    // alone, keeping PD - 1 blocks in flight.  Conditional loads make it wait
+    // for every load in flight, which short runs of blocks, and the FP32 and
+    // split steps, whose products per block hide more, tolerate better than
+    // the extra loads and registers.
+    constexpr bool DEEP = BF16 && !SPLIT && !COUNT && WV < 16;
     const int nbw = b < b1 ? (b1 - 1 - b) / WV + 1 : 0;
-    if (WV < 16 && nbw >= kDeepBlocks) {
+    if (DEEP && nbw >= kDeepBlocks) {
       const int bl = b + (nbw - 1) * WV;
 #pragma unroll
       for (int k = 0; k < PD - 1; ++k) load(k, min(b + k * WV, bl));
