@@ -834,15 +834,16 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
       }
     };
     // The first pixel blocks are requested before the seeds, so the loads
-    // overlap instead of queueing behind each other.  In plain BF16 steps a
-    // wave with at least kDeepBlocks blocks loads unconditionally, past its
-    // last block from that block again (a cache hit): the compiler then knows
-    // how many loads are younger than a block's and waits for that block
-    // alone, keeping PD - 1 blocks in flight.  Conditional loads make it wait
-    // for every load in flight, which short runs of blocks, and the FP32 and
-    // split steps, whose products per block hide more, tolerate better than
-    // the extra loads and registers.
-    constexpr bool DEEP = BF16 && !SPLIT && !COUNT && WV < 16;
+    // overlap instead of queueing behind each other.  A wave with at least
+    // kDeepBlocks blocks loads unconditionally, past its last block from that
+    // block again (a cache hit): the compiler then knows how many loads are
+    // younger than a block's and waits for that block alone, keeping PD - 1
+    // blocks in flight.  Conditional loads make it wait for every load in
+    // flight, which short runs of blocks tolerate better than the extra
+    // loads, and so do eight-wave groups of FP32 and split steps (two waves
+    // per SIMD, whose products per block hide more); four-wave groups (one
+    // wave per SIMD) and plain BF16 steps gain.
+    constexpr bool DEEP = WV == 4 || (BF16 && !SPLIT && !COUNT && WV == 8);
     const int nbw = b < b1 ? (b1 - 1 - b) / WV + 1 : 0;
     if (DEEP && nbw >= kDeepBlocks) {
       const int bl = b + (nbw - 1) * WV;
