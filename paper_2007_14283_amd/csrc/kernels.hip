@@ -792,11 +792,23 @@ __device__ __forceinline__ void shift_body(const void* __restrict__ xrm_, const 
           }
         }
         if constexpr (COUNT) {
-          const int pbase = b * kBlockPix + 8 * g;
+          if ((int64_t)(b + 1) * kBlockPix <= n_pix) {
+            // Every pixel of the block is real: the lane's eight results lose
+            // their negative ones, counted from the sign bits (v_perm
+            // selectors 9 and 11 give 0xff for a negative low or high source
+            // dword, 12 gives 0), four to a popcount.
+            const uint32_t n0 = __builtin_amdgcn_perm(fbits(s0[1]), fbits(s0[0]), 0x0C0C0B09u) |
+                                __builtin_amdgcn_perm(fbits(s0[3]), fbits(s0[2]), 0x0B090C0Cu);
+            const uint32_t n1 = __builtin_amdgcn_perm(fbits(s1[1]), fbits(s1[0]), 0x0C0C0B09u) |
+                                __builtin_amdgcn_perm(fbits(s1[3]), fbits(s1[2]), 0x0B090C0Cu);
+            cnt[s] += 8 - __builtin_popcount(n0 & 0x01010101u) - __builtin_popcount(n1 & 0x01010101u);
+          } else {
+            const int pbase = b * kBlockPix + 8 * g;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            cnt[s] += ((fbits(s0[i]) >> 31) == 0u && pbase + i < n_pix) ? 1 : 0;
-            cnt[s] += ((fbits(s1[i]) >> 31) == 0u && pbase + 4 + i < n_pix) ? 1 : 0;
+            for (int i = 0; i < 4; ++i) {
+              cnt[s] += ((fbits(s0[i]) >> 31) == 0u && pbase + i < n_pix) ? 1 : 0;
+              cnt[s] += ((fbits(s1[i]) >> 31) == 0u && pbase + 4 + i < n_pix) ? 1 : 0;
+            }
           }
         } else if constexpr (BF16) {
           // Pixels 8g..8g+3 come from tile 0, 8g+4..8g+7 from tile 1.
