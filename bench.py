@@ -201,7 +201,9 @@ def _roofline(agg, dim, n_fg, form, traffic_key=""):
     algorithmic work: 4 D flops per seed-pixel update, and per launch the
     pixels of the frames it steps once (n x D x b bytes, b from STEP_BYTES;
     the library counts n per stepped frame) plus the active centres in and out
-    (2 x N_act x D x 4).  A launch's floor is the larger of its MFMA
+    (2 x N_act x D x 4, N_act taken as updates / n: exact for one frame, a
+    size-weighted mean over a batch's frames, kilobytes against the pixels'
+    megabytes either way).  A launch's floor is the larger of its MFMA
     and HBM times (the min of the two update rates); `bound` is the term that
     dominates the summed floors, and `frac` its achieved rate over its peak,
     which is the summed floor over the measured time."""
